@@ -1,0 +1,438 @@
+"""FP64 particle-mesh TILD step: spread, transforms, k-space kernel, forces,
+energies, virial, bonds and the Euler-Maruyama update.
+
+Test infrastructure only (see the package docstring).
+
+Conventions (the paper leaves them open; these are the readings used):
+  * Grid nodes sit at g * h from the box corner, h_a = L_a / M_a; arrays are
+    indexed [x, y, z].
+  * "Order" P is the number of grid points per dimension that a bead touches
+    (P = 2 is the paper's two-nearest-points first-order scheme, Fig. pmm).
+    The weight is the centred cardinal B-spline B_P (the Deserno-Holm
+    charge-assignment function), evaluated here by the Cox-de Boor
+    recursion.  A bead at u = x/h touches g = g0 + j, j = 0..P-1 with
+    g0 = floor(u - P/2) + 1, indices taken modulo M.
+  * Forward DFT c^(n) = sum_g c(g) exp(-2 pi i n.g/M); signed index n' = n - M
+    for n > M/2; k = 2 pi n'/L.  For the ik derivative, k^D = k except on the
+    Nyquist plane of an even axis, where it is zero.
+  * Smeared pair kernel u_G = h * h with sigma^2 = 2 a^2, so its transform is
+    u^(k) = exp(-a^2 k^2) (analytic; the sampled variant is provided too).
+  * With c_K the assignment counts, the non-bonded energy is
+    E = (chi/N) sum_n u^ Re(c^_A* c^_B) + (kappa/2N) sum_{n != 0} u^ |c^_A + c^_B|^2,
+    i.e. Eqs. fh and HelfandP with rho_0 = N/V and the grid sums standing for
+    the integrals; the kappa term has no n = 0 part because rho_+ - rho_0
+    integrates to zero.
+  * The field seen by species K is phi_K(g) = dE/dc_K(g); its spectrum is
+    Phi^_K = (u^/N) sum_L eps_KL c^_L with eps_AA = eps_BB = kappa,
+    eps_AB = chi + kappa, except Phi^_K(0) = (chi/N) c^_{other}(0).
+  * Non-bonded force (ik route, Eq. PMM): F_i = -sum_g W_i(g) d_a phi_{s_i}(g)
+    with d_a phi = sum_n i k^D_a Phi^ exp(+2 pi i n.g/M) (no 1/M factor).
+  * Bonds: U = k_b sum |d|^2 over bonded pairs, d the minimum-image
+    separation; k_b = 3/(2 b^2) (Eq. bonds).
+  * Overdamped Euler-Maruyama: x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta),
+    Delta the mean displacement when centre-of-mass correction is on.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from .philox_ref import gaussian_noise
+
+__all__ = [
+    "Params", "bspline", "bspline_deriv", "stencil", "spread", "dft_matrix", "dft3",
+    "idft3", "wavenumbers", "kgrid", "uhat_analytic", "uhat_sampled", "field_spectra",
+    "gradient_fields", "potential_fields", "gather", "gather_gradient_weights",
+    "nonbonded_energy", "nonbonded_virial", "bond_terms", "evaluate", "em_update",
+    "trajectory", "structure_factor_exact", "min_image",
+]
+
+
+@dataclasses.dataclass
+class Params:
+    box: Sequence[float]
+    grid: Sequence[int]
+    order: int
+    smear_a: float
+    chi: float
+    kappa: float
+    bond_k: float = 1.5
+    dt: float = 0.005
+    gamma: float = 1.0
+    kT: float = 1.0
+    seed: int = 0
+    com_correct: bool = True
+    potential: str = "analytic"  # or "sampled"
+    transform: str = "dense"  # "dense" separable DFT matrices, or "numpy" FFT
+
+    @property
+    def L(self) -> np.ndarray:
+        return np.asarray(self.box, dtype=np.float64)
+
+    @property
+    def M(self) -> np.ndarray:
+        return np.asarray(self.grid, dtype=np.int64)
+
+
+# --------------------------------------------------------------------------
+# Assignment function (Sec. "Long-range interactions", Fig. pmm)
+# --------------------------------------------------------------------------
+
+def _uncentred_bspline(k: int, s: np.ndarray) -> np.ndarray:
+    """Cox-de Boor: M_1 = 1 on [0, 1); M_k(s) = [s M_{k-1}(s) + (k - s) M_{k-1}(s - 1)] / (k - 1)."""
+    if k == 1:
+        return ((s >= 0.0) & (s < 1.0)).astype(np.float64)
+    return (s * _uncentred_bspline(k - 1, s) + (k - s) * _uncentred_bspline(k - 1, s - 1.0)) / (k - 1)
+
+
+def bspline(P: int, t) -> np.ndarray:
+    """Centred cardinal B-spline of order P, support (-P/2, P/2)."""
+    t = np.asarray(t, dtype=np.float64)
+    return _uncentred_bspline(P, t + P / 2.0)
+
+
+def bspline_deriv(P: int, t) -> np.ndarray:
+    """dB_P/dt = B_{P-1}(t + 1/2) - B_{P-1}(t - 1/2)  (P >= 2)."""
+    if P < 2:
+        raise ValueError("the P = 1 assignment function has no derivative")
+    t = np.asarray(t, dtype=np.float64)
+    return bspline(P - 1, t + 0.5) - bspline(P - 1, t - 0.5)
+
+
+def stencil(x: np.ndarray, L: np.ndarray, M: np.ndarray, P: int, deriv: bool = False):
+    """Per-bead grid indices and 1D weights.
+
+    Returns idx (n, 3, P) int64 (already reduced mod M), w (n, 3, P) and, with
+    ``deriv``, dw (n, 3, P) = d w / d x_a (units 1/length).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    h = L / M
+    u = x / h
+    g0 = np.floor(u - P / 2.0).astype(np.int64) + 1
+    j = np.arange(P)
+    g = g0[:, :, None] + j[None, None, :]
+    t = u[:, :, None] - g
+    w = bspline(P, t)
+    idx = np.mod(g, M[None, :, None])
+    if not deriv:
+        return idx, w
+    dw = bspline_deriv(P, t) / h[None, :, None]
+    return idx, w, dw
+
+
+def _chunks(n: int, size: int):
+    for s in range(0, n, size):
+        yield s, min(n, s + size)
+
+
+def _flat_index(idx: np.ndarray, M: np.ndarray) -> np.ndarray:
+    ix, iy, iz = idx[:, 0, :], idx[:, 1, :], idx[:, 2, :]
+    return ((ix[:, :, None, None] * M[1] + iy[:, None, :, None]) * M[2] + iz[:, None, None, :])
+
+
+def spread(x: np.ndarray, types: np.ndarray, L, M, P: int, chunk: int = 200000) -> np.ndarray:
+    """Assignment counts c_K(g) = sum_{i in K} W_i(g)  (Eq. rhohat on the mesh).
+
+    Returns (2, Mx, My, Mz).  The density is c_K / dV.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    size = int(np.prod(M))
+    out = np.zeros((2, size))
+    types = np.asarray(types)
+    for s, e in _chunks(x.shape[0], chunk):
+        idx, w = stencil(x[s:e], L, M, P)
+        W = w[:, 0, :, None, None] * w[:, 1, None, :, None] * w[:, 2, None, None, :]
+        lin = _flat_index(idx, M)
+        for K in (0, 1):
+            sel = types[s:e] == K
+            if np.any(sel):
+                out[K] += np.bincount(lin[sel].ravel(), W[sel].ravel(), minlength=size)
+    return out.reshape((2,) + tuple(int(m) for m in M))
+
+
+# --------------------------------------------------------------------------
+# Discrete Fourier transforms
+# --------------------------------------------------------------------------
+
+def dft_matrix(m: int, sign: int) -> np.ndarray:
+    """F[n, g] = exp(sign * 2 pi i n g / m), with n g reduced mod m for accuracy."""
+    n = np.arange(m)
+    return np.exp(sign * 2j * np.pi * (np.mod(np.outer(n, n), m) / m))
+
+
+def _apply_axes(a: np.ndarray, sign: int) -> np.ndarray:
+    nd = a.ndim
+    out = a.astype(np.complex128)
+    for ax in range(nd - 3, nd):
+        F = dft_matrix(out.shape[ax], sign)
+        out = np.moveaxis(np.tensordot(out, F, axes=([ax], [1])), -1, ax)
+    return out
+
+
+def dft3(a: np.ndarray, transform: str = "dense") -> np.ndarray:
+    """Forward DFT over the last three axes (no normalisation)."""
+    if transform == "numpy":
+        return np.fft.fftn(a, axes=(-3, -2, -1))
+    return _apply_axes(a, -1)
+
+
+def idft3(a: np.ndarray, transform: str = "dense") -> np.ndarray:
+    """Inverse DFT over the last three axes WITHOUT the 1/M factor."""
+    if transform == "numpy":
+        m = a.shape[-3] * a.shape[-2] * a.shape[-1]
+        return np.fft.ifftn(a, axes=(-3, -2, -1)) * m
+    return _apply_axes(a, +1)
+
+
+# --------------------------------------------------------------------------
+# k-space factors
+# --------------------------------------------------------------------------
+
+def wavenumbers(L: float, m: int):
+    """(k, k^D) along one axis: k = 2 pi n'/L with n' = n - m for n > m/2; k^D zero at an even m's Nyquist."""
+    n = np.arange(m)
+    ns = np.where(n > m // 2, n - m, n)
+    k = 2.0 * np.pi * ns / L
+    kD = k.copy()
+    if m % 2 == 0:
+        kD[m // 2] = 0.0
+    return k, kD
+
+
+def kgrid(L, M):
+    """Broadcastable per-axis (k, k^D) arrays for a grid indexed [x, y, z]."""
+    ks, kDs = [], []
+    for a in range(3):
+        k, kD = wavenumbers(float(L[a]), int(M[a]))
+        shape = [1, 1, 1]
+        shape[a] = int(M[a])
+        ks.append(k.reshape(shape))
+        kDs.append(kD.reshape(shape))
+    return ks, kDs
+
+
+def uhat_analytic(a: float, L, M) -> np.ndarray:
+    """Transform of u_G = h*h (sigma^2 = 2a^2): exp(-a^2 |k|^2)  (Eqs. smearRho, fhF)."""
+    ks, _ = kgrid(L, M)
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    return np.exp(-a * a * k2)
+
+
+def uhat_sampled(a: float, L, M) -> np.ndarray:
+    """Variant: DFT of u_G sampled at minimum-image node separations, times dV.
+
+    This is the "potential built once by FFT and stored" route of the paper's
+    PM description; it differs from the analytic transform by aliasing.
+    """
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    h = L / M
+    sigma2 = 2.0 * a * a
+    r2 = 0.0
+    for ax in range(3):
+        g = np.arange(M[ax])
+        d = np.where(g > M[ax] // 2, g - M[ax], g) * h[ax]
+        shape = [1, 1, 1]
+        shape[ax] = int(M[ax])
+        r2 = r2 + (d ** 2).reshape(shape)
+    uG = (2.0 * np.pi * sigma2) ** -1.5 * np.exp(-r2 / (2.0 * sigma2))
+    dV = float(np.prod(h))
+    return np.real(np.fft.fftn(uG)) * dV
+
+
+def _uhat(p: Params) -> np.ndarray:
+    if p.potential == "sampled":
+        return uhat_sampled(p.smear_a, p.L, p.M)
+    return uhat_analytic(p.smear_a, p.L, p.M)
+
+
+def field_spectra(chat: np.ndarray, uhat: np.ndarray, chi: float, kappa: float, n_beads: int) -> np.ndarray:
+    """Phi^_K(n) = (u^/N) sum_L eps_KL c^_L(n); n = 0: (chi/N) c^_{other}(0)."""
+    eps = np.array([[kappa, chi + kappa], [chi + kappa, kappa]])
+    Phi = np.empty_like(chat, dtype=np.complex128)
+    for K in (0, 1):
+        Phi[K] = uhat / n_beads * (eps[K, 0] * chat[0] + eps[K, 1] * chat[1])
+        Phi[K][0, 0, 0] = chi / n_beads * chat[1 - K][0, 0, 0]
+    return Phi
+
+
+def gradient_fields(Phi: np.ndarray, L, M, transform: str = "dense") -> np.ndarray:
+    """d_a phi_K(g) = sum_n i k^D_a Phi^_K(n) exp(+2 pi i n.g/M); returns (2, 3, Mx, My, Mz) real."""
+    _, kDs = kgrid(L, M)
+    out = np.empty((2, 3) + Phi.shape[1:])
+    for K in (0, 1):
+        for a in range(3):
+            out[K, a] = np.real(idft3(1j * kDs[a] * Phi[K], transform))
+    return out
+
+
+def potential_fields(Phi: np.ndarray, transform: str = "dense") -> np.ndarray:
+    """phi_K(g) = sum_n Phi^_K(n) exp(+2 pi i n.g/M) = dE/dc_K(g); (2, Mx, My, Mz)."""
+    return np.real(idft3(Phi, transform))
+
+
+def gather(x: np.ndarray, types: np.ndarray, grad: np.ndarray, L, M, P: int,
+           chunk: int = 200000) -> np.ndarray:
+    """F_i = -sum_g W_i(g) d phi_{s_i}(g), same weights as the spread (Fig. pmm)."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    n = x.shape[0]
+    F = np.zeros((n, 3))
+    flat = grad.reshape(2, 3, -1)
+    types = np.asarray(types)
+    for s, e in _chunks(n, chunk):
+        idx, w = stencil(x[s:e], L, M, P)
+        W = (w[:, 0, :, None, None] * w[:, 1, None, :, None] * w[:, 2, None, None, :]).reshape(e - s, -1)
+        lin = _flat_index(idx, M).reshape(e - s, -1)
+        t = types[s:e]
+        for a in range(3):
+            vals = flat[t[:, None], a, lin]
+            F[s:e, a] = -np.sum(W * vals, axis=1)
+    return F
+
+
+def gather_gradient_weights(x: np.ndarray, types: np.ndarray, phi: np.ndarray, L, M, P: int,
+                            chunk: int = 200000) -> np.ndarray:
+    """Exact mesh-energy gradient: F_i = -sum_g grad_{x_i} W_i(g) phi_{s_i}(g)."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    n = x.shape[0]
+    F = np.zeros((n, 3))
+    flat = phi.reshape(2, -1)
+    types = np.asarray(types)
+    for s, e in _chunks(n, chunk):
+        idx, w, dw = stencil(x[s:e], L, M, P, deriv=True)
+        lin = _flat_index(idx, M).reshape(e - s, -1)
+        vals = flat[types[s:e][:, None], lin]
+        comps = [
+            dw[:, 0, :, None, None] * w[:, 1, None, :, None] * w[:, 2, None, None, :],
+            w[:, 0, :, None, None] * dw[:, 1, None, :, None] * w[:, 2, None, None, :],
+            w[:, 0, :, None, None] * w[:, 1, None, :, None] * dw[:, 2, None, None, :],
+        ]
+        for a in range(3):
+            F[s:e, a] = -np.sum(comps[a].reshape(e - s, -1) * vals, axis=1)
+    return F
+
+
+# --------------------------------------------------------------------------
+# Energies and virial (Eqs. fh, HelfandP)
+# --------------------------------------------------------------------------
+
+def nonbonded_energy(chat: np.ndarray, uhat: np.ndarray, chi: float, kappa: float, n_beads: int):
+    """(E_chi, E_kappa) in kT, FP64."""
+    cross = np.real(np.conj(chat[0]) * chat[1])
+    plus2 = np.abs(chat[0] + chat[1]) ** 2
+    plus2 = plus2.copy()
+    plus2[0, 0, 0] = 0.0
+    e_chi = chi / n_beads * float(np.sum(uhat * cross))
+    e_kappa = kappa / (2.0 * n_beads) * float(np.sum(uhat * plus2))
+    return e_chi, e_kappa
+
+
+def nonbonded_virial(chat: np.ndarray, a: float, L, M, chi: float, kappa: float, n_beads: int) -> np.ndarray:
+    """W_aa = -L_a dE/dL_a at fixed scaled coordinates (analytic kernel):
+    -2 a^2 sum_n k_a^2 u^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2 (n != 0)]."""
+    ks, _ = kgrid(L, M)
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    uhat = np.exp(-a * a * k2)
+    cross = np.real(np.conj(chat[0]) * chat[1])
+    plus2 = np.abs(chat[0] + chat[1]) ** 2
+    plus2[0, 0, 0] = 0.0
+    core = uhat * (chi / n_beads * cross + kappa / (2.0 * n_beads) * plus2)
+    return np.array([-2.0 * a * a * float(np.sum(ks[ax] ** 2 * core)) for ax in range(3)])
+
+
+# --------------------------------------------------------------------------
+# Bonds (Eq. bonds)
+# --------------------------------------------------------------------------
+
+def min_image(d: np.ndarray, L) -> np.ndarray:
+    L = np.asarray(L, dtype=np.float64)
+    return d - L * np.round(d / L)
+
+
+def bond_terms(x: np.ndarray, bonds: np.ndarray, L, k_b: float):
+    """(E_b, F_b (n, 3), W_b (3,)) for U = k_b sum |d_ij|^2."""
+    n = x.shape[0]
+    F = np.zeros((n, 3))
+    if bonds.shape[0] == 0:
+        return 0.0, F, np.zeros(3)
+    i, j = bonds[:, 0], bonds[:, 1]
+    d = min_image(x[i] - x[j], L)
+    e = k_b * float(np.sum(d * d))
+    f = -2.0 * k_b * d  # force on i
+    np.add.at(F, i, f)
+    np.add.at(F, j, -f)
+    W = np.sum(d * f, axis=0)
+    return e, F, W
+
+
+# --------------------------------------------------------------------------
+# One evaluation and the update
+# --------------------------------------------------------------------------
+
+def evaluate(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params,
+             want_ad: bool = False) -> Dict[str, object]:
+    """Everything at the current positions: forces, energies, virial, fields."""
+    L, M = p.L, p.M
+    n = x.shape[0]
+    c = spread(x, types, L, M, p.order)
+    chat = dft3(c, p.transform)
+    uhat = _uhat(p)
+    Phi = field_spectra(chat, uhat, p.chi, p.kappa, n)
+    grad = gradient_fields(Phi, L, M, p.transform)
+    F_nb = gather(x, types, grad, L, M, p.order)
+    e_chi, e_kappa = nonbonded_energy(chat, uhat, p.chi, p.kappa, n)
+    e_b, F_b, W_b = bond_terms(x, bonds, L, p.bond_k)
+    W_nb = nonbonded_virial(chat, p.smear_a, L, M, p.chi, p.kappa, n)
+    out = dict(F_nb=F_nb, F_bond=F_b, F=F_nb + F_b, E_bond=e_b, E_chi=e_chi, E_kappa=e_kappa,
+               E=e_b + e_chi + e_kappa, W_nb=W_nb, W_bond=W_b, W=W_nb + W_b,
+               counts=c, chat=chat, grad=grad)
+    if want_ad:
+        phi = potential_fields(Phi, p.transform)
+        out["F_nb_ad"] = gather_gradient_weights(x, types, phi, L, M, p.order)
+        out["phi"] = phi
+    return out
+
+
+def em_update(x: np.ndarray, F: np.ndarray, ids: np.ndarray, step: int, p: Params) -> np.ndarray:
+    """x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta)  (Eq. EM form, overdamped)."""
+    xi = gaussian_noise(ids, step, p.seed)
+    d = (p.dt / p.gamma) * F + np.sqrt(2.0 * p.kT * p.dt / p.gamma) * xi
+    if p.com_correct:
+        d = d - d.mean(axis=0)
+    L = p.L
+    y = np.mod(x + d, L)
+    y = np.where(y >= L, y - L, y)
+    return y
+
+
+def trajectory(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, steps: int,
+               t0: int = 0, record=None) -> np.ndarray:
+    """Run ``steps`` EM steps from step index t0; ``record(t, x, ev)`` is called before each update."""
+    x = np.array(x0, dtype=np.float64)
+    ids = np.arange(x.shape[0])
+    for t in range(t0, t0 + steps):
+        ev = evaluate(x, types, bonds, p)
+        if record is not None:
+            record(t, x, ev)
+        x = em_update(x, ev["F"], ids, t, p)
+    return x
+
+
+# --------------------------------------------------------------------------
+# Structure factor (Eq. sk), exact particle sum
+# --------------------------------------------------------------------------
+
+def structure_factor_exact(x: np.ndarray, L, nvecs: np.ndarray, weights: Optional[np.ndarray] = None) -> np.ndarray:
+    """S(k) = |sum_i e^{i k.r_i}|^2 / N for k = 2 pi n / L, n in ``nvecs`` (m, 3)."""
+    L = np.asarray(L, dtype=np.float64)
+    k = 2.0 * np.pi * np.asarray(nvecs, dtype=np.float64) / L[None, :]
+    phase = x @ k.T
+    wts = np.ones(x.shape[0]) if weights is None else weights
+    rho = (wts[:, None] * np.exp(1j * phase)).sum(axis=0)
+    return np.abs(rho) ** 2 / x.shape[0]

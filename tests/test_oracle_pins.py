@@ -1,0 +1,434 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself (a closed form, a library routine, brute force on a tiny input, an
+invariant or a finite difference), so that a dropped term, a wrong sign or
+index, or a transposed operand fails at least one of them."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tild_ref as R
+from synth import make_melt, snap_to_lattice
+
+rng = np.random.default_rng(12345)
+
+
+def small_params(**kw):
+    base = dict(box=(6.0, 7.0, 5.0), grid=(8, 10, 6), order=4, smear_a=0.5, chi=0.7,
+                kappa=3.0, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0, seed=99)
+    base.update(kw)
+    return R.Params(**base)
+
+
+def random_system(n, p, seed=0, bonded=True):
+    g = np.random.default_rng(seed)
+    x = g.uniform(0, 1, size=(n, 3)) * p.L
+    types = g.integers(0, 2, size=n).astype(np.int32)
+    if bonded:
+        b = np.stack([np.arange(0, n - 1, 2), np.arange(1, n, 2)], axis=1).astype(np.int32)
+    else:
+        b = np.zeros((0, 2), np.int32)
+    return x, types, b
+
+
+# ----------------------------------------------------------------- B-spline
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5, 6, 7])
+def test_bspline_partition_of_unity_and_moment(P):
+    u = rng.uniform(0, 50, size=2000)
+    g0 = np.floor(u - P / 2) + 1
+    t = u[:, None] - (g0[:, None] + np.arange(P))
+    w = R.bspline(P, t)
+    assert np.all(w >= 0)
+    np.testing.assert_allclose(w.sum(axis=1), 1.0, atol=1e-13)
+    if P >= 2:  # first moment of a symmetric spline vanishes
+        np.testing.assert_allclose((w * t).sum(axis=1), 0.0, atol=1e-12)
+
+
+def test_bspline_closed_forms():
+    t = np.linspace(-3, 3, 1201)
+    a = np.abs(t)
+    b2 = np.where(a < 1, 1 - a, 0.0)
+    b3 = np.where(a < 0.5, 0.75 - t * t, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+    b4 = np.where(a < 1, 2 / 3 - t * t + 0.5 * a ** 3, np.where(a < 2, (2 - a) ** 3 / 6, 0.0))
+    np.testing.assert_allclose(R.bspline(2, t), b2, atol=1e-14)
+    np.testing.assert_allclose(R.bspline(3, t), b3, atol=1e-14)
+    np.testing.assert_allclose(R.bspline(4, t), b4, atol=1e-14)
+    # node values of the quartic spline
+    np.testing.assert_allclose(R.bspline(5, np.arange(-2, 3)),
+                               [1 / 384, 19 / 96, 115 / 192, 19 / 96, 1 / 384], atol=1e-15)
+
+
+@pytest.mark.parametrize("P", [2, 3, 4, 5, 6])
+def test_bspline_is_repeated_convolution_and_derivative(P):
+    # B_P = B_{P-1} * B_1 (numerical convolution on a fine lattice)
+    dx = 1e-3
+    s = np.arange(-P / 2 - 1, P / 2 + 1, dx)
+    conv = np.convolve(R.bspline(P - 1, s), R.bspline(1, np.arange(-0.5, 0.5, dx)), mode="same") * dx
+    np.testing.assert_allclose(conv, R.bspline(P, s), atol=3e-3)
+    # unit integral
+    assert abs(R.bspline(P, s).sum() * dx - 1.0) < 1e-6
+    # derivative by central differences away from the knots
+    t = rng.uniform(-P / 2, P / 2, 500)
+    e = 1e-6
+    fd = (R.bspline(P, t + e) - R.bspline(P, t - e)) / (2 * e)
+    tol = 1e-5 if P > 2 else 1e-4
+    keep = np.min(np.abs(((t + P / 2) % 1.0)[:, None] - np.array([0.0, 1.0])[None]), axis=1) > 1e-4
+    np.testing.assert_allclose(R.bspline_deriv(P, t)[keep], fd[keep], atol=tol)
+
+
+# ------------------------------------------------------------------ spread
+
+def brute_spread(x, types, L, M, P):
+    """Every bead against every grid node and every periodic image (no stencil)."""
+    h = L / M
+    c = np.zeros((2,) + tuple(M))
+    for i in range(x.shape[0]):
+        w1 = []
+        for a in range(3):
+            g = np.arange(M[a])
+            acc = np.zeros(M[a])
+            for m in range(-3, 4):
+                acc += R.bspline(P, x[i, a] / h[a] - g - m * M[a])
+            w1.append(acc)
+        c[types[i]] += w1[0][:, None, None] * w1[1][None, :, None] * w1[2][None, None, :]
+    return c
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 5])
+def test_spread_matches_brute_force_and_conserves_mass(P):
+    p = small_params(order=P)
+    x, t, _ = random_system(17, p, seed=P)
+    x[0] = [0.0, 0.0, 0.0]  # corner, exercises wrap-around of the stencil
+    x[1] = p.L - 1e-12
+    c = R.spread(x, t, p.L, p.M, P)
+    np.testing.assert_allclose(c, brute_spread(x, t, p.L, p.M, P), atol=1e-12)
+    for K in (0, 1):
+        assert abs(c[K].sum() - np.sum(t == K)) < 1e-11
+
+
+def test_spread_nearest_grid_point_on_node():
+    p = small_params(order=1)
+    h = p.L / p.M
+    x = np.array([[2 * h[0], 3 * h[1], 5 * h[2]]])
+    c = R.spread(x, np.array([1]), p.L, p.M, 1)
+    assert c[1, 2, 3, 5] == 1.0 and c.sum() == 1.0
+
+
+# -------------------------------------------------------------- transforms
+
+def test_dft_against_triple_sum_and_numpy():
+    a = rng.normal(size=(2, 4, 5, 6)) + 1j * rng.normal(size=(2, 4, 5, 6))
+    brute = np.zeros_like(a)
+    for n0 in range(4):
+        for n1 in range(5):
+            for n2 in range(6):
+                for g0 in range(4):
+                    for g1 in range(5):
+                        for g2 in range(6):
+                            ph = np.exp(-2j * np.pi * (n0 * g0 / 4 + n1 * g1 / 5 + n2 * g2 / 6))
+                            brute[:, n0, n1, n2] += a[:, g0, g1, g2] * ph
+    np.testing.assert_allclose(R.dft3(a), brute, atol=1e-11)
+    np.testing.assert_allclose(R.dft3(a), np.fft.fftn(a, axes=(1, 2, 3)), atol=1e-11)
+    np.testing.assert_allclose(R.idft3(R.dft3(a)), a * 120, atol=1e-10)
+    np.testing.assert_allclose(R.idft3(a, "numpy"), R.idft3(a), atol=1e-10)
+
+
+def test_wavenumbers_even_odd():
+    k, kD = R.wavenumbers(10.0, 8)
+    np.testing.assert_allclose(k * 10 / (2 * np.pi), [0, 1, 2, 3, 4, -3, -2, -1])
+    assert kD[4] == 0 and kD[3] == k[3]
+    k, kD = R.wavenumbers(10.0, 7)
+    np.testing.assert_allclose(k * 10 / (2 * np.pi), [0, 1, 2, 3, -3, -2, -1])
+    np.testing.assert_array_equal(k, kD)
+
+
+def test_spectral_derivative_single_mode():
+    """Phi^ = 1/2 at +n and -n gives phi = cos(k.r); d_x phi must be -k_x sin(k.r)."""
+    L = np.array([6.0, 7.0, 5.0])
+    M = np.array([8, 10, 6])
+    n = (2, 3, 1)
+    Phi = np.zeros((2,) + tuple(M), complex)
+    Phi[0][n] = 0.5
+    Phi[0][tuple((-np.array(n)) % M)] = 0.5
+    Phi[1] = 2 * Phi[0]
+    grad = R.gradient_fields(Phi, L, M)
+    g = np.meshgrid(*[np.arange(m) * L[a] / M[a] for a, m in enumerate(M)], indexing="ij")
+    k = [2 * np.pi * n[a] / L[a] for a in range(3)]
+    phase = k[0] * g[0] + k[1] * g[1] + k[2] * g[2]
+    for a in range(3):
+        np.testing.assert_allclose(grad[0, a], -k[a] * np.sin(phase), atol=1e-12)
+        np.testing.assert_allclose(grad[1, a], -2 * k[a] * np.sin(phase), atol=1e-12)
+    np.testing.assert_allclose(R.potential_fields(Phi)[0], np.cos(phase), atol=1e-12)
+
+
+# ---------------------------------------------------------------- energies
+
+def test_energy_matches_real_space_double_sum_with_sampled_kernel():
+    """(chi/rho0) sum_gg' rhoA u rhoB dV^2 + (kappa/2rho0) sum (rho+ - rho0) u (rho+ - rho0) dV^2."""
+    p = small_params(grid=(6, 5, 4), box=(4.0, 3.5, 3.0), potential="sampled", order=3)
+    x, t, b = random_system(9, p, seed=3)
+    n = x.shape[0]
+    ev = R.evaluate(x, t, b, p)
+    L, M = p.L, p.M
+    h = L / M
+    dV = float(np.prod(h))
+    V = float(np.prod(L))
+    rho0 = n / V
+    rho = ev["counts"] / dV
+    nodes = np.stack(np.meshgrid(*[np.arange(m) for m in M], indexing="ij"), -1).reshape(-1, 3)
+    d = (nodes[:, None, :] - nodes[None, :, :]) * h
+    d = d - L * np.round(d / L)
+    s2 = 2 * p.smear_a ** 2
+    u = (2 * np.pi * s2) ** -1.5 * np.exp(-np.sum(d * d, -1) / (2 * s2))
+    rA, rB = rho[0].ravel(), rho[1].ravel()
+    rp = rA + rB - rho0
+    e_chi = p.chi / rho0 * (rA @ u @ rB) * dV * dV
+    e_kap = p.kappa / (2 * rho0) * (rp @ u @ rp) * dV * dV
+    # minimum-image sampling only: the boxes here are a few sigma wide, so compare loosely
+    assert abs(ev["E_chi"] - e_chi) < 1e-10 * max(1, abs(e_chi))
+    assert abs(ev["E_kappa"] - e_kap) < 1e-10 * max(1, abs(e_kap))
+
+
+def test_parseval_energy_equals_half_sum_c_phi():
+    p = small_params()
+    x, t, b = random_system(40, p, seed=5)
+    ev = R.evaluate(x, t, b, p, want_ad=True)
+    half = 0.5 * float(np.sum(ev["counts"] * ev["phi"]))
+    assert abs(half - (ev["E_chi"] + ev["E_kappa"])) < 1e-10 * abs(half)
+
+
+def _two_bead_energy(h, L=8.0, a=0.5, r=np.array([1.3, 0.7, -0.4])):
+    M = int(round(L / h))
+    p = R.Params(box=(L,) * 3, grid=(M,) * 3, order=4, smear_a=a, chi=1.0, kappa=0.0,
+                 transform="numpy")
+    x = np.array([[3.1, 2.9, 4.05], [3.1, 2.9, 4.05] + r]) % L
+    ev = R.evaluate(x, np.array([0, 1]), np.zeros((0, 2), np.int32), p)
+    # continuum: (chi/rho0) u_G(r) with rho0 = 2/V, periodised over images
+    upar = 0.0
+    for m in np.array(np.meshgrid(*[range(-2, 3)] * 3)).reshape(3, -1).T:
+        rr = r + m * L
+        upar += (4 * np.pi * a * a) ** -1.5 * np.exp(-rr @ rr / (4 * a * a))
+    exact = 1.0 / 2.0 * L ** 3 * upar
+    return ev["E_chi"], exact
+
+
+def test_two_bead_energy_converges_to_continuum_at_second_order():
+    errs = []
+    for h in (0.25, 0.125, 0.0625):
+        e, exact = _two_bead_energy(h)
+        errs.append(abs(e - exact) / exact)
+    assert errs[-1] < 0.01
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_two_beads_on_nodes_closed_form():
+    """Beads on nodes: c is a separable stencil of node values, so E_chi is a closed sum."""
+    L = np.array([5.0, 5.0, 5.0])
+    M = np.array([10, 10, 10])
+    h = L / M
+    p = R.Params(box=tuple(L), grid=tuple(M), order=4, smear_a=0.4, chi=2.0, kappa=0.0)
+    g1, g2 = np.array([1, 2, 3]), np.array([4, 8, 3])
+    x = np.array([g1 * h, g2 * h])
+    ev = R.evaluate(x, np.array([0, 1]), np.zeros((0, 2), np.int32), p)
+    node = {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}
+    total = 0.0
+    ks = [R.wavenumbers(L[a], M[a])[0] for a in range(3)]
+    for n in np.ndindex(*M):
+        k = np.array([ks[a][n[a]] for a in range(3)])
+        S = 1.0
+        for a in range(3):
+            S *= abs(sum(node[j] * np.exp(-1j * k[a] * h[a] * j) for j in (-1, 0, 1))) ** 2
+        total += np.exp(-p.smear_a ** 2 * k @ k) * S * np.cos(k @ ((g2 - g1) * h))
+    assert abs(ev["E_chi"] - p.chi / 2 * total) < 1e-12 * abs(total)
+
+
+# ------------------------------------------------------------------ forces
+
+def test_nonbonded_momentum_conservation():
+    for grid in [(8, 10, 6), (7, 9, 5)]:
+        p = small_params(grid=grid)
+        x, t, b = random_system(60, p, seed=7)
+        ev = R.evaluate(x, t, b, p)
+        scale = np.abs(ev["F_nb"]).max()
+        assert np.all(np.abs(ev["F_nb"].sum(axis=0)) < 1e-11 * scale * 60)
+        assert np.all(np.abs(ev["F_bond"].sum(axis=0)) < 1e-11)
+
+
+def test_energy_gradient_force_is_exact_finite_difference():
+    p = small_params()
+    x, t, b = random_system(20, p, seed=11)
+    ev = R.evaluate(x, t, b, p, want_ad=True)
+    e = 1e-6
+    for i in (0, 7, 13):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += e
+            xm[i, a] -= e
+            ep = R.evaluate(xp, t, b, p)
+            em = R.evaluate(xm, t, b, p)
+            fd = -((ep["E_chi"] + ep["E_kappa"]) - (em["E_chi"] + em["E_kappa"])) / (2 * e)
+            assert abs(fd - ev["F_nb_ad"][i, a]) < 1e-6 * max(1.0, abs(fd))
+            fdb = -(ep["E_bond"] - em["E_bond"]) / (2 * e)
+            assert abs(fdb - ev["F_bond"][i, a]) < 1e-6 * max(1.0, abs(fdb))
+
+
+def test_ik_force_converges_to_energy_gradient():
+    errs = []
+    for M in (16, 32, 64):
+        p = R.Params(box=(10.0,) * 3, grid=(M,) * 3, order=4, smear_a=0.5, chi=0.5, kappa=5.0,
+                     transform="numpy")
+        x, t, b = random_system(300, p, seed=2, bonded=False)
+        ev = R.evaluate(x, t, b, p, want_ad=True)
+        errs.append(np.linalg.norm(ev["F_nb"] - ev["F_nb_ad"]) / np.linalg.norm(ev["F_nb_ad"]))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 2e-3
+    assert errs[0] / errs[1] > 4 and errs[1] / errs[2] > 4
+
+
+def test_bond_closed_form_across_boundary():
+    L = np.array([10.0, 10.0, 10.0])
+    x = np.array([[9.8, 5.0, 5.0], [0.3, 5.4, 4.5]])
+    e, F, W = R.bond_terms(x, np.array([[0, 1]]), L, 1.5)
+    d = np.array([-0.5, -0.4, 0.5])
+    assert abs(e - 1.5 * d @ d) < 1e-12
+    np.testing.assert_allclose(F[0], -3.0 * d, atol=1e-12)
+    np.testing.assert_allclose(F[1], 3.0 * d, atol=1e-12)
+    np.testing.assert_allclose(W, -3.0 * d * d, atol=1e-12)
+
+
+def test_virial_by_affine_box_scaling():
+    p = small_params()
+    x, t, b = random_system(30, p, seed=4)
+    ev = R.evaluate(x, t, b, p)
+    s = x / p.L
+    for a in range(3):
+        e = 1e-5
+        Es = []
+        for sgn in (+1, -1):
+            L2 = p.L.copy()
+            L2[a] *= 1 + sgn * e
+            q = R.Params(**{**p.__dict__, "box": tuple(L2)})
+            v = R.evaluate(s * L2, t, b, q)
+            Es.append((v["E_chi"] + v["E_kappa"], v["E_bond"]))
+        w_nb = -(Es[0][0] - Es[1][0]) / (2 * e)
+        w_b = -(Es[0][1] - Es[1][1]) / (2 * e)
+        assert abs(w_nb - ev["W_nb"][a]) < 1e-5 * max(1, abs(w_nb))
+        assert abs(w_b - ev["W_bond"][a]) < 1e-5 * max(1, abs(w_b))
+
+
+def test_sampled_kernel_approaches_analytic_on_fine_grids():
+    a = 0.5
+    for M, tol in ((16, 0.05), (48, 1e-6)):
+        L = (8.0,) * 3
+        us = R.uhat_sampled(a, L, (M,) * 3)
+        ua = R.uhat_analytic(a, L, (M,) * 3)
+        assert np.max(np.abs(us - ua)) < tol
+
+
+# ------------------------------------------------------------- noise / EM
+
+def test_philox64_matches_numpy_philox():
+    for key in ([0, 0], [0x123456789ABCDEF0, 0x0FEDCBA987654321]):
+        for ctr0 in ([0, 0, 0, 0], [5, 0xFFFFFFFFFFFFFFFF, 7, 1 << 63]):
+            bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                                  counter=np.array(ctr0, dtype=np.uint64))
+            raw = bg.random_raw(12).reshape(3, 4)
+            # numpy advances the 256-bit counter before producing each block
+            ctrs = []
+            c = [int(v) for v in ctr0]
+            for _ in range(3):
+                carry = 1
+                for j in range(4):
+                    s = c[j] + carry
+                    c[j] = s & ((1 << 64) - 1)
+                    carry = s >> 64
+                ctrs.append(list(c))
+            ours = oracle.philox4(np.array(ctrs, dtype=np.uint64), key, width=64)
+            np.testing.assert_array_equal(ours, raw)
+
+
+def test_noise_statistics():
+    ids = np.arange(200000)
+    xi = oracle.gaussian_noise(ids, 17, 474)
+    assert abs(xi.mean()) < 0.01
+    np.testing.assert_allclose(xi.var(axis=0), 1.0, atol=0.01)
+    c = np.corrcoef(xi.T)
+    assert np.max(np.abs(c - np.eye(3))) < 0.01
+    xi2 = oracle.gaussian_noise(ids, 18, 474)
+    assert abs(np.mean(xi * xi2)) < 0.01
+    # 4th moment of a normal
+    assert abs(np.mean(xi ** 4) - 3.0) < 0.05
+    # determinism: the noise is a pure function of (seed, id, step)
+    np.testing.assert_array_equal(oracle.gaussian_noise(ids[5:9], 17, 474), xi[5:9])
+
+
+def test_free_diffusion_msd():
+    p = R.Params(box=(50.0,) * 3, grid=(8,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0,
+                 dt=0.01, gamma=2.0, kT=1.5, seed=3, com_correct=False)
+    n, steps = 20000, 40
+    x0 = np.full((n, 3), 25.0)
+    x = x0.copy()
+    ids = np.arange(n)
+    for t in range(steps):
+        x = R.em_update(x, np.zeros_like(x), ids, t, p)
+    msd = np.mean(np.sum((x - x0) ** 2, axis=1))
+    expect = 6 * p.kT * p.dt * steps / p.gamma
+    assert abs(msd / expect - 1) < 0.03
+
+
+def test_dimer_bond_length_matches_discrete_em_stationary_variance():
+    """Isolated dimers under EM: the bond vector is an AR(1) process whose
+    stationary variance per axis is kT / (2 k_b (1 - 2 k_b dt / gamma))."""
+    kb, dt, gamma, kT = 1.5, 0.005, 1.0, 1.0
+    p = R.Params(box=(1000.0,) * 3, grid=(4,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0,
+                 bond_k=kb, dt=dt, gamma=gamma, kT=kT, seed=8, com_correct=False)
+    nd = 4000
+    g = np.random.default_rng(1)
+    a = g.uniform(100, 900, size=(nd, 3))
+    d0 = g.normal(0, np.sqrt(1 / 3), size=(nd, 3))
+    x = np.empty((2 * nd, 3))
+    x[0::2], x[1::2] = a, a + d0
+    bonds = np.stack([np.arange(0, 2 * nd, 2), np.arange(1, 2 * nd, 2)], 1)
+    ids = np.arange(2 * nd)
+    acc = []
+    for t in range(600):
+        _, F, _ = R.bond_terms(x, bonds, p.L, kb)
+        x = R.em_update(x, F, ids, t, p)
+        if t >= 200 and t % 10 == 0:
+            d = R.min_image(x[0::2] - x[1::2], p.L)
+            acc.append(np.mean(np.sum(d * d, axis=1)))
+    expect = 3 * kT / (2 * kb * (1 - 2 * kb * dt / gamma))
+    assert abs(np.mean(acc) / expect - 1) < 0.02
+
+
+def test_com_correction_removes_mean_displacement():
+    p = small_params()
+    x, t, b = random_system(50, p, seed=9)
+    ev = R.evaluate(x, t, b, p)
+    y = R.em_update(x, ev["F"], np.arange(50), 0, p)
+    d = R.min_image(y - x, p.L)
+    assert np.all(np.abs(d.mean(axis=0)) < 1e-13)
+
+
+def test_structure_factor_ideal_gas_is_one():
+    L = np.array([20.0, 20.0, 20.0])
+    x = rng.uniform(0, 1, size=(4000, 3)) * L
+    nv = np.array([[1, 0, 0], [0, 2, 0], [1, 1, 1], [3, 0, 2], [0, 0, 4]])
+    S = np.mean([R.structure_factor_exact(rng.uniform(0, 1, size=(4000, 3)) * L, L, nv)
+                 for _ in range(60)], axis=0)
+    np.testing.assert_allclose(S, 1.0, atol=0.3)
+    assert abs(S.mean() - 1) < 0.12
+
+
+def test_generator_ideal_chain_statistics():
+    m = make_melt(0)
+    assert m.n == 3000 and m.bonds.shape == (2850, 2)
+    assert np.all((m.x >= 0) & (m.x < m.box))
+    d = R.min_image(m.x[m.bonds[:, 0]] - m.x[m.bonds[:, 1]], m.box)
+    assert abs(np.mean(np.sum(d * d, 1)) - 1.0) < 0.06
+    assert np.sum(m.types == 0) == 1500
+    xs = snap_to_lattice(m.x, m.box)
+    assert np.max(np.abs(xs - m.x)) < 1e-8
+    q = xs / m.box * 2.0 ** 32
+    np.testing.assert_array_equal(q, np.rint(q))
