@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the TILD particle-mesh step on one MI355X.
+
+One step = spread -> forward 3D FFT -> k-space chi/kappa kernel x ik ->
+inverse 3D FFT -> gather + harmonic bonds + Philox Euler-Maruyama update,
+for the A20B20 diblock melt of 648,000 beads in a 60^3 box on a 128^3 grid
+(P = 4, a = 0.5, chi = 0.3, kappa = 10, dt = 0.005).  Inputs are synthetic
+(seeded random-walk chains) and resident in HBM before timing starts.
+
+Prints one JSON line with bead-steps/s, the roofline of the dominant
+kernel (algorithmic bytes per launch / its mean duration from HIP events
+recorded on the library's stream) and the FP64 oracle timed on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "TILD bead-steps/s at 648k beads, 128^3 grid; HBM GB/s vs peak; fwd+adj ms"
+HBM_PEAK_GBPS = 8000.0
+
+
+def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
+    """Bytes each kernel must move at minimum (per launch): see the design doc, 'Byte model'."""
+    mx, my, mz = (int(v) for v in melt.grid)
+    m = mx * my * mz
+    hs = (mx // 2 + 1) * my * mz  # complex elements of one half spectrum
+    r, c = precision_bytes, 2 * precision_bytes
+    n = melt.n
+    nb = int(melt.bonds.shape[0])
+    bead = 16  # uint4 {qx, qy, qz, species}
+    return {
+        "fill_mean": 2 * m * r,
+        "spread": n * bead + 2 * m * r,
+        "fft_xy_r2c": 2 * m * r + 2 * hs * c,
+        "fft_z_kmul": 2 * hs * c + 4 * hs * c,
+        "fft_xy_c2r": 4 * hs * c + 6 * m * r,
+        "gather_bond_em": 2 * n * bead + 6 * m * r + 4 * (n + 1) + 8 * nb,
+    }
+
+
+def cpu_baseline(melt, steps: int = 1) -> dict:
+    """The FP64 oracle, as written, on the same workload: `steps` full steps."""
+    from oracle import tild_ref as R
+
+    p = R.Params(box=tuple(melt.box), grid=tuple(int(v) for v in melt.grid), order=melt.order,
+                 smear_a=melt.smear_a, chi=melt.chi, kappa=melt.kappa, bond_k=melt.bond_k, dt=melt.dt,
+                 gamma=melt.gamma, kT=melt.kT, seed=melt.seed)
+    threads = os.cpu_count() or 1
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(i.get("num_threads", 1)) for i in info)
+    except Exception:
+        pass
+    x = melt.x.copy()
+    ids = np.arange(melt.n)
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev = R.evaluate(x, melt.types, melt.bonds, p)
+        x = R.em_update(x, ev["F"], ids, s, p)
+    dt = time.perf_counter() - t0
+    return {"value": melt.n * steps / dt, "unit": "bead-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full FP64 oracle step(s) of the same {melt.n}-bead workload (dense separable "
+                      f"DFT matrices through BLAS, {dt:.1f} s) on {platform.processor() or platform.machine()}"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md, 'Sharding'); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2302_02474_amd as T
+    from synth import make_melt
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    melt = make_melt(1)
+    print(f"[bench] workload: {melt.name}; {melt.n} beads", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    t = T.from_melt(melt, precision=T.TILD_FP32, stream=stream)
+
+    t.step(args.warmup)
+    t.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t.step(args.steps)
+    t.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = melt.n * args.steps / elapsed
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # Per-kernel durations from HIP events on the library's stream.
+    kms = t.profile_steps(args.profile_steps)
+    abytes = algorithmic_bytes(melt)
+    dom = max(kms, key=kms.get)
+    achieved = abytes[dom] / (kms[dom] * 1e-3) / 1e9
+    kernels = {k: {"ms": round(v, 5), "algorithmic_MB": round(abytes[k] / 1e6, 3),
+                   "GBps": round(abytes[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None}
+               for k, v in kms.items()}
+    step_bytes = sum(abytes.values())
+    t.close()
+
+    # Achievable copy bandwidth with the library's own streaming kernel.
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    T.stream_copy_ms(a, b, nbytes, iters=3, stream=stream)
+    copy_ms = T.stream_copy_ms(a, b, nbytes, iters=20, stream=stream)
+    stream_gbps = 2 * nbytes / (copy_ms * 1e-3) / 1e9
+    del a, b
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "bead-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "A20B20 diblock melt, 16200 chains = 648000 beads, box 60^3, grid 128^3, P=4, "
+                               "a=0.5, chi=0.3, kappa=10, k_b=1.5, dt=0.005, gamma=1, kT=1",
+                   "beads": melt.n, "grid": [int(v) for v in melt.grid], "order": melt.order,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
+        "step_algorithmic_GBps": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "step_algorithmic_MB": round(step_bytes / 1e6, 2),
+        "stream_copy_GBps": round(stream_gbps, 1),
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(melt)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,218 @@
+/*
+ * tild.h -- C ABI of libtild, a gfx950 (MI355X) implementation of one
+ * theoretically-informed Langevin dynamics (TILD) step: the particle-mesh
+ * non-bonded force of a two-species (A/B) bead-spring melt, harmonic bond
+ * forces, and an overdamped Euler-Maruyama position update.
+ *
+ * Model (MATILDA.FT paper, Sec. "Structure of theoretically-informed
+ * coarse-grained and field-theoretic models"):
+ *   - microscopic densities rho_K = sum_j delta(r - r_j), Eq. rhohat;
+ *   - bonds beta U_0 = sum 3/(2 b^2) |r_s - r_{s+1}|^2, Eq. bonds
+ *     (here U = bond_k |d|^2, d the minimum-image bond vector);
+ *   - Flory term (chi/rho_0) int int rho_A u_G rho_B, Eq. fh, and Helfand
+ *     term (kappa/2 rho_0) int int (rho_+ - rho_0) u_G (rho_+ - rho_0),
+ *     Eq. HelfandP, with rho_0 = N/V and u_G a unit Gaussian of variance
+ *     sigma^2 = 2 a^2, i.e. u_G = h * h for the smearing h of width a
+ *     (Eqs. smearRho, fhF, HelfandF); its transform is exp(-a^2 k^2).
+ * Method (Sec. "Long-range interactions", Eq. PMM, Fig. pmm): beads are
+ * assigned to a periodic grid with order-P B-spline weights, the species
+ * densities are Fourier transformed, multiplied by the kernel and by i k,
+ * transformed back to field gradients and interpolated to the beads with the
+ * same weights.  Integrator: Euler-Maruyama with internally generated noise
+ * (Sec. "Integrator Class"), in the overdamped form of Eq. EM.
+ *
+ * Conventions shared by every call:
+ *   - Units: kT, bead mass and the segment length b are the reduced units of
+ *     the paper (Sec. "Units").
+ *   - Box: orthogonal, fully periodic, edges box[0..2] > 0.  Positions are
+ *     wrapped into [0, L).  Internally they are stored as 32-bit unsigned
+ *     fixed-point fractions of the box (resolution L / 2^32).
+ *   - Grid nodes sit at g * L/M from the box corner.  order = P is the number
+ *     of grid points per dimension touched by a bead (P = 2 is the paper's
+ *     "two nearest grid points" first-order scheme); weights are the
+ *     centred cardinal B-spline of order P.
+ *   - Non-bonded force: ik route; the derivative wavenumber is zero on the
+ *     Nyquist plane of an even grid axis, so the net non-bonded force is zero.
+ *   - Noise: Philox4x32-10 (Salmon et al., SC'11) with key (seed mod 2^32,
+ *     seed >> 32) and counter (bead id, step mod 2^32, step >> 32, 0); the
+ *     four words map to uniforms (w + 1/2) 2^-32 and Box-Muller gives the
+ *     x, y (from words 0, 1) and z (from words 2, 3) increments.  Bead id is
+ *     the bead's index in the arrays given to tild_create, so a run resumed
+ *     from (positions, step count, seed) continues the same noise stream.
+ *   - Bead order in every input and output array is the order of the types
+ *     array given to tild_create ("ABI order").
+ *
+ * Ownership: the caller owns every pointer it passes.  Input arrays are
+ * copied (or fully consumed) before the call returns and may be freed
+ * immediately after.  Output arrays are allocated by the caller.  The
+ * context owns all device memory it allocates and frees it in tild_destroy.
+ *
+ * Streams: all device work of a context is enqueued on the HIP stream given
+ * to tild_create (NULL = the null stream).  tild_step is asynchronous; calls
+ * that return host data (tild_energy, and tild_get_positions / tild_forces
+ * with on_device = 0) synchronise that stream.  Device-pointer inputs and
+ * outputs must be valid on the context's device and are read/written in
+ * stream order.
+ *
+ * Errors: every int-returning call returns TILD_OK (0) or a negative code.
+ * The message of the last failure is available from tild_last_error.  No C++
+ * exception crosses this interface.  A non-finite force or displacement seen
+ * during tild_step is latched on the device and reported as TILD_ENONFINITE
+ * by the next synchronising call (tild_synchronize, tild_energy, or a
+ * host-output call); the flag is then cleared.
+ */
+#ifndef TILD_H
+#define TILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define TILD_OK 0
+#define TILD_EINVAL (-1)     /* bad argument: NULL pointer, parameter out of range, bond index out of range */
+#define TILD_ENOMEM (-2)     /* a device or host allocation failed */
+#define TILD_EHIP (-3)       /* a HIP runtime call failed; the HIP error string is in tild_last_error */
+#define TILD_ENONFINITE (-4) /* NaN/Inf force or displacement detected during a step */
+#define TILD_ESTATE (-5)     /* call not valid in the current state (e.g. no positions set) */
+
+/* Arithmetic precision of grids, transforms and forces (tild_params.precision)
+ * and element type of position / force arrays (dtype arguments). */
+#define TILD_FP32 0
+#define TILD_FP64 1
+
+/* tild_params.flags */
+#define TILD_COM_CORRECT 1u /* subtract the mean displacement of every step (centre-of-mass drift correction) */
+
+/* tild_forces parts */
+#define TILD_PART_NONBONDED 1u
+#define TILD_PART_BOND 2u
+#define TILD_PART_TOTAL 3u
+
+/* Per-kernel timing slots reported by tild_profile_steps. */
+#define TILD_NUM_KERNELS 6
+
+typedef struct tild_ctx tild_ctx;
+
+typedef struct tild_params {
+    double box[3];     /* L_x, L_y, L_z > 0 (orthogonal periodic box) */
+    int32_t grid[3];   /* M_x, M_y, M_z: each 2..256 and a product of 2, 3 and 5 only */
+    int32_t order;     /* P, grid points per dimension of the assignment stencil: 1..7, P <= min(M) */
+    double smear_a;    /* smearing width a >= 0: kernel transform exp(-a^2 k^2) */
+    double chi;        /* Flory-Huggins chi_AB (Eq. fh) */
+    double kappa;      /* Helfand compressibility kappa (Eq. HelfandP) */
+    double bond_k;     /* bond energy bond_k |d|^2 per bond; 3/(2 b^2) = 1.5 at b = 1 (Eq. bonds) */
+    double dt;         /* time step > 0 */
+    double gamma;      /* friction > 0; mobility 1/gamma */
+    double kT;         /* temperature >= 0 (noise amplitude sqrt(2 kT dt / gamma)) */
+    uint64_t seed;     /* Philox key */
+    int32_t precision; /* TILD_FP32 (float grids, transforms and forces; float64 energy, virial and
+                          centre-of-mass sums) or TILD_FP64 (everything in float64) */
+    uint32_t flags;    /* TILD_COM_CORRECT or 0 */
+} tild_params;
+
+/*
+ * Create a context for n_beads beads.
+ *   types:  host array [n_beads] of int32, 0 = species A, 1 = species B.
+ *   bonds:  host array [2 * n_bonds] of int32 pairs (i, j), 0-based ABI
+ *           indices, i != j; may be NULL when n_bonds == 0.
+ *   hip_stream: a hipStream_t on the current device, or NULL.
+ * Positions must be set with tild_set_positions before the first step,
+ * force or energy call.  The step counter starts at 0.
+ * Returns TILD_EINVAL for invalid parameters (grid not 2,3,5-smooth or out
+ * of range, order out of range, non-positive box/dt/gamma, NULL arrays, bond
+ * index out of range, types other than 0/1, a grid plane too large for one
+ * workgroup's local memory in the chosen precision), TILD_ENOMEM or
+ * TILD_EHIP.  On failure *out is set to NULL and the message is available
+ * from tild_last_error(NULL) on the same thread.
+ */
+int tild_create(const tild_params* params, int64_t n_beads, const int32_t* types,
+                int64_t n_bonds, const int32_t* bonds, void* hip_stream, tild_ctx** out);
+
+/*
+ * Set all positions.  xyz: [n_beads][3] in ABI order, element type dtype
+ * (TILD_FP32 or TILD_FP64), host memory (on_device = 0) or device memory
+ * (on_device = 1).  Coordinates may lie outside the box; they are wrapped.
+ * Non-finite coordinates give TILD_EINVAL (host input) or TILD_ENONFINITE at
+ * the next synchronising call (device input).  Does not change the step
+ * counter.
+ */
+int tild_set_positions(tild_ctx* ctx, const void* xyz, int32_t dtype, int32_t on_device);
+
+/* Copy the current positions, wrapped into [0, L), to xyz ([n_beads][3], ABI order). */
+int tild_get_positions(tild_ctx* ctx, void* xyz, int32_t dtype, int32_t on_device);
+
+/*
+ * Enqueue n_steps >= 0 steps.  Each step evaluates the forces at the current
+ * positions (non-bonded + bonds) and applies
+ *   x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta),
+ * Delta being the mean displacement when TILD_COM_CORRECT is set, xi the
+ * Philox noise of the current step index; the step counter then advances.
+ * Asynchronous: returns after enqueueing.
+ */
+int tild_step(tild_ctx* ctx, int64_t n_steps);
+
+/*
+ * Forces at the current positions, without moving the beads.
+ *   out: [n_beads][3] in ABI order, dtype element type, host or device memory.
+ *   parts: TILD_PART_NONBONDED, TILD_PART_BOND or TILD_PART_TOTAL (their sum).
+ */
+int tild_forces(tild_ctx* ctx, void* out, int32_t dtype, int32_t on_device, uint32_t parts);
+
+/*
+ * Energies (kT) and virial at the current positions, accumulated in float64:
+ *   out[0] E_bond, out[1] E_chi, out[2] E_kappa, out[3] E_total,
+ *   out[4..6] W_xx, W_yy, W_zz with W_aa = -L_a dE/dL_a at fixed scaled
+ *   coordinates (bonded + non-bonded), out[7] = 0.
+ * E_chi includes the constant k = 0 term chi N_A N_B / N; both non-bonded
+ * terms include the grid-dependent bead self-interaction.  Synchronises.
+ */
+int tild_energy(tild_ctx* ctx, double out[8]);
+
+/* Number of steps taken since creation (or since tild_set_step_count). */
+int64_t tild_step_count(const tild_ctx* ctx);
+
+/* Set the step counter (the noise stream position), e.g. to resume a run. */
+int tild_set_step_count(tild_ctx* ctx, int64_t step);
+
+/* Wait for the context's stream; report a latched non-finite flag. */
+int tild_synchronize(tild_ctx* ctx);
+
+/* Free the context and all device memory it owns.  NULL is a no-op. */
+void tild_destroy(tild_ctx* ctx);
+
+/* Message of the last failure on ctx, or of the last failed tild_create on
+ * this thread when ctx is NULL.  Valid until the next call on ctx. */
+const char* tild_last_error(const tild_ctx* ctx);
+
+/*
+ * Instrumented steps for measurement: runs n_steps steps exactly like
+ * tild_step, with a HIP event pair recorded on the context's stream around
+ * every kernel launch, then synchronises and writes the mean duration in
+ * milliseconds of each kernel slot to kernel_ms[0 .. n_slots-1] (n_slots <=
+ * TILD_NUM_KERNELS) and the launches per step of each slot to
+ * launches_per_step (may be NULL).  Slot names: tild_kernel_name(slot).
+ */
+int tild_profile_steps(tild_ctx* ctx, int64_t n_steps, double* kernel_ms,
+                       int32_t* launches_per_step, int32_t n_slots);
+
+/* Name of a kernel timing slot, or NULL when slot is out of range. */
+const char* tild_kernel_name(int32_t slot);
+
+/*
+ * Device-to-device copy of `bytes` bytes (a multiple of 16) with the
+ * library's own streaming kernel, repeated `iters` times on `hip_stream`;
+ * writes the mean milliseconds per copy.  Used to calibrate achievable HBM
+ * bandwidth and hardware byte counters.  dst and src must not overlap.
+ */
+int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t iters,
+                     void* hip_stream, double* ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILD_H */

@@ -1,0 +1,203 @@
+"""Python binding of libtild (MI355X TILD particle-mesh step).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Host arrays are numpy arrays; device arrays are torch CUDA tensors
+(their data pointers are passed through), and the context runs on the torch
+stream that is current when it is created unless another is given.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as _L
+from ._lib import (  # noqa: F401
+    TILD_COM_CORRECT, TILD_EHIP, TILD_EINVAL, TILD_ENOMEM, TILD_ENONFINITE, TILD_ESTATE,
+    TILD_FP32, TILD_FP64, TILD_OK, TILD_PART_BOND, TILD_PART_NONBONDED, TILD_PART_TOTAL,
+    TildParams,
+)
+
+
+class TildError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libtild error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    return _L.load()
+
+
+def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0,
+                seed=0, precision=TILD_FP32, com_correct=True) -> TildParams:
+    p = TildParams()
+    for a in range(3):
+        p.box[a] = float(box[a])
+        p.grid[a] = int(grid[a])
+    p.order = int(order)
+    p.smear_a = float(smear_a)
+    p.chi = float(chi)
+    p.kappa = float(kappa)
+    p.bond_k = float(bond_k)
+    p.dt = float(dt)
+    p.gamma = float(gamma)
+    p.kT = float(kT)
+    p.seed = int(seed)
+    p.precision = int(precision)
+    p.flags = TILD_COM_CORRECT if com_correct else 0
+    return p
+
+
+def _dtype_code(arr) -> int:
+    dt = str(arr.dtype)
+    if dt.endswith("float32"):
+        return TILD_FP32
+    if dt.endswith("float64"):
+        return TILD_FP64
+    raise TypeError(f"positions/forces must be float32 or float64, got {arr.dtype}")
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    """(pointer, on_device) of a numpy array or torch tensor (contiguous)."""
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(x.data_ptr()), 1 if x.is_cuda else 0
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return ctypes.c_void_p(x.ctypes.data), 0
+
+
+class Tild:
+    """One TILD system on one GPU.
+
+    ``types`` (n,) int and ``bonds`` (n_bonds, 2) int are host arrays in ABI
+    order.  ``stream``: a torch.cuda.Stream, an integer hipStream_t, or None
+    for torch's current stream.
+    """
+
+    def __init__(self, params: TildParams, types, bonds=None, stream=None):
+        self._lib = lib()
+        self._ctx = ctypes.c_void_p(None)
+        types = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
+        bonds = np.zeros((0, 2), np.int32) if bonds is None else np.ascontiguousarray(np.asarray(bonds, dtype=np.int32))
+        self.n = int(types.shape[0])
+        self.params = params
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self._stream_obj = stream
+        handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
+        self._stream = ctypes.c_void_p(int(handle) if handle else None)
+        rc = self._lib.tild_create(ctypes.byref(params), self.n, types.ctypes.data, int(bonds.shape[0]),
+                                   bonds.ctypes.data if bonds.size else None, self._stream, ctypes.byref(self._ctx))
+        if rc != TILD_OK:
+            raise TildError(rc, self._lib.tild_last_error(None).decode())
+
+    # -- lifetime ----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self._lib.tild_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != TILD_OK:
+            raise TildError(rc, self._lib.tild_last_error(self._ctx).decode())
+
+    # -- calls -------------------------------------------------------------
+    def set_positions(self, x):
+        if _is_torch(x):
+            ptr, dev = _ptr(x)
+        else:
+            x = np.ascontiguousarray(x)
+            ptr, dev = _ptr(x)
+        self._check(self._lib.tild_set_positions(self._ctx, ptr, _dtype_code(x), dev))
+
+    def get_positions(self, out=None, dtype=np.float64):
+        if out is None:
+            out = np.empty((self.n, 3), dtype=dtype)
+        ptr, dev = _ptr(out)
+        self._check(self._lib.tild_get_positions(self._ctx, ptr, _dtype_code(out), dev))
+        return out
+
+    def step(self, n_steps: int = 1):
+        self._check(self._lib.tild_step(self._ctx, int(n_steps)))
+
+    def forces(self, parts: int = TILD_PART_TOTAL, out=None, dtype=np.float64):
+        if out is None:
+            out = np.empty((self.n, 3), dtype=dtype)
+        ptr, dev = _ptr(out)
+        self._check(self._lib.tild_forces(self._ctx, ptr, _dtype_code(out), dev, int(parts)))
+        return out
+
+    def energy(self) -> Dict[str, object]:
+        buf = (ctypes.c_double * 8)()
+        self._check(self._lib.tild_energy(self._ctx, buf))
+        v = list(buf)
+        return dict(E_bond=v[0], E_chi=v[1], E_kappa=v[2], E=v[3], W=np.array(v[4:7]))
+
+    @property
+    def step_count(self) -> int:
+        return int(self._lib.tild_step_count(self._ctx))
+
+    @step_count.setter
+    def step_count(self, s: int):
+        self._check(self._lib.tild_set_step_count(self._ctx, int(s)))
+
+    def synchronize(self):
+        self._check(self._lib.tild_synchronize(self._ctx))
+
+    def profile_steps(self, n_steps: int) -> Dict[str, float]:
+        k = _L.TILD_NUM_KERNELS
+        ms = (ctypes.c_double * k)()
+        lps = (ctypes.c_int32 * k)()
+        self._check(self._lib.tild_profile_steps(self._ctx, int(n_steps), ms, lps, k))
+        return {self._lib.tild_kernel_name(i).decode(): float(ms[i]) for i in range(k)}
+
+
+def kernel_names() -> Sequence[str]:
+    L = lib()
+    return [L.tild_kernel_name(i).decode() for i in range(_L.TILD_NUM_KERNELS)]
+
+
+def stream_copy_ms(dst, src, nbytes: int, iters: int = 20, stream=None) -> float:
+    """Mean milliseconds of the library's device copy kernel over ``nbytes``."""
+    L = lib()
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    handle = stream if isinstance(stream, int) else stream.cuda_stream
+    ms = ctypes.c_double(0.0)
+    rc = L.tild_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), int(nbytes), int(iters),
+                            ctypes.c_void_p(int(handle) if handle else None), ctypes.byref(ms))
+    if rc != TILD_OK:
+        raise TildError(rc, L.tild_last_error(None).decode())
+    return float(ms.value)
+
+
+def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None) -> Tild:
+    """Context for a synth.Melt workload (positions are set too)."""
+    p = make_params(melt.box, melt.grid, melt.order, melt.smear_a, melt.chi, melt.kappa, melt.bond_k, melt.dt,
+                    melt.gamma, melt.kT, melt.seed, precision, com_correct)
+    t = Tild(p, melt.types, melt.bonds, stream=stream)
+    t.set_positions(np.ascontiguousarray(melt.x, dtype=np.float64))
+    return t

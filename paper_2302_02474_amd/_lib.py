@@ -1,0 +1,94 @@
+"""ctypes declarations for libtild.so (see include/tild.h)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtild.so")
+
+TILD_OK = 0
+TILD_EINVAL = -1
+TILD_ENOMEM = -2
+TILD_EHIP = -3
+TILD_ENONFINITE = -4
+TILD_ESTATE = -5
+TILD_FP32 = 0
+TILD_FP64 = 1
+TILD_COM_CORRECT = 1
+TILD_PART_NONBONDED = 1
+TILD_PART_BOND = 2
+TILD_PART_TOTAL = 3
+TILD_NUM_KERNELS = 6
+
+EXPORTS = [
+    "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",
+    "tild_energy", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
+    "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
+]
+
+
+class TildParams(ctypes.Structure):
+    _fields_ = [
+        ("box", ctypes.c_double * 3),
+        ("grid", ctypes.c_int32 * 3),
+        ("order", ctypes.c_int32),
+        ("smear_a", ctypes.c_double),
+        ("chi", ctypes.c_double),
+        ("kappa", ctypes.c_double),
+        ("bond_k", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("kT", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtild.so and declare every exported signature.  Raises if the library is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libtild.so not found at {path}: build it with `python -m paper_2302_02474_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    P = ctypes.POINTER
+    lib.tild_create.argtypes = [P(TildParams), i64, vp, i64, vp, vp, P(vp)]
+    lib.tild_create.restype = ctypes.c_int
+    lib.tild_set_positions.argtypes = [vp, vp, i32, i32]
+    lib.tild_set_positions.restype = ctypes.c_int
+    lib.tild_get_positions.argtypes = [vp, vp, i32, i32]
+    lib.tild_get_positions.restype = ctypes.c_int
+    lib.tild_step.argtypes = [vp, i64]
+    lib.tild_step.restype = ctypes.c_int
+    lib.tild_forces.argtypes = [vp, vp, i32, i32, u32]
+    lib.tild_forces.restype = ctypes.c_int
+    lib.tild_energy.argtypes = [vp, P(ctypes.c_double)]
+    lib.tild_energy.restype = ctypes.c_int
+    lib.tild_step_count.argtypes = [vp]
+    lib.tild_step_count.restype = ctypes.c_int64
+    lib.tild_set_step_count.argtypes = [vp, i64]
+    lib.tild_set_step_count.restype = ctypes.c_int
+    lib.tild_synchronize.argtypes = [vp]
+    lib.tild_synchronize.restype = ctypes.c_int
+    lib.tild_destroy.argtypes = [vp]
+    lib.tild_destroy.restype = None
+    lib.tild_last_error.argtypes = [vp]
+    lib.tild_last_error.restype = ctypes.c_char_p
+    lib.tild_profile_steps.argtypes = [vp, i64, P(ctypes.c_double), P(i32), i32]
+    lib.tild_profile_steps.restype = ctypes.c_int
+    lib.tild_kernel_name.argtypes = [i32]
+    lib.tild_kernel_name.restype = ctypes.c_char_p
+    lib.tild_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, vp, P(ctypes.c_double)]
+    lib.tild_stream_copy.restype = ctypes.c_int
+    _lib = lib
+    return lib

@@ -1,0 +1,570 @@
+// C ABI of libtild: context creation, parameter validation, device memory,
+// step orchestration, I/O conversions and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tild.h"
+#include "tild_kernels.h"
+
+#define TILD_API extern "C" __attribute__((visibility("default")))
+
+using namespace tild;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum Slot { kFill = 0, kSpread, kXyR2c, kZKmul, kXyC2r, kGather, kNumSlots };
+static_assert(kNumSlots == TILD_NUM_KERNELS, "slot table");
+const char* kSlotNames[kNumSlots] = {"fill_mean", "spread", "fft_xy_r2c", "fft_z_kmul", "fft_xy_c2r",
+                                     "gather_bond_em"};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool smooth235(int n) {
+    if (n < 1) return false;
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Radix passes for one length: as many 8s as possible, then 4, 2, 3, 5.
+bool make_plan(int n, int tw_offset, FftPlan& pl) {
+    std::memset(&pl, 0, sizeof(pl));
+    pl.n = n;
+    pl.tw = tw_offset;
+    int r = n, k = 0;
+    auto push = [&](int R) {
+        if (k >= kMaxRadixStages) return false;
+        pl.radix[k++] = R;
+        r /= R;
+        return true;
+    };
+    while (r % 8 == 0)
+        if (!push(8)) return false;
+    while (r % 4 == 0)
+        if (!push(4)) return false;
+    while (r % 2 == 0)
+        if (!push(2)) return false;
+    while (r % 3 == 0)
+        if (!push(3)) return false;
+    while (r % 5 == 0)
+        if (!push(5)) return false;
+    pl.nst = k;
+    return r == 1;
+}
+
+}  // namespace
+
+struct tild_ctx {
+    tild_params p{};
+    int device = 0;
+    Launch L{};
+    DeviceState S{};
+    int64_t step = 0;
+    bool have_pos = false;
+    std::string err;
+    void* staging = nullptr;  // device [n][3] doubles for host transfers
+    std::vector<void*> allocs;
+    int64_t n_bonds = 0;
+
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return TILD_EHIP;
+    }
+    hipError_t alloc(void** p, size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) allocs.push_back(*p);
+        return e;
+    }
+};
+
+namespace {
+
+int validate(const tild_params* p, int64_t n, std::string& why) {
+    if (!p) return why = "params is NULL", TILD_EINVAL;
+    if (n < 0 || n >= (int64_t)1 << 31) return why = "n_beads must be in [0, 2^31)", TILD_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        if (!(p->box[a] > 0.0) || !std::isfinite(p->box[a])) return why = "box edges must be finite and > 0", TILD_EINVAL;
+        if (p->grid[a] < 2 || p->grid[a] > 256 || !smooth235(p->grid[a]))
+            return why = "grid sizes must be in [2, 256] and products of 2, 3 and 5", TILD_EINVAL;
+        if (p->order > p->grid[a]) return why = "order must not exceed any grid size", TILD_EINVAL;
+    }
+    if (p->order < 1 || p->order > 7) return why = "order must be in [1, 7]", TILD_EINVAL;
+    if (!(p->smear_a >= 0.0) || !std::isfinite(p->smear_a)) return why = "smear_a must be finite and >= 0", TILD_EINVAL;
+    if (!std::isfinite(p->chi) || !std::isfinite(p->kappa) || !std::isfinite(p->bond_k))
+        return why = "chi, kappa and bond_k must be finite", TILD_EINVAL;
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return why = "dt must be finite and > 0", TILD_EINVAL;
+    if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return why = "gamma must be finite and > 0", TILD_EINVAL;
+    if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return why = "kT must be finite and >= 0", TILD_EINVAL;
+    if (p->precision != TILD_FP32 && p->precision != TILD_FP64) return why = "precision must be TILD_FP32 or TILD_FP64", TILD_EINVAL;
+    if (p->flags & ~TILD_COM_CORRECT) return why = "unknown flag bits", TILD_EINVAL;
+    return TILD_OK;
+}
+
+// Choose workgroup shapes; false if the grid does not fit the kernels' limits.
+bool choose_shapes(Launch& L, std::string& why) {
+    const Dims& d = L.d;
+    const size_t lds_max = 160 * 1024;
+    const int cands_f[3] = {256, 512, 1024}, cands_d[2] = {256, 512};
+    const int* cands = L.precision == 0 ? cands_f : cands_d;
+    const int nc = L.precision == 0 ? 3 : 2;
+    L.plane_block = 0;
+    for (int i = 0; i < nc; ++i) {
+        const long long B = cands[i];
+        const long long xl = (long long)d.npair * d.mx, yl = (long long)d.hx * d.my;
+        if (xl <= 30 * B && yl <= 30 * B && (long long)d.npair * d.hx <= 20 * B && xl <= 20 * B) {
+            L.plane_block = (int)B;
+            break;
+        }
+    }
+    if (L.plane_block == 0) {
+        why = "grid plane too large for the in-LDS plane transform";
+        return false;
+    }
+    if (plane_lds_bytes(L) > lds_max) {
+        why = "grid plane does not fit one workgroup's LDS in this precision";
+        return false;
+    }
+    int cb = 7680 / (4 * d.mz);
+    if (cb > 16) cb = 16;
+    if (cb < 1) {
+        why = "grid too long along z";
+        return false;
+    }
+    L.z_cols = cb;
+    L.z_block = 256;
+    if (z_lds_bytes(L) > lds_max) {
+        why = "z columns do not fit LDS";
+        return false;
+    }
+    L.n_zblocks = (int)((d.hplane + cb - 1) / cb);
+    return true;
+}
+
+int check_flag(tild_ctx* c) {
+    uint32_t f = 0;
+    hipError_t e = hipMemcpyAsync(&f, c->S.flag, sizeof(f), hipMemcpyDeviceToHost, c->L.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "synchronize");
+    if (f) {
+        e = hipMemsetAsync(c->S.flag, 0, sizeof(uint32_t), c->L.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->L.stream);
+        if (e != hipSuccess) return c->hip_fail(e, "clear flag");
+        return c->fail(TILD_ENONFINITE, "non-finite force, displacement or position detected");
+    }
+    return TILD_OK;
+}
+
+// Forces on the mesh up to the gradient fields (no bead update).
+hipError_t mesh_forward(tild_ctx* c, bool energy_only) {
+    hipError_t e = launch_fill_mean(c->L, c->S);
+    if (e == hipSuccess) e = launch_spread(c->L, c->S);
+    if (e == hipSuccess) e = launch_xy_r2c(c->L, c->S);
+    if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, energy_only);
+    if (e == hipSuccess && !energy_only) e = launch_xy_c2r(c->L, c->S);
+    return e;
+}
+
+void swap_state(tild_ctx* c) {
+    std::swap(c->S.pos, c->S.pos_next);
+    std::swap(c->S.qshift, c->S.qshift_next);
+}
+
+int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
+    for (int64_t s = 0; s < n_steps; ++s) {
+        hipError_t e = hipSuccess;
+        auto mark = [&](int slot, int which) {
+            if (ev && e == hipSuccess) e = hipEventRecord((*ev)[(size_t)(s * kNumSlots + slot) * 2 + which], c->L.stream);
+        };
+        mark(kFill, 0);
+        if (e == hipSuccess) e = launch_fill_mean(c->L, c->S);
+        mark(kFill, 1);
+        mark(kSpread, 0);
+        if (e == hipSuccess) e = launch_spread(c->L, c->S);
+        mark(kSpread, 1);
+        mark(kXyR2c, 0);
+        if (e == hipSuccess) e = launch_xy_r2c(c->L, c->S);
+        mark(kXyR2c, 1);
+        mark(kZKmul, 0);
+        if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);
+        mark(kZKmul, 1);
+        mark(kXyC2r, 0);
+        if (e == hipSuccess) e = launch_xy_c2r(c->L, c->S);
+        mark(kXyC2r, 1);
+        mark(kGather, 0);
+        if (e == hipSuccess) e = launch_gather(c->L, c->S, 0, (uint64_t)c->step, nullptr, 0, 0);
+        mark(kGather, 1);
+        if (e != hipSuccess) return c->hip_fail(e, "step launch");
+        swap_state(c);
+        ++c->step;
+    }
+    return TILD_OK;
+}
+
+}  // namespace
+
+TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32_t* types, int64_t n_bonds,
+                         const int32_t* bonds, void* hip_stream, tild_ctx** out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return TILD_EINVAL;
+    }
+    *out = nullptr;
+    std::string why;
+    int rc = validate(params, n_beads, why);
+    if (rc != TILD_OK) {
+        g_create_error = why;
+        return rc;
+    }
+    if (n_beads > 0 && !types) {
+        g_create_error = "types is NULL";
+        return TILD_EINVAL;
+    }
+    if (n_bonds < 0 || (n_bonds > 0 && !bonds) || n_bonds >= (int64_t)1 << 30) {
+        g_create_error = "invalid bond list";
+        return TILD_EINVAL;
+    }
+    // Host-side checks and bond CSR (both ends of every bond).
+    int64_t n_a = 0, n_b = 0;
+    for (int64_t i = 0; i < n_beads; ++i) {
+        if (types[i] == 0) ++n_a;
+        else if (types[i] == 1) ++n_b;
+        else {
+            g_create_error = "types must be 0 (A) or 1 (B)";
+            return TILD_EINVAL;
+        }
+    }
+    std::vector<int32_t> off((size_t)n_beads + 1, 0), nbr((size_t)(2 * n_bonds));
+    for (int64_t b = 0; b < n_bonds; ++b) {
+        const int32_t i = bonds[2 * b], j = bonds[2 * b + 1];
+        if (i < 0 || j < 0 || i >= n_beads || j >= n_beads || i == j) {
+            g_create_error = "bond index out of range or self-bond at bond " + std::to_string(b);
+            return TILD_EINVAL;
+        }
+        ++off[(size_t)i + 1];
+        ++off[(size_t)j + 1];
+    }
+    for (int64_t i = 0; i < n_beads; ++i) off[(size_t)i + 1] += off[(size_t)i];
+    {
+        std::vector<int32_t> fill(off.begin(), off.end() - 1);
+        for (int64_t b = 0; b < n_bonds; ++b) {
+            const int32_t i = bonds[2 * b], j = bonds[2 * b + 1];
+            nbr[(size_t)fill[(size_t)i]++] = j;
+            nbr[(size_t)fill[(size_t)j]++] = i;
+        }
+    }
+
+    tild_ctx* c = new (std::nothrow) tild_ctx();
+    if (!c) {
+        g_create_error = "out of host memory";
+        return TILD_ENOMEM;
+    }
+    c->p = *params;
+    c->n_bonds = n_bonds;
+    Launch& L = c->L;
+    L.stream = (hipStream_t)hip_stream;
+    L.precision = params->precision;
+    L.order = params->order;
+    Dims& d = L.d;
+    d.mx = params->grid[0];
+    d.my = params->grid[1];
+    d.mz = params->grid[2];
+    d.hx = d.mx / 2 + 1;
+    d.npair = (d.my + 1) / 2;
+    d.m = (long long)d.mx * d.my * d.mz;
+    d.hplane = (long long)d.my * d.hx;
+    d.lx = params->box[0];
+    d.ly = params->box[1];
+    d.lz = params->box[2];
+    if (!make_plan(d.mx, 0, L.px) || !make_plan(d.my, d.mx, L.py) || !make_plan(d.mz, d.mx + d.my, L.pz)) {
+        g_create_error = "internal: radix plan";
+        delete c;
+        return TILD_EINVAL;
+    }
+    if (!choose_shapes(L, why)) {
+        g_create_error = why;
+        delete c;
+        return TILD_EINVAL;
+    }
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        g_create_error = "no HIP device";
+        delete c;
+        return TILD_EHIP;
+    }
+    L.n_bblocks = (int)((n_beads + 255) / 256);
+    if (L.n_bblocks < 1) L.n_bblocks = 1;
+    Phys& ph = L.ph;
+    ph.lx = d.lx;
+    ph.ly = d.ly;
+    ph.lz = d.lz;
+    ph.a2 = params->smear_a * params->smear_a;
+    ph.chi = params->chi;
+    ph.kappa = params->kappa;
+    ph.inv_n = n_beads > 0 ? 1.0 / (double)n_beads : 0.0;
+    ph.bond_k = params->bond_k;
+    ph.mob_dt = params->dt / params->gamma;
+    ph.noise_amp = std::sqrt(2.0 * params->kT * params->dt / params->gamma);
+    ph.seed = params->seed;
+    ph.com_correct = (params->flags & TILD_COM_CORRECT) ? 1 : 0;
+
+    DeviceState& S = c->S;
+    S.n = n_beads;
+    S.n_a = n_a;
+    S.n_b = n_b;
+    const size_t real_sz = L.precision == 0 ? 4 : 8;
+    const size_t cplx_sz = 2 * real_sz;
+    const size_t npos = (size_t)(n_beads > 0 ? n_beads : 1);
+    hipError_t e = hipSuccess;
+    auto A = [&](void** ptr, size_t bytes) {
+        if (e == hipSuccess) e = c->alloc(ptr, bytes);
+    };
+    A((void**)&S.pos, npos * sizeof(uint4));
+    A((void**)&S.pos_next, npos * sizeof(uint4));
+    A((void**)&S.qshift, 4 * sizeof(uint32_t));
+    A((void**)&S.qshift_next, 4 * sizeof(uint32_t));
+    A((void**)&S.bond_off, off.size() * sizeof(int32_t));
+    A((void**)&S.bond_nbr, (nbr.size() > 0 ? nbr.size() : 1) * sizeof(int32_t));
+    A(&S.dens, 2 * (size_t)d.m * real_sz);
+    A(&S.spec, 2 * (size_t)d.mz * d.hplane * cplx_sz);
+    A(&S.zout, 4 * (size_t)d.mz * d.hplane * cplx_sz);
+    A(&S.grad, 6 * (size_t)d.m * real_sz);
+    A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
+    A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
+    A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(double));
+    A((void**)&S.com_acc, 4 * sizeof(unsigned long long));
+    A((void**)&S.flag, sizeof(uint32_t));
+    A((void**)&S.eout, 8 * sizeof(double));
+    A(&c->staging, npos * 3 * sizeof(double));
+    if (e != hipSuccess) {
+        g_create_error = std::string("device allocation: ") + hipGetErrorString(e);
+        tild_destroy(c);
+        return e == hipErrorOutOfMemory ? TILD_ENOMEM : TILD_EHIP;
+    }
+    // Twiddles exp(-2 pi i m / n) in float64, rounded to the working precision.
+    std::vector<double> tw;
+    for (int a = 0; a < 3; ++a) {
+        const int n = a == 0 ? d.mx : (a == 1 ? d.my : d.mz);
+        for (int m = 0; m < n; ++m) {
+            const double ang = 2.0 * M_PI * (double)m / (double)n;
+            tw.push_back(std::cos(ang));
+            tw.push_back(-std::sin(ang));
+        }
+    }
+    std::vector<float> twf(tw.begin(), tw.end());
+    std::vector<uint4> pos0((size_t)npos, uint4{0, 0, 0, 0});
+    for (int64_t i = 0; i < n_beads; ++i) pos0[(size_t)i].w = (uint32_t)types[i];
+    const uint32_t zeros4[4] = {0, 0, 0, 0};
+    const unsigned long long zacc[4] = {0, 0, 0, 0};
+    auto H2D = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    H2D(S.pos, pos0.data(), npos * sizeof(uint4));
+    H2D(S.pos_next, pos0.data(), npos * sizeof(uint4));
+    H2D(S.qshift, zeros4, sizeof(zeros4));
+    H2D(S.qshift_next, zeros4, sizeof(zeros4));
+    H2D(S.bond_off, off.data(), off.size() * sizeof(int32_t));
+    H2D(S.bond_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
+    if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
+    else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
+    H2D(S.com_acc, zacc, sizeof(zacc));
+    H2D(S.flag, zeros4, sizeof(uint32_t));
+    if (e == hipSuccess) e = configure_kernel_attributes(L);
+    if (e != hipSuccess) {
+        g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+        tild_destroy(c);
+        return TILD_EHIP;
+    }
+    *out = c;
+    return TILD_OK;
+}
+
+TILD_API void tild_destroy(tild_ctx* c) {
+    if (!c) return;
+    {
+        DeviceGuard g(c->device);
+        (void)hipStreamSynchronize(c->L.stream);
+        for (void* p : c->allocs) (void)hipFree(p);
+    }
+    delete c;
+}
+
+TILD_API const char* tild_last_error(const tild_ctx* c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+TILD_API int tild_set_positions(tild_ctx* c, const void* xyz, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if ((!xyz && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "set_positions: NULL array or bad dtype");
+    DeviceGuard g(c->device);
+    const size_t esz = dtype == TILD_FP32 ? 4 : 8;
+    const size_t bytes = (size_t)c->S.n * 3 * esz;
+    const void* src = xyz;
+    hipError_t e = hipSuccess;
+    if (!on_device && c->S.n > 0) {
+        for (int64_t i = 0; i < c->S.n * 3; ++i) {
+            const double v = dtype == TILD_FP32 ? (double)((const float*)xyz)[i] : ((const double*)xyz)[i];
+            if (!std::isfinite(v)) return c->fail(TILD_EINVAL, "set_positions: non-finite coordinate");
+        }
+        e = hipMemcpyAsync(c->staging, xyz, bytes, hipMemcpyHostToDevice, c->L.stream);
+        src = c->staging;
+    }
+    if (e == hipSuccess) e = launch_set_positions(c->L, c->S, src, dtype);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "set_positions");
+    c->have_pos = true;
+    return TILD_OK;
+}
+
+TILD_API int tild_get_positions(tild_ctx* c, void* xyz, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if ((!xyz && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "get_positions: NULL array or bad dtype");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    void* dst = on_device ? xyz : c->staging;
+    hipError_t e = launch_get_positions(c->L, c->S, dst, dtype);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(xyz, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "get_positions");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
+TILD_API int tild_step(tild_ctx* c, int64_t n_steps) {
+    if (!c) return TILD_EINVAL;
+    if (n_steps < 0) return c->fail(TILD_EINVAL, "n_steps < 0");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    return run_steps(c, n_steps, nullptr);
+}
+
+TILD_API int tild_forces(tild_ctx* c, void* out, int32_t dtype, int32_t on_device, uint32_t parts) {
+    if (!c) return TILD_EINVAL;
+    if ((!out && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64) || parts == 0 || (parts & ~3u))
+        return c->fail(TILD_EINVAL, "forces: NULL array, bad dtype or bad parts");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    hipError_t e = hipSuccess;
+    if (parts & TILD_PART_NONBONDED) e = mesh_forward(c, false);
+    void* dst = on_device ? out : c->staging;
+    if (e == hipSuccess) e = launch_gather(c->L, c->S, 1, (uint64_t)c->step, dst, dtype, parts);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(out, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "forces");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
+TILD_API int tild_energy(tild_ctx* c, double out[8]) {
+    if (!c) return TILD_EINVAL;
+    if (!out) return c->fail(TILD_EINVAL, "energy: out is NULL");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    hipError_t e = mesh_forward(c, true);
+    if (e == hipSuccess) e = launch_bond_energy(c->L, c->S);
+    if (e == hipSuccess) e = launch_reduce_energy(c->L, c->S);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, c->S.eout, 8 * sizeof(double), hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "energy");
+    return check_flag(c);
+}
+
+TILD_API int64_t tild_step_count(const tild_ctx* c) { return c ? c->step : -1; }
+
+TILD_API int tild_set_step_count(tild_ctx* c, int64_t step) {
+    if (!c) return TILD_EINVAL;
+    if (step < 0) return c->fail(TILD_EINVAL, "step < 0");
+    c->step = step;
+    return TILD_OK;
+}
+
+TILD_API int tild_synchronize(tild_ctx* c) {
+    if (!c) return TILD_EINVAL;
+    DeviceGuard g(c->device);
+    return check_flag(c);
+}
+
+TILD_API int tild_profile_steps(tild_ctx* c, int64_t n_steps, double* kernel_ms, int32_t* launches_per_step,
+                                int32_t n_slots) {
+    if (!c) return TILD_EINVAL;
+    if (n_steps < 1 || !kernel_ms || n_slots < 1 || n_slots > kNumSlots)
+        return c->fail(TILD_EINVAL, "profile_steps: bad arguments");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    std::vector<hipEvent_t> ev((size_t)n_steps * kNumSlots * 2, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    int rc = TILD_OK;
+    if (e == hipSuccess) rc = run_steps(c, n_steps, &ev);
+    if (e == hipSuccess && rc == TILD_OK) e = hipStreamSynchronize(c->L.stream);
+    std::vector<double> sum(kNumSlots, 0.0);
+    for (int64_t s = 0; e == hipSuccess && rc == TILD_OK && s < n_steps; ++s)
+        for (int k = 0; k < kNumSlots; ++k) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[(size_t)(s * kNumSlots + k) * 2], ev[(size_t)(s * kNumSlots + k) * 2 + 1]);
+            if (e != hipSuccess) break;
+            sum[(size_t)k] += ms;
+        }
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc != TILD_OK) return rc;
+    if (e != hipSuccess) return c->hip_fail(e, "profile_steps");
+    for (int k = 0; k < n_slots; ++k) {
+        kernel_ms[k] = sum[(size_t)k] / (double)n_steps;
+        if (launches_per_step) launches_per_step[k] = 1;
+    }
+    return check_flag(c);
+}
+
+TILD_API const char* tild_kernel_name(int32_t slot) {
+    if (slot < 0 || slot >= kNumSlots) return nullptr;
+    return kSlotNames[slot];
+}
+
+TILD_API int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t iters, void* hip_stream,
+                              double* ms_per_copy) {
+    if (!dst || !src || bytes == 0 || bytes % 16 || iters < 1 || !ms_per_copy) {
+        g_create_error = "stream_copy: bad arguments";
+        return TILD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    for (int i = 0; e == hipSuccess && i < iters; ++i) e = launch_stream_copy(dst, src, bytes, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+        g_create_error = std::string("stream_copy: ") + hipGetErrorString(e);
+        return TILD_EHIP;
+    }
+    *ms_per_copy = ms / iters;
+    return TILD_OK;
+}

@@ -1,0 +1,148 @@
+// Device-side helpers shared by the TILD kernels: complex arithmetic, grid
+// geometry, fixed-point positions, B-spline assignment weights and the Philox
+// noise generator.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tild {
+
+template <typename T> struct CplxOf;
+template <> struct CplxOf<float> { using type = float2; };
+template <> struct CplxOf<double> { using type = double2; };
+template <typename T> using cplx = typename CplxOf<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+    return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename C, typename T> __device__ __forceinline__ C cscale(C a, T s) { return C{a.x * s, a.y * s}; }
+// -i * a and +i * a
+template <typename C> __device__ __forceinline__ C mul_mi(C a) { return C{a.y, -a.x}; }
+template <typename C> __device__ __forceinline__ C mul_pi(C a) { return C{-a.y, a.x}; }
+
+// Grid geometry.  Real grids are stored [z][y][x] (x fastest); half spectra
+// (real-to-complex along x) are stored [z][ky][kx] with hx = mx/2 + 1.
+struct Dims {
+    int mx, my, mz;  // grid points
+    int hx;          // mx/2 + 1
+    int npair;       // (my + 1) / 2: row pairs packed into one complex row
+    long long m;     // mx*my*mz
+    long long hplane;  // my*hx complex per half-spectrum plane
+    double lx, ly, lz;
+};
+
+// Positions are unsigned 32-bit fractions of the box edge: x = q * L / 2^32.
+// The grid coordinate u = x / h = q * M / 2^32 is a 64-bit fixed-point number
+// with 32 fractional bits, so cell indices and fractional offsets are exact.
+//
+// Assignment: a bead at u touches the P nodes g0 .. g0+P-1 with
+// g0 = floor(u - P/2) + 1, and the node g0+j has weight B_P(u - g0 - j), B_P
+// the centred cardinal B-spline of order P.  With f = frac(u - P/2) that
+// weight is the uncentred spline M_P(f + P-1-j), which the recursion below
+// evaluates for all j at once:
+//   M_1 = 1 on [0,1);  M_k(s) = [s M_{k-1}(s) + (k-s) M_{k-1}(s-1)] / (k-1).
+template <typename T, int P>
+__device__ __forceinline__ void assignment_weights(uint32_t q, int m, int& g0, T w[P]) {
+    const int64_t v = (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m);  // < 2^40
+    const int64_t s = v - ((int64_t)P << 31);                         // (u - P/2) * 2^32
+    const int64_t fl = s >> 32;                                          // floor (arithmetic shift)
+    const uint32_t fr = (uint32_t)(s & 0xffffffffLL);
+    int g = (int)fl + 1;
+    g %= m;
+    if (g < 0) g += m;
+    g0 = g;
+    const T f = (T)fr * (T)2.3283064365386963e-10;  // 2^-32
+    // mk[j] holds M_k(f + j), j = 0 .. k-1
+    T mk[P];
+    mk[0] = (T)1;
+#pragma unroll
+    for (int k = 2; k <= P; ++k) {
+        const T inv = (T)1 / (T)(k - 1);
+        mk[k - 1] = inv * ((T)1 - f) * mk[k - 2];
+#pragma unroll
+        for (int j = k - 2; j >= 1; --j) mk[j] = inv * ((f + (T)j) * mk[j] + ((T)(k - j) - f) * mk[j - 1]);
+        mk[0] = inv * f * mk[0];
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) w[j] = mk[P - 1 - j];
+}
+
+// Minimum-image separation (in box units * 2^32) of two fixed-point coordinates.
+__device__ __forceinline__ int32_t fixed_delta(uint32_t a, uint32_t b) { return (int32_t)(a - b); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of
+//   (c0, c1, c2, c3) <- (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0))
+// with the key advanced by the Weyl increments between rounds.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+    constexpr uint32_t A = 0xD2511F53u, B = 0xCD9E8D57u;
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += WA;
+            k1 += WB;
+        }
+        const uint32_t hi0 = __umulhi(A, c.x), lo0 = A * c.x;
+        const uint32_t hi1 = __umulhi(B, c.z), lo1 = B * c.z;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+// -2 ln(u) for u = (w + 1/2) 2^-32, accurate also when u is close to 1.
+__device__ __forceinline__ float neg2log_u(uint32_t w) {
+    if (w >= 0x80000000u) {
+        const float tail = ((float)(0xffffffffu - w) + 0.5f) * 2.3283064365386963e-10f;  // 1 - u
+        return -2.0f * log1pf(-tail);
+    }
+    return -2.0f * logf(((float)w + 0.5f) * 2.3283064365386963e-10f);
+}
+__device__ __forceinline__ double neg2log_u_d(uint32_t w) {
+    return -2.0 * log(((double)w + 0.5) * 2.3283064365386963e-10);
+}
+
+// Unit Gaussian increments of bead `id` at step `step` (Box-Muller on the
+// four Philox words: x, y from words 0, 1 and z from words 2, 3).
+template <typename T> struct Noise;
+template <> struct Noise<float> {
+    __device__ static void draw(uint32_t id, uint64_t step, uint64_t seed, float xi[3]) {
+        const U4 r = philox4x32_10(U4{id, (uint32_t)step, (uint32_t)(step >> 32), 0u}, (uint32_t)seed,
+                                   (uint32_t)(seed >> 32));
+        const float r01 = sqrtf(neg2log_u(r.x));
+        const float r23 = sqrtf(neg2log_u(r.z));
+        float s1, c1, s3, c3;
+        sincospif(2.0f * (((float)r.y + 0.5f) * 2.3283064365386963e-10f), &s1, &c1);
+        sincospif(2.0f * (((float)r.w + 0.5f) * 2.3283064365386963e-10f), &s3, &c3);
+        xi[0] = r01 * c1;
+        xi[1] = r01 * s1;
+        xi[2] = r23 * c3;
+    }
+};
+template <> struct Noise<double> {
+    __device__ static void draw(uint32_t id, uint64_t step, uint64_t seed, double xi[3]) {
+        const U4 r = philox4x32_10(U4{id, (uint32_t)step, (uint32_t)(step >> 32), 0u}, (uint32_t)seed,
+                                   (uint32_t)(seed >> 32));
+        const double r01 = sqrt(neg2log_u_d(r.x));
+        const double r23 = sqrt(neg2log_u_d(r.z));
+        double s1, c1, s3, c3;
+        sincospi(2.0 * (((double)r.y + 0.5) * 2.3283064365386963e-10), &s1, &c1);
+        sincospi(2.0 * (((double)r.w + 0.5) * 2.3283064365386963e-10), &s3, &c3);
+        xi[0] = r01 * c1;
+        xi[1] = r01 * s1;
+        xi[2] = r23 * c3;
+    }
+};
+
+}  // namespace tild

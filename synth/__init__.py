@@ -10,6 +10,7 @@ from .melts import (  # noqa: F401
     CONFIGS,
     Melt,
     config,
+    make_custom,
     make_melt,
     make_replicas,
     snap_to_lattice,

@@ -206,6 +206,19 @@ def make_replicas(count: int = 64, seed_init: int = 2305) -> List[Melt]:
     return out
 
 
+def make_custom(n_chains: int, n_a: int, n_b: int, box, grid, order: int, chi: float, kappa: float,
+                smear_a: float = 0.5, seed_init: int = 1, noise_seed: int = 7, bond_k: float = 1.5,
+                dt: float = 0.005, gamma: float = 1.0, kT: float = 1.0) -> Melt:
+    """A random-walk diblock melt with arbitrary box, grid and parameters."""
+    rng = np.random.Generator(np.random.PCG64(seed_init))
+    box = np.asarray(box, dtype=np.float64).reshape(3)
+    grid = np.asarray(grid, dtype=np.int64).reshape(3)
+    x, types, bonds = _build("custom", [(n_chains, n_a, n_b)], box, grid, rng)
+    return Melt(name=f"custom {n_chains}x(A{n_a}B{n_b}) box {box.tolist()} grid {grid.tolist()} P={order}",
+                x=x, types=types, bonds=bonds, box=box, grid=grid, order=order, smear_a=smear_a,
+                chi=chi, kappa=kappa, bond_k=bond_k, dt=dt, gamma=gamma, kT=kT, seed=noise_seed, steps=1)
+
+
 def snap_to_lattice(x: np.ndarray, box: np.ndarray, bits: int = 32) -> np.ndarray:
     """Round positions onto the lattice L * j / 2**bits, j integer in [0, 2**bits).
 

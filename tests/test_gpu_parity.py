@@ -1,0 +1,262 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Bar: relative RMS force error <= 1e-5 in FP32 (separately for the
+non-bonded, bond and total forces), energies within 1e-5 relative; FP64 mode
+to 1e-9.  Inputs are snapped to the 2^-32 box lattice so both sides start
+from identical coordinates."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2302_02474_amd as T
+from oracle import tild_ref as R
+from oracle.philox_ref import gaussian_noise
+from synth import make_custom, make_melt, snap_to_lattice
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel_rms(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_params(m, com=True, transform="dense"):
+    return R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
+                    chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed,
+                    com_correct=com, transform=transform)
+
+
+def gpu_ctx(m, precision, com=True):
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      precision, com)
+    t = T.Tild(p, m.types, m.bonds)
+    return t
+
+
+def compare_forces(m, precision, tol, transform="dense"):
+    x = snap_to_lattice(m.x, m.box)
+    say(f"[forces] {m.name} precision={precision} n={m.n}")
+    t = gpu_ctx(m, precision)
+    t.set_positions(x)
+    f_nb = t.forces(T.TILD_PART_NONBONDED)
+    f_b = t.forces(T.TILD_PART_BOND)
+    f = t.forces(T.TILD_PART_TOTAL)
+    e = t.energy()
+    t.close()
+    ev = R.evaluate(x, m.types, m.bonds, oracle_params(m, transform=transform))
+    errs = dict(nb=rel_rms(f_nb, ev["F_nb"]), bond=rel_rms(f_b, ev["F_bond"]), total=rel_rms(f, ev["F"]))
+    say("   rel-RMS", errs)
+    for k, v in errs.items():
+        assert v <= tol, (k, v)
+    for k in ("E_bond", "E_chi", "E_kappa", "E"):
+        assert abs(e[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e[k], ev[k])
+    np.testing.assert_allclose(e["W"], ev["W"], rtol=tol, atol=tol * np.abs(ev["W"]).max())
+    return errs
+
+
+SMALL = [
+    # (n_chains, nA, nB, box, grid, P, chi, kappa)
+    (30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0),
+    (25, 5, 5, (5.0, 6.0, 7.5), (10, 12, 18), 3, 0.8, 3.0),
+    (40, 4, 4, (7.0, 7.0, 7.0), (20, 24, 30), 5, 0.3, 8.0),
+    (20, 3, 3, (4.0, 3.0, 5.0), (8, 6, 10), 2, 1.0, 2.0),
+    (20, 4, 4, (6.0, 6.0, 6.0), (16, 16, 16), 1, 0.5, 5.0),
+    (20, 5, 5, (6.0, 6.0, 6.0), (32, 32, 32), 7, 0.5, 5.0),
+    (30, 5, 5, (8.0, 8.0, 8.0), (15, 25, 9), 6, 0.5, 5.0),  # odd sizes: no Nyquist plane
+    (15, 8, 0, (6.0, 6.0, 6.0), (48, 40, 36), 4, 0.7, 4.0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_small_systems_fp64(case):
+    nc, na, nb, box, grid, P, chi, kap = SMALL[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=100 + case)
+    compare_forces(m, T.TILD_FP64, TOL64)
+
+
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_small_systems_fp32(case):
+    nc, na, nb, box, grid, P, chi, kap = SMALL[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=100 + case)
+    compare_forces(m, T.TILD_FP32, TOL32)
+
+
+def test_workload0_forces_fp32_and_fp64():
+    m = make_melt(0)
+    compare_forces(m, T.TILD_FP32, TOL32)
+    compare_forces(m, T.TILD_FP64, TOL64)
+
+
+def test_workload0_nonbonded_momentum():
+    m = make_melt(0)
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(snap_to_lattice(m.x, m.box))
+    f = t.forces(T.TILD_PART_NONBONDED)
+    t.close()
+    assert np.all(np.abs(f.sum(axis=0)) < 1e-4 * np.abs(f).sum(axis=0))
+
+
+def test_noise_matches_oracle_philox():
+    """Free beads (no field, no bonds, no centre-of-mass correction): one
+    step moves each bead by sqrt(2 kT dt/gamma) xi, xi the Philox noise."""
+    n = 5000
+    m = make_custom(n, 1, 0, (9.0, 9.0, 9.0), (8, 8, 8), 2, 0.0, 0.0, seed_init=3, noise_seed=0x123456789AB)
+    say("[noise] free beads", n)
+    t = gpu_ctx(m, T.TILD_FP32, com=False)
+    x0 = snap_to_lattice(m.x, m.box)
+    t.set_positions(x0)
+    t.step_count = 77
+    t.step(1)
+    x1 = t.get_positions()
+    t.close()
+    amp = np.sqrt(2 * m.kT * m.dt / m.gamma)
+    xi_gpu = R.min_image(x1 - x0, m.box) / amp
+    xi_ref = gaussian_noise(np.arange(n), 77, m.seed)
+    assert np.max(np.abs(xi_gpu - xi_ref)) < 1e-5
+
+
+def test_workload0_trajectory_100_steps():
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    p = oracle_params(m)
+    say("[trajectory] workload 0, 100 steps, fp32")
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(x0)
+    t.step(100)
+    assert t.step_count == 100
+    xg = t.get_positions()
+    fg = t.forces(T.TILD_PART_TOTAL)
+    fng = t.forces(T.TILD_PART_NONBONDED)
+    eg = t.energy()
+    t.close()
+    xr = R.trajectory(x0, m.types, m.bonds, p, 100)
+    ev = R.evaluate(xr, m.types, m.bonds, p)
+    disp_ref = R.min_image(xr - x0, m.box)
+    disp_gpu = R.min_image(xg - x0, m.box)
+    err_x = rel_rms(disp_gpu, disp_ref)
+    err_f = rel_rms(fg, ev["F"])
+    err_fn = rel_rms(fng, ev["F_nb"])
+    say("   displacement rel-RMS", err_x, "force", err_f, "nb force", err_fn)
+    assert err_x <= TOL32
+    assert err_f <= TOL32 and err_fn <= TOL32
+    for k in ("E_bond", "E_chi", "E_kappa"):
+        assert abs(eg[k] - ev[k]) <= TOL32 * abs(ev[k]), k
+
+
+def test_workload1_full_size_forces():
+    m = make_melt(1)
+    compare_forces(m, T.TILD_FP32, TOL32, transform="numpy")
+
+
+def test_resume_and_run_to_run_spread():
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    a = gpu_ctx(m, T.TILD_FP32)
+    a.set_positions(x0)
+    a.step(20)
+    xa = a.get_positions()
+    b = gpu_ctx(m, T.TILD_FP32)
+    b.set_positions(x0)
+    b.step(10)
+    mid = b.get_positions()
+    step = b.step_count
+    b.close()
+    c = gpu_ctx(m, T.TILD_FP32)
+    c.set_positions(mid)
+    c.step_count = step
+    c.step(10)
+    xc = c.get_positions()
+    c.close()
+    a.close()
+    d = R.min_image(xc - xa, m.box)
+    assert np.max(np.abs(d)) < 1e-5
+
+
+def test_device_io_and_dtypes():
+    import torch
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(torch.tensor(x0, device="cuda"))
+    out = torch.empty((m.n, 3), dtype=torch.float32, device="cuda")
+    t.forces(T.TILD_PART_TOTAL, out=out)
+    torch.cuda.synchronize()
+    host = t.forces(T.TILD_PART_TOTAL, dtype=np.float64)
+    assert rel_rms(out.cpu().numpy().astype(np.float64), host) < 1e-6
+    pos = torch.empty((m.n, 3), dtype=torch.float64, device="cuda")
+    t.get_positions(out=pos)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(R.min_image(pos.cpu().numpy() - x0, m.box))) < 1e-12
+    t.close()
+
+
+def test_nonfinite_input_is_reported():
+    import torch
+    m = make_melt(0)
+    t = gpu_ctx(m, T.TILD_FP32)
+    x = torch.tensor(snap_to_lattice(m.x, m.box), device="cuda")
+    x[5, 1] = float("nan")
+    t.set_positions(x)
+    with pytest.raises(T.TildError) as e:
+        t.synchronize()
+    assert e.value.code == T.TILD_ENONFINITE
+    t.synchronize()  # latch cleared
+    with pytest.raises(T.TildError) as e:
+        t.set_positions(np.full((m.n, 3), np.inf))
+    assert e.value.code == T.TILD_EINVAL
+    t.close()
+
+
+def test_huge_step_sets_nonfinite_flag():
+    m = make_custom(10, 5, 5, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0, dt=1e30)
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(snap_to_lattice(m.x, m.box))
+    t.step(1)
+    with pytest.raises(T.TildError) as e:
+        t.synchronize()
+    assert e.value.code == T.TILD_ENONFINITE
+    t.close()
+
+
+def test_state_errors():
+    m = make_melt(0)
+    t = gpu_ctx(m, T.TILD_FP32)
+    with pytest.raises(T.TildError) as e:
+        t.step(1)
+    assert e.value.code == T.TILD_ESTATE
+    with pytest.raises(T.TildError) as e:
+        t.energy()
+    assert e.value.code == T.TILD_ESTATE
+    t.close()
+
+
+def test_empty_system():
+    p = T.make_params((5, 5, 5), (16, 16, 16), 4, 0.5, 0.5, 5.0)
+    t = T.Tild(p, np.zeros(0, np.int32))
+    t.set_positions(np.zeros((0, 3)))
+    t.step(2)
+    e = t.energy()
+    assert e["E"] == 0.0
+    assert t.forces().shape == (0, 3)
+    t.close()
