@@ -32,21 +32,23 @@ HBM_PEAK_GBPS = 8000.0
 
 
 def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
-    """Bytes each kernel must move at minimum (per launch): see the design doc, 'Byte model'."""
+    """Bytes each kernel must move at minimum per launch ('Byte model')."""
     mx, my, mz = (int(v) for v in melt.grid)
     m = mx * my * mz
     hs = (mx // 2 + 1) * my * mz  # complex elements of one half spectrum
     r, c = precision_bytes, 2 * precision_bytes
     n = melt.n
-    nb = int(melt.bonds.shape[0])
-    bead = 16  # uint4 {qx, qy, qz, species}
+    deg = int(np.bincount(melt.bonds.ravel(), minlength=n).max()) if melt.bonds.size else 0
+    nbins = 2 * mz * my
+    bead = 16  # uint4 {qx, qy, qz, id << 1 | species}
     return {
-        "fill_mean": 2 * m * r,
-        "spread": n * bead + 2 * m * r,
-        "fft_xy_r2c": 2 * m * r + 2 * hs * c,
+        "spread_fft_xy": n * bead + 2 * hs * c,
         "fft_z_kmul": 2 * hs * c + 4 * hs * c,
         "fft_xy_c2r": 4 * hs * c + 6 * m * r,
-        "gather_bond_em": 2 * n * bead + 6 * m * r + 4 * (n + 1) + 8 * nb,
+        "gather_bond_em": n * (bead + 4 * deg) + 6 * m * r + n * bead,
+        "bin_keys": n * bead + n * 8,
+        "bin_scan": 4 * nbins * 3 + 4,
+        "bin_scatter": n * (bead + 8 + 4 * deg) + n * (bead + 4 * deg),
     }
 
 

@@ -2,13 +2,14 @@
 // step orchestration, I/O conversions and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "../../include/tild.h"
+#include "tild.h"
 #include "tild_kernels.h"
 
 #define TILD_API extern "C" __attribute__((visibility("default")))
@@ -19,10 +20,17 @@ namespace {
 
 thread_local std::string g_create_error;
 
-enum Slot { kFill = 0, kSpread, kXyR2c, kZKmul, kXyC2r, kGather, kNumSlots };
+enum Slot { kSpreadXy = 0, kZKmul, kXyC2r, kGather, kKeys, kBinScan, kScatter, kNumSlots };
 static_assert(kNumSlots == TILD_NUM_KERNELS, "slot table");
-const char* kSlotNames[kNumSlots] = {"fill_mean", "spread", "fft_xy_r2c", "fft_z_kmul", "fft_xy_c2r",
-                                     "gather_bond_em"};
+const char* kSlotNames[kNumSlots] = {"spread_fft_xy", "fft_z_kmul", "fft_xy_c2r", "gather_bond_em",
+                                     "bin_keys",      "bin_scan",   "bin_scatter"};
+
+// Uncentred cardinal B-spline M_k(s) (support [0, k)), by its recursion.
+double uncentred_bspline(int k, double s) {
+    if (k == 1) return (s >= 0.0 && s < 1.0) ? 1.0 : 0.0;
+    return (s * uncentred_bspline(k - 1, s) + (k - s) * uncentred_bspline(k - 1, s - 1.0)) / (k - 1);
+}
+constexpr int kMaxDegree = 64;
 
 struct DeviceGuard {
     int prev = -1;
@@ -122,43 +130,57 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
     return TILD_OK;
 }
 
+// Smallest power-of-two lane group (<= 64, >= min_g) for which every radix
+// pass of `pl` fits the per-lane register budget of the line transform.
+int choose_group(const FftPlan& pl, int min_g) {
+    for (int G = 1; G <= 64; G <<= 1) {
+        if (G < min_g) continue;
+        bool ok = true;
+        for (int st = 0; st < pl.nst; ++st) {
+            const int R = pl.radix[st], bpl = pl.n / R;
+            if ((bpl + G - 1) / G > kFftRegElems / R) ok = false;
+        }
+        if (ok) return G;
+    }
+    return 0;
+}
+
 // Choose workgroup shapes; false if the grid does not fit the kernels' limits.
 bool choose_shapes(Launch& L, std::string& why) {
     const Dims& d = L.d;
     const size_t lds_max = 160 * 1024;
-    const int cands_f[3] = {256, 512, 1024}, cands_d[2] = {256, 512};
-    const int* cands = L.precision == 0 ? cands_f : cands_d;
-    const int nc = L.precision == 0 ? 3 : 2;
-    L.plane_block = 0;
-    for (int i = 0; i < nc; ++i) {
-        const long long B = cands[i];
-        const long long xl = (long long)d.npair * d.mx, yl = (long long)d.hx * d.my;
-        if (xl <= 30 * B && yl <= 30 * B && (long long)d.npair * d.hx <= 20 * B && xl <= 20 * B) {
-            L.plane_block = (int)B;
-            break;
-        }
-    }
-    if (L.plane_block == 0) {
-        why = "grid plane too large for the in-LDS plane transform";
+    const int pair_items = 8;  // row-pair (un)packing items per lane in the plane kernels
+    L.px.group = choose_group(L.px, (d.mx + pair_items - 1) / pair_items);
+    L.py.group = choose_group(L.py, 1);
+    L.pz.group = choose_group(L.pz, 1);
+    if (!L.px.group || !L.py.group || !L.pz.group) {
+        why = "internal: no lane group fits a transform length";
         return false;
     }
+    const long long need = std::max((long long)d.npair * L.px.group, (long long)d.hx * L.py.group);
+    L.plane_block = need <= 256 ? 256 : 512;
     if (plane_lds_bytes(L) > lds_max) {
         why = "grid plane does not fit one workgroup's LDS in this precision";
         return false;
     }
-    int cb = 7680 / (4 * d.mz);
-    if (cb > 16) cb = 16;
-    if (cb < 1) {
-        why = "grid too long along z";
-        return false;
-    }
-    L.z_cols = cb;
     L.z_block = 256;
+    const size_t zbudget = L.precision == 0 ? 80 * 1024 : 160 * 1024;
+    for (L.z_cols = 16; L.z_cols > 1 && z_lds_bytes(L) > zbudget; L.z_cols /= 2) {
+    }
     if (z_lds_bytes(L) > lds_max) {
         why = "z columns do not fit LDS";
         return false;
     }
-    L.n_zblocks = (int)((d.hplane + cb - 1) / cb);
+    L.n_zblocks = (int)((d.hplane + L.z_cols - 1) / L.z_cols);
+    // gather tiles: rows of stencil starts (all x) x slabs, the P staged planes within budget
+    const size_t gbudget = L.precision == 0 ? 80 * 1024 : 160 * 1024;
+    L.gather_zc = 8;
+    for (L.gather_ty = 8; L.gather_ty > 1 && gather_lds_bytes(L, L.gather_ty) > gbudget; L.gather_ty /= 2) {
+    }
+    if (gather_lds_bytes(L, L.gather_ty) > lds_max) {
+        why = "gather tile does not fit LDS (grid too wide along x for this order and precision)";
+        return false;
+    }
     return true;
 }
 
@@ -171,24 +193,30 @@ int check_flag(tild_ctx* c) {
         e = hipMemsetAsync(c->S.flag, 0, sizeof(uint32_t), c->L.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->L.stream);
         if (e != hipSuccess) return c->hip_fail(e, "clear flag");
-        return c->fail(TILD_ENONFINITE, "non-finite force, displacement or position detected");
+        std::string why;
+        if (f & 1u) why += "non-finite force, displacement or position detected; ";
+        if (f & 4u) why += "a grid plane is too dense for the fixed-point spread; ";
+        if (f & 8u) why += "internal: a bead was found outside its bin; ";
+        return c->fail(TILD_ENONFINITE, why);
     }
     return TILD_OK;
 }
 
 // Forces on the mesh up to the gradient fields (no bead update).
 hipError_t mesh_forward(tild_ctx* c, bool energy_only) {
-    hipError_t e = launch_fill_mean(c->L, c->S);
-    if (e == hipSuccess) e = launch_spread(c->L, c->S);
-    if (e == hipSuccess) e = launch_xy_r2c(c->L, c->S);
+    hipError_t e = launch_spread_xy(c->L, c->S);
     if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, energy_only);
     if (e == hipSuccess && !energy_only) e = launch_xy_c2r(c->L, c->S);
     return e;
 }
 
-void swap_state(tild_ctx* c) {
-    std::swap(c->S.pos, c->S.pos_next);
-    std::swap(c->S.qshift, c->S.qshift_next);
+// Sort the beads held in pos_tmp (keys and ranks already counted) into pos,
+// translating bond partners given as slots of pos_tmp's order.
+hipError_t sort_beads(tild_ctx* c, const int32_t* nbr_src) {
+    hipError_t e = launch_bin_scan(c->L, c->S);
+    if (e == hipSuccess) e = launch_scatter(c->L, c->S, nbr_src);
+    if (e == hipSuccess) std::swap(c->S.nbr, c->S.nbr_old);
+    return e;
 }
 
 int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
@@ -197,15 +225,9 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         auto mark = [&](int slot, int which) {
             if (ev && e == hipSuccess) e = hipEventRecord((*ev)[(size_t)(s * kNumSlots + slot) * 2 + which], c->L.stream);
         };
-        mark(kFill, 0);
-        if (e == hipSuccess) e = launch_fill_mean(c->L, c->S);
-        mark(kFill, 1);
-        mark(kSpread, 0);
-        if (e == hipSuccess) e = launch_spread(c->L, c->S);
-        mark(kSpread, 1);
-        mark(kXyR2c, 0);
-        if (e == hipSuccess) e = launch_xy_r2c(c->L, c->S);
-        mark(kXyR2c, 1);
+        mark(kSpreadXy, 0);
+        if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);
+        mark(kSpreadXy, 1);
         mark(kZKmul, 0);
         if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);
         mark(kZKmul, 1);
@@ -215,8 +237,18 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         mark(kGather, 0);
         if (e == hipSuccess) e = launch_gather(c->L, c->S, 0, (uint64_t)c->step, nullptr, 0, 0);
         mark(kGather, 1);
+        if (e == hipSuccess) std::swap(c->S.qshift, c->S.qshift_next);  // keys use the new shift
+        mark(kKeys, 0);
+        if (e == hipSuccess) e = launch_keys(c->L, c->S);
+        mark(kKeys, 1);
+        mark(kBinScan, 0);
+        if (e == hipSuccess) e = launch_bin_scan(c->L, c->S);
+        mark(kBinScan, 1);
+        mark(kScatter, 0);
+        if (e == hipSuccess) e = launch_scatter(c->L, c->S, c->S.nbr);
+        mark(kScatter, 1);
+        if (e == hipSuccess) std::swap(c->S.nbr, c->S.nbr_old);
         if (e != hipSuccess) return c->hip_fail(e, "step launch");
-        swap_state(c);
         ++c->step;
     }
     return TILD_OK;
@@ -275,6 +307,18 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
         }
     }
 
+    int deg = 0;
+    for (int64_t i = 0; i < n_beads; ++i) deg = std::max(deg, off[(size_t)i + 1] - off[(size_t)i]);
+    if (deg > kMaxDegree) {
+        g_create_error = "a bead has more than 64 bonds";
+        return TILD_EINVAL;
+    }
+    // Partners of every bead at fixed width `deg`, -1 padded (ABI order).
+    std::vector<int32_t> nbr_tab((size_t)n_beads * (size_t)deg, -1);
+    for (int64_t i = 0; i < n_beads; ++i)
+        for (int32_t k = off[(size_t)i]; k < off[(size_t)i + 1]; ++k)
+            nbr_tab[(size_t)i * deg + (size_t)(k - off[(size_t)i])] = nbr[(size_t)k];
+
     tild_ctx* c = new (std::nothrow) tild_ctx();
     if (!c) {
         g_create_error = "out of host memory";
@@ -332,6 +376,14 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     S.n = n_beads;
     S.n_a = n_a;
     S.n_b = n_b;
+    S.deg = deg;
+    S.nbins = 2 * d.mz * d.my;
+    ph.mean_a = (double)n_a / (double)d.m;
+    ph.mean_b = (double)n_b / (double)d.m;
+    {
+        const double peak = uncentred_bspline(params->order, 0.5 * params->order);
+        ph.wmax = peak * peak * peak;
+    }
     const size_t real_sz = L.precision == 0 ? 4 : 8;
     const size_t cplx_sz = 2 * real_sz;
     const size_t npos = (size_t)(n_beads > 0 ? n_beads : 1);
@@ -339,13 +391,19 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     auto A = [&](void** ptr, size_t bytes) {
         if (e == hipSuccess) e = c->alloc(ptr, bytes);
     };
+    const size_t ntab = nbr_tab.size() > 0 ? nbr_tab.size() : 1;
     A((void**)&S.pos, npos * sizeof(uint4));
-    A((void**)&S.pos_next, npos * sizeof(uint4));
+    A((void**)&S.pos_tmp, npos * sizeof(uint4));
+    A((void**)&S.key, npos * sizeof(uint32_t));
+    A((void**)&S.rank, npos * sizeof(uint32_t));
+    A((void**)&S.counts, (size_t)S.nbins * sizeof(uint32_t));
+    A((void**)&S.bin_start, ((size_t)S.nbins + 1) * sizeof(uint32_t));
+    A((void**)&S.nbr, ntab * sizeof(int32_t));
+    A((void**)&S.nbr_old, ntab * sizeof(int32_t));
+    A((void**)&S.nbr_abi, ntab * sizeof(int32_t));
+    A((void**)&S.types_abi, npos * sizeof(uint32_t));
     A((void**)&S.qshift, 4 * sizeof(uint32_t));
     A((void**)&S.qshift_next, 4 * sizeof(uint32_t));
-    A((void**)&S.bond_off, off.size() * sizeof(int32_t));
-    A((void**)&S.bond_nbr, (nbr.size() > 0 ? nbr.size() : 1) * sizeof(int32_t));
-    A(&S.dens, 2 * (size_t)d.m * real_sz);
     A(&S.spec, 2 * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.zout, 4 * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.grad, 6 * (size_t)d.m * real_sz);
@@ -372,19 +430,20 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
         }
     }
     std::vector<float> twf(tw.begin(), tw.end());
-    std::vector<uint4> pos0((size_t)npos, uint4{0, 0, 0, 0});
-    for (int64_t i = 0; i < n_beads; ++i) pos0[(size_t)i].w = (uint32_t)types[i];
+    std::vector<uint32_t> types_u((size_t)npos, 0u);
+    for (int64_t i = 0; i < n_beads; ++i) types_u[(size_t)i] = (uint32_t)types[i];
+    std::vector<uint32_t> zero_bins((size_t)S.nbins + 1, 0u);
     const uint32_t zeros4[4] = {0, 0, 0, 0};
     const unsigned long long zacc[4] = {0, 0, 0, 0};
     auto H2D = [&](void* dst, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
     };
-    H2D(S.pos, pos0.data(), npos * sizeof(uint4));
-    H2D(S.pos_next, pos0.data(), npos * sizeof(uint4));
+    H2D(S.types_abi, types_u.data(), npos * sizeof(uint32_t));
+    H2D(S.nbr_abi, nbr_tab.data(), nbr_tab.size() * sizeof(int32_t));
+    H2D(S.counts, zero_bins.data(), (size_t)S.nbins * sizeof(uint32_t));
+    H2D(S.bin_start, zero_bins.data(), ((size_t)S.nbins + 1) * sizeof(uint32_t));
     H2D(S.qshift, zeros4, sizeof(zeros4));
     H2D(S.qshift_next, zeros4, sizeof(zeros4));
-    H2D(S.bond_off, off.data(), off.size() * sizeof(int32_t));
-    H2D(S.bond_nbr, nbr.data(), nbr.size() * sizeof(int32_t));
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
     else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
     H2D(S.com_acc, zacc, sizeof(zacc));
@@ -430,7 +489,8 @@ TILD_API int tild_set_positions(tild_ctx* c, const void* xyz, int32_t dtype, int
         e = hipMemcpyAsync(c->staging, xyz, bytes, hipMemcpyHostToDevice, c->L.stream);
         src = c->staging;
     }
-    if (e == hipSuccess) e = launch_set_positions(c->L, c->S, src, dtype);
+    if (e == hipSuccess) e = launch_place(c->L, c->S, src, dtype);
+    if (e == hipSuccess) e = sort_beads(c, c->S.nbr_abi);
     if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->L.stream);
     if (e != hipSuccess) return c->hip_fail(e, "set_positions");
     c->have_pos = true;

@@ -48,16 +48,24 @@ struct Dims {
 // weight is the uncentred spline M_P(f + P-1-j), which the recursion below
 // evaluates for all j at once:
 //   M_1 = 1 on [0,1);  M_k(s) = [s M_{k-1}(s) + (k-s) M_{k-1}(s-1)] / (k-1).
+__device__ __forceinline__ int wrap_index(int g, int m) {
+    g %= m;
+    return g < 0 ? g + m : g;
+}
+
+// First stencil node g0 = floor(u - P/2) + 1 (mod m) of coordinate q.
+__device__ __forceinline__ int stencil_start(uint32_t q, int m, int P) {
+    const int64_t s = (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m) - ((int64_t)P << 31);
+    return wrap_index((int)(s >> 32) + 1, m);
+}
+
 template <typename T, int P>
 __device__ __forceinline__ void assignment_weights(uint32_t q, int m, int& g0, T w[P]) {
     const int64_t v = (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m);  // < 2^40
     const int64_t s = v - ((int64_t)P << 31);                         // (u - P/2) * 2^32
     const int64_t fl = s >> 32;                                          // floor (arithmetic shift)
     const uint32_t fr = (uint32_t)(s & 0xffffffffLL);
-    int g = (int)fl + 1;
-    g %= m;
-    if (g < 0) g += m;
-    g0 = g;
+    g0 = wrap_index((int)fl + 1, m);
     const T f = (T)fr * (T)2.3283064365386963e-10;  // 2^-32
     // mk[j] holds M_k(f + j), j = 0 .. k-1
     T mk[P];

@@ -1,11 +1,14 @@
-// Batched complex FFTs of lines held in LDS, for lengths that are products of
-// 2, 3 and 5 (radix 8, 4, 2, 3, 5 passes).  Each pass is a Stockham
-// autosort pass: butterfly j of a line reads elements j + r*n/R, multiplies by
-// the twiddles w^(r*(j mod s)) with w = exp(-+2 pi i/(s R)), applies a
-// radix-R DFT and writes elements (j - j mod s)*R + j mod s + r*s, where s is
-// the product of the radices already applied.  After the last pass the line
-// is in natural order.  Every pass reads all of its inputs into registers
-// before a barrier and writes after it, so passes run in place.
+// Complex FFTs of lines held in LDS, for lengths that are products of 2, 3
+// and 5 (radix 8, 4, 2, 3 and 5 passes).
+//
+// Each line is owned by a group of G lanes of one wavefront (G divides 64),
+// so the passes of a line synchronise at wavefront scope only.  A pass is a
+// Stockham autosort pass: butterfly j reads elements j + r*n/R, multiplies
+// them by w^(r*(j mod s)) with w = exp(-+2 pi i/(s R)), applies a radix-R DFT
+// and writes elements (j - j mod s)*R + j mod s + r*s, s being the product of
+// the radices already applied; after the last pass the line is in natural
+// order.  A lane holds at most kFftRegElems elements of a pass in registers,
+// all loads of a pass precede its stores, so passes run in place.
 #pragma once
 
 #include "tild_common.h"
@@ -13,13 +16,16 @@
 namespace tild {
 
 constexpr int kMaxRadixStages = 16;
+constexpr int kFftRegElems = 8;
 
-// Factorisation of one transform length and the offset of its twiddle table
-// (exp(-2 pi i m/n), m = 0..n-1) inside the context's twiddle array.
+// Factorisation of one transform length, the offset of its twiddle table
+// (exp(-2 pi i m/n), m = 0..n-1) inside the context's twiddle array, and the
+// lanes per line.
 struct FftPlan {
     int n;
     int nst;
     int tw;
+    int group;  // lanes per line: a power of two <= 64
     int radix[kMaxRadixStages];
 };
 
@@ -27,10 +33,15 @@ struct FftPlan {
 // (l % l1) * s1 + (l / l1) * s2 and its elements are `es` apart.
 struct LineMap {
     int lines, l1, s1, s2, es;
+    __device__ __forceinline__ int base(int l) const { return (l % l1) * s1 + (l / l1) * s2; }
 };
 
-// Elements each thread may hold in registers during one pass.
-constexpr int kFftRegElems = 32;
+// Order LDS traffic of the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Radix kernels.  INV = 0: exp(-2 pi i jk/R); INV = 1: exp(+2 pi i jk/R).
 template <int INV, typename C> __device__ __forceinline__ void dft2(C* a) {
@@ -114,26 +125,23 @@ template <int R, int INV, typename C> __device__ __forceinline__ void dft_r(C* a
     else dft8<INV>(a);
 }
 
+// One radix-R pass of the line at `base` by lane `lane` of its group of G.
 template <typename C, int R, int INV>
-__device__ void fft_pass(C* buf, const LineMap lm, const int n, const int s, const C* __restrict__ tw, const int tid,
-                         const int nthr) {
+__device__ __forceinline__ void line_pass(C* buf, const int base, const int es, const int n, const int s,
+                                          const C* __restrict__ tw, const int lane, const int G) {
     constexpr int MAXB = kFftRegElems / R;
     const int bpl = n / R;
-    const int total = lm.lines * bpl;
     const int tstride = n / (s * R);
     C v[MAXB][R];
-    int obase[MAXB];
+    int ob[MAXB];
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-        const int id = tid + b * nthr;
-        obase[b] = -1;
-        if (id < total) {
-            const int line = id / bpl;
-            const int j = id - line * bpl;
-            const int base = (line % lm.l1) * lm.s1 + (line / lm.l1) * lm.s2;
+        const int j = lane + b * G;
+        ob[b] = -1;
+        if (j < bpl) {
             const int k = j % s;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * bpl) * lm.es];
+            for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * bpl) * es];
             if (s > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -142,39 +150,51 @@ __device__ void fft_pass(C* buf, const LineMap lm, const int n, const int s, con
                     v[b][r] = cmul(v[b][r], w);
                 }
             }
-            obase[b] = base + ((j - k) * R + k) * lm.es;
+            ob[b] = base + ((j - k) * R + k) * es;
         }
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-        if (obase[b] >= 0) {
+        if (ob[b] >= 0) {
             dft_r<R, INV>(v[b]);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[obase[b] + r * s * lm.es] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[ob[b] + r * s * es] = v[b][r];
         }
     }
-    __syncthreads();
+    wave_sync();
 }
 
-// Transform every line described by `lm` in place.  Requires
-// lm.lines * plan.n <= 30 * nthr (checked on the host) and a preceding barrier.
+// Transform the line at `base` (elements `es` apart) in place; called by all
+// G lanes of the owning group.
 template <typename C, int INV>
-__device__ void fft_lines(C* buf, const LineMap lm, const FftPlan& plan, const C* __restrict__ twiddles, int tid,
-                          int nthr) {
+__device__ void fft_line(C* buf, const int base, const int es, const FftPlan& plan, const C* __restrict__ twiddles,
+                         const int lane) {
     const C* tw = twiddles + plan.tw;
+    const int G = plan.group;
     int s = 1;
     for (int st = 0; st < plan.nst; ++st) {
         const int R = plan.radix[st];
         switch (R) {
-            case 8: fft_pass<C, 8, INV>(buf, lm, plan.n, s, tw, tid, nthr); break;
-            case 4: fft_pass<C, 4, INV>(buf, lm, plan.n, s, tw, tid, nthr); break;
-            case 2: fft_pass<C, 2, INV>(buf, lm, plan.n, s, tw, tid, nthr); break;
-            case 3: fft_pass<C, 3, INV>(buf, lm, plan.n, s, tw, tid, nthr); break;
-            default: fft_pass<C, 5, INV>(buf, lm, plan.n, s, tw, tid, nthr); break;
+            case 8: line_pass<C, 8, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
+            case 4: line_pass<C, 4, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
+            case 2: line_pass<C, 2, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
+            case 3: line_pass<C, 3, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
+            default: line_pass<C, 5, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
         }
         s *= R;
     }
+}
+
+// Transform every line of `lm` with the block's threads split into groups of
+// plan.group lanes.  Needs a block barrier before (inputs written by other
+// waves) and, if other waves read the result, after.
+template <typename C, int INV>
+__device__ void fft_lines(C* buf, const LineMap lm, const FftPlan& plan, const C* __restrict__ twiddles, int tid,
+                          int nthr) {
+    const int G = plan.group;
+    const int lane = tid % G, grp = tid / G, ngrp = nthr / G;
+    for (int l = grp; l < lm.lines; l += ngrp) fft_line<C, INV>(buf, lm.base(l), lm.es, plan, twiddles, lane);
 }
 
 }  // namespace tild

@@ -19,30 +19,50 @@ struct Phys {
     double bond_k;
     double mob_dt;      // dt / gamma
     double noise_amp;   // sqrt(2 kT dt / gamma)
+    double mean_a, mean_b;  // N_A / M, N_B / M: subtracted from the counts
+    double wmax;            // largest single-bead weight of one grid point, (max B_P)^3
     uint64_t seed;
     int com_correct;
 };
 
-// Everything a step needs on the device.
+// Device memory of one context.
+//
+// Beads live in "sorted order": grouped by bin key
+//   key = (species * mz + g0z) * my + g0y,
+// g0 the first grid index of the bead's assignment stencil, so that the
+// beads touching one z-plane of one species occupy a few contiguous slot
+// ranges.  A bead is a uint4 {qx, qy, qz, (abi_id << 1) | species}; qx.. are
+// 32-bit fixed-point box fractions; the true coordinate is
+// (q - qshift) * L / 2^32.  Every step the update kernel writes the new
+// positions in the old order, a key pass forms each bead's new key and its
+// rank within the key's bin, a scan turns bin counts into bin starts, and a
+// scatter moves beads (and re-maps bond partner slots) into the new order.
 struct DeviceState {
-    uint4* pos;            // [n] {qx, qy, qz, species}: current positions
-    uint4* pos_next;       // [n] positions after the step being computed (swapped with pos by the host)
-    uint32_t* qshift;      // [4] global fixed-point shift (centre-of-mass correction); x = (q - qshift) L / 2^32
-    uint32_t* qshift_next; // [4] shift after the step being computed
-    int32_t* bond_off;     // [n + 1]
-    int32_t* bond_nbr;     // [2 n_bonds]
-    void* dens;            // real [2][mz][my][mx]
-    void* spec;            // complex [2][mz][my][hx]
-    void* zout;            // complex [4][mz][my][hx]: z-inverted phi_A, phi_B, then ik_z phi_A, ik_z phi_B
-    void* grad;            // real [2][3][mz][my][mx]
-    void* tw;              // complex twiddle tables
-    double* epart;         // [n_zblocks][5] energy partials of the k-space pass
-    double* bpart;         // [n_bblocks][4] bond energy / virial partials
+    uint4* pos;           // [n] sorted beads
+    uint4* pos_tmp;       // [n] beads in the previous order (new positions or ABI input)
+    uint32_t* key;        // [n] bin key of pos_tmp[j]
+    uint32_t* rank;       // [n] rank of pos_tmp[j] within its bin
+    uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
+    uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
+    int32_t* nbr;         // [n][deg] bond partners of sorted slot j as sorted slots, -1 padded
+    int32_t* nbr_old;     // [n][deg] partners in the previous order
+    int32_t* nbr_abi;     // [n][deg] partners in ABI order (static)
+    uint32_t* types_abi;  // [n] species in ABI order (static)
+    uint32_t* qshift;       // [4] fixed-point centre-of-mass shift
+    uint32_t* qshift_next;  // [4] shift after the step being computed
+    void* spec;           // complex [2][mz][my][hx] half spectra of the counts
+    void* zout;           // complex [4][mz][my][hx]: z-inverted Phi_A, Phi_B, then ik_z Phi_A, ik_z Phi_B
+    void* grad;           // real [2][3][mz][my][mx] gradient fields
+    void* tw;             // complex twiddle tables
+    double* epart;        // [n_zblocks][5] energy partials of the k-space pass
+    double* bpart;        // [n_bblocks][4] bond energy / virial partials
     unsigned long long* com_acc;  // [4]: int64 displacement sums (x, y, z) and a block counter
-    uint32_t* flag;        // [1] non-finite latch
-    double* eout;          // [8] reduced energies
+    uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
+    double* eout;         // [8] reduced energies
     long long n;
     long long n_a, n_b;
+    int deg;              // bond slots per bead (maximum degree)
+    int nbins;            // 2 * mz * my
 };
 
 struct Launch {
@@ -56,27 +76,34 @@ struct Launch {
     int z_block;
     int n_zblocks;
     int n_bblocks;
+    int gather_ty;    // rows of stencil starts per gather tile
+    int gather_zc;    // slabs per gather tile
     Phys ph;
 };
 
 // Launch helpers; each returns the hipError_t of the launch.
-hipError_t launch_fill_mean(const Launch& L, DeviceState& S);
-hipError_t launch_spread(const Launch& L, DeviceState& S);
-hipError_t launch_xy_r2c(const Launch& L, DeviceState& S);
+hipError_t launch_spread_xy(const Launch& L, DeviceState& S);
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only);
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S);
-// mode 0: Euler-Maruyama step; mode 1: write forces (parts) to out (out_dtype 0 float / 1 double)
+// mode 0: Euler-Maruyama step (writes pos_tmp and qshift_next);
+// mode 1: write forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
 hipError_t launch_gather(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts);
+// key and rank of every bead of pos_tmp (counts incremented)
+hipError_t launch_keys(const Launch& L, DeviceState& S);
+hipError_t launch_bin_scan(const Launch& L, DeviceState& S);
+hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src);
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S);
 hipError_t launch_reduce_energy(const Launch& L, DeviceState& S);
-hipError_t launch_set_positions(const Launch& L, DeviceState& S, const void* xyz, int dtype);
+// ABI-order input -> pos_tmp, key, rank (qshift reset to 0)
+hipError_t launch_place(const Launch& L, DeviceState& S, const void* xyz, int dtype);
 hipError_t launch_get_positions(const Launch& L, DeviceState& S, void* xyz, int dtype);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
-// Largest dynamic LDS a plane / z workgroup needs (bytes), used for validation.
+// Dynamic LDS a plane / z workgroup needs (bytes), used for validation.
 size_t plane_lds_bytes(const Launch& L);
 size_t z_lds_bytes(const Launch& L);
+size_t gather_lds_bytes(const Launch& L, int ty);
 hipError_t configure_kernel_attributes(const Launch& L);
 
 }  // namespace tild

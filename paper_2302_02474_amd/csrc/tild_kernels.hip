@@ -1,20 +1,23 @@
 // HIP kernels of the TILD particle-mesh step for gfx950.
 //
 // Per step (paper, Sec. "Long-range interactions", Eq. PMM and Fig. pmm):
-//   fill_mean   counts grids start at -N_K/M (the mean is carried analytically)
-//   spread      c_K(g) += W_i(g) for every bead (order-P B-spline weights)
-//   xy_r2c      per z-plane: real-to-complex FFT along x, complex FFT along y
+//   spread_xy   per (z-plane, species): the beads whose order-P B-spline
+//               stencil reaches the plane are accumulated in LDS (counts minus
+//               their mean), then real-to-complex FFT along x, FFT along y
 //   z_kmul      per column block: FFT along z, multiply by the smeared
 //               chi/kappa kernel, inverse FFT along z of Phi_K and ik_z Phi_K
-//   xy_c2r      per z-plane: ik_x, ik_y applied, inverse FFT along y and
-//               complex-to-real along x -> the three gradient fields of phi_K
-//   gather      F_i = -sum_g W_i(g) grad phi_{s_i}(g), harmonic bonds, Philox
-//               noise and the Euler-Maruyama update
+//   xy_c2r      per (z-plane, species): ik_x, ik_y applied, inverse FFT along
+//               y and complex-to-real along x -> the three gradient fields
+//   gather      F_i = -sum_g W_i(g) grad phi_{s_i}(g) with the same weights,
+//               harmonic bonds, Philox noise and the Euler-Maruyama update;
+//               emits each moved bead's bin key and rank
+//   bin_scan    bin counts -> bin starts
+//   scatter     beads and bond partners into the new sorted order
 #include "tild_kernels.h"
 
 namespace tild {
 
-constexpr int kPairItems = 20;  // row-pair (un)packing items per thread
+constexpr int kPairItems = 8;  // row-pair (un)packing items per lane
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kInvTwo32 = 2.3283064365386962890625e-10;
@@ -48,101 +51,182 @@ __device__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */, int tid, int n
     __syncthreads();
 }
 
-// ------------------------------------------------------------ fill / spread
+// ------------------------------------------------------------ bins
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_fill_mean(T* __restrict__ dens, long long m, T va, T vb) {
-    const long long stride = (long long)gridDim.x * 256;
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < 2 * m; i += stride) dens[i] = i < m ? va : vb;
+// Bin key of a bead: (species, first stencil plane in z, first stencil row in y).
+__device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t species, const Dims& d, int P) {
+    const int gy = stencil_start(qy, d.my, P), gz = stencil_start(qz, d.mz, P);
+    return (uint32_t)((species * (uint32_t)d.mz + (uint32_t)gz) * (uint32_t)d.my + (uint32_t)gy);
 }
 
+// ------------------------------------------------------------ spread + xy forward
+
+// Accumulate the counts of every species-K bead whose stencil reaches plane z
+// (the beads of the P slabs z-P+1 .. z) into the LDS plane: row y of the
+// plane lives in component y & 1 of complex row y >> 1, rows pitch 2hx
+// complex.  Single precision accumulates fixed-point integers (each
+// contribution rounded to a multiple of 1/scale): integer LDS atomics are
+// order-independent, and far faster than float ones on this hardware.
+// Double precision accumulates doubles.
 template <typename T, int P>
-__global__ void __launch_bounds__(256) k_spread_atomic(const uint4* __restrict__ pos, const uint32_t* __restrict__ qs,
-                                                       long long n, Dims d, T* __restrict__ dens) {
-    const long long i = blockIdx.x * 256LL + threadIdx.x;
-    if (i >= n) return;
-    const uint4 q = pos[i];
-    int gx, gy, gz;
-    T wx[P], wy[P], wz[P];
-    assignment_weights<T, P>(q.x - qs[0], d.mx, gx, wx);
-    assignment_weights<T, P>(q.y - qs[1], d.my, gy, wy);
-    assignment_weights<T, P>(q.z - qs[2], d.mz, gz, wz);
-    T* g = dens + (q.w ? d.m : 0);
+__device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
+                             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims& d,
+                             int z, int K, T scale, int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-        int z = gz + c;
-        if (z >= d.mz) z -= d.mz;
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const uint4 q = pos[j];
+            int gx, gy, gz;
+            T wx[P], wy[P], wz[P];
+            assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
+            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+            const T w0 = wz[c] * scale;
 #pragma unroll
-        for (int b = 0; b < P; ++b) {
-            int y = gy + b;
-            if (y >= d.my) y -= d.my;
-            T* row = g + ((long long)z * d.my + y) * d.mx;
-            const T wzy = wz[c] * wy[b];
+            for (int b = 0; b < P; ++b) {
+                int y = gy + b;
+                if (y >= d.my) y -= d.my;
+                const int row = 4 * (y >> 1) * d.hx + (y & 1);
+                const T wyz = w0 * wy[b];
 #pragma unroll
-            for (int a = 0; a < P; ++a) {
-                int x = gx + a;
-                if (x >= d.mx) x -= d.mx;
-                unsafeAtomicAdd(row + x, wzy * wx[a]);
+                for (int a = 0; a < P; ++a) {
+                    int x = gx + a;
+                    if (x >= d.mx) x -= d.mx;
+                    if constexpr (sizeof(T) == 4) {
+                        atomicAdd(reinterpret_cast<uint32_t*>(lds) + row + 2 * x, (uint32_t)__float2int_rn(wyz * wx[a]));
+                    } else {
+                        atomicAdd(reinterpret_cast<T*>(lds) + row + 2 * x, wyz * wx[a]);
+                    }
+                }
             }
         }
     }
 }
 
-// ------------------------------------------------------------ xy plane passes
+// Scale of the fixed-point spread of plane z: the largest 2^k (k <= 24) for
+// which no cell can overflow int32.  A cell of row y is reached only by beads
+// of the P slabs z-P+1 .. z and the P row bins y-P+1 .. y, each contributing at
+// most wmax, so their number times wmax bounds its count.
+__device__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims& d, int z, int K, int P, double wmax,
+                              uint32_t* __restrict__ flag, uint32_t* smax, int tid, int nthr) {
+    if (tid == 0) *smax = 0u;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (int y = tid; y < d.my; y += nthr) {
+        uint32_t sum = 0;
+        for (int c = 0; c < P; ++c) {
+            int s = z - c;
+            if (s < 0) s += d.mz;
+            for (int b = 0; b < P; ++b) {
+                int yy = y - b;
+                if (yy < 0) yy += d.my;
+                const int bin = (K * d.mz + s) * d.my + yy;
+                sum += bin_start[bin + 1] - bin_start[bin];
+            }
+        }
+        mine = mine > sum ? mine : sum;
+    }
+    atomicMax(smax, mine);
+    __syncthreads();
+    const double bound = (double)(*smax) * wmax + 1.0;
+    int k = 24;
+    while (k > 8 && bound * (double)(1 << k) >= 2147483647.0) --k;
+    if (bound * (double)(1 << k) >= 2147483647.0 && tid == 0) atomicOr(flag, 4u);
+    return (float)(1 << k);
+}
 
-// Forward: real plane c[y][x] -> half spectrum H[ky][kx], kx = 0 .. mx/2.
-// Rows 2p and 2p+1 are transformed together as one complex row
-// z = c_2p + i c_2p+1, then separated with Z(-k)* symmetry.
+// Plane z of species K: counts minus their mean N_K/M, then the forward
+// transform to the half spectrum H[ky][kx], kx = 0 .. mx/2.  Rows 2p and 2p+1
+// are transformed together as one complex row c_2p + i c_2p+1, stored at
+// complex offset p * 2hx, and separated in place, by the lanes that
+// transformed them, with the symmetry Z(-k)*: H row 2p lands at p * 2hx and
+// row 2p+1 at p * 2hx + hx, i.e. H has row pitch hx.
 template <typename T, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_xy_r2c(const T* __restrict__ dens, cplx<T>* __restrict__ spec, Dims d,
-                                                  FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw) {
+__global__ void __launch_bounds__(BLOCK)
+    k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
+                cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
+                int order, uint32_t* __restrict__ flag) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t smax;
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     const int z = blockIdx.x, K = blockIdx.y;
-    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair;
-    const T* src = dens + ((long long)K * d.mz + z) * (long long)my * mx;
-    for (int i = tid; i < np * mx; i += BLOCK) {
-        const int p = i / mx, x = i - p * mx;
-        const T re = src[(2 * p) * mx + x];
-        const T im = (2 * p + 1 < my) ? src[(2 * p + 1) * mx + x] : (T)0;
-        S[i] = C{re, im};
+    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
+    const T mean = (T)(K ? ph.mean_b : ph.mean_a);
+    constexpr bool kFixed = sizeof(T) == 4;
+    T scale = (T)1;
+    if constexpr (kFixed) scale = spread_scale(bin_start, d, z, K, order, ph.wmax, flag, &smax, tid, BLOCK);
+    for (int i = tid; i < np * zp; i += BLOCK) {
+        const int p = i / zp, x = i - p * zp;
+        if constexpr (kFixed) S[i] = C{0, 0};  // integer zero
+        else S[i] = x < mx ? C{-mean, (2 * p + 1 < my) ? -mean : (T)0} : C{0, 0};
     }
     __syncthreads();
-    fft_lines<C, 0>(S, LineMap{np, np, mx, 0, 1}, px, tw, tid, BLOCK);
-    C ra[kPairItems], rb[kPairItems];
-    const int items = np * hx;
-#pragma unroll
-    for (int u = 0; u < kPairItems; ++u) {
-        const int i = tid + u * BLOCK;
-        if (i < items) {
-            const int p = i / hx, kx = i - p * hx;
-            const C a = S[p * mx + kx];
-            const C b = S[p * mx + (kx == 0 ? 0 : mx - kx)];
-            ra[u] = C{(T)0.5 * (a.x + b.x), (T)0.5 * (a.y - b.y)};
-            rb[u] = C{(T)0.5 * (a.y + b.y), (T)0.5 * (b.x - a.x)};
+    switch (order) {
+        case 1: spread_plane<T, 1>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 2: spread_plane<T, 2>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 3: spread_plane<T, 3>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 4: spread_plane<T, 4>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 5: spread_plane<T, 5>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 6: spread_plane<T, 6>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        default: spread_plane<T, 7>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+    }
+    __syncthreads();
+    if constexpr (kFixed) {
+        const T inv = (T)1 / scale;
+        const int32_t* Si = reinterpret_cast<const int32_t*>(smem);
+        for (int i = tid; i < np * zp; i += BLOCK) {
+            const int p = i / zp, x = i - p * zp;
+            const int32_t re = Si[2 * i], im = Si[2 * i + 1];
+            S[i] = x < mx ? C{(T)re * inv - mean, (2 * p + 1 < my) ? (T)im * inv - mean : (T)0} : C{0, 0};
         }
     }
     __syncthreads();
+    {
+        const int G = px.group, lane = tid % G;
+        for (int p = tid / G; p < np; p += BLOCK / G) {
+            const int base = p * zp;
+            fft_line<C, 0>(S, base, 1, px, tw, lane);
+            C ra[kPairItems], rb[kPairItems];
 #pragma unroll
-    for (int u = 0; u < kPairItems; ++u) {
-        const int i = tid + u * BLOCK;
-        if (i < items) {
-            const int p = i / hx, kx = i - p * hx;
-            S[(2 * p) * hx + kx] = ra[u];
-            if (2 * p + 1 < my) S[(2 * p + 1) * hx + kx] = rb[u];
+            for (int u = 0; u < kPairItems; ++u) {
+                const int kx = lane + u * G;
+                if (kx < hx) {
+                    const C a = S[base + kx];
+                    const C b = S[base + (kx == 0 ? 0 : mx - kx)];
+                    ra[u] = C{(T)0.5 * (a.x + b.x), (T)0.5 * (a.y - b.y)};
+                    rb[u] = C{(T)0.5 * (a.y + b.y), (T)0.5 * (b.x - a.x)};
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < kPairItems; ++u) {
+                const int kx = lane + u * G;
+                if (kx < hx) {
+                    S[base + kx] = ra[u];
+                    if (2 * p + 1 < my) S[base + hx + kx] = rb[u];
+                }
+            }
+            wave_sync();
         }
     }
     __syncthreads();
     fft_lines<C, 0>(S, LineMap{hx, hx, 1, 0, hx}, py, tw, tid, BLOCK);
+    __syncthreads();
     C* dst = spec + ((long long)K * d.mz + z) * d.hplane;
     for (int i = tid; i < my * hx; i += BLOCK) dst[i] = S[i];
 }
 
-// Inverse: for a = x, y, z build the half spectrum of d_a phi_K on plane z,
-// inverse FFT along y, then complex-to-real along x with rows 2p and 2p+1
-// carried as the real and imaginary parts of one complex row.
+// Inverse: for a = x, y, z build the half spectrum of d_a phi_K on plane z
+// (pitch hx), inverse FFT along y, then complex-to-real along x with rows 2p
+// and 2p+1 carried as the real and imaginary parts of one complex row, packed
+// in place at complex offset p * 2hx by the lanes that then transform it.
 template <typename T, int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ grad, Dims d,
                                                   FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph) {
@@ -151,7 +235,7 @@ __global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zo
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     const int z = blockIdx.x, K = blockIdx.y;
-    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair;
+    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     for (int a = 0; a < 3; ++a) {
         const C* src = zout + ((long long)(a < 2 ? K : 2 + K) * d.mz + z) * d.hplane;
@@ -170,39 +254,46 @@ __global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zo
         }
         __syncthreads();
         fft_lines<C, 1>(S, LineMap{hx, hx, 1, 0, hx}, py, tw, tid, BLOCK);
-        C rz[kPairItems];
-        const int items = np * mx;
+        __syncthreads();
+        {
+            const int G = px.group, lane = tid % G;
+            for (int p = tid / G; p < np; p += BLOCK / G) {
+                const int base = p * zp;
+                const bool odd = 2 * p + 1 < my;
+                C rz[kPairItems];
 #pragma unroll
-        for (int u = 0; u < kPairItems; ++u) {
-            const int i = tid + u * BLOCK;
-            if (i < items) {
-                const int p = i / mx, x = i - p * mx;
-                C A, B;
-                if (x < hx) {
-                    A = S[(2 * p) * hx + x];
-                    B = (2 * p + 1 < my) ? S[(2 * p + 1) * hx + x] : C{0, 0};
-                } else {
-                    const int xs = mx - x;
-                    const C a0 = S[(2 * p) * hx + xs];
-                    const C b0 = (2 * p + 1 < my) ? S[(2 * p + 1) * hx + xs] : C{0, 0};
-                    A = C{a0.x, -a0.y};
-                    B = C{b0.x, -b0.y};
+                for (int u = 0; u < kPairItems; ++u) {
+                    const int x = lane + u * G;
+                    if (x < mx) {
+                        C A, B;
+                        if (x < hx) {
+                            A = S[base + x];
+                            B = odd ? S[base + hx + x] : C{0, 0};
+                        } else {
+                            const int xs = mx - x;
+                            const C a0 = S[base + xs];
+                            const C b0 = odd ? S[base + hx + xs] : C{0, 0};
+                            A = C{a0.x, -a0.y};
+                            B = C{b0.x, -b0.y};
+                        }
+                        rz[u] = C{A.x - B.y, A.y + B.x};
+                    }
                 }
-                rz[u] = C{A.x - B.y, A.y + B.x};
+                wave_sync();
+#pragma unroll
+                for (int u = 0; u < kPairItems; ++u) {
+                    const int x = lane + u * G;
+                    if (x < mx) S[base + x] = rz[u];
+                }
+                wave_sync();
+                fft_line<C, 1>(S, base, 1, px, tw, lane);
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kPairItems; ++u) {
-            const int i = tid + u * BLOCK;
-            if (i < items) S[i] = rz[u];
-        }
-        __syncthreads();
-        fft_lines<C, 1>(S, LineMap{np, np, mx, 0, 1}, px, tw, tid, BLOCK);
         T* dst = grad + (((long long)K * 3 + a) * d.mz + z) * (long long)my * mx;
-        for (int i = tid; i < items; i += BLOCK) {
+        for (int i = tid; i < np * mx; i += BLOCK) {
             const int p = i / mx, x = i - p * mx;
-            const C v = S[i];
+            const C v = S[p * zp + x];
             dst[(2 * p) * mx + x] = v.x;
             if (2 * p + 1 < my) dst[(2 * p + 1) * mx + x] = v.y;
         }
@@ -244,6 +335,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     }
     __syncthreads();
     fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp}, pz, tw, tid, BLOCK);
+    __syncthreads();
 
     double acc[5] = {0, 0, 0, 0, 0};
     const double kfx = kTwoPi / ph.lx, kfy = kTwoPi / ph.ly, kfz = kTwoPi / ph.lz;
@@ -300,6 +392,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     if (ENERGY_ONLY) return;
     __syncthreads();
     fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp}, pz, tw, tid, BLOCK);
+    __syncthreads();
     for (int i = tid; i < 4 * mz * cb; i += BLOCK) {
         const int q = i / (mz * cb);
         const int r = i - q * mz * cb;
@@ -311,126 +404,169 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 
 // ------------------------------------------------------------ gather + bonds + update
 
-// MODE 0: one Euler-Maruyama step, positions pin -> pout, global shift
-//         qs_in -> qs_out (centre-of-mass correction by the last block).
-// MODE 1: forces only, written to `out` ([n][3], float or double).
+// One tile: species K, beads whose stencil starts in rows [y0, y0 + ty) (all
+// x) and in the slabs s0 .. s0 + zc - 1.  For slab s the gradient fields of
+// planes s .. s+P-1, rows y0 .. y0+ty+P-2 (all x), are staged in LDS as a
+// ring of P planes; each bead then reads its P^3 stencil from LDS.
+// MODE 0: Euler-Maruyama step, the moved bead goes to pout[j]; the exact
+//         integer sum of all displacements becomes, in the last block, the new
+//         global shift qs_out (centre-of-mass correction).
+// MODE 1: forces only, written to out[abi id] ([n][3], float or double).
 template <typename T, int P, int MODE>
 __global__ void __launch_bounds__(256)
-    k_gather(const uint4* __restrict__ pin, uint4* __restrict__ pout, const uint32_t* __restrict__ qs_in,
-             uint32_t* __restrict__ qs_out, long long n, Dims d, const T* __restrict__ grad,
-             const int32_t* __restrict__ boff, const int32_t* __restrict__ bnbr, Phys ph, uint64_t step, void* out,
-             int out_dtype, unsigned parts, unsigned long long* __restrict__ com_acc, uint32_t* __restrict__ flag) {
+    k_gather_tile(const uint4* __restrict__ pin, uint4* __restrict__ pout, const uint32_t* __restrict__ bin_start,
+                  const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out, long long n, Dims d,
+                  const T* __restrict__ grad, const int32_t* __restrict__ nbr, int deg, Phys ph, uint64_t step,
+                  void* out, int out_dtype, unsigned parts, unsigned long long* __restrict__ com_acc,
+                  uint32_t* __restrict__ flag, int ty, int zc) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* ring = reinterpret_cast<T*>(smem);  // [P][3][ry][mx]
     __shared__ long long red[3 * 4];
     const int tid = threadIdx.x;
-    const long long i = blockIdx.x * 256LL + tid;
-    long long dq[3] = {0, 0, 0};
-    const uint32_t s0 = qs_in[0], s1 = qs_in[1], s2 = qs_in[2];
-    if (i < n) {
-        const uint4 q = pin[i];
-        T fn[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
-        if (MODE == 0 || (parts & 1u)) {
-            int gx, gy, gz;
-            T wx[P], wy[P], wz[P];
-            assignment_weights<T, P>(q.x - s0, d.mx, gx, wx);
-            assignment_weights<T, P>(q.y - s1, d.my, gy, wy);
-            assignment_weights<T, P>(q.z - s2, d.mz, gz, wz);
-            const T* gf = grad + (long long)q.w * 3 * d.m;
+    const int mx = d.mx, my = d.my, mz = d.mz;
+    const int nty = (my + ty - 1) / ty, nzc = (mz + zc - 1) / zc;
+    int w = blockIdx.x;
+    const int zi = w % nzc;
+    w /= nzc;
+    const int yi = w % nty;
+    const int K = w / nty;
+    const int y0 = yi * ty, y1 = (y0 + ty < my) ? y0 + ty : my;
+    const int s0 = zi * zc, s1 = (s0 + zc < mz) ? s0 + zc : mz;
+    const int ry = ty + P - 1;
+    const long long plane = (long long)my * mx;
+    const T* gK = grad + (long long)K * 3 * d.m;
+    const bool need_field = MODE == 0 || (parts & 1u);
+    const uint32_t sh0 = qs_in[0], sh1 = qs_in[1], sh2 = qs_in[2];
+    const T lsx = (T)(ph.lx * kInvTwo32), lsy = (T)(ph.ly * kInvTwo32), lsz = (T)(ph.lz * kInvTwo32);
+    const T k2 = (T)(2.0 * ph.bond_k);
+    const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
+    const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
+    long long dq_sum[3] = {0, 0, 0};
+
+    for (int s = s0; s < s1; ++s) {
+        if (need_field) {
+            // planes s .. s+P-1: the first slab loads all, later slabs only the newest
+            const int t_first = (s == s0) ? 0 : P - 1;
+            for (int t = t_first; t < P; ++t) {
+                int z = s + t;
+                if (z >= mz) z -= mz;
+                T* slot = ring + (size_t)((s - s0 + t) % P) * 3 * ry * mx;
+                for (int i = tid; i < 3 * ry * mx; i += 256) {
+                    const int comp = i / (ry * mx);
+                    const int r = (i / mx) % ry;
+                    const int x = i % mx;
+                    int y = y0 + r;
+                    while (y >= my) y -= my;
+                    slot[i] = gK[comp * d.m + z * plane + (long long)y * mx + x];
+                }
+            }
+            __syncthreads();
+        }
+        const int bb = (K * mz + s) * my;
+        const uint32_t j0 = bin_start[bb + y0], j1 = bin_start[bb + y1];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += 256u) {
+            const uint4 q = pin[j];
+            const uint32_t id = q.w >> 1;
+            T fn[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
+            if (need_field) {
+                int gx, gy, gz;
+                T wx[P], wy[P], wz[P];
+                assignment_weights<T, P>(q.x - sh0, mx, gx, wx);
+                assignment_weights<T, P>(q.y - sh1, my, gy, wy);
+                assignment_weights<T, P>(q.z - sh2, mz, gz, wz);
+                const int r0 = gy - y0;
+                // the bin key guarantees gz == s and y0 <= gy < y1; anything else is a bookkeeping error
+                const bool inside = gz == s && r0 >= 0 && r0 < ty;
+                if (!inside) atomicOr(flag, 8u);
+#pragma unroll 1
+                for (int c = 0; c < (inside ? P : 0); ++c) {
+                    const T* slot = ring + (size_t)((s - s0 + c) % P) * 3 * ry * mx;
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
-                int z = gz + c;
-                if (z >= d.mz) z -= d.mz;
+                    for (int b = 0; b < P; ++b) {
+                        const T* row = slot + (r0 + b) * mx;
+                        const T wzy = wz[c] * wy[b];
 #pragma unroll
-                for (int b = 0; b < P; ++b) {
-                    int y = gy + b;
-                    if (y >= d.my) y -= d.my;
-                    const long long row = ((long long)z * d.my + y) * d.mx;
-                    const T wzy = wz[c] * wy[b];
-#pragma unroll
-                    for (int a = 0; a < P; ++a) {
-                        int x = gx + a;
-                        if (x >= d.mx) x -= d.mx;
-                        const T w = wzy * wx[a];
-                        const long long g = row + x;
-                        fn[0] -= w * gf[g];
-                        fn[1] -= w * gf[d.m + g];
-                        fn[2] -= w * gf[2 * d.m + g];
+                        for (int a = 0; a < P; ++a) {
+                            int x = gx + a;
+                            if (x >= mx) x -= mx;
+                            const T wgt = wzy * wx[a];
+                            fn[0] -= wgt * row[x];
+                            fn[1] -= wgt * row[ry * mx + x];
+                            fn[2] -= wgt * row[2 * ry * mx + x];
+                        }
                     }
                 }
             }
-        }
-        if (MODE == 0 || (parts & 2u)) {
-            const T sx = (T)(ph.lx * kInvTwo32), sy = (T)(ph.ly * kInvTwo32), sz = (T)(ph.lz * kInvTwo32);
-            const T k2 = (T)(2.0 * ph.bond_k);
-            const int jb = boff[i], je = boff[i + 1];
-            for (int j = jb; j < je; ++j) {
-                const uint4 p = pin[bnbr[j]];
-                fb[0] -= k2 * sx * (T)fixed_delta(q.x, p.x);
-                fb[1] -= k2 * sy * (T)fixed_delta(q.y, p.y);
-                fb[2] -= k2 * sz * (T)fixed_delta(q.z, p.z);
-            }
-        }
-        if (MODE == 1) {
-            T f[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) f[a] = ((parts & 1u) ? fn[a] : (T)0) + ((parts & 2u) ? fb[a] : (T)0);
-            if (out_dtype == 0) {
-                float* o = reinterpret_cast<float*>(out) + 3 * i;
-                o[0] = (float)f[0];
-                o[1] = (float)f[1];
-                o[2] = (float)f[2];
-            } else {
-                double* o = reinterpret_cast<double*>(out) + 3 * i;
-                o[0] = (double)f[0];
-                o[1] = (double)f[1];
-                o[2] = (double)f[2];
-            }
-        } else {
-            T xi[3];
-            Noise<T>::draw((uint32_t)i, step, ph.seed, xi);
-            const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
-            const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
-            bool bad = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T disp = mob * (fn[a] + fb[a]) + amp * xi[a];
-                const double s = (double)disp * inv_l[a];
-                if (!(fabs(s) < 4.0e18)) {  // also false for NaN
-                    bad = true;
-                } else {
-                    dq[a] = llrint(s);
+            if (MODE == 0 || (parts & 2u)) {
+                for (int e = 0; e < deg; ++e) {
+                    const int p = nbr[(long long)j * deg + e];
+                    if (p < 0) break;
+                    const uint4 qp = pin[p];
+                    fb[0] -= k2 * lsx * (T)fixed_delta(q.x, qp.x);
+                    fb[1] -= k2 * lsy * (T)fixed_delta(q.y, qp.y);
+                    fb[2] -= k2 * lsz * (T)fixed_delta(q.z, qp.z);
                 }
             }
-            if (bad) {
-                atomicOr(flag, 1u);
-                dq[0] = dq[1] = dq[2] = 0;
+            if (MODE == 1) {
+                T f[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) f[a] = ((parts & 1u) ? fn[a] : (T)0) + ((parts & 2u) ? fb[a] : (T)0);
+                if (out_dtype == 0) {
+                    float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
+                    o[0] = (float)f[0];
+                    o[1] = (float)f[1];
+                    o[2] = (float)f[2];
+                } else {
+                    double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
+                    o[0] = (double)f[0];
+                    o[1] = (double)f[1];
+                    o[2] = (double)f[2];
+                }
+            } else {
+                T xi[3];
+                Noise<T>::draw(id, step, ph.seed, xi);
+                long long dq[3] = {0, 0, 0};
+                bool bad = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T disp = mob * (fn[a] + fb[a]) + amp * xi[a];
+                    const double sd = (double)disp * inv_l[a];
+                    if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
+                    else dq[a] = llrint(sd);
+                }
+                if (bad) {
+                    atomicOr(flag, 1u);
+                    dq[0] = dq[1] = dq[2] = 0;
+                }
+                pout[j] = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
+                dq_sum[0] += dq[0];
+                dq_sum[1] += dq[1];
+                dq_sum[2] += dq[2];
             }
-            pout[i] = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
         }
+        if (need_field) __syncthreads();  // the ring slot of plane s is reloaded next
     }
     if (MODE == 0) {
-        // Exact integer sum of the applied displacements; the last block to
-        // finish turns it into the new global shift.
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            long long v = wave_sum(dq[a]);
+            long long v = wave_sum(dq_sum[a]);
             if ((tid & 63) == 0) red[a * 4 + (tid >> 6)] = v;
         }
         __syncthreads();
         if (tid == 0) {
             for (int a = 0; a < 3; ++a) {
-                const long long s = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
-                atomicAdd(&com_acc[a], (unsigned long long)s);
+                const long long sa = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
+                atomicAdd(&com_acc[a], (unsigned long long)sa);
             }
             __threadfence();
             const unsigned long long ticket = atomicAdd(&com_acc[3], 1ull);
             if (ticket == (unsigned long long)gridDim.x - 1) {
                 __threadfence();
-                const uint32_t sh[3] = {s0, s1, s2};
+                const uint32_t shv[3] = {sh0, sh1, sh2};
                 for (int a = 0; a < 3; ++a) {
                     const long long tot = (long long)atomicAdd(&com_acc[a], 0ull);
-                    long long shift = 0;
-                    if (ph.com_correct) shift = llround((double)tot / (double)n);
-                    qs_out[a] = sh[a] + (uint32_t)shift;
+                    const long long shift = ph.com_correct && n > 0 ? llround((double)tot / (double)n) : 0;
+                    qs_out[a] = shv[a] + (uint32_t)shift;
                     com_acc[a] = 0ull;
                 }
                 qs_out[3] = 0u;
@@ -440,23 +576,130 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ------------------------------------------------------------ counting sort
+
+// Rank of the calling lane among the active lanes of its wavefront that hold
+// the same key in one run of consecutive lanes; the run's first lane takes
+// the whole run's places in the bin with a single atomic.
+__device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t* __restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(kb, 1, 64);
+    const bool head = !active || lane == 0 || prev != kb;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int hl = 63 - __clzll(hm & upto);
+    const unsigned long long above = hm & ~upto;
+    const int nl = above ? __ffsll((long long)above) - 1 : 64;
+    uint32_t base = 0;
+    if (active && lane == hl) base = atomicAdd(&counts[kb], (uint32_t)(nl - hl));
+    base = __shfl(base, hl, 64);
+    return base + (uint32_t)(lane - hl);
+}
+
+// Bin key and in-bin rank of every bead of pos_tmp, with the global shift of
+// the step just taken, so that every key is the bead's exact stencil start.
+__global__ void __launch_bounds__(256) k_keys(const uint4* __restrict__ pos_tmp, const uint32_t* __restrict__ qs,
+                                              uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
+                                              uint32_t* __restrict__ counts, long long n, Dims d, int P) {
+    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    const bool active = j < n;
+    uint32_t kb = 0xffffffffu;
+    if (active) {
+        const uint4 q = pos_tmp[j];
+        kb = bin_key(q.y - qs[1], q.z - qs[2], q.w & 1u, d, P);
+    }
+    const uint32_t r = bin_rank(kb, active, counts);
+    if (active) {
+        key[j] = kb;
+        rank[j] = r;
+    }
+}
+
+// One workgroup: bin_start = exclusive prefix sum of counts (bin_start[nbins]
+// = total); counts are cleared for the next use.  Chunks of 32768 bins are
+// staged in LDS (skewed by one word per 32 against bank conflicts).
+__global__ void __launch_bounds__(1024) k_bin_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ bin_start,
+                                                   int nbins) {
+    constexpr int CH = 32768;
+    __shared__ uint32_t buf[CH + CH / 32];
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t carry = 0;
+    for (int base = 0; base < nbins; base += CH) {
+        const int len = (nbins - base < CH) ? nbins - base : CH;
+        for (int i = tid; i < len; i += 1024) {
+            buf[i + (i >> 5)] = counts[base + i];
+            counts[base + i] = 0u;
+        }
+        __syncthreads();
+        const int lo = tid * 32;
+        uint32_t sum = 0;
+        for (int k = 0; k < 32; ++k)
+            if (lo + k < len) sum += buf[lo + k + ((lo + k) >> 5)];
+        uint32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t wpre = 0, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) wpre += wsum[w];
+            total += wsum[w];
+        }
+        uint32_t run = carry + wpre + inc - sum;
+        for (int k = 0; k < 32; ++k)
+            if (lo + k < len) {
+                const int ix = lo + k + ((lo + k) >> 5);
+                const uint32_t v = buf[ix];
+                buf[ix] = run;
+                run += v;
+            }
+        __syncthreads();
+        for (int i = tid; i < len; i += 1024) bin_start[base + i] = buf[i + (i >> 5)];
+        carry += total;
+        __syncthreads();
+    }
+    if (tid == 0) bin_start[nbins] = carry;
+}
+
+// Move every bead of the previous order to its sorted slot and translate its
+// bond partners (slots of the previous order) into sorted slots.
+__global__ void __launch_bounds__(256) k_scatter(const uint4* __restrict__ pos_tmp, const uint32_t* __restrict__ key,
+                                                 const uint32_t* __restrict__ rank,
+                                                 const uint32_t* __restrict__ bin_start,
+                                                 const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos,
+                                                 int32_t* __restrict__ nbr_dst, long long n, int deg) {
+    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    if (j >= n) return;
+    const long long nw = (long long)bin_start[key[j]] + rank[j];
+    pos[nw] = pos_tmp[j];
+    for (int b = 0; b < deg; ++b) {
+        const int p = nbr_src[j * deg + b];
+        nbr_dst[nw * deg + b] = p < 0 ? -1 : (int32_t)(bin_start[key[p]] + rank[p]);
+    }
+}
+
 // Bond energy and virial: E = k_b sum |d|^2, W_aa = -2 k_b sum d_a^2 (each
 // bond is visited from both ends, hence the factor 1/2).
 __global__ void __launch_bounds__(256) k_bond_energy(const uint4* __restrict__ pin, long long n,
-                                                     const int32_t* __restrict__ boff,
-                                                     const int32_t* __restrict__ bnbr, Phys ph,
+                                                     const int32_t* __restrict__ nbr, int deg, Phys ph,
                                                      double* __restrict__ bpart) {
     __shared__ double red[4 * 4];
     const int tid = threadIdx.x;
-    const long long i = blockIdx.x * 256LL + tid;
+    const long long j = blockIdx.x * 256LL + tid;
     double acc[4] = {0, 0, 0, 0};
-    if (i < n) {
-        const uint4 q = pin[i];
+    if (j < n) {
+        const uint4 q = pin[j];
         const double sx = ph.lx * kInvTwo32, sy = ph.ly * kInvTwo32, sz = ph.lz * kInvTwo32;
-        for (int j = boff[i]; j < boff[i + 1]; ++j) {
-            const uint4 p = pin[bnbr[j]];
-            const double dx = sx * fixed_delta(q.x, p.x), dy = sy * fixed_delta(q.y, p.y),
-                         dz = sz * fixed_delta(q.z, p.z);
+        for (int b = 0; b < deg; ++b) {
+            const int p = nbr[j * deg + b];
+            if (p < 0) break;
+            const uint4 qp = pin[p];
+            const double dx = sx * fixed_delta(q.x, qp.x), dy = sy * fixed_delta(q.y, qp.y),
+                         dz = sz * fixed_delta(q.z, qp.z);
             acc[0] += 0.5 * ph.bond_k * (dx * dx + dy * dy + dz * dz);
             acc[1] -= ph.bond_k * dx * dx;
             acc[2] -= ph.bond_k * dy * dy;
@@ -495,14 +738,17 @@ __global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict_
 
 // ------------------------------------------------------------ positions I/O
 
+// ABI-order coordinates -> fixed point in pos_tmp with keys and ranks; the
+// global shift restarts at zero.
 template <typename TI>
-__global__ void __launch_bounds__(256) k_set_positions(const TI* __restrict__ xyz, uint4* __restrict__ pos,
-                                                       uint32_t* __restrict__ qs, long long n, double lx, double ly,
-                                                       double lz, uint32_t* __restrict__ flag) {
+__global__ void __launch_bounds__(256)
+    k_place(const TI* __restrict__ xyz, const uint32_t* __restrict__ types, uint4* __restrict__ pos_tmp,
+            uint32_t* __restrict__ key_out, uint32_t* __restrict__ rank_out, uint32_t* __restrict__ counts,
+            uint32_t* __restrict__ qs, long long n, Dims d, int P, uint32_t* __restrict__ flag) {
     const long long i = blockIdx.x * 256LL + threadIdx.x;
     if (i == 0) qs[0] = qs[1] = qs[2] = qs[3] = 0u;
     if (i >= n) return;
-    const double L[3] = {lx, ly, lz};
+    const double L[3] = {d.lx, d.ly, d.lz};
     uint32_t q[3];
     for (int a = 0; a < 3; ++a) {
         const double x = (double)xyz[3 * i + a];
@@ -515,20 +761,24 @@ __global__ void __launch_bounds__(256) k_set_positions(const TI* __restrict__ xy
         f -= floor(f);
         q[a] = (uint32_t)(unsigned long long)llrint(f * kTwo32);  // 2^32 wraps to 0
     }
-    const uint4 old = pos[i];
-    pos[i] = uint4{q[0], q[1], q[2], old.w};
+    const uint32_t K = types[i];
+    pos_tmp[i] = uint4{q[0], q[1], q[2], ((uint32_t)i << 1) | K};
+    const uint32_t kb = bin_key(q[1], q[2], K, d, P);
+    key_out[i] = kb;
+    rank_out[i] = atomicAdd(&counts[kb], 1u);
 }
 
 template <typename TO>
 __global__ void __launch_bounds__(256) k_get_positions(const uint4* __restrict__ pos, const uint32_t* __restrict__ qs,
                                                        long long n, double lx, double ly, double lz,
                                                        TO* __restrict__ xyz) {
-    const long long i = blockIdx.x * 256LL + threadIdx.x;
-    if (i >= n) return;
-    const uint4 q = pos[i];
-    xyz[3 * i + 0] = (TO)((double)(q.x - qs[0]) * (lx * kInvTwo32));
-    xyz[3 * i + 1] = (TO)((double)(q.y - qs[1]) * (ly * kInvTwo32));
-    xyz[3 * i + 2] = (TO)((double)(q.z - qs[2]) * (lz * kInvTwo32));
+    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    if (j >= n) return;
+    const uint4 q = pos[j];
+    const long long id = q.w >> 1;
+    xyz[3 * id + 0] = (TO)((double)(q.x - qs[0]) * (lx * kInvTwo32));
+    xyz[3 * id + 1] = (TO)((double)(q.y - qs[1]) * (ly * kInvTwo32));
+    xyz[3 * id + 2] = (TO)((double)(q.z - qs[2]) * (lz * kInvTwo32));
 }
 
 __global__ void __launch_bounds__(256) k_stream_copy(uint4* __restrict__ dst, const uint4* __restrict__ src,
@@ -537,49 +787,14 @@ __global__ void __launch_bounds__(256) k_stream_copy(uint4* __restrict__ dst, co
     for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
 }
 
+
 // ============================================================ launchers
 
 static inline unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
-hipError_t launch_fill_mean(const Launch& L, DeviceState& S) {
-    const double va = -(double)S.n_a / (double)L.d.m, vb = -(double)S.n_b / (double)L.d.m;
-    const unsigned g = (unsigned)std::min<long long>(blocks_for(2 * L.d.m, 256), 4096);
-    if (L.precision == 0)
-        hipLaunchKernelGGL(k_fill_mean<float>, dim3(g), dim3(256), 0, L.stream, (float*)S.dens, L.d.m, (float)va,
-                           (float)vb);
-    else
-        hipLaunchKernelGGL(k_fill_mean<double>, dim3(g), dim3(256), 0, L.stream, (double*)S.dens, L.d.m, va, vb);
-    return hipGetLastError();
-}
-
-template <typename T, int P> static void spread_p(const Launch& L, DeviceState& S, const uint32_t* qs) {
-    hipLaunchKernelGGL((k_spread_atomic<T, P>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos, qs, S.n,
-                       L.d, (T*)S.dens);
-}
-
-template <typename T> static void spread_t(const Launch& L, DeviceState& S, const uint32_t* qs) {
-    switch (L.order) {
-        case 1: spread_p<T, 1>(L, S, qs); break;
-        case 2: spread_p<T, 2>(L, S, qs); break;
-        case 3: spread_p<T, 3>(L, S, qs); break;
-        case 4: spread_p<T, 4>(L, S, qs); break;
-        case 5: spread_p<T, 5>(L, S, qs); break;
-        case 6: spread_p<T, 6>(L, S, qs); break;
-        default: spread_p<T, 7>(L, S, qs); break;
-    }
-}
-
-hipError_t launch_spread(const Launch& L, DeviceState& S) {
-    if (S.n == 0) return hipSuccess;
-    if (L.precision == 0) spread_t<float>(L, S, S.qshift);
-    else spread_t<double>(L, S, S.qshift);
-    return hipGetLastError();
-}
-
 size_t plane_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    const size_t a = (size_t)L.d.npair * L.d.mx, b = (size_t)L.d.my * L.d.hx;
-    return c * (a > b ? a : b);
+    return c * (size_t)L.d.npair * (size_t)(2 * L.d.hx);
 }
 
 size_t z_lds_bytes(const Launch& L) {
@@ -587,23 +802,24 @@ size_t z_lds_bytes(const Launch& L) {
     return c * 4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1);
 }
 
-template <typename T, int B> static void xy_r2c_b(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL((k_xy_r2c<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream, (const T*)S.dens,
-                       (cplx<T>*)S.spec, L.d, L.px, L.py, (const cplx<T>*)S.tw);
+template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceState& S) {
+    hipLaunchKernelGGL((k_spread_xy<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream, S.pos,
+                       S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                       L.order, S.flag);
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
     hipLaunchKernelGGL((k_xy_c2r<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.zout, (T*)S.grad, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph);
 }
 
-hipError_t launch_xy_r2c(const Launch& L, DeviceState& S) {
+hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
     if (L.precision == 0) {
-        if (L.plane_block == 256) xy_r2c_b<float, 256>(L, S);
-        else if (L.plane_block == 512) xy_r2c_b<float, 512>(L, S);
-        else xy_r2c_b<float, 1024>(L, S);
+        if (L.plane_block == 256) spread_xy_b<float, 256>(L, S);
+        else if (L.plane_block == 512) spread_xy_b<float, 512>(L, S);
+        else spread_xy_b<float, 1024>(L, S);
     } else {
-        if (L.plane_block == 256) xy_r2c_b<double, 256>(L, S);
-        else xy_r2c_b<double, 512>(L, S);
+        if (L.plane_block == 256) spread_xy_b<double, 256>(L, S);
+        else spread_xy_b<double, 512>(L, S);
     }
     return hipGetLastError();
 }
@@ -637,11 +853,17 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
     return hipGetLastError();
 }
 
+size_t gather_lds_bytes(const Launch& L, int ty) {
+    const size_t r = L.precision == 0 ? sizeof(float) : sizeof(double);
+    return r * (size_t)L.order * 3 * (size_t)(ty + L.order - 1) * (size_t)L.d.mx;
+}
+
 template <typename T, int P, int MODE>
 static void gather_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
-    hipLaunchKernelGGL((k_gather<T, P, MODE>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos, S.pos_next,
-                       S.qshift, S.qshift_next, S.n, L.d, (const T*)S.grad, S.bond_off, S.bond_nbr, L.ph, step, out,
-                       out_dtype, parts, S.com_acc, S.flag);
+    const int nty = (L.d.my + L.gather_ty - 1) / L.gather_ty, nzc = (L.d.mz + L.gather_zc - 1) / L.gather_zc;
+    hipLaunchKernelGGL((k_gather_tile<T, P, MODE>), dim3(2 * nty * nzc), dim3(256), gather_lds_bytes(L, L.gather_ty),
+                       L.stream, S.pos, S.pos_tmp, S.bin_start, S.qshift, S.qshift_next, S.n, L.d, (const T*)S.grad,
+                       S.nbr, S.deg, L.ph, step, out, out_dtype, parts, S.com_acc, S.flag, L.gather_ty, L.gather_zc);
 }
 
 template <typename T, int MODE>
@@ -659,7 +881,6 @@ static void gather_t(const Launch& L, DeviceState& S, uint64_t step, void* out, 
 
 hipError_t launch_gather(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts) {
-    if (S.n == 0) return hipSuccess;
     if (L.precision == 0) {
         if (mode == 0) gather_t<float, 0>(L, S, step, out, out_dtype, parts);
         else gather_t<float, 1>(L, S, step, out, out_dtype, parts);
@@ -670,9 +891,28 @@ hipError_t launch_gather(const Launch& L, DeviceState& S, int mode, uint64_t ste
     return hipGetLastError();
 }
 
+hipError_t launch_keys(const Launch& L, DeviceState& S) {
+    if (S.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.qshift, S.key, S.rank,
+                       S.counts, S.n, L.d, L.order);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, L.stream, S.counts, S.bin_start, S.nbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src) {
+    if (S.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.key, S.rank,
+                       S.bin_start, nbr_src, S.pos, S.nbr_old, S.n, S.deg);
+    return hipGetLastError();
+}
+
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL(k_bond_energy, dim3(L.n_bblocks), dim3(256), 0, L.stream, S.pos, S.n, S.bond_off, S.bond_nbr,
-                       L.ph, S.bpart);
+    hipLaunchKernelGGL(k_bond_energy, dim3(L.n_bblocks), dim3(256), 0, L.stream, S.pos, S.n, S.nbr, S.deg, L.ph,
+                       S.bpart);
     return hipGetLastError();
 }
 
@@ -682,14 +922,14 @@ hipError_t launch_reduce_energy(const Launch& L, DeviceState& S) {
     return hipGetLastError();
 }
 
-hipError_t launch_set_positions(const Launch& L, DeviceState& S, const void* xyz, int dtype) {
+hipError_t launch_place(const Launch& L, DeviceState& S, const void* xyz, int dtype) {
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     if (dtype == 0)
-        hipLaunchKernelGGL(k_set_positions<float>, dim3(g), dim3(256), 0, L.stream, (const float*)xyz, S.pos,
-                           S.qshift, S.n, L.ph.lx, L.ph.ly, L.ph.lz, S.flag);
+        hipLaunchKernelGGL(k_place<float>, dim3(g), dim3(256), 0, L.stream, (const float*)xyz, S.types_abi, S.pos_tmp,
+                           S.key, S.rank, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
     else
-        hipLaunchKernelGGL(k_set_positions<double>, dim3(g), dim3(256), 0, L.stream, (const double*)xyz, S.pos,
-                           S.qshift, S.n, L.ph.lx, L.ph.ly, L.ph.lz, S.flag);
+        hipLaunchKernelGGL(k_place<double>, dim3(g), dim3(256), 0, L.stream, (const double*)xyz, S.types_abi,
+                           S.pos_tmp, S.key, S.rank, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
     return hipGetLastError();
 }
 
@@ -713,35 +953,56 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 }
 
 template <typename T, int B> static hipError_t attr_plane(size_t lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_xy_r2c<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_spread_xy<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_xy_c2r<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+template <typename T> static hipError_t attr_z(size_t lds) {
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_z_kmul<T, 256, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_z_kmul<T, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T, int P> static hipError_t attr_gather_p(size_t lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gather_tile<T, P, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_gather_tile<T, P, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <typename T> static hipError_t attr_gather(int P, size_t lds) {
+    switch (P) {
+        case 1: return attr_gather_p<T, 1>(lds);
+        case 2: return attr_gather_p<T, 2>(lds);
+        case 3: return attr_gather_p<T, 3>(lds);
+        case 4: return attr_gather_p<T, 4>(lds);
+        case 5: return attr_gather_p<T, 5>(lds);
+        case 6: return attr_gather_p<T, 6>(lds);
+        default: return attr_gather_p<T, 7>(lds);
+    }
+}
+
 hipError_t configure_kernel_attributes(const Launch& L) {
-    const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L);
+    const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L), lg = gather_lds_bytes(L, L.gather_ty);
     hipError_t e = hipSuccess;
     if (L.precision == 0) {
         if (L.plane_block == 256) e = attr_plane<float, 256>(lp);
         else if (L.plane_block == 512) e = attr_plane<float, 512>(lp);
         else e = attr_plane<float, 1024>(lp);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_z_kmul<float, 256, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lz);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_z_kmul<float, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lz);
+        if (e == hipSuccess) e = attr_z<float>(lz);
+        if (e == hipSuccess) e = attr_gather<float>(L.order, lg);
     } else {
         if (L.plane_block == 256) e = attr_plane<double, 256>(lp);
         else e = attr_plane<double, 512>(lp);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_z_kmul<double, 256, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lz);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute((const void*)k_z_kmul<double, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lz);
+        if (e == hipSuccess) e = attr_z<double>(lz);
+        if (e == hipSuccess) e = attr_gather<double>(L.order, lg);
     }
     return e;
 }
 
 }  // namespace tild
+
