@@ -41,14 +41,15 @@ def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
     deg = int(np.bincount(melt.bonds.ravel(), minlength=n).max()) if melt.bonds.size else 0
     nbins = 2 * mz * my
     bead = 16  # uint4 {qx, qy, qz, id << 1 | species}
+    P = int(melt.order)
     return {
         "spread_fft_xy": n * bead + 2 * hs * c,
         "fft_z_kmul": 2 * hs * c + 4 * hs * c,
-        "fft_xy_c2r": 4 * hs * c + 6 * m * r,
-        "gather_bond_em": n * (bead + 4 * deg) + 6 * m * r + n * bead,
+        "fft_xy_c2r_gather": 4 * hs * c + n * bead + 3 * P * n * r,
+        "update_em": n * bead + n * 4 * r + 3 * P * n * r + n * bead,
         "bin_keys": n * bead + n * 8,
         "bin_scan": 4 * nbins * 3 + 4,
-        "bin_scatter": n * (bead + 8 + 4 * deg) + n * (bead + 4 * deg),
+        "bin_scatter_bonds": n * (bead + 8 + 4 * deg) + n * (bead + 4 * deg + 4 * r),
     }
 
 

@@ -22,8 +22,8 @@ thread_local std::string g_create_error;
 
 enum Slot { kSpreadXy = 0, kZKmul, kXyC2r, kGather, kKeys, kBinScan, kScatter, kNumSlots };
 static_assert(kNumSlots == TILD_NUM_KERNELS, "slot table");
-const char* kSlotNames[kNumSlots] = {"spread_fft_xy", "fft_z_kmul", "fft_xy_c2r", "gather_bond_em",
-                                     "bin_keys",      "bin_scan",   "bin_scatter"};
+const char* kSlotNames[kNumSlots] = {"spread_fft_xy", "fft_z_kmul", "fft_xy_c2r_gather", "update_em",
+                                     "bin_keys",      "bin_scan",   "bin_scatter_bonds"};
 
 // Uncentred cardinal B-spline M_k(s) (support [0, k)), by its recursion.
 double uncentred_bspline(int k, double s) {
@@ -172,15 +172,6 @@ bool choose_shapes(Launch& L, std::string& why) {
         return false;
     }
     L.n_zblocks = (int)((d.hplane + L.z_cols - 1) / L.z_cols);
-    // gather tiles: rows of stencil starts (all x) x slabs, the P staged planes within budget
-    const size_t gbudget = L.precision == 0 ? 80 * 1024 : 160 * 1024;
-    L.gather_zc = 8;
-    for (L.gather_ty = 8; L.gather_ty > 1 && gather_lds_bytes(L, L.gather_ty) > gbudget; L.gather_ty /= 2) {
-    }
-    if (gather_lds_bytes(L, L.gather_ty) > lds_max) {
-        why = "gather tile does not fit LDS (grid too wide along x for this order and precision)";
-        return false;
-    }
     return true;
 }
 
@@ -235,7 +226,7 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         if (e == hipSuccess) e = launch_xy_c2r(c->L, c->S);
         mark(kXyC2r, 1);
         mark(kGather, 0);
-        if (e == hipSuccess) e = launch_gather(c->L, c->S, 0, (uint64_t)c->step, nullptr, 0, 0);
+        if (e == hipSuccess) e = launch_update(c->L, c->S, 0, (uint64_t)c->step, nullptr, 0, 0);
         mark(kGather, 1);
         if (e == hipSuccess) std::swap(c->S.qshift, c->S.qshift_next);  // keys use the new shift
         mark(kKeys, 0);
@@ -394,8 +385,8 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     const size_t ntab = nbr_tab.size() > 0 ? nbr_tab.size() : 1;
     A((void**)&S.pos, npos * sizeof(uint4));
     A((void**)&S.pos_tmp, npos * sizeof(uint4));
-    A((void**)&S.key, npos * sizeof(uint32_t));
-    A((void**)&S.rank, npos * sizeof(uint32_t));
+    A((void**)&S.kr, npos * sizeof(uint2));
+    A(&S.fbond, npos * 4 * real_sz);
     A((void**)&S.counts, (size_t)S.nbins * sizeof(uint32_t));
     A((void**)&S.bin_start, ((size_t)S.nbins + 1) * sizeof(uint32_t));
     A((void**)&S.nbr, ntab * sizeof(int32_t));
@@ -406,11 +397,12 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     A((void**)&S.qshift_next, 4 * sizeof(uint32_t));
     A(&S.spec, 2 * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.zout, 4 * (size_t)d.mz * d.hplane * cplx_sz);
-    A(&S.grad, 6 * (size_t)d.m * real_sz);
+    A(&S.fpart, 3 * (size_t)params->order * npos * real_sz);
     A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
     A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
     A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(double));
-    A((void**)&S.com_acc, 4 * sizeof(unsigned long long));
+    A((void**)&S.com_part, (size_t)kUpdateBlocks * 3 * sizeof(long long));
+    A((void**)&S.ticket, sizeof(unsigned int));
     A((void**)&S.flag, sizeof(uint32_t));
     A((void**)&S.eout, 8 * sizeof(double));
     A(&c->staging, npos * 3 * sizeof(double));
@@ -434,7 +426,6 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     for (int64_t i = 0; i < n_beads; ++i) types_u[(size_t)i] = (uint32_t)types[i];
     std::vector<uint32_t> zero_bins((size_t)S.nbins + 1, 0u);
     const uint32_t zeros4[4] = {0, 0, 0, 0};
-    const unsigned long long zacc[4] = {0, 0, 0, 0};
     auto H2D = [&](void* dst, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
     };
@@ -446,7 +437,7 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     H2D(S.qshift_next, zeros4, sizeof(zeros4));
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
     else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
-    H2D(S.com_acc, zacc, sizeof(zacc));
+    H2D(S.ticket, zeros4, sizeof(unsigned int));
     H2D(S.flag, zeros4, sizeof(uint32_t));
     if (e == hipSuccess) e = configure_kernel_attributes(L);
     if (e != hipSuccess) {
@@ -529,7 +520,7 @@ TILD_API int tild_forces(tild_ctx* c, void* out, int32_t dtype, int32_t on_devic
     hipError_t e = hipSuccess;
     if (parts & TILD_PART_NONBONDED) e = mesh_forward(c, false);
     void* dst = on_device ? out : c->staging;
-    if (e == hipSuccess) e = launch_gather(c->L, c->S, 1, (uint64_t)c->step, dst, dtype, parts);
+    if (e == hipSuccess) e = launch_update(c->L, c->S, 1, (uint64_t)c->step, dst, dtype, parts);
     const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
     if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(out, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
     if (e != hipSuccess) return c->hip_fail(e, "forces");

@@ -10,6 +10,8 @@
 
 namespace tild {
 
+constexpr int kUpdateBlocks = 1024;  // workgroups of the (grid-stride) update kernel
+
 // Physical constants of one context, passed by value to kernels.
 struct Phys {
     double lx, ly, lz;
@@ -36,12 +38,13 @@ struct Phys {
 // (q - qshift) * L / 2^32.  Every step the update kernel writes the new
 // positions in the old order, a key pass forms each bead's new key and its
 // rank within the key's bin, a scan turns bin counts into bin starts, and a
-// scatter moves beads (and re-maps bond partner slots) into the new order.
+// scatter moves beads into the new order, re-maps bond partner slots and
+// stores each bead's bond force.
 struct DeviceState {
     uint4* pos;           // [n] sorted beads
     uint4* pos_tmp;       // [n] beads in the previous order (new positions or ABI input)
-    uint32_t* key;        // [n] bin key of pos_tmp[j]
-    uint32_t* rank;       // [n] rank of pos_tmp[j] within its bin
+    uint2* kr;            // [n] {bin key, rank within the bin} of pos_tmp[j]
+    void* fbond;          // [n][4] harmonic bond force of sorted bead j {Fx, Fy, Fz, 0} (working precision)
     uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
     uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
     int32_t* nbr;         // [n][deg] bond partners of sorted slot j as sorted slots, -1 padded
@@ -52,11 +55,12 @@ struct DeviceState {
     uint32_t* qshift_next;  // [4] shift after the step being computed
     void* spec;           // complex [2][mz][my][hx] half spectra of the counts
     void* zout;           // complex [4][mz][my][hx]: z-inverted Phi_A, Phi_B, then ik_z Phi_A, ik_z Phi_B
-    void* grad;           // real [2][3][mz][my][mx] gradient fields
+    void* fpart;          // real [3][P][n] non-bonded force partials: axis, stencil plane offset, sorted bead
     void* tw;             // complex twiddle tables
     double* epart;        // [n_zblocks][5] energy partials of the k-space pass
     double* bpart;        // [n_bblocks][4] bond energy / virial partials
-    unsigned long long* com_acc;  // [4]: int64 displacement sums (x, y, z) and a block counter
+    long long* com_part;  // [kUpdateBlocks][3] per-block integer displacement sums of a step
+    unsigned int* ticket; // [1] blocks of the update kernel finished (reset by the last one)
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
     double* eout;         // [8] reduced energies
     long long n;
@@ -76,8 +80,6 @@ struct Launch {
     int z_block;
     int n_zblocks;
     int n_bblocks;
-    int gather_ty;    // rows of stencil starts per gather tile
-    int gather_zc;    // slabs per gather tile
     Phys ph;
 };
 
@@ -87,7 +89,7 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only);
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S);
 // mode 0: Euler-Maruyama step (writes pos_tmp and qshift_next);
 // mode 1: write forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
-hipError_t launch_gather(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
+hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts);
 // key and rank of every bead of pos_tmp (counts incremented)
 hipError_t launch_keys(const Launch& L, DeviceState& S);
@@ -103,7 +105,6 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 // Dynamic LDS a plane / z workgroup needs (bytes), used for validation.
 size_t plane_lds_bytes(const Launch& L);
 size_t z_lds_bytes(const Launch& L);
-size_t gather_lds_bytes(const Launch& L, int ty);
 hipError_t configure_kernel_attributes(const Launch& L);
 
 }  // namespace tild

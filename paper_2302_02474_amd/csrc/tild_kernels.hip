@@ -6,11 +6,13 @@
 //               their mean), then real-to-complex FFT along x, FFT along y
 //   z_kmul      per column block: FFT along z, multiply by the smeared
 //               chi/kappa kernel, inverse FFT along z of Phi_K and ik_z Phi_K
-//   xy_c2r      per (z-plane, species): ik_x, ik_y applied, inverse FFT along
-//               y and complex-to-real along x -> the three gradient fields
-//   gather      F_i = -sum_g W_i(g) grad phi_{s_i}(g) with the same weights,
-//               harmonic bonds, Philox noise and the Euler-Maruyama update;
-//               emits each moved bead's bin key and rank
+//   xy_c2r      per (z-plane, species, axis): ik_x or ik_y applied, inverse
+//               FFT along y and complex-to-real along x -> one gradient plane
+//               in LDS, interpolated onto the beads that reach it with the
+//               same weights (one partial force per bead, plane and axis)
+//   update      F_i = -sum_g W_i(g) grad phi_{s_i}(g) (the sum of its
+//               partials) + bond force, Philox noise, Euler-Maruyama update
+//   keys        each moved bead's bin key and rank
 //   bin_scan    bin counts -> bin starts
 //   scatter     beads and bond partners into the new sorted order
 #include "tild_kernels.h"
@@ -51,6 +53,13 @@ __device__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */, int tid, int n
     __syncthreads();
 }
 
+// Copy the twiddle tables (x, y and z axes, concatenated) into LDS.
+template <typename C>
+__device__ __forceinline__ const C* stage_twiddles(C* dst, const C* __restrict__ tw, const Dims& d, int tid, int nthr) {
+    for (int i = tid; i < d.mx + d.my + d.mz; i += nthr) dst[i] = tw[i];
+    return dst;
+}
+
 // ------------------------------------------------------------ bins
 
 // Bin key of a bead: (species, first stencil plane in z, first stencil row in y).
@@ -79,8 +88,18 @@ __device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __res
         if (s < 0) s += d.mz;
         const int b0 = (K * d.mz + s) * d.my;
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
-        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
-            const uint4 q = pos[j];
+        constexpr int U = 4;  // beads in flight per thread
+        for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
+          uint4 qv[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+              const uint32_t j = jb + (uint32_t)(u * nthr);
+              qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (jb + (uint32_t)(u * nthr) >= j1) break;
+            const uint4 q = qv[u];
             int gx, gy, gz;
             T wx[P], wy[P], wz[P];
             assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
@@ -104,6 +123,7 @@ __device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __res
                     }
                 }
             }
+          }
         }
     }
 }
@@ -159,6 +179,7 @@ __global__ void __launch_bounds__(BLOCK)
     const int z = blockIdx.x, K = blockIdx.y;
     const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
+    const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
     constexpr bool kFixed = sizeof(T) == 4;
     T scale = (T)1;
     if constexpr (kFixed) scale = spread_scale(bin_start, d, z, K, order, ph.wmax, flag, &smax, tid, BLOCK);
@@ -192,7 +213,7 @@ __global__ void __launch_bounds__(BLOCK)
         const int G = px.group, lane = tid % G;
         for (int p = tid / G; p < np; p += BLOCK / G) {
             const int base = p * zp;
-            fft_line<C, 0>(S, base, 1, px, tw, lane);
+            fft_line<C, 0>(S, base, 1, px, twl, lane);
             C ra[kPairItems], rb[kPairItems];
 #pragma unroll
             for (int u = 0; u < kPairItems; ++u) {
@@ -217,27 +238,88 @@ __global__ void __launch_bounds__(BLOCK)
         }
     }
     __syncthreads();
-    fft_lines<C, 0>(S, LineMap{hx, hx, 1, 0, hx}, py, tw, tid, BLOCK);
+    fft_lines<C, 0>(S, LineMap{hx, hx, 1, 0, hx}, py, twl, tid, BLOCK);
     __syncthreads();
     C* dst = spec + ((long long)K * d.mz + z) * d.hplane;
     for (int i = tid; i < my * hx; i += BLOCK) dst[i] = S[i];
 }
 
-// Inverse: for a = x, y, z build the half spectrum of d_a phi_K on plane z
+// Contribution of gradient plane z (component a, species K, held in LDS in the
+// row-pair layout) to the non-bonded force of every bead whose stencil reaches
+// the plane: the beads of the P slabs z-P+1 .. z.  A bead of slab z - c gets
+//   fpart[a][c][j] = -w_z[c] sum_{b,a'} w_y[b] w_x[a'] d_a phi(g0y + b, g0x + a'),
+// so that its force component a is the sum of fpart[a][0 .. P-1][j].
+template <typename T, int P>
+__device__ void push_plane(const T* __restrict__ Sr, const uint4* __restrict__ pos,
+                           const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims& d,
+                           int z, int K, int a, long long n, T* __restrict__ fpart, int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        T* out = fpart + ((long long)a * P + c) * n;
+        constexpr int U = 4;  // beads in flight per thread
+        for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
+            uint4 qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                if (j >= j1) break;
+                const uint4 q = qv[u];
+                int gx, gy, gz;
+                T wx[P], wy[P], wz[P];
+                assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
+                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                T acc = 0;
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    int y = gy + b;
+                    if (y >= d.my) y -= d.my;
+                    const T* row = Sr + 4 * (y >> 1) * d.hx + (y & 1);
+                    T ra = 0;
+#pragma unroll
+                    for (int a2 = 0; a2 < P; ++a2) {
+                        int x = gx + a2;
+                        if (x >= d.mx) x -= d.mx;
+                        ra += wx[a2] * row[2 * x];
+                    }
+                    acc += wy[b] * ra;
+                }
+                out[j] = -wz[c] * acc;
+            }
+        }
+    }
+}
+
+// Inverse (one workgroup per plane z, species K and axis a = x, y, z): build
+// the half spectrum of d_a phi_K on plane z
 // (pitch hx), inverse FFT along y, then complex-to-real along x with rows 2p
 // and 2p+1 carried as the real and imaginary parts of one complex row, packed
-// in place at complex offset p * 2hx by the lanes that then transform it.
+// in place at complex offset p * 2hx by the lanes that then transform it; the
+// finished plane d_a phi_K(z) is interpolated onto the beads that reach it.
 template <typename T, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ grad, Dims d,
-                                                  FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph) {
+__global__ void __launch_bounds__(BLOCK)
+    k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
+             const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
+             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n, int order) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
-    const int z = blockIdx.x, K = blockIdx.y;
+    const int z = blockIdx.x, K = blockIdx.y, a = blockIdx.z;
     const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
-    for (int a = 0; a < 3; ++a) {
+    const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
+    {
         const C* src = zout + ((long long)(a < 2 ? K : 2 + K) * d.mz + z) * d.hplane;
         for (int i = tid; i < my * hx; i += BLOCK) {
             const int ky = i / hx, kx = i - ky * hx;
@@ -253,7 +335,7 @@ __global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zo
             S[i] = v;
         }
         __syncthreads();
-        fft_lines<C, 1>(S, LineMap{hx, hx, 1, 0, hx}, py, tw, tid, BLOCK);
+        fft_lines<C, 1>(S, LineMap{hx, hx, 1, 0, hx}, py, twl, tid, BLOCK);
         __syncthreads();
         {
             const int G = px.group, lane = tid % G;
@@ -286,18 +368,20 @@ __global__ void __launch_bounds__(BLOCK) k_xy_c2r(const cplx<T>* __restrict__ zo
                     if (x < mx) S[base + x] = rz[u];
                 }
                 wave_sync();
-                fft_line<C, 1>(S, base, 1, px, tw, lane);
+                fft_line<C, 1>(S, base, 1, px, twl, lane);
             }
         }
         __syncthreads();
-        T* dst = grad + (((long long)K * 3 + a) * d.mz + z) * (long long)my * mx;
-        for (int i = tid; i < np * mx; i += BLOCK) {
-            const int p = i / mx, x = i - p * mx;
-            const C v = S[p * zp + x];
-            dst[(2 * p) * mx + x] = v.x;
-            if (2 * p + 1 < my) dst[(2 * p + 1) * mx + x] = v.y;
+        const T* Sr = reinterpret_cast<const T*>(smem);
+        switch (order) {
+            case 1: push_plane<T, 1>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            case 2: push_plane<T, 2>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            case 3: push_plane<T, 3>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            case 4: push_plane<T, 4>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            case 5: push_plane<T, 5>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            case 6: push_plane<T, 6>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
+            default: push_plane<T, 7>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
         }
-        __syncthreads();
     }
 }
 
@@ -324,6 +408,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     const int mz = d.mz, my = d.my, mx = d.mx, hx = d.hx;
     const int cbp = cb + 1;
     C* b1 = b0 + 2 * mz * cbp;
+    const C* twl = stage_twiddles(b0 + 4 * mz * cbp, tw, d, tid, BLOCK);
     const long long cn = d.hplane;
     const long long c0 = (long long)blockIdx.x * cb;
     for (int i = tid; i < 2 * mz * cb; i += BLOCK) {
@@ -334,7 +419,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
         b0[(K * mz + z) * cbp + j] = c < cn ? spec[((long long)K * mz + z) * cn + c] : C{0, 0};
     }
     __syncthreads();
-    fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp}, pz, tw, tid, BLOCK);
+    fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp}, pz, twl, tid, BLOCK);
     __syncthreads();
 
     double acc[5] = {0, 0, 0, 0, 0};
@@ -391,7 +476,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     }
     if (ENERGY_ONLY) return;
     __syncthreads();
-    fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp}, pz, tw, tid, BLOCK);
+    fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp}, pz, twl, tid, BLOCK);
     __syncthreads();
     for (int i = tid; i < 4 * mz * cb; i += BLOCK) {
         const int q = i / (mz * cb);
@@ -404,173 +489,112 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 
 // ------------------------------------------------------------ gather + bonds + update
 
-// One tile: species K, beads whose stencil starts in rows [y0, y0 + ty) (all
-// x) and in the slabs s0 .. s0 + zc - 1.  For slab s the gradient fields of
-// planes s .. s+P-1, rows y0 .. y0+ty+P-2 (all x), are staged in LDS as a
-// ring of P planes; each bead then reads its P^3 stencil from LDS.
-// MODE 0: Euler-Maruyama step, the moved bead goes to pout[j]; the exact
-//         integer sum of all displacements becomes, in the last block, the new
-//         global shift qs_out (centre-of-mass correction).
+// Beads in sorted order (grid-stride): F = sum of the P plane partials of each
+// component (non-bonded, ik route) + the stored bond force.
+// MODE 0: Euler-Maruyama step, the moved bead goes to pout[j].  Each block
+//         writes the exact integer sum of its displacements to com_part; the
+//         last block to finish adds them up in block order and turns the mean
+//         into the new global shift qs_out (centre-of-mass correction).
 // MODE 1: forces only, written to out[abi id] ([n][3], float or double).
-template <typename T, int P, int MODE>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(256)
-    k_gather_tile(const uint4* __restrict__ pin, uint4* __restrict__ pout, const uint32_t* __restrict__ bin_start,
-                  const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out, long long n, Dims d,
-                  const T* __restrict__ grad, const int32_t* __restrict__ nbr, int deg, Phys ph, uint64_t step,
-                  void* out, int out_dtype, unsigned parts, unsigned long long* __restrict__ com_acc,
-                  uint32_t* __restrict__ flag, int ty, int zc) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* ring = reinterpret_cast<T*>(smem);  // [P][3][ry][mx]
+    k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
+             const T* __restrict__ fpart, int P, const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out,
+             long long n, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts,
+             long long* __restrict__ com_part, unsigned int* __restrict__ ticket, uint32_t* __restrict__ flag) {
     __shared__ long long red[3 * 4];
+    __shared__ bool last;
     const int tid = threadIdx.x;
-    const int mx = d.mx, my = d.my, mz = d.mz;
-    const int nty = (my + ty - 1) / ty, nzc = (mz + zc - 1) / zc;
-    int w = blockIdx.x;
-    const int zi = w % nzc;
-    w /= nzc;
-    const int yi = w % nty;
-    const int K = w / nty;
-    const int y0 = yi * ty, y1 = (y0 + ty < my) ? y0 + ty : my;
-    const int s0 = zi * zc, s1 = (s0 + zc < mz) ? s0 + zc : mz;
-    const int ry = ty + P - 1;
-    const long long plane = (long long)my * mx;
-    const T* gK = grad + (long long)K * 3 * d.m;
     const bool need_field = MODE == 0 || (parts & 1u);
-    const uint32_t sh0 = qs_in[0], sh1 = qs_in[1], sh2 = qs_in[2];
-    const T lsx = (T)(ph.lx * kInvTwo32), lsy = (T)(ph.ly * kInvTwo32), lsz = (T)(ph.lz * kInvTwo32);
-    const T k2 = (T)(2.0 * ph.bond_k);
+    const bool need_bond = MODE == 0 || (parts & 2u);
+    long long dsum[3] = {0, 0, 0};
     const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
     const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
-    long long dq_sum[3] = {0, 0, 0};
-
-    for (int s = s0; s < s1; ++s) {
+    for (long long j = blockIdx.x * 256LL + tid; j < n; j += (long long)gridDim.x * 256) {
+        const uint4 q = pin[j];
+        const uint32_t id = q.w >> 1;
+        T f[3] = {0, 0, 0};
+        if (need_bond) {
+            f[0] = fbond[4 * j + 0];
+            f[1] = fbond[4 * j + 1];
+            f[2] = fbond[4 * j + 2];
+        }
         if (need_field) {
-            // planes s .. s+P-1: the first slab loads all, later slabs only the newest
-            const int t_first = (s == s0) ? 0 : P - 1;
-            for (int t = t_first; t < P; ++t) {
-                int z = s + t;
-                if (z >= mz) z -= mz;
-                T* slot = ring + (size_t)((s - s0 + t) % P) * 3 * ry * mx;
-                for (int i = tid; i < 3 * ry * mx; i += 256) {
-                    const int comp = i / (ry * mx);
-                    const int r = (i / mx) % ry;
-                    const int x = i % mx;
-                    int y = y0 + r;
-                    while (y >= my) y -= my;
-                    slot[i] = gK[comp * d.m + z * plane + (long long)y * mx + x];
-                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                T sa = 0;
+                for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
+                f[a] += sa;
             }
-            __syncthreads();
         }
-        const int bb = (K * mz + s) * my;
-        const uint32_t j0 = bin_start[bb + y0], j1 = bin_start[bb + y1];
-        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += 256u) {
-            const uint4 q = pin[j];
-            const uint32_t id = q.w >> 1;
-            T fn[3] = {0, 0, 0}, fb[3] = {0, 0, 0};
-            if (need_field) {
-                int gx, gy, gz;
-                T wx[P], wy[P], wz[P];
-                assignment_weights<T, P>(q.x - sh0, mx, gx, wx);
-                assignment_weights<T, P>(q.y - sh1, my, gy, wy);
-                assignment_weights<T, P>(q.z - sh2, mz, gz, wz);
-                const int r0 = gy - y0;
-                // the bin key guarantees gz == s and y0 <= gy < y1; anything else is a bookkeeping error
-                const bool inside = gz == s && r0 >= 0 && r0 < ty;
-                if (!inside) atomicOr(flag, 8u);
-#pragma unroll 1
-                for (int c = 0; c < (inside ? P : 0); ++c) {
-                    const T* slot = ring + (size_t)((s - s0 + c) % P) * 3 * ry * mx;
-#pragma unroll
-                    for (int b = 0; b < P; ++b) {
-                        const T* row = slot + (r0 + b) * mx;
-                        const T wzy = wz[c] * wy[b];
-#pragma unroll
-                        for (int a = 0; a < P; ++a) {
-                            int x = gx + a;
-                            if (x >= mx) x -= mx;
-                            const T wgt = wzy * wx[a];
-                            fn[0] -= wgt * row[x];
-                            fn[1] -= wgt * row[ry * mx + x];
-                            fn[2] -= wgt * row[2 * ry * mx + x];
-                        }
-                    }
-                }
-            }
-            if (MODE == 0 || (parts & 2u)) {
-                for (int e = 0; e < deg; ++e) {
-                    const int p = nbr[(long long)j * deg + e];
-                    if (p < 0) break;
-                    const uint4 qp = pin[p];
-                    fb[0] -= k2 * lsx * (T)fixed_delta(q.x, qp.x);
-                    fb[1] -= k2 * lsy * (T)fixed_delta(q.y, qp.y);
-                    fb[2] -= k2 * lsz * (T)fixed_delta(q.z, qp.z);
-                }
-            }
-            if (MODE == 1) {
-                T f[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) f[a] = ((parts & 1u) ? fn[a] : (T)0) + ((parts & 2u) ? fb[a] : (T)0);
-                if (out_dtype == 0) {
-                    float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
-                    o[0] = (float)f[0];
-                    o[1] = (float)f[1];
-                    o[2] = (float)f[2];
-                } else {
-                    double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
-                    o[0] = (double)f[0];
-                    o[1] = (double)f[1];
-                    o[2] = (double)f[2];
-                }
+        if (MODE == 1) {
+            if (out_dtype == 0) {
+                float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
+                o[0] = (float)f[0];
+                o[1] = (float)f[1];
+                o[2] = (float)f[2];
             } else {
-                T xi[3];
-                Noise<T>::draw(id, step, ph.seed, xi);
-                long long dq[3] = {0, 0, 0};
-                bool bad = false;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T disp = mob * (fn[a] + fb[a]) + amp * xi[a];
-                    const double sd = (double)disp * inv_l[a];
-                    if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
-                    else dq[a] = llrint(sd);
-                }
-                if (bad) {
-                    atomicOr(flag, 1u);
-                    dq[0] = dq[1] = dq[2] = 0;
-                }
-                pout[j] = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
-                dq_sum[0] += dq[0];
-                dq_sum[1] += dq[1];
-                dq_sum[2] += dq[2];
+                double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
+                o[0] = (double)f[0];
+                o[1] = (double)f[1];
+                o[2] = (double)f[2];
             }
+        } else {
+            T xi[3];
+            Noise<T>::draw(id, step, ph.seed, xi);
+            long long dq[3] = {0, 0, 0};
+            bool bad = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const T disp = mob * f[a] + amp * xi[a];
+                const double sd = (double)disp * inv_l[a];
+                if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
+                else dq[a] = llrint(sd);
+            }
+            if (bad) {
+                atomicOr(flag, 1u);
+                dq[0] = dq[1] = dq[2] = 0;
+            }
+            pout[j] = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
+            dsum[0] += dq[0];
+            dsum[1] += dq[1];
+            dsum[2] += dq[2];
         }
-        if (need_field) __syncthreads();  // the ring slot of plane s is reloaded next
     }
     if (MODE == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            long long v = wave_sum(dq_sum[a]);
+            long long v = wave_sum(dsum[a]);
             if ((tid & 63) == 0) red[a * 4 + (tid >> 6)] = v;
         }
         __syncthreads();
         if (tid == 0) {
-            for (int a = 0; a < 3; ++a) {
-                const long long sa = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
-                atomicAdd(&com_acc[a], (unsigned long long)sa);
-            }
+            for (int a = 0; a < 3; ++a)
+                com_part[3 * blockIdx.x + a] = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
             __threadfence();
-            const unsigned long long ticket = atomicAdd(&com_acc[3], 1ull);
-            if (ticket == (unsigned long long)gridDim.x - 1) {
-                __threadfence();
-                const uint32_t shv[3] = {sh0, sh1, sh2};
+            last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            long long v[3] = {0, 0, 0};
+            for (int b = tid; b < (int)gridDim.x; b += 256)
+                for (int a = 0; a < 3; ++a) v[a] += __atomic_load_n(&com_part[3 * b + a], __ATOMIC_RELAXED);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                long long w = wave_sum(v[a]);
+                if ((tid & 63) == 0) red[a * 4 + (tid >> 6)] = w;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const uint32_t shv[3] = {qs_in[0], qs_in[1], qs_in[2]};
                 for (int a = 0; a < 3; ++a) {
-                    const long long tot = (long long)atomicAdd(&com_acc[a], 0ull);
+                    const long long tot = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
                     const long long shift = ph.com_correct && n > 0 ? llround((double)tot / (double)n) : 0;
                     qs_out[a] = shv[a] + (uint32_t)shift;
-                    com_acc[a] = 0ull;
                 }
                 qs_out[3] = 0u;
-                com_acc[3] = 0ull;
+                *ticket = 0u;
             }
         }
     }
@@ -599,8 +623,8 @@ __device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t*
 // Bin key and in-bin rank of every bead of pos_tmp, with the global shift of
 // the step just taken, so that every key is the bead's exact stencil start.
 __global__ void __launch_bounds__(256) k_keys(const uint4* __restrict__ pos_tmp, const uint32_t* __restrict__ qs,
-                                              uint32_t* __restrict__ key, uint32_t* __restrict__ rank,
-                                              uint32_t* __restrict__ counts, long long n, Dims d, int P) {
+                                              uint2* __restrict__ kr, uint32_t* __restrict__ counts, long long n,
+                                              Dims d, int P) {
     const long long j = blockIdx.x * 256LL + threadIdx.x;
     const bool active = j < n;
     uint32_t kb = 0xffffffffu;
@@ -609,10 +633,7 @@ __global__ void __launch_bounds__(256) k_keys(const uint4* __restrict__ pos_tmp,
         kb = bin_key(q.y - qs[1], q.z - qs[2], q.w & 1u, d, P);
     }
     const uint32_t r = bin_rank(kb, active, counts);
-    if (active) {
-        key[j] = kb;
-        rank[j] = r;
-    }
+    if (active) kr[j] = uint2{kb, r};
 }
 
 // One workgroup: bin_start = exclusive prefix sum of counts (bin_start[nbins]
@@ -665,21 +686,41 @@ __global__ void __launch_bounds__(1024) k_bin_scan(uint32_t* __restrict__ counts
     if (tid == 0) bin_start[nbins] = carry;
 }
 
-// Move every bead of the previous order to its sorted slot and translate its
-// bond partners (slots of the previous order) into sorted slots.
-__global__ void __launch_bounds__(256) k_scatter(const uint4* __restrict__ pos_tmp, const uint32_t* __restrict__ key,
-                                                 const uint32_t* __restrict__ rank,
-                                                 const uint32_t* __restrict__ bin_start,
-                                                 const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos,
-                                                 int32_t* __restrict__ nbr_dst, long long n, int deg) {
+// Move every bead of the previous order to its sorted slot, translate its
+// bond partners (slots of the previous order) into sorted slots, and store
+// its harmonic bond force F = -2 k_b sum_partners d (d the minimum-image bond
+// vector, shift-free in fixed point) as {Fx, Fy, Fz, 0}.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
+              const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
+              T* __restrict__ fbond, long long n, int deg, Phys ph) {
     const long long j = blockIdx.x * 256LL + threadIdx.x;
     if (j >= n) return;
-    const long long nw = (long long)bin_start[key[j]] + rank[j];
-    pos[nw] = pos_tmp[j];
+    const uint2 kj = kr[j];
+    const long long nw = (long long)bin_start[kj.x] + kj.y;
+    const uint4 q = pos_tmp[j];
+    pos[nw] = q;
+    const T c = (T)(-2.0 * ph.bond_k);
+    const T sx = (T)(ph.lx * kInvTwo32), sy = (T)(ph.ly * kInvTwo32), sz = (T)(ph.lz * kInvTwo32);
+    T f[3] = {0, 0, 0};
     for (int b = 0; b < deg; ++b) {
         const int p = nbr_src[j * deg + b];
-        nbr_dst[nw * deg + b] = p < 0 ? -1 : (int32_t)(bin_start[key[p]] + rank[p]);
+        int32_t np_ = -1;
+        if (p >= 0) {
+            const uint2 kp = kr[p];
+            np_ = (int32_t)(bin_start[kp.x] + kp.y);
+            const uint4 qp = pos_tmp[p];
+            f[0] += c * sx * (T)fixed_delta(q.x, qp.x);
+            f[1] += c * sy * (T)fixed_delta(q.y, qp.y);
+            f[2] += c * sz * (T)fixed_delta(q.z, qp.z);
+        }
+        nbr_dst[nw * deg + b] = np_;
     }
+    fbond[4 * nw + 0] = f[0];
+    fbond[4 * nw + 1] = f[1];
+    fbond[4 * nw + 2] = f[2];
+    fbond[4 * nw + 3] = (T)0;
 }
 
 // Bond energy and virial: E = k_b sum |d|^2, W_aa = -2 k_b sum d_a^2 (each
@@ -743,7 +784,7 @@ __global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict_
 template <typename TI>
 __global__ void __launch_bounds__(256)
     k_place(const TI* __restrict__ xyz, const uint32_t* __restrict__ types, uint4* __restrict__ pos_tmp,
-            uint32_t* __restrict__ key_out, uint32_t* __restrict__ rank_out, uint32_t* __restrict__ counts,
+            uint2* __restrict__ kr, uint32_t* __restrict__ counts,
             uint32_t* __restrict__ qs, long long n, Dims d, int P, uint32_t* __restrict__ flag) {
     const long long i = blockIdx.x * 256LL + threadIdx.x;
     if (i == 0) qs[0] = qs[1] = qs[2] = qs[3] = 0u;
@@ -764,8 +805,7 @@ __global__ void __launch_bounds__(256)
     const uint32_t K = types[i];
     pos_tmp[i] = uint4{q[0], q[1], q[2], ((uint32_t)i << 1) | K};
     const uint32_t kb = bin_key(q[1], q[2], K, d, P);
-    key_out[i] = kb;
-    rank_out[i] = atomicAdd(&counts[kb], 1u);
+    kr[i] = uint2{kb, atomicAdd(&counts[kb], 1u)};
 }
 
 template <typename TO>
@@ -794,12 +834,12 @@ static inline unsigned blocks_for(long long n, int per) { return (unsigned)((n +
 
 size_t plane_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * (size_t)L.d.npair * (size_t)(2 * L.d.hx);
+    return c * ((size_t)L.d.npair * (size_t)(2 * L.d.hx) + (size_t)(L.d.mx + L.d.my + L.d.mz));
 }
 
 size_t z_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * 4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1);
+    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1) + (size_t)(L.d.mx + L.d.my + L.d.mz));
 }
 
 template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceState& S) {
@@ -808,8 +848,9 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
                        L.order, S.flag);
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL((k_xy_c2r<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
-                       (const cplx<T>*)S.zout, (T*)S.grad, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph);
+    hipLaunchKernelGGL((k_xy_c2r<T, B>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L), L.stream,
+                       (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph, S.pos,
+                       S.bin_start, S.qshift, S.n, L.order);
 }
 
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
@@ -853,47 +894,30 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
     return hipGetLastError();
 }
 
-size_t gather_lds_bytes(const Launch& L, int ty) {
-    const size_t r = L.precision == 0 ? sizeof(float) : sizeof(double);
-    return r * (size_t)L.order * 3 * (size_t)(ty + L.order - 1) * (size_t)L.d.mx;
-}
-
-template <typename T, int P, int MODE>
-static void gather_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
-    const int nty = (L.d.my + L.gather_ty - 1) / L.gather_ty, nzc = (L.d.mz + L.gather_zc - 1) / L.gather_zc;
-    hipLaunchKernelGGL((k_gather_tile<T, P, MODE>), dim3(2 * nty * nzc), dim3(256), gather_lds_bytes(L, L.gather_ty),
-                       L.stream, S.pos, S.pos_tmp, S.bin_start, S.qshift, S.qshift_next, S.n, L.d, (const T*)S.grad,
-                       S.nbr, S.deg, L.ph, step, out, out_dtype, parts, S.com_acc, S.flag, L.gather_ty, L.gather_zc);
-}
-
 template <typename T, int MODE>
-static void gather_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int od, unsigned parts) {
-    switch (L.order) {
-        case 1: gather_p<T, 1, MODE>(L, S, step, out, od, parts); break;
-        case 2: gather_p<T, 2, MODE>(L, S, step, out, od, parts); break;
-        case 3: gather_p<T, 3, MODE>(L, S, step, out, od, parts); break;
-        case 4: gather_p<T, 4, MODE>(L, S, step, out, od, parts); break;
-        case 5: gather_p<T, 5, MODE>(L, S, step, out, od, parts); break;
-        case 6: gather_p<T, 6, MODE>(L, S, step, out, od, parts); break;
-        default: gather_p<T, 7, MODE>(L, S, step, out, od, parts); break;
-    }
+static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
+    // at least one block: in MODE 0 the last block also carries the shift over
+    const unsigned g = std::min<unsigned>(blocks_for(S.n > 0 ? S.n : 1, 256), (unsigned)kUpdateBlocks);
+    hipLaunchKernelGGL((k_update<T, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
+                       (const T*)S.fpart, L.order, S.qshift, S.qshift_next, S.n, L.ph, step, out, out_dtype, parts,
+                       S.com_part, S.ticket, S.flag);
 }
 
-hipError_t launch_gather(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
+hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts) {
     if (L.precision == 0) {
-        if (mode == 0) gather_t<float, 0>(L, S, step, out, out_dtype, parts);
-        else gather_t<float, 1>(L, S, step, out, out_dtype, parts);
+        if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts);
+        else update_t<float, 1>(L, S, step, out, out_dtype, parts);
     } else {
-        if (mode == 0) gather_t<double, 0>(L, S, step, out, out_dtype, parts);
-        else gather_t<double, 1>(L, S, step, out, out_dtype, parts);
+        if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts);
+        else update_t<double, 1>(L, S, step, out, out_dtype, parts);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_keys(const Launch& L, DeviceState& S) {
     if (S.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.qshift, S.key, S.rank,
+    hipLaunchKernelGGL(k_keys, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.qshift, S.kr,
                        S.counts, S.n, L.d, L.order);
     return hipGetLastError();
 }
@@ -905,8 +929,12 @@ hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
 
 hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src) {
     if (S.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.key, S.rank,
-                       S.bin_start, nbr_src, S.pos, S.nbr_old, S.n, S.deg);
+    if (L.precision == 0)
+        hipLaunchKernelGGL(k_scatter<float>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
+                           S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph);
+    else
+        hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
+                           S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph);
     return hipGetLastError();
 }
 
@@ -926,10 +954,10 @@ hipError_t launch_place(const Launch& L, DeviceState& S, const void* xyz, int dt
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     if (dtype == 0)
         hipLaunchKernelGGL(k_place<float>, dim3(g), dim3(256), 0, L.stream, (const float*)xyz, S.types_abi, S.pos_tmp,
-                           S.key, S.rank, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
+                           S.kr, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
     else
         hipLaunchKernelGGL(k_place<double>, dim3(g), dim3(256), 0, L.stream, (const double*)xyz, S.types_abi,
-                           S.pos_tmp, S.key, S.rank, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
+                           S.pos_tmp, S.kr, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
     return hipGetLastError();
 }
 
@@ -966,40 +994,18 @@ template <typename T> static hipError_t attr_z(size_t lds) {
     return hipFuncSetAttribute((const void*)k_z_kmul<T, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename T, int P> static hipError_t attr_gather_p(size_t lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gather_tile<T, P, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_gather_tile<T, P, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
-}
-
-template <typename T> static hipError_t attr_gather(int P, size_t lds) {
-    switch (P) {
-        case 1: return attr_gather_p<T, 1>(lds);
-        case 2: return attr_gather_p<T, 2>(lds);
-        case 3: return attr_gather_p<T, 3>(lds);
-        case 4: return attr_gather_p<T, 4>(lds);
-        case 5: return attr_gather_p<T, 5>(lds);
-        case 6: return attr_gather_p<T, 6>(lds);
-        default: return attr_gather_p<T, 7>(lds);
-    }
-}
-
 hipError_t configure_kernel_attributes(const Launch& L) {
-    const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L), lg = gather_lds_bytes(L, L.gather_ty);
+    const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L);
     hipError_t e = hipSuccess;
     if (L.precision == 0) {
         if (L.plane_block == 256) e = attr_plane<float, 256>(lp);
         else if (L.plane_block == 512) e = attr_plane<float, 512>(lp);
         else e = attr_plane<float, 1024>(lp);
         if (e == hipSuccess) e = attr_z<float>(lz);
-        if (e == hipSuccess) e = attr_gather<float>(L.order, lg);
     } else {
         if (L.plane_block == 256) e = attr_plane<double, 256>(lp);
         else e = attr_plane<double, 512>(lp);
         if (e == hipSuccess) e = attr_z<double>(lz);
-        if (e == hipSuccess) e = attr_gather<double>(L.order, lg);
     }
     return e;
 }
