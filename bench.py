@@ -46,8 +46,7 @@ def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
         "spread_fft_xy": n * bead + 2 * hs * c,
         "fft_z_kmul": 2 * hs * c + 4 * hs * c,
         "fft_xy_c2r_gather": 4 * hs * c + n * bead + 3 * P * n * r,
-        "update_em": n * bead + n * 4 * r + 3 * P * n * r + n * bead,
-        "bin_keys": n * bead + n * 8,
+        "update_em_keys": n * bead + n * 4 * r + 3 * P * n * r + n * bead + n * 8,
         "bin_scan": 4 * nbins * 3 + 4,
         "bin_scatter_bonds": n * (bead + 8 + 4 * deg) + n * (bead + 4 * deg + 4 * r),
     }

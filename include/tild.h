@@ -93,7 +93,7 @@ extern "C" {
 #define TILD_PART_TOTAL 3u
 
 /* Per-kernel timing slots reported by tild_profile_steps. */
-#define TILD_NUM_KERNELS 7
+#define TILD_NUM_KERNELS 6
 
 typedef struct tild_ctx tild_ctx;
 

@@ -20,7 +20,7 @@ TILD_COM_CORRECT = 1
 TILD_PART_NONBONDED = 1
 TILD_PART_BOND = 2
 TILD_PART_TOTAL = 3
-TILD_NUM_KERNELS = 7
+TILD_NUM_KERNELS = 6
 
 EXPORTS = [
     "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",

@@ -20,10 +20,10 @@ namespace {
 
 thread_local std::string g_create_error;
 
-enum Slot { kSpreadXy = 0, kZKmul, kXyC2r, kGather, kKeys, kBinScan, kScatter, kNumSlots };
+enum Slot { kSpreadXy = 0, kZKmul, kXyC2r, kUpdate, kBinScan, kScatter, kNumSlots };
 static_assert(kNumSlots == TILD_NUM_KERNELS, "slot table");
-const char* kSlotNames[kNumSlots] = {"spread_fft_xy", "fft_z_kmul", "fft_xy_c2r_gather", "update_em",
-                                     "bin_keys",      "bin_scan",   "bin_scatter_bonds"};
+const char* kSlotNames[kNumSlots] = {"spread_fft_xy", "fft_z_kmul", "fft_xy_c2r_gather",
+                                     "update_em_keys", "bin_scan",  "bin_scatter_bonds"};
 
 // Uncentred cardinal B-spline M_k(s) (support [0, k)), by its recursion.
 double uncentred_bspline(int k, double s) {
@@ -158,18 +158,37 @@ bool choose_shapes(Launch& L, std::string& why) {
         return false;
     }
     const long long need = std::max((long long)d.npair * L.px.group, (long long)d.hx * L.py.group);
+    // measured on MI355X at 128^2 planes: the fused spread prefers 1024 threads, the inverse pass 512
     L.plane_block = need <= 256 ? 256 : 512;
+    L.spread_block = need <= 256 ? 256 : (need <= 512 || L.precision == 1 ? 512 : 1024);
     if (plane_lds_bytes(L) > lds_max) {
         why = "grid plane does not fit one workgroup's LDS in this precision";
         return false;
     }
-    L.z_block = 256;
-    const size_t zbudget = L.precision == 0 ? 80 * 1024 : 160 * 1024;
-    for (L.z_cols = 16; L.z_cols > 1 && z_lds_bytes(L) > zbudget; L.z_cols /= 2) {
-    }
-    if (z_lds_bytes(L) > lds_max) {
-        why = "z columns do not fit LDS";
-        return false;
+    // z pass: columns per workgroup chosen to minimise (rounds of resident workgroups) x (columns each),
+    // with at most two 512-thread workgroups per CU (registers) and the LDS they need
+    L.z_block = kZBlock;
+    {
+        int best_cb = 0;
+        long long best = 0;
+        for (int cb = 1; cb <= 32; ++cb) {
+            L.z_cols = cb;
+            const size_t lds = z_lds_bytes(L);
+            if (lds > lds_max) break;
+            const long long per_cu = std::min<long long>(2, (long long)(lds_max / lds));
+            const long long slots = per_cu * L.cu_count;
+            const long long nblk = (d.hplane + cb - 1) / cb;
+            const long long cost = ((nblk + slots - 1) / slots) * cb;
+            if (best_cb == 0 || cost < best || (cost == best && cb > best_cb)) {
+                best = cost;
+                best_cb = cb;
+            }
+        }
+        if (best_cb == 0) {
+            why = "z columns do not fit LDS";
+            return false;
+        }
+        L.z_cols = best_cb;
     }
     L.n_zblocks = (int)((d.hplane + L.z_cols - 1) / L.z_cols);
     return true;
@@ -217,7 +236,10 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
             if (ev && e == hipSuccess) e = hipEventRecord((*ev)[(size_t)(s * kNumSlots + slot) * 2 + which], c->L.stream);
         };
         mark(kSpreadXy, 0);
+        c->S.noise_step = 1;
+        c->S.step = c->step;
         if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);
+        c->S.noise_step = 0;
         mark(kSpreadXy, 1);
         mark(kZKmul, 0);
         if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);
@@ -225,13 +247,10 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         mark(kXyC2r, 0);
         if (e == hipSuccess) e = launch_xy_c2r(c->L, c->S);
         mark(kXyC2r, 1);
-        mark(kGather, 0);
+        mark(kUpdate, 0);
         if (e == hipSuccess) e = launch_update(c->L, c->S, 0, (uint64_t)c->step, nullptr, 0, 0);
-        mark(kGather, 1);
-        if (e == hipSuccess) std::swap(c->S.qshift, c->S.qshift_next);  // keys use the new shift
-        mark(kKeys, 0);
-        if (e == hipSuccess) e = launch_keys(c->L, c->S);
-        mark(kKeys, 1);
+        mark(kUpdate, 1);
+        if (e == hipSuccess) std::swap(c->S.qshift, c->S.qshift_next);
         mark(kBinScan, 0);
         if (e == hipSuccess) e = launch_bin_scan(c->L, c->S);
         mark(kBinScan, 1);
@@ -337,6 +356,13 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
         delete c;
         return TILD_EINVAL;
     }
+    L.cu_count = 256;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            L.cu_count = cus;
+    }
     if (!choose_shapes(L, why)) {
         g_create_error = why;
         delete c;
@@ -387,8 +413,9 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     A((void**)&S.pos_tmp, npos * sizeof(uint4));
     A((void**)&S.kr, npos * sizeof(uint2));
     A(&S.fbond, npos * 4 * real_sz);
-    A((void**)&S.counts, (size_t)S.nbins * sizeof(uint32_t));
-    A((void**)&S.bin_start, ((size_t)S.nbins + 1) * sizeof(uint32_t));
+    const size_t nbins_pad = ((size_t)S.nbins + 32) / 32 * 32 + 32;  // vector scan reads whole 32-bin groups
+    A((void**)&S.counts, nbins_pad * sizeof(uint32_t));
+    A((void**)&S.bin_start, nbins_pad * sizeof(uint32_t));
     A((void**)&S.nbr, ntab * sizeof(int32_t));
     A((void**)&S.nbr_old, ntab * sizeof(int32_t));
     A((void**)&S.nbr_abi, ntab * sizeof(int32_t));
@@ -401,8 +428,7 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
     A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
     A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(double));
-    A((void**)&S.com_part, (size_t)kUpdateBlocks * 3 * sizeof(long long));
-    A((void**)&S.ticket, sizeof(unsigned int));
+    A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(double));
     A((void**)&S.flag, sizeof(uint32_t));
     A((void**)&S.eout, 8 * sizeof(double));
     A(&c->staging, npos * 3 * sizeof(double));
@@ -424,20 +450,19 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     std::vector<float> twf(tw.begin(), tw.end());
     std::vector<uint32_t> types_u((size_t)npos, 0u);
     for (int64_t i = 0; i < n_beads; ++i) types_u[(size_t)i] = (uint32_t)types[i];
-    std::vector<uint32_t> zero_bins((size_t)S.nbins + 1, 0u);
+    std::vector<uint32_t> zero_bins(((size_t)S.nbins + 32) / 32 * 32 + 32, 0u);
     const uint32_t zeros4[4] = {0, 0, 0, 0};
     auto H2D = [&](void* dst, const void* src, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
     };
     H2D(S.types_abi, types_u.data(), npos * sizeof(uint32_t));
     H2D(S.nbr_abi, nbr_tab.data(), nbr_tab.size() * sizeof(int32_t));
-    H2D(S.counts, zero_bins.data(), (size_t)S.nbins * sizeof(uint32_t));
-    H2D(S.bin_start, zero_bins.data(), ((size_t)S.nbins + 1) * sizeof(uint32_t));
+    H2D(S.counts, zero_bins.data(), zero_bins.size() * sizeof(uint32_t));
+    H2D(S.bin_start, zero_bins.data(), zero_bins.size() * sizeof(uint32_t));
     H2D(S.qshift, zeros4, sizeof(zeros4));
     H2D(S.qshift_next, zeros4, sizeof(zeros4));
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
     else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
-    H2D(S.ticket, zeros4, sizeof(unsigned int));
     H2D(S.flag, zeros4, sizeof(uint32_t));
     if (e == hipSuccess) e = configure_kernel_attributes(L);
     if (e != hipSuccess) {

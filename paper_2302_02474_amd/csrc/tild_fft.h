@@ -143,12 +143,23 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * bpl) * es];
             if (s > 1) {
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    C w = tw[k * r * tstride];
-                    if (INV) w.y = -w.y;
-                    v[b][r] = cmul(v[b][r], w);
+                // w^r for r < R from two table reads (w, w^2) and at most three products
+                C w[R];
+                w[1] = tw[k * tstride];
+                if (INV) w[1].y = -w[1].y;
+                if constexpr (R > 2) {
+                    w[2] = tw[2 * k * tstride];
+                    if (INV) w[2].y = -w[2].y;
                 }
+                if constexpr (R > 3) w[3] = cmul(w[1], w[2]);
+                if constexpr (R > 4) w[4] = cmul(w[2], w[2]);
+                if constexpr (R > 5) {
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                }
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[r]);
             }
             ob[b] = base + ((j - k) * R + k) * es;
         }

@@ -11,6 +11,7 @@
 namespace tild {
 
 constexpr int kUpdateBlocks = 1024;  // workgroups of the (grid-stride) update kernel
+constexpr int kZBlock = 512;         // threads per workgroup of the z pass
 
 // Physical constants of one context, passed by value to kernels.
 struct Phys {
@@ -36,8 +37,8 @@ struct Phys {
 // ranges.  A bead is a uint4 {qx, qy, qz, (abi_id << 1) | species}; qx.. are
 // 32-bit fixed-point box fractions; the true coordinate is
 // (q - qshift) * L / 2^32.  Every step the update kernel writes the new
-// positions in the old order, a key pass forms each bead's new key and its
-// rank within the key's bin, a scan turns bin counts into bin starts, and a
+// positions in the old order together with each bead's new key and its rank
+// within the key's bin, a scan turns bin counts into bin starts, and a
 // scatter moves beads into the new order, re-maps bond partner slots and
 // stores each bead's bond force.
 struct DeviceState {
@@ -59,13 +60,14 @@ struct DeviceState {
     void* tw;             // complex twiddle tables
     double* epart;        // [n_zblocks][5] energy partials of the k-space pass
     double* bpart;        // [n_bblocks][4] bond energy / virial partials
-    long long* com_part;  // [kUpdateBlocks][3] per-block integer displacement sums of a step
-    unsigned int* ticket; // [1] blocks of the update kernel finished (reset by the last one)
+    double* noise_part;   // [2 mz][3] per-plane sums of the Gaussian increments of the step being taken
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
     double* eout;         // [8] reduced energies
     long long n;
     long long n_a, n_b;
     int deg;              // bond slots per bead (maximum degree)
+    int noise_step;       // the spread also sums the noise of step `step` (set while stepping)
+    long long step;       // step index of the noise the spread sums
     int nbins;            // 2 * mz * my
 };
 
@@ -75,11 +77,13 @@ struct Launch {
     int order;       // P
     Dims d;
     FftPlan px, py, pz;
-    int plane_block;  // threads per workgroup of the plane passes
+    int plane_block;  // threads per workgroup of the inverse plane pass
+    int spread_block; // threads per workgroup of the fused spread + forward plane pass
     int z_cols;       // columns per workgroup of the z pass
     int z_block;
     int n_zblocks;
     int n_bblocks;
+    int cu_count;     // compute units of the device
     Phys ph;
 };
 
@@ -87,12 +91,10 @@ struct Launch {
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S);
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only);
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S);
-// mode 0: Euler-Maruyama step (writes pos_tmp and qshift_next);
+// mode 0: Euler-Maruyama step (writes pos_tmp, kr, counts and qshift_next);
 // mode 1: write forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts);
-// key and rank of every bead of pos_tmp (counts incremented)
-hipError_t launch_keys(const Launch& L, DeviceState& S);
 hipError_t launch_bin_scan(const Launch& L, DeviceState& S);
 hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src);
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S);

@@ -11,8 +11,8 @@
 //               in LDS, interpolated onto the beads that reach it with the
 //               same weights (one partial force per bead, plane and axis)
 //   update      F_i = -sum_g W_i(g) grad phi_{s_i}(g) (the sum of its
-//               partials) + bond force, Philox noise, Euler-Maruyama update
-//   keys        each moved bead's bin key and rank
+//               partials) + bond force, Philox noise, Euler-Maruyama update,
+//               each moved bead's bin key and rank
 //   bin_scan    bin counts -> bin starts
 //   scatter     beads and bond partners into the new sorted order
 #include "tild_kernels.h"
@@ -77,10 +77,14 @@ __device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t s
 // contribution rounded to a multiple of 1/scale): integer LDS atomics are
 // order-independent, and far faster than float ones on this hardware.
 // Double precision accumulates doubles.
+//
+// With `noise`, every bead of the plane's own slab (c = 0, so each bead once
+// over the grid) also adds its Gaussian increment of step `step` to nsum.
 template <typename T, int P>
 __device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
                              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims& d,
-                             int z, int K, T scale, int tid, int nthr) {
+                             int z, int K, T scale, bool noise, uint64_t step, uint64_t seed, double nsum[3], int tid,
+                             int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
 #pragma unroll
     for (int c = 0; c < P; ++c) {
@@ -100,6 +104,13 @@ __device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __res
           for (int u = 0; u < U; ++u) {
             if (jb + (uint32_t)(u * nthr) >= j1) break;
             const uint4 q = qv[u];
+            if (c == 0 && noise) {
+                T xi[3];
+                Noise<T>::draw(q.w >> 1, step, seed, xi);
+                nsum[0] += (double)xi[0];
+                nsum[1] += (double)xi[1];
+                nsum[2] += (double)xi[2];
+            }
             int gx, gy, gz;
             T wx[P], wy[P], wz[P];
             assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
@@ -170,10 +181,11 @@ template <typename T, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
-                int order, uint32_t* __restrict__ flag) {
+                int order, uint32_t* __restrict__ flag, int noise, uint64_t step, double* __restrict__ noise_part) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax;
+    __shared__ double nred[3 * (BLOCK / 64)];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     const int z = blockIdx.x, K = blockIdx.y;
@@ -189,16 +201,23 @@ __global__ void __launch_bounds__(BLOCK)
         else S[i] = x < mx ? C{-mean, (2 * p + 1 < my) ? -mean : (T)0} : C{0, 0};
     }
     __syncthreads();
+    double nsum[3] = {0, 0, 0};
     switch (order) {
-        case 1: spread_plane<T, 1>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        case 2: spread_plane<T, 2>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        case 3: spread_plane<T, 3>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        case 4: spread_plane<T, 4>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        case 5: spread_plane<T, 5>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        case 6: spread_plane<T, 6>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
-        default: spread_plane<T, 7>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK); break;
+        case 1: spread_plane<T, 1>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        case 2: spread_plane<T, 2>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        case 3: spread_plane<T, 3>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        case 4: spread_plane<T, 4>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        case 5: spread_plane<T, 5>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        case 6: spread_plane<T, 6>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
+        default: spread_plane<T, 7>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
     }
-    __syncthreads();
+    if (noise) {
+        block_sum<double, 3>(nsum, nred, tid, BLOCK);  // contains the barrier the conversion below needs
+        if (tid == 0)
+            for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
+    } else {
+        __syncthreads();
+    }
     if constexpr (kFixed) {
         const T inv = (T)1 / scale;
         const int32_t* Si = reinterpret_cast<const int32_t*>(smem);
@@ -489,119 +508,6 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 
 // ------------------------------------------------------------ gather + bonds + update
 
-// Beads in sorted order (grid-stride): F = sum of the P plane partials of each
-// component (non-bonded, ik route) + the stored bond force.
-// MODE 0: Euler-Maruyama step, the moved bead goes to pout[j].  Each block
-//         writes the exact integer sum of its displacements to com_part; the
-//         last block to finish adds them up in block order and turns the mean
-//         into the new global shift qs_out (centre-of-mass correction).
-// MODE 1: forces only, written to out[abi id] ([n][3], float or double).
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256)
-    k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
-             const T* __restrict__ fpart, int P, const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out,
-             long long n, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts,
-             long long* __restrict__ com_part, unsigned int* __restrict__ ticket, uint32_t* __restrict__ flag) {
-    __shared__ long long red[3 * 4];
-    __shared__ bool last;
-    const int tid = threadIdx.x;
-    const bool need_field = MODE == 0 || (parts & 1u);
-    const bool need_bond = MODE == 0 || (parts & 2u);
-    long long dsum[3] = {0, 0, 0};
-    const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
-    const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
-    for (long long j = blockIdx.x * 256LL + tid; j < n; j += (long long)gridDim.x * 256) {
-        const uint4 q = pin[j];
-        const uint32_t id = q.w >> 1;
-        T f[3] = {0, 0, 0};
-        if (need_bond) {
-            f[0] = fbond[4 * j + 0];
-            f[1] = fbond[4 * j + 1];
-            f[2] = fbond[4 * j + 2];
-        }
-        if (need_field) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                T sa = 0;
-                for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
-                f[a] += sa;
-            }
-        }
-        if (MODE == 1) {
-            if (out_dtype == 0) {
-                float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
-                o[0] = (float)f[0];
-                o[1] = (float)f[1];
-                o[2] = (float)f[2];
-            } else {
-                double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
-                o[0] = (double)f[0];
-                o[1] = (double)f[1];
-                o[2] = (double)f[2];
-            }
-        } else {
-            T xi[3];
-            Noise<T>::draw(id, step, ph.seed, xi);
-            long long dq[3] = {0, 0, 0};
-            bool bad = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const T disp = mob * f[a] + amp * xi[a];
-                const double sd = (double)disp * inv_l[a];
-                if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
-                else dq[a] = llrint(sd);
-            }
-            if (bad) {
-                atomicOr(flag, 1u);
-                dq[0] = dq[1] = dq[2] = 0;
-            }
-            pout[j] = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
-            dsum[0] += dq[0];
-            dsum[1] += dq[1];
-            dsum[2] += dq[2];
-        }
-    }
-    if (MODE == 0) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            long long v = wave_sum(dsum[a]);
-            if ((tid & 63) == 0) red[a * 4 + (tid >> 6)] = v;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int a = 0; a < 3; ++a)
-                com_part[3 * blockIdx.x + a] = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
-            __threadfence();
-            last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-        }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            long long v[3] = {0, 0, 0};
-            for (int b = tid; b < (int)gridDim.x; b += 256)
-                for (int a = 0; a < 3; ++a) v[a] += __atomic_load_n(&com_part[3 * b + a], __ATOMIC_RELAXED);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                long long w = wave_sum(v[a]);
-                if ((tid & 63) == 0) red[a * 4 + (tid >> 6)] = w;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                const uint32_t shv[3] = {qs_in[0], qs_in[1], qs_in[2]};
-                for (int a = 0; a < 3; ++a) {
-                    const long long tot = red[a * 4] + red[a * 4 + 1] + red[a * 4 + 2] + red[a * 4 + 3];
-                    const long long shift = ph.com_correct && n > 0 ? llround((double)tot / (double)n) : 0;
-                    qs_out[a] = shv[a] + (uint32_t)shift;
-                }
-                qs_out[3] = 0u;
-                *ticket = 0u;
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------ counting sort
-
 // Rank of the calling lane among the active lanes of its wavefront that hold
 // the same key in one run of consecutive lanes; the run's first lane takes
 // the whole run's places in the bin with a single atomic.
@@ -620,66 +526,181 @@ __device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t*
     return base + (uint32_t)(lane - hl);
 }
 
-// Bin key and in-bin rank of every bead of pos_tmp, with the global shift of
-// the step just taken, so that every key is the bead's exact stencil start.
-__global__ void __launch_bounds__(256) k_keys(const uint4* __restrict__ pos_tmp, const uint32_t* __restrict__ qs,
-                                              uint2* __restrict__ kr, uint32_t* __restrict__ counts, long long n,
-                                              Dims d, int P) {
-    const long long j = blockIdx.x * 256LL + threadIdx.x;
-    const bool active = j < n;
-    uint32_t kb = 0xffffffffu;
-    if (active) {
-        const uint4 q = pos_tmp[j];
-        kb = bin_key(q.y - qs[1], q.z - qs[2], q.w & 1u, d, P);
+// Beads in sorted order (grid-stride): F = sum of the P plane partials of each
+// component (non-bonded, ik route) + the stored bond force.
+// MODE 0: Euler-Maruyama step.  The centre-of-mass correction subtracts the
+//         mean displacement; the forces sum to zero exactly (pairwise bonds;
+//         the ik route with the Nyquist derivative zeroed conserves momentum),
+//         so that mean is sqrt(2 kT dt/gamma) times the mean noise, which the
+//         spread pass has already summed per plane (noise_part).  Every block
+//         forms the same integer shift from it, so each moved bead goes to
+//         pout[j] with its exact new bin key and its rank in that bin.
+// MODE 1: forces only, written to out[abi id] ([n][3], float or double).
+template <typename T, int P, int MODE>
+__global__ void __launch_bounds__(256)
+    k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
+             const T* __restrict__ fpart, const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out,
+             long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts,
+             const double* __restrict__ noise_part, int n_noise, uint2* __restrict__ kr,
+             uint32_t* __restrict__ counts, uint32_t* __restrict__ flag) {
+    __shared__ uint32_t shs[3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool need_field = MODE == 0 || (parts & 1u);
+    const bool need_bond = MODE == 0 || (parts & 2u);
+    if (MODE == 0) {
+        const uint32_t sh[3] = {qs_in[0], qs_in[1], qs_in[2]};
+        if (wave == 0) {
+            double v[3] = {0, 0, 0};
+            for (int i = lane; i < n_noise; i += 64)
+                for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
+            const double L[3] = {ph.lx, ph.ly, ph.lz};
+            for (int a = 0; a < 3; ++a) {
+                const double tot = wave_sum(v[a]);
+                long long shift = 0;
+                if (ph.com_correct && n > 0) shift = llround(ph.noise_amp * tot / (double)n * (kTwo32 / L[a]));
+                if (lane == 0) shs[a] = sh[a] + (uint32_t)shift;
+            }
+        }
+        __syncthreads();
+        const uint32_t nsh[3] = {shs[0], shs[1], shs[2]};
+        if (blockIdx.x == 0 && tid == 0) {
+            qs_out[0] = nsh[0];
+            qs_out[1] = nsh[1];
+            qs_out[2] = nsh[2];
+            qs_out[3] = 0u;
+        }
+        const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
+        const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
+        // whole wavefronts step together so that the rank aggregation sees full waves
+        for (long long base = ((long long)blockIdx.x * 4 + wave) * 64; base < n; base += (long long)gridDim.x * 256) {
+            const long long j = base + lane;
+            const bool active = j < n;
+            uint32_t kb = 0xffffffffu;
+            uint4 qn = uint4{0u, 0u, 0u, 0u};
+            if (active) {
+                const uint4 q = pin[j];
+                T f[3] = {fbond[4 * j + 0], fbond[4 * j + 1], fbond[4 * j + 2]};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    T sa = 0;
+#pragma unroll
+                    for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
+                    f[a] += sa;
+                }
+                T xi[3];
+                Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
+                long long dq[3] = {0, 0, 0};
+                bool bad = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T disp = mob * f[a] + amp * xi[a];
+                    const double sd = (double)disp * inv_l[a];
+                    if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
+                    else dq[a] = llrint(sd);
+                }
+                if (bad) {
+                    atomicOr(flag, 1u);
+                    dq[0] = dq[1] = dq[2] = 0;
+                }
+                qn = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
+                pout[j] = qn;
+                kb = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
+            }
+            const uint32_t r = bin_rank(kb, active, counts);
+            if (active) kr[j] = uint2{kb, r};
+        }
+    } else {
+        for (long long j = blockIdx.x * 256LL + tid; j < n; j += (long long)gridDim.x * 256) {
+            const uint4 q = pin[j];
+            const uint32_t id = q.w >> 1;
+            T f[3] = {0, 0, 0};
+            if (need_bond) {
+                f[0] = fbond[4 * j + 0];
+                f[1] = fbond[4 * j + 1];
+                f[2] = fbond[4 * j + 2];
+            }
+            if (need_field) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    T sa = 0;
+#pragma unroll
+                    for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
+                    f[a] += sa;
+                }
+            }
+            if (out_dtype == 0) {
+                float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
+                o[0] = (float)f[0];
+                o[1] = (float)f[1];
+                o[2] = (float)f[2];
+            } else {
+                double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
+                o[0] = (double)f[0];
+                o[1] = (double)f[1];
+                o[2] = (double)f[2];
+            }
+        }
     }
-    const uint32_t r = bin_rank(kb, active, counts);
-    if (active) kr[j] = uint2{kb, r};
 }
 
+// ------------------------------------------------------------ counting sort
+
 // One workgroup: bin_start = exclusive prefix sum of counts (bin_start[nbins]
-// = total); counts are cleared for the next use.  Chunks of 32768 bins are
-// staged in LDS (skewed by one word per 32 against bank conflicts).
+// = total); counts are cleared for the next use.  Each thread owns 32
+// consecutive bins per chunk of 32768 (loaded and stored as eight 16-byte
+// vectors), the block scans the per-thread sums with wavefront shuffles.
+// `counts` and `bin_start` hold at least ceil(nbins / 32) * 32 entries.
 __global__ void __launch_bounds__(1024) k_bin_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ bin_start,
                                                    int nbins) {
     constexpr int CH = 32768;
-    __shared__ uint32_t buf[CH + CH / 32];
     __shared__ uint32_t wsum[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint32_t carry = 0;
     for (int base = 0; base < nbins; base += CH) {
-        const int len = (nbins - base < CH) ? nbins - base : CH;
-        for (int i = tid; i < len; i += 1024) {
-            buf[i + (i >> 5)] = counts[base + i];
-            counts[base + i] = 0u;
-        }
-        __syncthreads();
-        const int lo = tid * 32;
+        const int lo = base + tid * 32;
+        uint4 v[8];
         uint32_t sum = 0;
-        for (int k = 0; k < 32; ++k)
-            if (lo + k < len) sum += buf[lo + k + ((lo + k) >> 5)];
+        if (lo < nbins) {
+            const uint4* src = reinterpret_cast<const uint4*>(counts + lo);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += v[k].x + v[k].y + v[k].z + v[k].w;
+        }
         uint32_t inc = sum;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += v;
+            const uint32_t t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
         }
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
         uint32_t wpre = 0, total = 0;
+#pragma unroll
         for (int w = 0; w < 16; ++w) {
-            if (w < wave) wpre += wsum[w];
-            total += wsum[w];
+            const uint32_t ws = wsum[w];
+            wpre += w < wave ? ws : 0u;
+            total += ws;
         }
-        uint32_t run = carry + wpre + inc - sum;
-        for (int k = 0; k < 32; ++k)
-            if (lo + k < len) {
-                const int ix = lo + k + ((lo + k) >> 5);
-                const uint32_t v = buf[ix];
-                buf[ix] = run;
-                run += v;
+        if (lo < nbins) {
+            uint32_t run = carry + wpre + inc - sum;
+            uint4* dst = reinterpret_cast<uint4*>(bin_start + lo);
+            uint4* clr = reinterpret_cast<uint4*>(counts + lo);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                uint4 o;
+                o.x = run;
+                run += v[k].x;
+                o.y = run;
+                run += v[k].y;
+                o.z = run;
+                run += v[k].z;
+                o.w = run;
+                run += v[k].w;
+                dst[k] = o;
+                clr[k] = uint4{0u, 0u, 0u, 0u};
             }
-        __syncthreads();
-        for (int i = tid; i < len; i += 1024) bin_start[base + i] = buf[i + (i >> 5)];
+        }
         carry += total;
         __syncthreads();
     }
@@ -845,7 +866,7 @@ size_t z_lds_bytes(const Launch& L) {
 template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceState& S) {
     hipLaunchKernelGGL((k_spread_xy<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream, S.pos,
                        S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
-                       L.order, S.flag);
+                       L.order, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part);
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
     hipLaunchKernelGGL((k_xy_c2r<T, B>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L), L.stream,
@@ -855,11 +876,11 @@ template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& 
 
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
     if (L.precision == 0) {
-        if (L.plane_block == 256) spread_xy_b<float, 256>(L, S);
-        else if (L.plane_block == 512) spread_xy_b<float, 512>(L, S);
+        if (L.spread_block == 256) spread_xy_b<float, 256>(L, S);
+        else if (L.spread_block == 512) spread_xy_b<float, 512>(L, S);
         else spread_xy_b<float, 1024>(L, S);
     } else {
-        if (L.plane_block == 256) spread_xy_b<double, 256>(L, S);
+        if (L.spread_block == 256) spread_xy_b<double, 256>(L, S);
         else spread_xy_b<double, 512>(L, S);
     }
     return hipGetLastError();
@@ -878,7 +899,7 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
 }
 
 template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
-    hipLaunchKernelGGL((k_z_kmul<T, 256, EO>), dim3(L.n_zblocks), dim3(256), z_lds_bytes(L), L.stream,
+    hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
                        S.epart, want_energy);
 }
@@ -894,13 +915,26 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
     return hipGetLastError();
 }
 
-template <typename T, int MODE>
-static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
-    // at least one block: in MODE 0 the last block also carries the shift over
+template <typename T, int P, int MODE>
+static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
+    // at least one block: in MODE 0 block 0 writes the new shift
     const unsigned g = std::min<unsigned>(blocks_for(S.n > 0 ? S.n : 1, 256), (unsigned)kUpdateBlocks);
-    hipLaunchKernelGGL((k_update<T, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
-                       (const T*)S.fpart, L.order, S.qshift, S.qshift_next, S.n, L.ph, step, out, out_dtype, parts,
-                       S.com_part, S.ticket, S.flag);
+    hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
+                       (const T*)S.fpart, S.qshift, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts,
+                       S.noise_part, 2 * L.d.mz, S.kr, S.counts, S.flag);
+}
+
+template <typename T, int MODE>
+static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int od, unsigned parts) {
+    switch (L.order) {
+        case 1: update_p<T, 1, MODE>(L, S, step, out, od, parts); break;
+        case 2: update_p<T, 2, MODE>(L, S, step, out, od, parts); break;
+        case 3: update_p<T, 3, MODE>(L, S, step, out, od, parts); break;
+        case 4: update_p<T, 4, MODE>(L, S, step, out, od, parts); break;
+        case 5: update_p<T, 5, MODE>(L, S, step, out, od, parts); break;
+        case 6: update_p<T, 6, MODE>(L, S, step, out, od, parts); break;
+        default: update_p<T, 7, MODE>(L, S, step, out, od, parts); break;
+    }
 }
 
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
@@ -912,13 +946,6 @@ hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t ste
         if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts);
         else update_t<double, 1>(L, S, step, out, out_dtype, parts);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_keys(const Launch& L, DeviceState& S) {
-    if (S.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_keys, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.qshift, S.kr,
-                       S.counts, S.n, L.d, L.order);
     return hipGetLastError();
 }
 
@@ -980,31 +1007,34 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
     return hipGetLastError();
 }
 
-template <typename T, int B> static hipError_t attr_plane(size_t lds) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_spread_xy<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+template <typename T> static hipError_t attr_plane(int spread_block, int plane_block, size_t lds) {
+    const void* fs = spread_block == 256 ? (const void*)k_spread_xy<T, 256>
+                     : spread_block == 512 ? (const void*)k_spread_xy<T, 512>
+                                           : (const void*)k_spread_xy<T, 1024>;
+    const void* fc = plane_block == 256 ? (const void*)k_xy_c2r<T, 256>
+                     : plane_block == 512 ? (const void*)k_xy_c2r<T, 512>
+                                          : (const void*)k_xy_c2r<T, 1024>;
+    hipError_t e = hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_xy_c2r<T, B>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute(fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename T> static hipError_t attr_z(size_t lds) {
     hipError_t e =
-        hipFuncSetAttribute((const void*)k_z_kmul<T, 256, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipFuncSetAttribute((const void*)k_z_kmul<T, kZBlock, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_z_kmul<T, 256, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute((const void*)k_z_kmul<T, kZBlock, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
 }
 
 hipError_t configure_kernel_attributes(const Launch& L) {
     const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L);
     hipError_t e = hipSuccess;
     if (L.precision == 0) {
-        if (L.plane_block == 256) e = attr_plane<float, 256>(lp);
-        else if (L.plane_block == 512) e = attr_plane<float, 512>(lp);
-        else e = attr_plane<float, 1024>(lp);
+        e = attr_plane<float>(L.spread_block, L.plane_block, lp);
         if (e == hipSuccess) e = attr_z<float>(lz);
     } else {
-        if (L.plane_block == 256) e = attr_plane<double, 256>(lp);
-        else e = attr_plane<double, 512>(lp);
+        e = attr_plane<double>(L.spread_block, L.plane_block, lp);
         if (e == hipSuccess) e = attr_z<double>(lz);
     }
     return e;

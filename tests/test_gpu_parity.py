@@ -260,3 +260,37 @@ def test_empty_system():
     assert e["E"] == 0.0
     assert t.forces().shape == (0, 3)
     t.close()
+
+
+def test_workload2_precision_study_sampled():
+    """5,000,000-bead A50/B50 blend, 192^3 grid, P = 5: FP32 grids and transforms
+    against the FP64 oracle.  The oracle field is exact (full spread + FFT);
+    forces are compared on 20,000 sampled beads, energies and virial in full."""
+    m = make_melt(2)
+    x = snap_to_lattice(m.x, m.box)
+    say(f"[precision] {m.name}")
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(x)
+    f_nb = t.forces(T.TILD_PART_NONBONDED)
+    f_b = t.forces(T.TILD_PART_BOND)
+    e = t.energy()
+    t.close()
+    p = oracle_params(m, transform="numpy")
+    c = R.spread(x, m.types, p.L, p.M, p.order, chunk=250000)
+    chat = R.dft3(c, "numpy")
+    uh = R.uhat_analytic(p.smear_a, p.L, p.M)
+    Phi = R.field_spectra(chat, uh, p.chi, p.kappa, m.n)
+    grad = R.gradient_fields(Phi, p.L, p.M, "numpy")
+    idx = np.sort(np.random.default_rng(5).choice(m.n, 20000, replace=False))
+    F_nb = R.gather(x[idx], m.types[idx], grad, p.L, p.M, p.order)
+    e_chi, e_kap = R.nonbonded_energy(chat, uh, p.chi, p.kappa, m.n)
+    e_b, F_b, W_b = R.bond_terms(x, m.bonds, p.L, p.bond_k)
+    W_nb = R.nonbonded_virial(chat, p.smear_a, p.L, p.M, p.chi, p.kappa, m.n)
+    errs = dict(F_nb=rel_rms(f_nb[idx], F_nb), F_bond=rel_rms(f_b[idx], F_b[idx]),
+                F_total=rel_rms(f_nb[idx] + f_b[idx], F_nb + F_b[idx]),
+                E_chi=abs(e["E_chi"] - e_chi) / abs(e_chi), E_kappa=abs(e["E_kappa"] - e_kap) / abs(e_kap),
+                E_bond=abs(e["E_bond"] - e_b) / abs(e_b),
+                W=float(np.max(np.abs(e["W"] - (W_nb + W_b)) / np.abs(W_nb + W_b))))
+    say("   relative errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL32, (k, v)
