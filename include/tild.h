@@ -59,7 +59,11 @@
  * exception crosses this interface.  A non-finite force or displacement seen
  * during tild_step is latched on the device and reported as TILD_ENONFINITE
  * by the next synchronising call (tild_synchronize, tild_energy, or a
- * host-output call); the flag is then cleared.
+ * host-output call); the flag is then cleared.  So is a grid plane too dense
+ * for the fixed-point spread (of the order of 10^7 beads reaching one
+ * plane of one species).  An internal consistency failure latched on the
+ * device (a bead outside its bin, a prefix scan that gave up waiting) is
+ * reported the same way as TILD_EHIP.
  */
 #ifndef TILD_H
 #define TILD_H

@@ -59,7 +59,7 @@ bool make_plan(int n, int tw_offset, FftPlan& pl) {
     int r = n, k = 0;
     auto push = [&](int R) {
         if (k >= kMaxRadixStages) return false;
-        pl.radix[k++] = R;
+        pl.codes |= (uint32_t)R << (4 * k++);
         r /= R;
         return true;
     };
@@ -137,7 +137,7 @@ int choose_group(const FftPlan& pl, int min_g) {
         if (G < min_g) continue;
         bool ok = true;
         for (int st = 0; st < pl.nst; ++st) {
-            const int R = pl.radix[st], bpl = pl.n / R;
+            const int R = pl.radix(st), bpl = pl.n / R;
             if ((bpl + G - 1) / G > kFftRegElems / R) ok = false;
         }
         if (ok) return G;
@@ -207,7 +207,8 @@ int check_flag(tild_ctx* c) {
         if (f & 1u) why += "non-finite force, displacement or position detected; ";
         if (f & 4u) why += "a grid plane is too dense for the fixed-point spread; ";
         if (f & 8u) why += "internal: a bead was found outside its bin; ";
-        return c->fail(TILD_ENONFINITE, why);
+        if (f & 16u) why += "internal: the bin prefix scan gave up waiting for a preceding tile; ";
+        return c->fail((f & 24u) ? TILD_EHIP : TILD_ENONFINITE, why);
     }
     return TILD_OK;
 }
@@ -416,6 +417,8 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     const size_t nbins_pad = ((size_t)S.nbins + 32) / 32 * 32 + 32;  // vector scan reads whole 32-bin groups
     A((void**)&S.counts, nbins_pad * sizeof(uint32_t));
     A((void**)&S.bin_start, nbins_pad * sizeof(uint32_t));
+    const size_t scan_words = (size_t)(S.nbins + kScanBins - 1) / kScanBins + 1;
+    A((void**)&S.scan_status, scan_words * sizeof(unsigned long long));
     A((void**)&S.nbr, ntab * sizeof(int32_t));
     A((void**)&S.nbr_old, ntab * sizeof(int32_t));
     A((void**)&S.nbr_abi, ntab * sizeof(int32_t));
@@ -459,6 +462,10 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     H2D(S.nbr_abi, nbr_tab.data(), nbr_tab.size() * sizeof(int32_t));
     H2D(S.counts, zero_bins.data(), zero_bins.size() * sizeof(uint32_t));
     H2D(S.bin_start, zero_bins.data(), zero_bins.size() * sizeof(uint32_t));
+    {
+        const std::vector<unsigned long long> zero_words(scan_words, 0ull);
+        H2D(S.scan_status, zero_words.data(), scan_words * sizeof(unsigned long long));
+    }
     H2D(S.qshift, zeros4, sizeof(zeros4));
     H2D(S.qshift_next, zeros4, sizeof(zeros4));
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));

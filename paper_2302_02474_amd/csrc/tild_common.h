@@ -48,6 +48,17 @@ struct Dims {
 // weight is the uncentred spline M_P(f + P-1-j), which the recursion below
 // evaluates for all j at once:
 //   M_1 = 1 on [0,1);  M_k(s) = [s M_{k-1}(s) + (k-s) M_{k-1}(s-1)] / (k-1).
+// The dispatcher hands consecutive workgroups of a launch to the device's 8
+// XCDs in turn (linear id mod 8), and each XCD has its own L2.  This maps the
+// linear id b of a launch of G workgroups to a logical tile id such that each
+// XCD receives one contiguous range of tiles (a bijection of [0, G)): tiles
+// that read overlapping data then share one L2.
+__device__ __forceinline__ int xcd_contiguous(int b, int G) {
+    constexpr int kXcds = 8;
+    const int q = G / kXcds, r = G % kXcds, x = b % kXcds, s = b / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
+}
+
 __device__ __forceinline__ int wrap_index(int g, int m) {
     g %= m;
     return g < 0 ? g + m : g;

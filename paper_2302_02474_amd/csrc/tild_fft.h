@@ -15,7 +15,7 @@
 
 namespace tild {
 
-constexpr int kMaxRadixStages = 16;
+constexpr int kMaxRadixStages = 8;  // 4-bit radix codes in one 32-bit word
 constexpr int kFftRegElems = 8;
 
 // Factorisation of one transform length, the offset of its twiddle table
@@ -26,7 +26,8 @@ struct FftPlan {
     int nst;
     int tw;
     int group;  // lanes per line: a power of two <= 64
-    int radix[kMaxRadixStages];
+    uint32_t codes;  // radix of pass st in bits 4 st .. 4 st + 3
+    __host__ __device__ __forceinline__ int radix(int st) const { return (int)((codes >> (4 * st)) & 15u); }
 };
 
 // Which LDS elements form the lines: line l starts at
@@ -179,13 +180,13 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
 // Transform the line at `base` (elements `es` apart) in place; called by all
 // G lanes of the owning group.
 template <typename C, int INV>
-__device__ void fft_line(C* buf, const int base, const int es, const FftPlan& plan, const C* __restrict__ twiddles,
+__device__ __forceinline__ void fft_line(C* buf, const int base, const int es, const FftPlan plan, const C* __restrict__ twiddles,
                          const int lane) {
     const C* tw = twiddles + plan.tw;
     const int G = plan.group;
     int s = 1;
     for (int st = 0; st < plan.nst; ++st) {
-        const int R = plan.radix[st];
+        const int R = plan.radix(st);
         switch (R) {
             case 8: line_pass<C, 8, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
             case 4: line_pass<C, 4, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
@@ -201,7 +202,7 @@ __device__ void fft_line(C* buf, const int base, const int es, const FftPlan& pl
 // plan.group lanes.  Needs a block barrier before (inputs written by other
 // waves) and, if other waves read the result, after.
 template <typename C, int INV>
-__device__ void fft_lines(C* buf, const LineMap lm, const FftPlan& plan, const C* __restrict__ twiddles, int tid,
+__device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPlan plan, const C* __restrict__ twiddles, int tid,
                           int nthr) {
     const int G = plan.group;
     const int lane = tid % G, grp = tid / G, ngrp = nthr / G;

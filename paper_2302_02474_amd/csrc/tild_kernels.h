@@ -12,6 +12,7 @@ namespace tild {
 
 constexpr int kUpdateBlocks = 1024;  // workgroups of the (grid-stride) update kernel
 constexpr int kZBlock = 512;         // threads per workgroup of the z pass
+constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
 
 // Physical constants of one context, passed by value to kernels.
 struct Phys {
@@ -48,6 +49,7 @@ struct DeviceState {
     void* fbond;          // [n][4] harmonic bond force of sorted bead j {Fx, Fy, Fz, 0} (working precision)
     uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
     uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
+    unsigned long long* scan_status;  // [ntiles + 1] look-back status words of the bin scan, then its ticket
     int32_t* nbr;         // [n][deg] bond partners of sorted slot j as sorted slots, -1 padded
     int32_t* nbr_old;     // [n][deg] partners in the previous order
     int32_t* nbr_abi;     // [n][deg] partners in ABI order (static)

@@ -17,6 +17,8 @@
 //   scatter     beads and bond partners into the new sorted order
 #include "tild_kernels.h"
 
+#include <type_traits>
+
 namespace tild {
 
 constexpr int kPairItems = 8;  // row-pair (un)packing items per lane
@@ -34,7 +36,7 @@ template <typename V> __device__ __forceinline__ V wave_sum(V v) {
 
 // Sum NV values over the block; thread 0 receives the totals.
 template <typename V, int NV>
-__device__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */, int tid, int nthr) {
+__device__ __forceinline__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */, int tid, int nthr) {
     const int lane = tid & 63, wave = tid >> 6, nw = nthr >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -55,7 +57,7 @@ __device__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */, int tid, int n
 
 // Copy the twiddle tables (x, y and z axes, concatenated) into LDS.
 template <typename C>
-__device__ __forceinline__ const C* stage_twiddles(C* dst, const C* __restrict__ tw, const Dims& d, int tid, int nthr) {
+__device__ __forceinline__ const C* stage_twiddles(C* dst, const C* __restrict__ tw, const Dims d, int tid, int nthr) {
     for (int i = tid; i < d.mx + d.my + d.mz; i += nthr) dst[i] = tw[i];
     return dst;
 }
@@ -63,7 +65,7 @@ __device__ __forceinline__ const C* stage_twiddles(C* dst, const C* __restrict__
 // ------------------------------------------------------------ bins
 
 // Bin key of a bead: (species, first stencil plane in z, first stencil row in y).
-__device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t species, const Dims& d, int P) {
+__device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t species, const Dims d, int P) {
     const int gy = stencil_start(qy, d.my, P), gz = stencil_start(qz, d.mz, P);
     return (uint32_t)((species * (uint32_t)d.mz + (uint32_t)gz) * (uint32_t)d.my + (uint32_t)gy);
 }
@@ -81,8 +83,8 @@ __device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t s
 // With `noise`, every bead of the plane's own slab (c = 0, so each bead once
 // over the grid) also adds its Gaussian increment of step `step` to nsum.
 template <typename T, int P>
-__device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
-                             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims& d,
+__device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
+                             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims d,
                              int z, int K, T scale, bool noise, uint64_t step, uint64_t seed, double nsum[3], int tid,
                              int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
@@ -143,7 +145,7 @@ __device__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __res
 // which no cell can overflow int32.  A cell of row y is reached only by beads
 // of the P slabs z-P+1 .. z and the P row bins y-P+1 .. y, each contributing at
 // most wmax, so their number times wmax bounds its count.
-__device__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims& d, int z, int K, int P, double wmax,
+__device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K, int P, double wmax,
                               uint32_t* __restrict__ flag, uint32_t* smax, int tid, int nthr) {
     if (tid == 0) *smax = 0u;
     __syncthreads();
@@ -177,24 +179,26 @@ __device__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims
 // complex offset p * 2hx, and separated in place, by the lanes that
 // transformed them, with the symmetry Z(-k)*: H row 2p lands at p * 2hx and
 // row 2p+1 at p * 2hx + hx, i.e. H has row pitch hx.
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int P>
 __global__ void __launch_bounds__(BLOCK)
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
-                int order, uint32_t* __restrict__ flag, int noise, uint64_t step, double* __restrict__ noise_part) {
+                uint32_t* __restrict__ flag, int noise, uint64_t step, double* __restrict__ noise_part) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax;
     __shared__ double nred[3 * (BLOCK / 64)];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
-    const int z = blockIdx.x, K = blockIdx.y;
+    // one XCD takes a run of consecutive planes, whose bead slabs overlap
+    const int t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
+    const int z = t % d.mz, K = t / d.mz;
     const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
     const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
     constexpr bool kFixed = sizeof(T) == 4;
     T scale = (T)1;
-    if constexpr (kFixed) scale = spread_scale(bin_start, d, z, K, order, ph.wmax, flag, &smax, tid, BLOCK);
+    if constexpr (kFixed) scale = spread_scale(bin_start, d, z, K, P, ph.wmax, flag, &smax, tid, BLOCK);
     for (int i = tid; i < np * zp; i += BLOCK) {
         const int p = i / zp, x = i - p * zp;
         if constexpr (kFixed) S[i] = C{0, 0};  // integer zero
@@ -202,15 +206,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
     __syncthreads();
     double nsum[3] = {0, 0, 0};
-    switch (order) {
-        case 1: spread_plane<T, 1>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        case 2: spread_plane<T, 2>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        case 3: spread_plane<T, 3>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        case 4: spread_plane<T, 4>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        case 5: spread_plane<T, 5>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        case 6: spread_plane<T, 6>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-        default: spread_plane<T, 7>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK); break;
-    }
+    spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK);
     if (noise) {
         block_sum<double, 3>(nsum, nred, tid, BLOCK);  // contains the barrier the conversion below needs
         if (tid == 0)
@@ -269,8 +265,8 @@ __global__ void __launch_bounds__(BLOCK)
 //   fpart[a][c][j] = -w_z[c] sum_{b,a'} w_y[b] w_x[a'] d_a phi(g0y + b, g0x + a'),
 // so that its force component a is the sum of fpart[a][0 .. P-1][j].
 template <typename T, int P>
-__device__ void push_plane(const T* __restrict__ Sr, const uint4* __restrict__ pos,
-                           const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims& d,
+__device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4* __restrict__ pos,
+                           const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims d,
                            int z, int K, int a, long long n, T* __restrict__ fpart, int tid, int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
 #pragma unroll
@@ -325,16 +321,19 @@ __device__ void push_plane(const T* __restrict__ Sr, const uint4* __restrict__ p
 // and 2p+1 carried as the real and imaginary parts of one complex row, packed
 // in place at complex offset p * 2hx by the lanes that then transform it; the
 // finished plane d_a phi_K(z) is interpolated onto the beads that reach it.
-template <typename T, int BLOCK>
+template <typename T, int BLOCK, int P>
 __global__ void __launch_bounds__(BLOCK)
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
-             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n, int order) {
+             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
-    const int z = blockIdx.x, K = blockIdx.y, a = blockIdx.z;
+    // one XCD takes the three axes of a run of consecutive planes of one
+    // species: all of them read the same bead slabs
+    const int t = xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
+    const int a = t % 3, z = (t / 3) % d.mz, K = t / (3 * d.mz);
     const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
@@ -392,15 +391,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
         __syncthreads();
         const T* Sr = reinterpret_cast<const T*>(smem);
-        switch (order) {
-            case 1: push_plane<T, 1>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            case 2: push_plane<T, 2>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            case 3: push_plane<T, 3>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            case 4: push_plane<T, 4>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            case 5: push_plane<T, 5>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            case 6: push_plane<T, 6>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-            default: push_plane<T, 7>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK); break;
-        }
+        push_plane<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK);
     }
 }
 
@@ -645,66 +636,103 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------------ counting sort
 
-// One workgroup: bin_start = exclusive prefix sum of counts (bin_start[nbins]
-// = total); counts are cleared for the next use.  Each thread owns 32
-// consecutive bins per chunk of 32768 (loaded and stored as eight 16-byte
-// vectors), the block scans the per-thread sums with wavefront shuffles.
-// `counts` and `bin_start` hold at least ceil(nbins / 32) * 32 entries.
-__global__ void __launch_bounds__(1024) k_bin_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ bin_start,
-                                                   int nbins) {
-    constexpr int CH = 32768;
-    __shared__ uint32_t wsum[16];
+// bin_start = exclusive prefix sum of counts over tiles of kScanBins bins (one
+// per thread group of 4 in a 256-thread workgroup)
+// (bin_start[nbins] = total); counts are cleared for the next use.  Tiles are
+// claimed in launch order from a 64-bit ticket and combined by a decoupled
+// look-back: each tile publishes its aggregate, then its inclusive prefix, in
+// one status word {epoch:30, flag:2, value:32} (flag 1 aggregate, 2
+// inclusive), so a tile never waits on a later one.  The ticket also yields
+// the launch's epoch (ticket / ntiles), which tells this launch's statuses
+// from the previous one's without any clearing.  A wait that outlasts
+// kScanSpin polls sets flag bit 4 and gives up.
+constexpr int kScanSpin = 1 << 22;
+
+__device__ __forceinline__ unsigned long long scan_status(uint32_t epoch, uint32_t flag, uint32_t value) {
+    return ((unsigned long long)((epoch << 2) | flag) << 32) | value;
+}
+
+__global__ void __launch_bounds__(256)
+    k_bin_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ bin_start, int nbins,
+               unsigned long long* __restrict__ status, unsigned long long* __restrict__ ticket,
+               uint32_t* __restrict__ flag) {
+    __shared__ uint32_t s_tile, s_excl;
+    __shared__ uint32_t wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t carry = 0;
-    for (int base = 0; base < nbins; base += CH) {
-        const int lo = base + tid * 32;
-        uint4 v[8];
-        uint32_t sum = 0;
-        if (lo < nbins) {
-            const uint4* src = reinterpret_cast<const uint4*>(counts + lo);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = src[k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) sum += v[k].x + v[k].y + v[k].z + v[k].w;
-        }
-        uint32_t inc = sum;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t t = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += t;
-        }
-        if (lane == 63) wsum[wave] = inc;
-        __syncthreads();
-        uint32_t wpre = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t ws = wsum[w];
-            wpre += w < wave ? ws : 0u;
-            total += ws;
-        }
-        if (lo < nbins) {
-            uint32_t run = carry + wpre + inc - sum;
-            uint4* dst = reinterpret_cast<uint4*>(bin_start + lo);
-            uint4* clr = reinterpret_cast<uint4*>(counts + lo);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                uint4 o;
-                o.x = run;
-                run += v[k].x;
-                o.y = run;
-                run += v[k].y;
-                o.z = run;
-                run += v[k].z;
-                o.w = run;
-                run += v[k].w;
-                dst[k] = o;
-                clr[k] = uint4{0u, 0u, 0u, 0u};
-            }
-        }
-        carry += total;
-        __syncthreads();
+    const unsigned ntiles = gridDim.x;
+    if (tid == 0) {
+        const unsigned long long t = atomicAdd(ticket, 1ull);
+        s_tile = (uint32_t)(t % ntiles);
+        s_excl = (uint32_t)((t / ntiles) & 0x3fffffffull);  // epoch, until the prefix is known
     }
-    if (tid == 0) bin_start[nbins] = carry;
+    __syncthreads();
+    const uint32_t tile = s_tile, epoch = s_excl;
+    const int lo = (int)tile * kScanBins + 4 * tid;
+    uint4 v = uint4{0u, 0u, 0u, 0u};
+    if (lo < nbins) v = *reinterpret_cast<const uint4*>(counts + lo);
+    const uint32_t sum = v.x + v.y + v.z + v.w;
+    uint32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    const uint32_t agg = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (wave == 0) {
+        uint32_t excl = 0;
+        if (tile == 0) {
+            if (lane == 0) __hip_atomic_store(&status[0], scan_status(epoch, 2u, agg), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0) __hip_atomic_store(&status[tile], scan_status(epoch, 1u, agg), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+            int hi = (int)tile - 1;  // nearest predecessor not yet added
+            int spins = 0;
+            while (true) {
+                const int idx = hi - lane;
+                uint32_t f = 2u, val = 0u;
+                if (idx >= 0) {
+                    const unsigned long long st =
+                        __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t w = (uint32_t)(st >> 32);
+                    f = (w >> 2) == epoch ? (w & 3u) : 0u;
+                    val = (uint32_t)st;
+                }
+                const unsigned long long incl_mask = __ballot(f == 2u);
+                const int first = incl_mask ? __ffsll((long long)incl_mask) - 1 : 64;
+                const unsigned long long need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+                if (__ballot(f == 0u) & need) {
+                    if (++spins > kScanSpin) {
+                        if (lane == 0) atomicOr(flag, 16u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += wave_sum(lane <= first ? val : 0u);
+                if (first < 64) break;
+                hi -= 64;
+            }
+            if (lane == 0) __hip_atomic_store(&status[tile], scan_status(epoch, 2u, excl + agg), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    uint32_t run = s_excl + inc - sum;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    if (lo < nbins) {
+        uint4 o;
+        o.x = run;
+        o.y = run + v.x;
+        o.z = o.y + v.y;
+        o.w = o.z + v.z;
+        *reinterpret_cast<uint4*>(bin_start + lo) = o;
+        *reinterpret_cast<uint4*>(counts + lo) = uint4{0u, 0u, 0u, 0u};
+    }
+    if (tile == ntiles - 1 && tid == 0) bin_start[nbins] = s_excl + agg;
 }
 
 // Move every bead of the previous order to its sorted slot, translate its
@@ -716,7 +744,8 @@ __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
               T* __restrict__ fbond, long long n, int deg, Phys ph) {
-    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    // contiguous bead ranges per XCD: bond partners are near in the order
+    const long long j = xcd_contiguous(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (j >= n) return;
     const uint2 kj = kr[j];
     const long long nw = (long long)bin_start[kj.x] + kj.y;
@@ -863,15 +892,32 @@ size_t z_lds_bytes(const Launch& L) {
     return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1) + (size_t)(L.d.mx + L.d.my + L.d.mz));
 }
 
+// Calls f(std::integral_constant<int, P>{}) for the stencil order P = order.
+template <typename F> static void with_order(int order, F&& f) {
+    switch (order) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        case 6: f(std::integral_constant<int, 6>{}); break;
+        default: f(std::integral_constant<int, 7>{}); break;
+    }
+}
+
 template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL((k_spread_xy<T, B>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream, S.pos,
-                       S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
-                       L.order, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part);
+    with_order(L.order, [&](auto Pc) {
+        hipLaunchKernelGGL((k_spread_xy<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                           L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                           (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part);
+    });
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL((k_xy_c2r<T, B>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L), L.stream,
-                       (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph, S.pos,
-                       S.bin_start, S.qshift, S.n, L.order);
+    with_order(L.order, [&](auto Pc) {
+        hipLaunchKernelGGL((k_xy_c2r<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
+                           L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
+                           L.ph, S.pos, S.bin_start, S.qshift, S.n);
+    });
 }
 
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
@@ -889,8 +935,7 @@ hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
     if (L.precision == 0) {
         if (L.plane_block == 256) xy_c2r_b<float, 256>(L, S);
-        else if (L.plane_block == 512) xy_c2r_b<float, 512>(L, S);
-        else xy_c2r_b<float, 1024>(L, S);
+        else xy_c2r_b<float, 512>(L, S);
     } else {
         if (L.plane_block == 256) xy_c2r_b<double, 256>(L, S);
         else xy_c2r_b<double, 512>(L, S);
@@ -950,7 +995,9 @@ hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t ste
 }
 
 hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, L.stream, S.counts, S.bin_start, S.nbins);
+    const unsigned ntiles = (unsigned)((S.nbins + kScanBins - 1) / kScanBins);
+    hipLaunchKernelGGL(k_bin_scan, dim3(ntiles), dim3(256), 0, L.stream, S.counts, S.bin_start, S.nbins, S.scan_status,
+                       S.scan_status + ntiles, S.flag);
     return hipGetLastError();
 }
 
@@ -1007,16 +1054,22 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
     return hipGetLastError();
 }
 
-template <typename T> static hipError_t attr_plane(int spread_block, int plane_block, size_t lds) {
-    const void* fs = spread_block == 256 ? (const void*)k_spread_xy<T, 256>
-                     : spread_block == 512 ? (const void*)k_spread_xy<T, 512>
-                                           : (const void*)k_spread_xy<T, 1024>;
-    const void* fc = plane_block == 256 ? (const void*)k_xy_c2r<T, 256>
-                     : plane_block == 512 ? (const void*)k_xy_c2r<T, 512>
-                                          : (const void*)k_xy_c2r<T, 1024>;
-    hipError_t e = hipFuncSetAttribute(fs, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(fc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+// The plane kernels of one context: the same block sizes and order as the launchers above pick.
+template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if (L.spread_block == 256) set((const void*)k_spread_xy<T, 256, P>);
+        else if constexpr (sizeof(T) == 8) set((const void*)k_spread_xy<T, 512, P>);
+        else if (L.spread_block == 512) set((const void*)k_spread_xy<T, 512, P>);
+        else set((const void*)k_spread_xy<T, 1024, P>);
+        if (L.plane_block == 256) set((const void*)k_xy_c2r<T, 256, P>);
+        else set((const void*)k_xy_c2r<T, 512, P>);
+    });
+    return e;
 }
 
 template <typename T> static hipError_t attr_z(size_t lds) {
@@ -1031,10 +1084,10 @@ hipError_t configure_kernel_attributes(const Launch& L) {
     const size_t lp = plane_lds_bytes(L), lz = z_lds_bytes(L);
     hipError_t e = hipSuccess;
     if (L.precision == 0) {
-        e = attr_plane<float>(L.spread_block, L.plane_block, lp);
+        e = attr_plane<float>(L, lp);
         if (e == hipSuccess) e = attr_z<float>(lz);
     } else {
-        e = attr_plane<double>(L.spread_block, L.plane_block, lp);
+        e = attr_plane<double>(L, lp);
         if (e == hipSuccess) e = attr_z<double>(lz);
     }
     return e;
