@@ -347,6 +347,12 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     d.mz = params->grid[2];
     d.hx = d.mx / 2 + 1;
     d.npair = (d.my + 1) / 2;
+    // LDS plane: pair rows of 2 hxp complex, with room for P - 1 ghost columns
+    // and P - 1 ghost rows past the periodic edge
+    d.hxp = std::max(d.hx, (d.mx + params->order) / 2);
+    d.npg = (d.my + params->order) / 2;
+    d.ylines = (d.mx % 2 == 0 && d.hx > 1) ? d.hx - 1 : d.hx;
+    d.swc = d.ylines % 16 == 0 ? d.ylines : 0;
     d.m = (long long)d.mx * d.my * d.mz;
     d.hplane = (long long)d.my * d.hx;
     d.lx = params->box[0];

@@ -33,21 +33,15 @@ struct Dims {
     int mx, my, mz;  // grid points
     int hx;          // mx/2 + 1
     int npair;       // (my + 1) / 2: row pairs packed into one complex row
+    int hxp;         // LDS half-row pitch: >= hx and 2 hxp >= mx + P - 1
+    int npg;         // LDS row pairs including ghost rows: ceil((my + P - 1) / 2)
+    int ylines;      // y transforms per plane: hx, or hx - 1 when the kx = 0 and mx/2 columns share one
+    int swc;         // columns kx < swc of an LDS half spectrum are swizzled (ylines or 0)
     long long m;     // mx*my*mz
     long long hplane;  // my*hx complex per half-spectrum plane
     double lx, ly, lz;
 };
 
-// Positions are unsigned 32-bit fractions of the box edge: x = q * L / 2^32.
-// The grid coordinate u = x / h = q * M / 2^32 is a 64-bit fixed-point number
-// with 32 fractional bits, so cell indices and fractional offsets are exact.
-//
-// Assignment: a bead at u touches the P nodes g0 .. g0+P-1 with
-// g0 = floor(u - P/2) + 1, and the node g0+j has weight B_P(u - g0 - j), B_P
-// the centred cardinal B-spline of order P.  With f = frac(u - P/2) that
-// weight is the uncentred spline M_P(f + P-1-j), which the recursion below
-// evaluates for all j at once:
-//   M_1 = 1 on [0,1);  M_k(s) = [s M_{k-1}(s) + (k-s) M_{k-1}(s-1)] / (k-1).
 // The dispatcher hands consecutive workgroups of a launch to the device's 8
 // XCDs in turn (linear id mod 8), and each XCD has its own L2.  This maps the
 // linear id b of a launch of G workgroups to a logical tile id such that each
@@ -59,38 +53,92 @@ __device__ __forceinline__ int xcd_contiguous(int b, int G) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + s;
 }
 
-__device__ __forceinline__ int wrap_index(int g, int m) {
-    g %= m;
+// Positions are unsigned 32-bit fractions of the box edge: x = q * L / 2^32.
+// The grid coordinate u = x / h = q * M / 2^32 is a 64-bit fixed-point number
+// with 32 fractional bits, so cell indices and fractional offsets are exact.
+//
+// Assignment: a bead at u touches the P nodes g0 .. g0+P-1 with
+// g0 = floor(u - P/2) + 1, and the node g0+j has weight B_P(u - g0 - j), B_P
+// the centred cardinal B-spline of order P.  With f = frac(u - P/2) that
+// weight is the uncentred spline M_P(f + P-1-j), where
+//   M_1 = 1 on [0,1);  M_k(s) = [s M_{k-1}(s) + (k-s) M_{k-1}(s-1)] / (k-1).
+// On [i, i+1), M_P is a polynomial of degree P-1 in f = s - i; its
+// coefficients follow from the recursion by polynomial arithmetic and are
+// formed at compile time, so a weight costs P-1 fused multiply-adds.
+template <int P> struct SplinePieces {
+    double c[P][P];  // M_P(f + i) = sum_k c[i][k] f^k, 0 <= f < 1
+};
+
+template <int P> constexpr SplinePieces<P> spline_pieces() {
+    SplinePieces<P> r{};
+    if constexpr (P == 1) {
+        r.c[0][0] = 1.0;
+    } else {
+        const SplinePieces<P - 1> m = spline_pieces<P - 1>();
+        for (int i = 0; i < P; ++i)
+            for (int k = 0; k < P; ++k) {
+                double v = 0.0;
+                if (i <= P - 2) {  // (f + i) M_{P-1}(f + i)
+                    if (k >= 1) v += m.c[i][k - 1];
+                    if (k <= P - 2) v += i * m.c[i][k];
+                }
+                if (i >= 1) {  // (P - i - f) M_{P-1}(f + i - 1)
+                    if (k <= P - 2) v += (P - i) * m.c[i - 1][k];
+                    if (k >= 1) v -= m.c[i - 1][k - 1];
+                }
+                r.c[i][k] = v / (P - 1);
+            }
+    }
+    return r;
+}
+
+// Weight of stencil node j (0 <= j < P) at fraction f: M_P(f + P-1-j).
+template <typename T, int P, int J> __device__ __forceinline__ T spline_weight(T f) {
+    constexpr SplinePieces<P> sp = spline_pieces<P>();
+    constexpr int i = P - 1 - J;
+    T v = (T)sp.c[i][P - 1];
+#pragma unroll
+    for (int k = P - 2; k >= 0; --k) v = v * f + (T)sp.c[i][k];
+    return v;
+}
+
+template <typename T, int P, int J = 0> __device__ __forceinline__ void spline_weights(T f, T w[P]) {
+    if constexpr (J < P) {
+        w[J] = spline_weight<T, P, J>(f);
+        spline_weights<T, P, J + 1>(f, w);
+    }
+}
+
+// (u - P/2) * 2^32 for fixed-point q on an axis of m points.
+__device__ __forceinline__ int64_t stencil_fixed(uint32_t q, int m, int P) {
+    return (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m) - ((int64_t)P << 31);
+}
+
+// First stencil node g0 = floor(u - P/2) + 1, wrapped into [0, m).  Before
+// wrapping 1 - P/2 <= g0 <= m - P/2 (m only for P = 1, the nearest node of a
+// bead just below the upper edge), so with m >= P one add or subtract wraps.
+__device__ __forceinline__ int wrap_start(int g, int m, int P) {
+    if (P == 1) return g >= m ? g - m : g;
     return g < 0 ? g + m : g;
 }
 
-// First stencil node g0 = floor(u - P/2) + 1 (mod m) of coordinate q.
 __device__ __forceinline__ int stencil_start(uint32_t q, int m, int P) {
-    const int64_t s = (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m) - ((int64_t)P << 31);
-    return wrap_index((int)(s >> 32) + 1, m);
+    return wrap_start((int)(stencil_fixed(q, m, P) >> 32) + 1, m, P);
 }
 
+// Fraction f = frac(u - P/2) of fixed-point q.
+template <typename T> __device__ __forceinline__ T stencil_fraction(uint32_t q, int m, int P) {
+    const uint32_t fr = q * (uint32_t)m - ((uint32_t)P << 31);  // low 32 bits, modulo 2^32
+    return (T)fr * (T)2.3283064365386963e-10;                  // 2^-32
+}
+
+// g0 (wrapped) and the P weights of coordinate q.
 template <typename T, int P>
 __device__ __forceinline__ void assignment_weights(uint32_t q, int m, int& g0, T w[P]) {
-    const int64_t v = (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m);  // < 2^40
-    const int64_t s = v - ((int64_t)P << 31);                         // (u - P/2) * 2^32
-    const int64_t fl = s >> 32;                                          // floor (arithmetic shift)
-    const uint32_t fr = (uint32_t)(s & 0xffffffffLL);
-    g0 = wrap_index((int)fl + 1, m);
-    const T f = (T)fr * (T)2.3283064365386963e-10;  // 2^-32
-    // mk[j] holds M_k(f + j), j = 0 .. k-1
-    T mk[P];
-    mk[0] = (T)1;
-#pragma unroll
-    for (int k = 2; k <= P; ++k) {
-        const T inv = (T)1 / (T)(k - 1);
-        mk[k - 1] = inv * ((T)1 - f) * mk[k - 2];
-#pragma unroll
-        for (int j = k - 2; j >= 1; --j) mk[j] = inv * ((f + (T)j) * mk[j] + ((T)(k - j) - f) * mk[j - 1]);
-        mk[0] = inv * f * mk[0];
-    }
-#pragma unroll
-    for (int j = 0; j < P; ++j) w[j] = mk[P - 1 - j];
+    const int64_t s = stencil_fixed(q, m, P);
+    g0 = wrap_start((int)(s >> 32) + 1, m, P);
+    const T f = (T)(uint32_t)(s & 0xffffffffLL) * (T)2.3283064365386963e-10;  // 2^-32
+    spline_weights<T, P>(f, w);
 }
 
 // Minimum-image separation (in box units * 2^32) of two fixed-point coordinates.

@@ -31,11 +31,22 @@ struct FftPlan {
 };
 
 // Which LDS elements form the lines: line l starts at
-// (l % l1) * s1 + (l / l1) * s2 and its elements are `es` apart.
+// (l % l1) * s1 + (l / l1) * s2 and its elements are `es` apart.  With a
+// non-zero swizzle mask (lines of one column each: s1 = 1, s2 = 0), element e
+// of line l sits in column l ^ ((e >> 3) & swz) instead of l: the eight
+// outputs of a radix-8 butterfly, written to consecutive elements, then fall
+// into different LDS banks.
 struct LineMap {
-    int lines, l1, s1, s2, es;
+    int lines, l1, s1, s2, es, swz;
     __device__ __forceinline__ int base(int l) const { return (l % l1) * s1 + (l / l1) * s2; }
 };
+
+// LDS index of element e of the line starting at `base`.
+template <bool SWZ>
+__device__ __forceinline__ int line_index(int base, int e, int es, int swz) {
+    if constexpr (SWZ) return (base ^ ((e >> 3) & swz)) + e * es;
+    else return base + e * es;
+}
 
 // Order LDS traffic of the lanes of one wavefront.
 __device__ __forceinline__ void wave_sync() {
@@ -127,9 +138,9 @@ template <int R, int INV, typename C> __device__ __forceinline__ void dft_r(C* a
 }
 
 // One radix-R pass of the line at `base` by lane `lane` of its group of G.
-template <typename C, int R, int INV>
-__device__ __forceinline__ void line_pass(C* buf, const int base, const int es, const int n, const int s,
-                                          const C* __restrict__ tw, const int lane, const int G) {
+template <typename C, int R, int INV, bool SWZ>
+__device__ __forceinline__ void line_pass(C* buf, const int base, const int es, const int swz, const int n,
+                                          const int s, const C* __restrict__ tw, const int lane, const int G) {
     constexpr int MAXB = kFftRegElems / R;
     const int bpl = n / R;
     const int tstride = n / (s * R);
@@ -142,7 +153,7 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
         if (j < bpl) {
             const int k = j % s;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[base + (j + r * bpl) * es];
+            for (int r = 0; r < R; ++r) v[b][r] = buf[line_index<SWZ>(base, j + r * bpl, es, swz)];
             if (s > 1) {
                 // w^r for r < R from two table reads (w, w^2) and at most three products
                 C w[R];
@@ -162,7 +173,7 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[r]);
             }
-            ob[b] = base + ((j - k) * R + k) * es;
+            ob[b] = (j - k) * R + k;  // first output element
         }
     }
     wave_sync();
@@ -171,28 +182,28 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
         if (ob[b] >= 0) {
             dft_r<R, INV>(v[b]);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[ob[b] + r * s * es] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[line_index<SWZ>(base, ob[b] + r * s, es, swz)] = v[b][r];
         }
     }
     wave_sync();
 }
 
-// Transform the line at `base` (elements `es` apart) in place; called by all
-// G lanes of the owning group.
-template <typename C, int INV>
-__device__ __forceinline__ void fft_line(C* buf, const int base, const int es, const FftPlan plan, const C* __restrict__ twiddles,
-                         const int lane) {
+// Transform the line at `base` (elements `es` apart, swizzled with mask swz
+// when SWZ) in place; called by all G lanes of the owning group.
+template <typename C, int INV, bool SWZ = false>
+__device__ __forceinline__ void fft_line(C* buf, const int base, const int es, const FftPlan plan,
+                                         const C* __restrict__ twiddles, const int lane, const int swz = 0) {
     const C* tw = twiddles + plan.tw;
     const int G = plan.group;
     int s = 1;
     for (int st = 0; st < plan.nst; ++st) {
         const int R = plan.radix(st);
         switch (R) {
-            case 8: line_pass<C, 8, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
-            case 4: line_pass<C, 4, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
-            case 2: line_pass<C, 2, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
-            case 3: line_pass<C, 3, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
-            default: line_pass<C, 5, INV>(buf, base, es, plan.n, s, tw, lane, G); break;
+            case 8: line_pass<C, 8, INV, SWZ>(buf, base, es, swz, plan.n, s, tw, lane, G); break;
+            case 4: line_pass<C, 4, INV, SWZ>(buf, base, es, swz, plan.n, s, tw, lane, G); break;
+            case 2: line_pass<C, 2, INV, SWZ>(buf, base, es, swz, plan.n, s, tw, lane, G); break;
+            case 3: line_pass<C, 3, INV, SWZ>(buf, base, es, swz, plan.n, s, tw, lane, G); break;
+            default: line_pass<C, 5, INV, SWZ>(buf, base, es, swz, plan.n, s, tw, lane, G); break;
         }
         s *= R;
     }
@@ -201,12 +212,13 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
 // Transform every line of `lm` with the block's threads split into groups of
 // plan.group lanes.  Needs a block barrier before (inputs written by other
 // waves) and, if other waves read the result, after.
-template <typename C, int INV>
-__device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPlan plan, const C* __restrict__ twiddles, int tid,
-                          int nthr) {
+template <typename C, int INV, bool SWZ = false>
+__device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPlan plan, const C* __restrict__ twiddles,
+                                          int tid, int nthr) {
     const int G = plan.group;
     const int lane = tid % G, grp = tid / G, ngrp = nthr / G;
-    for (int l = grp; l < lm.lines; l += ngrp) fft_line<C, INV>(buf, lm.base(l), lm.es, plan, twiddles, lane);
+    for (int l = grp; l < lm.lines; l += ngrp)
+        fft_line<C, INV, SWZ>(buf, lm.base(l), lm.es, plan, twiddles, lane, lm.swz);
 }
 
 }  // namespace tild

@@ -70,12 +70,63 @@ __device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t s
     return (uint32_t)((species * (uint32_t)d.mz + (uint32_t)gz) * (uint32_t)d.my + (uint32_t)gy);
 }
 
+// ------------------------------------------------------------ LDS plane layout
+//
+// A real plane r[y][x] sits in LDS as complex rows of pitch zp = 2 hxp:
+// complex row p holds rows 2p (real parts) and 2p+1 (imaginary parts), so
+// r[y][x] is float number pr * (y >> 1) + (y & 1) + 2x, pr = 2 zp.  Columns
+// mx .. mx+P-2 and rows my .. my+P-2 are ghosts of columns and rows 0 .. P-2,
+// so that a stencil starting at any (g0y, g0x) in [0, my) x [0, mx) is read or
+// written without wrapping.  The half spectrum of the same plane keeps row ky
+// at complex offset ky * hxp.
+
+// LDS index of half-spectrum element (ky, kx): row pitch hxp; columns
+// kx < swc are swizzled within aligned groups of 16 by (ky >> 3) & 15, the
+// layout the y transforms use (LineMap swz).
+__device__ __forceinline__ int hidx(const Dims d, int ky, int kx) {
+    return ky * d.hxp + (kx < d.swc ? kx ^ ((ky >> 3) & 15) : kx);
+}
+
+// Float offsets of rows gy .. gy+P-1 (gy in [0, my)).
+template <int P> struct RowOffsets {
+    int o[P];
+    __device__ __forceinline__ RowOffsets(int gy, int pr) {
+        const int e = gy & 1;
+        const int o0 = __mul24(gy >> 1, pr) + e;
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+            // rows gy + b: (gy + b) >> 1 = (gy >> 1) + ((e + b) >> 1), parity (e + b) & 1
+            const int even = (b >> 1) * pr + (b & 1);                    // e == 0
+            const int odd = ((b + 1) >> 1) * pr + ((b + 1) & 1) - 1;     // e == 1
+            o[b] = o0 + (e ? odd : even);
+        }
+    }
+};
+
+// Walk (p, x) over a row-major range of pitch w, in steps of n elements.
+struct Walk2 {
+    int p, x, dp, dx, w;
+    __device__ __forceinline__ Walk2(int i0, int w_, int n) : w(w_) {
+        p = i0 / w;
+        x = i0 - p * w;
+        dp = n / w;
+        dx = n - dp * w;
+    }
+    __device__ __forceinline__ void next() {
+        p += dp;
+        x += dx;
+        if (x >= w) {
+            x -= w;
+            ++p;
+        }
+    }
+};
+
 // ------------------------------------------------------------ spread + xy forward
 
 // Accumulate the counts of every species-K bead whose stencil reaches plane z
-// (the beads of the P slabs z-P+1 .. z) into the LDS plane: row y of the
-// plane lives in component y & 1 of complex row y >> 1, rows pitch 2hx
-// complex.  Single precision accumulates fixed-point integers (each
+// (the beads of the P slabs z-P+1 .. z) into the extended LDS plane (ghost
+// cells included).  Single precision accumulates fixed-point integers (each
 // contribution rounded to a multiple of 1/scale): integer LDS atomics are
 // order-independent, and far faster than float ones on this hardware.
 // Double precision accumulates doubles.
@@ -84,10 +135,14 @@ __device__ __forceinline__ uint32_t bin_key(uint32_t qy, uint32_t qz, uint32_t s
 // over the grid) also adds its Gaussian increment of step `step` to nsum.
 template <typename T, int P>
 __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
-                             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims d,
-                             int z, int K, T scale, bool noise, uint64_t step, uint64_t seed, double nsum[3], int tid,
-                             int nthr) {
+                                             const uint32_t* __restrict__ bin_start,
+                                             const uint32_t* __restrict__ qs, const Dims d, int z, int K, T scale,
+                                             bool noise, uint64_t step, uint64_t seed, double nsum[3], int tid,
+                                             int nthr) {
+    using A = typename std::conditional<sizeof(T) == 4, uint32_t, T>::type;
+    A* acc = reinterpret_cast<A*>(lds);
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         int s = z - c;
@@ -96,72 +151,106 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
         constexpr int U = 4;  // beads in flight per thread
         for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
-          uint4 qv[U];
+            uint4 qv[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-              const uint32_t j = jb + (uint32_t)(u * nthr);
-              qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (jb + (uint32_t)(u * nthr) >= j1) break;
-            const uint4 q = qv[u];
-            if (c == 0 && noise) {
-                T xi[3];
-                Noise<T>::draw(q.w >> 1, step, seed, xi);
-                nsum[0] += (double)xi[0];
-                nsum[1] += (double)xi[1];
-                nsum[2] += (double)xi[2];
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
             }
-            int gx, gy, gz;
-            T wx[P], wy[P], wz[P];
-            assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
-            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
-            const T w0 = wz[c] * scale;
 #pragma unroll
-            for (int b = 0; b < P; ++b) {
-                int y = gy + b;
-                if (y >= d.my) y -= d.my;
-                const int row = 4 * (y >> 1) * d.hx + (y & 1);
-                const T wyz = w0 * wy[b];
+            for (int u = 0; u < U; ++u) {
+                if (jb + (uint32_t)(u * nthr) >= j1) break;
+                const uint4 q = qv[u];
+                if (c == 0 && noise) {
+                    T xi[3];
+                    Noise<T>::draw(q.w >> 1, step, seed, xi);
+                    nsum[0] += (double)xi[0];
+                    nsum[1] += (double)xi[1];
+                    nsum[2] += (double)xi[2];
+                }
+                int gx, gy;
+                T wx[P], wy[P];
+                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                // the bead's slab is s: its z weight on plane z = s + c is w_c (c is
+                // a constant after unrolling, so only that weight is evaluated)
+                T wz[P];
+                spline_weights<T, P>(stencil_fraction<T>(q.z - sz, d.mz, P), wz);
+                const T w0 = wz[c] * scale;
+                const RowOffsets<P> ro(gy, pr);
 #pragma unroll
-                for (int a = 0; a < P; ++a) {
-                    int x = gx + a;
-                    if (x >= d.mx) x -= d.mx;
-                    if constexpr (sizeof(T) == 4) {
-                        atomicAdd(reinterpret_cast<uint32_t*>(lds) + row + 2 * x, (uint32_t)__float2int_rn(wyz * wx[a]));
-                    } else {
-                        atomicAdd(reinterpret_cast<T*>(lds) + row + 2 * x, wyz * wx[a]);
+                for (int b = 0; b < P; ++b) {
+                    A* row = acc + ro.o[b] + 2 * gx;
+                    const T wyz = w0 * wy[b];
+#pragma unroll
+                    for (int a = 0; a < P; ++a) {
+                        if constexpr (sizeof(T) == 4) atomicAdd(row + 2 * a, (uint32_t)__float2int_rn(wyz * wx[a]));
+                        else atomicAdd(row + 2 * a, wyz * wx[a]);
                     }
                 }
             }
-          }
         }
     }
+}
+
+// Add the ghost cells of the extended plane into the cells they alias
+// (columns first, over real and ghost rows, then rows).  A: uint32_t (fixed
+// point, wrapping integer sums) or double.  Ends with a barrier.
+template <typename A, int P>
+__device__ __forceinline__ void fold_ghosts(A* acc, const Dims d, int tid, int nthr) {
+    if constexpr (P > 1) {
+        const int pr = 4 * d.hxp;
+        for (int i = tid; i < (d.my + P - 1) * (P - 1); i += nthr) {
+            const int y = i / (P - 1), e = i - y * (P - 1);
+            const int o = __mul24(y >> 1, pr) + (y & 1);
+            acc[o + 2 * e] += acc[o + 2 * (d.mx + e)];
+        }
+        __syncthreads();
+        for (int i = tid; i < (P - 1) * d.mx; i += nthr) {
+            const int e = i / d.mx, x = i - e * d.mx;
+            const int yg = d.my + e;
+            const int og = __mul24(yg >> 1, pr) + (yg & 1), o = __mul24(e >> 1, pr) + (e & 1);
+            acc[o + 2 * x] += acc[og + 2 * x];
+        }
+    }
+    __syncthreads();
 }
 
 // Scale of the fixed-point spread of plane z: the largest 2^k (k <= 24) for
 // which no cell can overflow int32.  A cell of row y is reached only by beads
 // of the P slabs z-P+1 .. z and the P row bins y-P+1 .. y, each contributing at
-// most wmax, so their number times wmax bounds its count.
-__device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K, int P, double wmax,
-                              uint32_t* __restrict__ flag, uint32_t* smax, int tid, int nthr) {
+// most wmax, so their number times wmax bounds its count.  The P row bins of
+// one slab are consecutive (modulo the row wrap), so each slab's share is a
+// difference of two bin starts.
+template <int P>
+__device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K,
+                                              double wmax, uint32_t* __restrict__ flag, uint32_t* smax, int tid,
+                                              int nthr) {
     if (tid == 0) *smax = 0u;
     __syncthreads();
     uint32_t mine = 0;
     for (int y = tid; y < d.my; y += nthr) {
-        uint32_t sum = 0;
+        uint32_t lo[P], hi[P], lo2[P], hi2[P];
+        const int y0 = y - (P - 1);  // rows y0 .. y, wrapped
+#pragma unroll
         for (int c = 0; c < P; ++c) {
             int s = z - c;
             if (s < 0) s += d.mz;
-            for (int b = 0; b < P; ++b) {
-                int yy = y - b;
-                if (yy < 0) yy += d.my;
-                const int bin = (K * d.mz + s) * d.my + yy;
-                sum += bin_start[bin + 1] - bin_start[bin];
+            const int b0 = (K * d.mz + s) * d.my;
+            if (y0 >= 0) {
+                lo[c] = bin_start[b0 + y0];
+                hi[c] = bin_start[b0 + y + 1];
+                lo2[c] = hi2[c] = 0u;
+            } else {
+                lo[c] = bin_start[b0];
+                hi[c] = bin_start[b0 + y + 1];
+                lo2[c] = bin_start[b0 + d.my + y0];
+                hi2[c] = bin_start[b0 + d.my];
             }
         }
+        uint32_t sum = 0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) sum += (hi[c] - lo[c]) + (hi2[c] - lo2[c]);
         mine = mine > sum ? mine : sum;
     }
     atomicMax(smax, mine);
@@ -176,15 +265,18 @@ __device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_s
 // Plane z of species K: counts minus their mean N_K/M, then the forward
 // transform to the half spectrum H[ky][kx], kx = 0 .. mx/2.  Rows 2p and 2p+1
 // are transformed together as one complex row c_2p + i c_2p+1, stored at
-// complex offset p * 2hx, and separated in place, by the lanes that
-// transformed them, with the symmetry Z(-k)*: H row 2p lands at p * 2hx and
-// row 2p+1 at p * 2hx + hx, i.e. H has row pitch hx.
+// complex offset p * zp, and separated in place, by the lanes that
+// transformed them, with the symmetry Z(-k)*: H row 2p lands at p * zp and
+// row 2p+1 at p * zp + hxp, i.e. H has row pitch hxp.
+// At least four waves per SIMD (128 VGPRs): two 512-thread or one
+// 1024-thread workgroup per CU, as the plane's LDS allows.
 template <typename T, int BLOCK, int P>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
                 uint32_t* __restrict__ flag, int noise, uint64_t step, double* __restrict__ noise_part) {
     using C = cplx<T>;
+    using A = typename std::conditional<sizeof(T) == 4, uint32_t, T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax;
     __shared__ double nred[3 * (BLOCK / 64)];
@@ -193,34 +285,42 @@ __global__ void __launch_bounds__(BLOCK)
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
     const int t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
     const int z = t % d.mz, K = t / d.mz;
-    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
+    const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
-    const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
+    const C* twl = stage_twiddles(S + d.npg * zp, tw, d, tid, BLOCK);
     constexpr bool kFixed = sizeof(T) == 4;
     T scale = (T)1;
-    if constexpr (kFixed) scale = spread_scale(bin_start, d, z, K, P, ph.wmax, flag, &smax, tid, BLOCK);
-    for (int i = tid; i < np * zp; i += BLOCK) {
-        const int p = i / zp, x = i - p * zp;
-        if constexpr (kFixed) S[i] = C{0, 0};  // integer zero
-        else S[i] = x < mx ? C{-mean, (2 * p + 1 < my) ? -mean : (T)0} : C{0, 0};
-    }
+    if constexpr (kFixed) scale = spread_scale<P>(bin_start, d, z, K, ph.wmax, flag, &smax, tid, BLOCK);
+    for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
     __syncthreads();
     double nsum[3] = {0, 0, 0};
     spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK);
     if (noise) {
-        block_sum<double, 3>(nsum, nred, tid, BLOCK);  // contains the barrier the conversion below needs
+        block_sum<double, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
         if (tid == 0)
             for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
     } else {
         __syncthreads();
     }
-    if constexpr (kFixed) {
+    fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
+    {
+        // counts (minus their mean) of the real cells; zero elsewhere
         const T inv = (T)1 / scale;
-        const int32_t* Si = reinterpret_cast<const int32_t*>(smem);
-        for (int i = tid; i < np * zp; i += BLOCK) {
-            const int p = i / zp, x = i - p * zp;
-            const int32_t re = Si[2 * i], im = Si[2 * i + 1];
-            S[i] = x < mx ? C{(T)re * inv - mean, (2 * p + 1 < my) ? (T)im * inv - mean : (T)0} : C{0, 0};
+        const A* Si = reinterpret_cast<const A*>(smem);
+        Walk2 w(tid, zp, BLOCK);
+        for (int i = tid; i < np * zp; i += BLOCK, w.next()) {
+            const A re = Si[2 * i], im = Si[2 * i + 1];
+            T vr = 0, vi = 0;
+            if (w.x < mx) {
+                if constexpr (kFixed) {
+                    vr = (T)(int32_t)re * inv - mean;
+                    if (2 * w.p + 1 < my) vi = (T)(int32_t)im * inv - mean;
+                } else {
+                    vr = re - mean;
+                    if (2 * w.p + 1 < my) vi = im - mean;
+                }
+            }
+            S[i] = C{vr, vi};
         }
     }
     __syncthreads();
@@ -245,30 +345,59 @@ __global__ void __launch_bounds__(BLOCK)
             for (int u = 0; u < kPairItems; ++u) {
                 const int kx = lane + u * G;
                 if (kx < hx) {
-                    S[base + kx] = ra[u];
-                    if (2 * p + 1 < my) S[base + hx + kx] = rb[u];
+                    S[hidx(d, 2 * p, kx)] = ra[u];
+                    if (2 * p + 1 < my) S[hidx(d, 2 * p + 1, kx)] = rb[u];
                 }
             }
             wave_sync();
         }
     }
     __syncthreads();
-    fft_lines<C, 0>(S, LineMap{hx, hx, 1, 0, hx}, py, twl, tid, BLOCK);
+    // For even mx the columns kx = 0 and kx = mx/2 are real for every row (x
+    // transforms of real rows at frequencies 0 and pi).  They share one y
+    // transform as Z = H_0 + i H_N, separated afterwards with the symmetry of
+    // transforms of real sequences, which saves one of hx lines.
+    const bool pair_n = (mx & 1) == 0 && hx > 1;
+    if (pair_n) {
+        for (int y = tid; y < my; y += BLOCK) S[hidx(d, y, 0)] = C{S[hidx(d, y, 0)].x, S[hidx(d, y, hx - 1)].x};
+        __syncthreads();
+    }
+    if (d.swc) fft_lines<C, 0, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
+    else fft_lines<C, 0>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
     __syncthreads();
+    if (pair_n) {
+        for (int ky = tid; ky <= my / 2; ky += BLOCK) {
+            const int kn = ky == 0 ? 0 : my - ky;
+            const C zp = S[hidx(d, ky, 0)], zm = S[hidx(d, kn, 0)];
+            const C h0 = C{(T)0.5 * (zp.x + zm.x), (T)0.5 * (zp.y - zm.y)};  // (Z(k) + Z(-k)*) / 2
+            const C hn = C{(T)0.5 * (zp.y + zm.y), (T)0.5 * (zm.x - zp.x)};  // (Z(k) - Z(-k)*) / 2i
+            S[hidx(d, ky, 0)] = h0;
+            S[hidx(d, ky, hx - 1)] = hn;
+            if (kn != ky) {
+                S[hidx(d, kn, 0)] = C{h0.x, -h0.y};
+                S[hidx(d, kn, hx - 1)] = C{hn.x, -hn.y};
+            }
+        }
+        __syncthreads();
+    }
     C* dst = spec + ((long long)K * d.mz + z) * d.hplane;
-    for (int i = tid; i < my * hx; i += BLOCK) dst[i] = S[i];
+    Walk2 w(tid, hx, BLOCK);
+    for (int i = tid; i < my * hx; i += BLOCK, w.next()) dst[i] = S[hidx(d, w.p, w.x)];
 }
 
 // Contribution of gradient plane z (component a, species K, held in LDS in the
-// row-pair layout) to the non-bonded force of every bead whose stencil reaches
-// the plane: the beads of the P slabs z-P+1 .. z.  A bead of slab z - c gets
+// extended row-pair layout) to the non-bonded force of every bead whose
+// stencil reaches the plane: the beads of the P slabs z-P+1 .. z.  A bead of
+// slab z - c gets
 //   fpart[a][c][j] = -w_z[c] sum_{b,a'} w_y[b] w_x[a'] d_a phi(g0y + b, g0x + a'),
 // so that its force component a is the sum of fpart[a][0 .. P-1][j].
 template <typename T, int P>
 __device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4* __restrict__ pos,
-                           const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, const Dims d,
-                           int z, int K, int a, long long n, T* __restrict__ fpart, int tid, int nthr) {
+                                           const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
+                                           const Dims d, int z, int K, int a, long long n, T* __restrict__ fpart,
+                                           int tid, int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
         int s = z - c;
@@ -289,40 +418,38 @@ __device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4
                 const uint32_t j = jb + (uint32_t)(u * nthr);
                 if (j >= j1) break;
                 const uint4 q = qv[u];
-                int gx, gy, gz;
-                T wx[P], wy[P], wz[P];
-                assignment_weights<T, P>(q.z - sz, d.mz, gz, wz);  // gz == s: keys are exact
+                int gx, gy;
+                T wx[P], wy[P];
                 assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
                 assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                T wzs[P];  // only wzs[c] survives unrolling
+                spline_weights<T, P>(stencil_fraction<T>(q.z - sz, d.mz, P), wzs);
+                const T wz = wzs[c];
+                const RowOffsets<P> ro(gy, pr);
                 T acc = 0;
 #pragma unroll
                 for (int b = 0; b < P; ++b) {
-                    int y = gy + b;
-                    if (y >= d.my) y -= d.my;
-                    const T* row = Sr + 4 * (y >> 1) * d.hx + (y & 1);
+                    const T* row = Sr + ro.o[b] + 2 * gx;
                     T ra = 0;
 #pragma unroll
-                    for (int a2 = 0; a2 < P; ++a2) {
-                        int x = gx + a2;
-                        if (x >= d.mx) x -= d.mx;
-                        ra += wx[a2] * row[2 * x];
-                    }
+                    for (int a2 = 0; a2 < P; ++a2) ra += wx[a2] * row[2 * a2];
                     acc += wy[b] * ra;
                 }
-                out[j] = -wz[c] * acc;
+                out[j] = -wz * acc;
             }
         }
     }
 }
 
 // Inverse (one workgroup per plane z, species K and axis a = x, y, z): build
-// the half spectrum of d_a phi_K on plane z
-// (pitch hx), inverse FFT along y, then complex-to-real along x with rows 2p
-// and 2p+1 carried as the real and imaginary parts of one complex row, packed
-// in place at complex offset p * 2hx by the lanes that then transform it; the
-// finished plane d_a phi_K(z) is interpolated onto the beads that reach it.
+// the half spectrum of d_a phi_K on plane z (row pitch hxp), inverse FFT
+// along y, then complex-to-real along x with rows 2p and 2p+1 carried as the
+// real and imaginary parts of one complex row, packed in place at complex
+// offset p * zp by the lanes that then transform it; the ghost columns and
+// rows are filled in, and the finished plane d_a phi_K(z) is interpolated
+// onto the beads that reach it.
 template <typename T, int BLOCK, int P>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n) {
@@ -334,27 +461,62 @@ __global__ void __launch_bounds__(BLOCK)
     // species: all of them read the same bead slabs
     const int t = xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
     const int a = t % 3, z = (t / 3) % d.mz, K = t / (3 * d.mz);
-    const int mx = d.mx, my = d.my, hx = d.hx, np = d.npair, zp = 2 * d.hx;
+    const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
-    const C* twl = stage_twiddles(S + np * zp, tw, d, tid, BLOCK);
+    const C* twl = stage_twiddles(S + d.npg * zp, tw, d, tid, BLOCK);
     {
+        // the plane's half spectrum, sixteen loads in flight per thread
         const C* src = zout + ((long long)(a < 2 ? K : 2 + K) * d.mz + z) * d.hplane;
-        for (int i = tid; i < my * hx; i += BLOCK) {
-            const int ky = i / hx, kx = i - ky * hx;
-            C v = src[i];
-            if (a == 0) {
-                const T k = (2 * kx == mx) ? (T)0 : kfx * (T)kx;
-                v = C{-k * v.y, k * v.x};
-            } else if (a == 1) {
-                const int ny = ky > my / 2 ? ky - my : ky;
-                const T k = (2 * ky == my) ? (T)0 : kfy * (T)ny;
-                v = C{-k * v.y, k * v.x};
+        constexpr int LB = 16;
+        const int tot = my * hx;
+        Walk2 w(tid, hx, BLOCK);
+        for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
+            C v[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int i = i0 + u * BLOCK;
+                v[u] = i < tot ? src[i] : C{0, 0};
             }
-            S[i] = v;
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                if (i0 + u * BLOCK < tot) {
+                    const int ky = w.p, kx = w.x;
+                    C vv = v[u];
+                    if (a == 0) {
+                        const T k = (2 * kx == mx) ? (T)0 : kfx * (T)kx;
+                        vv = C{-k * vv.y, k * vv.x};
+                    } else if (a == 1) {
+                        const int ny = ky > my / 2 ? ky - my : ky;
+                        const T k = (2 * ky == my) ? (T)0 : kfy * (T)ny;
+                        vv = C{-k * vv.y, k * vv.x};
+                    }
+                    S[hidx(d, ky, kx)] = vv;
+                }
+                w.next();
+            }
         }
         __syncthreads();
-        fft_lines<C, 1>(S, LineMap{hx, hx, 1, 0, hx}, py, twl, tid, BLOCK);
+        // For even mx the columns kx = 0 and kx = mx/2 transform back to real
+        // rows; one y transform of Z = G_0 + i G_N gives both.
+        const bool pair_n = (mx & 1) == 0 && hx > 1;
+        if (pair_n) {
+            for (int y = tid; y < my; y += BLOCK) {
+                const C g0 = S[hidx(d, y, 0)], gn = S[hidx(d, y, hx - 1)];
+                S[hidx(d, y, 0)] = C{g0.x - gn.y, g0.y + gn.x};
+            }
+            __syncthreads();
+        }
+        if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
+        else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
         __syncthreads();
+        if (pair_n) {
+            for (int y = tid; y < my; y += BLOCK) {
+                const C zv = S[hidx(d, y, 0)];
+                S[hidx(d, y, 0)] = C{zv.x, (T)0};
+                S[hidx(d, y, hx - 1)] = C{zv.y, (T)0};
+            }
+            __syncthreads();
+        }
         {
             const int G = px.group, lane = tid % G;
             for (int p = tid / G; p < np; p += BLOCK / G) {
@@ -367,12 +529,12 @@ __global__ void __launch_bounds__(BLOCK)
                     if (x < mx) {
                         C A, B;
                         if (x < hx) {
-                            A = S[base + x];
-                            B = odd ? S[base + hx + x] : C{0, 0};
+                            A = S[hidx(d, 2 * p, x)];
+                            B = odd ? S[hidx(d, 2 * p + 1, x)] : C{0, 0};
                         } else {
                             const int xs = mx - x;
-                            const C a0 = S[base + xs];
-                            const C b0 = odd ? S[base + hx + xs] : C{0, 0};
+                            const C a0 = S[hidx(d, 2 * p, xs)];
+                            const C b0 = odd ? S[hidx(d, 2 * p + 1, xs)] : C{0, 0};
                             A = C{a0.x, -a0.y};
                             B = C{b0.x, -b0.y};
                         }
@@ -390,7 +552,23 @@ __global__ void __launch_bounds__(BLOCK)
             }
         }
         __syncthreads();
-        const T* Sr = reinterpret_cast<const T*>(smem);
+        T* Sr = reinterpret_cast<T*>(smem);
+        if constexpr (P > 1) {
+            // ghost columns of the real rows, then ghost rows (ghost columns included)
+            const int pr = 4 * hxp;
+            for (int i = tid; i < my * (P - 1); i += BLOCK) {
+                const int y = i / (P - 1), e = i - y * (P - 1);
+                const int o = __mul24(y >> 1, pr) + (y & 1);
+                Sr[o + 2 * (mx + e)] = Sr[o + 2 * e];
+            }
+            __syncthreads();
+            for (int i = tid; i < (P - 1) * (mx + P - 1); i += BLOCK) {
+                const int e = i / (mx + P - 1), x = i - e * (mx + P - 1);
+                const int yg = my + e;
+                Sr[__mul24(yg >> 1, pr) + (yg & 1) + 2 * x] = Sr[__mul24(e >> 1, pr) + (e & 1) + 2 * x];
+            }
+            __syncthreads();
+        }
         push_plane<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK);
     }
 }
@@ -401,11 +579,22 @@ __global__ void __launch_bounds__(BLOCK)
 // all z.  After the forward z FFT the spectra c^_A, c^_B become
 //   Phi^_K = (u^/N) sum_L eps_KL c^_L,  eps_AA = eps_BB = kappa, eps_AB = chi + kappa,
 // with u^ = exp(-a^2 k^2) (zero at k = 0: the k = 0 field has no gradient),
-// and both Phi^_K and ik_z Phi^_K are transformed back along z.  With
-// `want_energy` the block also accumulates, in float64 over the half
-// spectrum (weight 2 for kx strictly between 0 and mx/2):
+// and both Phi^_K and ik_z Phi^_K are transformed back along z.  u^ factors
+// into exp(-a^2 (kx^2 + ky^2)) per column and exp(-a^2 kz^2) per plane, both
+// tabulated in LDS once per block.  With `want_energy` the block also
+// accumulates, in float64 over the half spectrum (weight 2 for kx strictly
+// between 0 and mx/2):
 //   sum u^ Re(c^_A* c^_B), sum_{k!=0} u^ |c^_A + c^_B|^2 and, per axis,
 //   sum k_a^2 u^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2].
+//
+// LDS: [4 mz][cb + 1] complex, twiddles, then the tables (z_lds_bytes).
+struct ZColumn {
+    double uxy, kx, ky, w;  // exp(-a^2 (kx^2+ky^2)) (0 past the last column), wavenumbers, energy weight
+};
+struct ZPlane {
+    double uz, kz;  // exp(-a^2 kz^2), wavenumber
+};
+
 template <typename T, int BLOCK, int ENERGY_ONLY>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
@@ -417,66 +606,90 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     const int tid = threadIdx.x;
     const int mz = d.mz, my = d.my, mx = d.mx, hx = d.hx;
     const int cbp = cb + 1;
-    C* b1 = b0 + 2 * mz * cbp;
     const C* twl = stage_twiddles(b0 + 4 * mz * cbp, tw, d, tid, BLOCK);
-    const long long cn = d.hplane;
-    const long long c0 = (long long)blockIdx.x * cb;
-    for (int i = tid; i < 2 * mz * cb; i += BLOCK) {
-        const int K = i / (mz * cb);
-        const int r = i - K * mz * cb;
-        const int z = r / cb, j = r - z * cb;
-        const long long c = c0 + j;
-        b0[(K * mz + z) * cbp + j] = c < cn ? spec[((long long)K * mz + z) * cn + c] : C{0, 0};
+    ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + d.mx + d.my + d.mz);
+    ZColumn* ct = reinterpret_cast<ZColumn*>(zt + mz);
+    const int cn = (int)d.hplane;
+    const int c0 = blockIdx.x * cb;
+    const double kfx = kTwoPi / ph.lx, kfy = kTwoPi / ph.ly, kfz = kTwoPi / ph.lz;
+    {
+        // both spectra of the block's columns, eight loads in flight per thread
+        constexpr int LB = 8;
+        const int tot = 2 * mz * cb;
+        Walk2 w(tid, cb, BLOCK);
+        for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
+            C v[LB];
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                const int i = i0 + u * BLOCK;
+                v[u] = C{0, 0};
+                if (i < tot) {
+                    const int row = w.p, j = w.x;
+                    if (c0 + j < cn) v[u] = spec[(long long)row * cn + c0 + j];
+                }
+                w.next();
+            }
+            Walk2 w2(i0, cb, BLOCK);
+#pragma unroll
+            for (int u = 0; u < LB; ++u) {
+                if (i0 + u * BLOCK < tot) b0[w2.p * cbp + w2.x] = v[u];
+                w2.next();
+            }
+        }
+        for (int z = tid; z < mz; z += BLOCK) {
+            const double kz = kfz * (double)(z > mz / 2 ? z - mz : z);
+            zt[z] = ZPlane{::exp(-ph.a2 * kz * kz), kz};
+        }
+        for (int j = tid; j < cb; j += BLOCK) {
+            const int c = c0 + j;
+            const int ky = c / hx, kx = c - ky * hx;
+            const double kxv = kfx * (double)kx, kyv = kfy * (double)(ky > my / 2 ? ky - my : ky);
+            const double u = c < cn ? ::exp(-ph.a2 * (kxv * kxv + kyv * kyv)) : 0.0;
+            ct[j] = ZColumn{u, kxv, kyv, (kx == 0 || 2 * kx == mx) ? 1.0 : 2.0};
+        }
     }
     __syncthreads();
-    fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp}, pz, twl, tid, BLOCK);
+    fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
     __syncthreads();
 
     double acc[5] = {0, 0, 0, 0, 0};
-    const double kfx = kTwoPi / ph.lx, kfy = kTwoPi / ph.ly, kfz = kTwoPi / ph.lz;
-    const T a2 = (T)ph.a2, inv_n = (T)ph.inv_n, kap = (T)ph.kappa, cpk = (T)(ph.chi + ph.kappa);
-    for (int i = tid; i < mz * cb; i += BLOCK) {
-        const int z = i / cb, j = i - z * cb;
-        const long long c = c0 + j;
-        const C A = b0[z * cbp + j], B = b0[(mz + z) * cbp + j];
-        C PA{0, 0}, PB{0, 0}, QA{0, 0}, QB{0, 0};
-        if (c < cn) {
-            const int ky = (int)(c / hx), kx = (int)(c - (long long)ky * hx);
-            const int ny = ky > my / 2 ? ky - my : ky;
-            const int nz = z > mz / 2 ? z - mz : z;
-            if (kx != 0 || ny != 0 || nz != 0) {
-                const T kxv = (T)(kfx * kx), kyv = (T)(kfy * ny), kzv = (T)(kfz * nz);
-                const T k2 = kxv * kxv + kyv * kyv + kzv * kzv;
-                const T f = exp(-a2 * k2) * inv_n;
+    const T inv_n = (T)ph.inv_n, kap = (T)ph.kappa, cpk = (T)(ph.chi + ph.kappa);
+    {
+        Walk2 w(tid, cb, BLOCK);
+        for (int i = tid; i < mz * cb; i += BLOCK, w.next()) {
+            const int z = w.p, j = w.x;
+            const C A = b0[z * cbp + j], B = b0[(mz + z) * cbp + j];
+            const ZColumn col = ct[j];
+            const ZPlane pl = zt[z];
+            C PA{0, 0}, PB{0, 0}, QA{0, 0}, QB{0, 0};
+            if (col.uxy != 0.0 && (c0 + j != 0 || z != 0)) {
+                const T f = (T)col.uxy * (T)pl.uz * inv_n;
                 PA = C{f * (kap * A.x + cpk * B.x), f * (kap * A.y + cpk * B.y)};
                 PB = C{f * (cpk * A.x + kap * B.x), f * (cpk * A.y + kap * B.y)};
-                const T kzd = (2 * z == mz) ? (T)0 : kzv;
+                const T kzd = (2 * z == mz) ? (T)0 : (T)pl.kz;
                 QA = C{-kzd * PA.y, kzd * PA.x};
                 QB = C{-kzd * PB.y, kzd * PB.x};
                 if (want_energy) {
-                    const double w = (kx == 0 || 2 * kx == mx) ? 1.0 : 2.0;
-                    const double dkx = kfx * kx, dky = kfy * ny, dkz = kfz * nz;
-                    const double uh = w * ::exp(-ph.a2 * (dkx * dkx + dky * dky + dkz * dkz));
+                    const double uh = col.w * col.uxy * pl.uz;
                     const double cross = (double)A.x * B.x + (double)A.y * B.y;
                     const double sx = (double)A.x + B.x, sy = (double)A.y + B.y;
                     const double plus = sx * sx + sy * sy;
                     const double core = uh * (ph.chi * ph.inv_n * cross + 0.5 * ph.kappa * ph.inv_n * plus);
                     acc[0] += uh * cross;
                     acc[1] += uh * plus;
-                    acc[2] += dkx * dkx * core;
-                    acc[3] += dky * dky * core;
-                    acc[4] += dkz * dkz * core;
+                    acc[2] += col.kx * col.kx * core;
+                    acc[3] += col.ky * col.ky * core;
+                    acc[4] += pl.kz * pl.kz * core;
                 }
-            } else if (want_energy) {
-                // k = 0 of the mean-subtracted counts is zero; the constant
-                // chi N_A N_B / N is added when the partials are reduced.
             }
-        }
-        if (!ENERGY_ONLY) {
-            b0[z * cbp + j] = PA;
-            b0[(mz + z) * cbp + j] = PB;
-            b1[z * cbp + j] = QA;
-            b1[(mz + z) * cbp + j] = QB;
+            // k = 0 of the mean-subtracted counts is zero; the constant
+            // chi N_A N_B / N is added when the partials are reduced.
+            if (!ENERGY_ONLY) {
+                b0[z * cbp + j] = PA;
+                b0[(mz + z) * cbp + j] = PB;
+                b0[(2 * mz + z) * cbp + j] = QA;
+                b0[(3 * mz + z) * cbp + j] = QB;
+            }
         }
     }
     if (want_energy) {
@@ -486,14 +699,14 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     }
     if (ENERGY_ONLY) return;
     __syncthreads();
-    fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp}, pz, twl, tid, BLOCK);
+    fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
     __syncthreads();
-    for (int i = tid; i < 4 * mz * cb; i += BLOCK) {
-        const int q = i / (mz * cb);
-        const int r = i - q * mz * cb;
-        const int z = r / cb, j = r - z * cb;
-        const long long c = c0 + j;
-        if (c < cn) zout[((long long)q * mz + z) * cn + c] = b0[(q * mz + z) * cbp + j];
+    {
+        Walk2 w(tid, cb, BLOCK);
+        for (int i = tid; i < 4 * mz * cb; i += BLOCK, w.next()) {
+            const int c = c0 + w.x;
+            if (c < cn) zout[(long long)w.p * cn + c] = b0[w.p * cbp + w.x];
+        }
     }
 }
 
@@ -884,12 +1097,13 @@ static inline unsigned blocks_for(long long n, int per) { return (unsigned)((n +
 
 size_t plane_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * ((size_t)L.d.npair * (size_t)(2 * L.d.hx) + (size_t)(L.d.mx + L.d.my + L.d.mz));
+    return c * ((size_t)L.d.npg * (size_t)(2 * L.d.hxp) + (size_t)(L.d.mx + L.d.my + L.d.mz));
 }
 
 size_t z_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1) + (size_t)(L.d.mx + L.d.my + L.d.mz));
+    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1) + (size_t)(L.d.mx + L.d.my + L.d.mz)) +
+           sizeof(ZPlane) * (size_t)L.d.mz + sizeof(ZColumn) * (size_t)L.z_cols;
 }
 
 // Calls f(std::integral_constant<int, P>{}) for the stencil order P = order.
