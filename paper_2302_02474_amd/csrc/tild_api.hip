@@ -239,11 +239,11 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         mark(kSpreadXy, 0);
         c->S.noise_step = 1;
         c->S.step = c->step;
-        if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);
-        c->S.noise_step = 0;
+        if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);  // also sums the step's noise per plane
         mark(kSpreadXy, 1);
         mark(kZKmul, 0);
-        if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);
+        if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);  // also forms the new shift
+        c->S.noise_step = 0;
         mark(kZKmul, 1);
         mark(kXyC2r, 0);
         if (e == hipSuccess) e = launch_xy_c2r(c->L, c->S);
@@ -349,7 +349,8 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     d.npair = (d.my + 1) / 2;
     // LDS plane: pair rows of 2 hxp complex, with room for P - 1 ghost columns
     // and P - 1 ghost rows past the periodic edge
-    d.hxp = std::max(d.hx, (d.mx + params->order) / 2);
+    // (odd, so that consecutive pair rows start in different LDS bank groups)
+    d.hxp = std::max(d.hx, (d.mx + params->order) / 2) | 1;
     d.npg = (d.my + params->order) / 2;
     d.ylines = (d.mx % 2 == 0 && d.hx > 1) ? d.hx - 1 : d.hx;
     d.swc = d.ylines % 16 == 0 ? d.ylines : 0;

@@ -10,7 +10,6 @@
 
 namespace tild {
 
-constexpr int kUpdateBlocks = 1024;  // workgroups of the (grid-stride) update kernel
 constexpr int kZBlock = 512;         // threads per workgroup of the z pass
 constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
 
@@ -68,7 +67,8 @@ struct DeviceState {
     long long n;
     long long n_a, n_b;
     int deg;              // bond slots per bead (maximum degree)
-    int noise_step;       // the spread also sums the noise of step `step` (set while stepping)
+    int noise_step;       // set while stepping: the spread sums the noise of step `step`, the k-space
+                          // pass forms qshift_next from it
     long long step;       // step index of the noise the spread sums
     int nbins;            // 2 * mz * my
 };
@@ -93,7 +93,8 @@ struct Launch {
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S);
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only);
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S);
-// mode 0: Euler-Maruyama step (writes pos_tmp, kr, counts and qshift_next);
+// mode 0: Euler-Maruyama step with the shift the k-space pass formed in qshift_next
+// (writes pos_tmp, kr, counts);
 // mode 1: write forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts);

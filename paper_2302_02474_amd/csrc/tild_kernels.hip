@@ -587,7 +587,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 //   sum u^ Re(c^_A* c^_B), sum_{k!=0} u^ |c^_A + c^_B|^2 and, per axis,
 //   sum k_a^2 u^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2].
 //
-// LDS: [4 mz][cb + 1] complex, twiddles, then the tables (z_lds_bytes).
+// LDS: [4 mz][cbp] complex with the odd pitch cbp = cb | 1 (the radix-8
+// outputs of a line, eight rows apart, then spread over four LDS bank
+// groups), twiddles, then the tables (z_lds_bytes).
 struct ZColumn {
     double uxy, kx, ky, w;  // exp(-a^2 (kx^2+ky^2)) (0 past the last column), wavenumbers, energy weight
 };
@@ -595,17 +597,40 @@ struct ZPlane {
     double uz, kz;  // exp(-a^2 kz^2), wavenumber
 };
 
+//
+// While stepping (noise_part given), the last block, whose column range is
+// the shortest, also forms the step's centre-of-mass shift: the forces sum to
+// zero exactly (pairwise bonds; the ik route with the Nyquist derivative
+// zeroed), so the mean displacement is sqrt(2 kT dt/gamma) times the mean
+// Gaussian increment, which the spread pass summed per plane.
 template <typename T, int BLOCK, int ENERGY_ONLY>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
-                                                  double* __restrict__ epart, int want_energy) {
+                                                  double* __restrict__ epart, int want_energy,
+                                                  const double* __restrict__ noise_part, long long n,
+                                                  const uint32_t* __restrict__ qs, uint32_t* __restrict__ qs_next) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[5 * (BLOCK / 64)];
+    if (noise_part && blockIdx.x == gridDim.x - 1) {
+        double v[3] = {0, 0, 0};
+        for (int i = threadIdx.x; i < 2 * d.mz; i += BLOCK)
+            for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
+        block_sum<double, 3>(v, red, threadIdx.x, BLOCK);
+        if (threadIdx.x == 0) {
+            const double L[3] = {ph.lx, ph.ly, ph.lz};
+            for (int a = 0; a < 3; ++a) {
+                long long shift = 0;
+                if (ph.com_correct && n > 0) shift = llround(ph.noise_amp * v[a] / (double)n * (kTwo32 / L[a]));
+                qs_next[a] = qs[a] + (uint32_t)shift;
+            }
+            qs_next[3] = 0u;
+        }
+    }
     C* b0 = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     const int mz = d.mz, my = d.my, mx = d.mx, hx = d.hx;
-    const int cbp = cb + 1;
+    const int cbp = cb | 1;
     const C* twl = stage_twiddles(b0 + 4 * mz * cbp, tw, d, tid, BLOCK);
     ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + d.mx + d.my + d.mz);
     ZColumn* ct = reinterpret_cast<ZColumn*>(zt + mz);
@@ -730,91 +755,73 @@ __device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t*
     return base + (uint32_t)(lane - hl);
 }
 
-// Beads in sorted order (grid-stride): F = sum of the P plane partials of each
+// Beads in sorted order, one per thread: F = sum of the P plane partials of each
 // component (non-bonded, ik route) + the stored bond force.
 // MODE 0: Euler-Maruyama step.  The centre-of-mass correction subtracts the
 //         mean displacement; the forces sum to zero exactly (pairwise bonds;
 //         the ik route with the Nyquist derivative zeroed conserves momentum),
-//         so that mean is sqrt(2 kT dt/gamma) times the mean noise, which the
-//         spread pass has already summed per plane (noise_part).  Every block
-//         forms the same integer shift from it, so each moved bead goes to
-//         pout[j] with its exact new bin key and its rank in that bin.
+//         so that mean is sqrt(2 kT dt/gamma) times the mean noise, from which
+//         the k-space pass has already formed the new integer shift (qs_new).
+//         Each moved bead goes to pout[j] with its exact new bin key and its
+//         rank in that bin.
 // MODE 1: forces only, written to out[abi id] ([n][3], float or double).
 template <typename T, int P, int MODE>
 __global__ void __launch_bounds__(256)
     k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
-             const T* __restrict__ fpart, const uint32_t* __restrict__ qs_in, uint32_t* __restrict__ qs_out,
-             long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts,
-             const double* __restrict__ noise_part, int n_noise, uint2* __restrict__ kr,
+             const T* __restrict__ fpart, const uint32_t* __restrict__ qs_new,
+             long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts, uint2* __restrict__ kr,
              uint32_t* __restrict__ counts, uint32_t* __restrict__ flag) {
-    __shared__ uint32_t shs[3];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const bool need_field = MODE == 0 || (parts & 1u);
     const bool need_bond = MODE == 0 || (parts & 2u);
     if (MODE == 0) {
-        const uint32_t sh[3] = {qs_in[0], qs_in[1], qs_in[2]};
-        if (wave == 0) {
-            double v[3] = {0, 0, 0};
-            for (int i = lane; i < n_noise; i += 64)
-                for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
-            const double L[3] = {ph.lx, ph.ly, ph.lz};
+        // one bead per thread; its loads are issued before the shift is formed
+        const long long j = blockIdx.x * 256LL + tid;
+        const bool active = j < n;
+        uint4 q = uint4{0u, 0u, 0u, 0u};
+        T f[3] = {0, 0, 0};
+        if (active) {
+            q = pin[j];
+            f[0] = fbond[4 * j + 0];
+            f[1] = fbond[4 * j + 1];
+            f[2] = fbond[4 * j + 2];
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const double tot = wave_sum(v[a]);
-                long long shift = 0;
-                if (ph.com_correct && n > 0) shift = llround(ph.noise_amp * tot / (double)n * (kTwo32 / L[a]));
-                if (lane == 0) shs[a] = sh[a] + (uint32_t)shift;
+                T sa = 0;
+#pragma unroll
+                for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
+                f[a] += sa;
             }
         }
-        __syncthreads();
-        const uint32_t nsh[3] = {shs[0], shs[1], shs[2]};
-        if (blockIdx.x == 0 && tid == 0) {
-            qs_out[0] = nsh[0];
-            qs_out[1] = nsh[1];
-            qs_out[2] = nsh[2];
-            qs_out[3] = 0u;
-        }
-        const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
-        const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
-        // whole wavefronts step together so that the rank aggregation sees full waves
-        for (long long base = ((long long)blockIdx.x * 4 + wave) * 64; base < n; base += (long long)gridDim.x * 256) {
-            const long long j = base + lane;
-            const bool active = j < n;
-            uint32_t kb = 0xffffffffu;
-            uint4 qn = uint4{0u, 0u, 0u, 0u};
-            if (active) {
-                const uint4 q = pin[j];
-                T f[3] = {fbond[4 * j + 0], fbond[4 * j + 1], fbond[4 * j + 2]};
+        const uint32_t nsh[3] = {qs_new[0], qs_new[1], qs_new[2]};  // formed by the k-space pass
+        uint32_t kb = 0xffffffffu;
+        if (active) {
+            const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
+            const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
+            T xi[3];
+            Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
+            long long dq[3] = {0, 0, 0};
+            bool bad = false;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    T sa = 0;
-#pragma unroll
-                    for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
-                    f[a] += sa;
-                }
-                T xi[3];
-                Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
-                long long dq[3] = {0, 0, 0};
-                bool bad = false;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T disp = mob * f[a] + amp * xi[a];
-                    const double sd = (double)disp * inv_l[a];
-                    if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
-                    else dq[a] = llrint(sd);
-                }
-                if (bad) {
-                    atomicOr(flag, 1u);
-                    dq[0] = dq[1] = dq[2] = 0;
-                }
-                qn = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
-                pout[j] = qn;
-                kb = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
+            for (int a = 0; a < 3; ++a) {
+                const T disp = mob * f[a] + amp * xi[a];
+                const double sd = (double)disp * inv_l[a];
+                if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
+                else dq[a] = llrint(sd);
             }
-            const uint32_t r = bin_rank(kb, active, counts);
-            if (active) kr[j] = uint2{kb, r};
+            if (bad) {
+                atomicOr(flag, 1u);
+                dq[0] = dq[1] = dq[2] = 0;
+            }
+            const uint4 qn = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
+            pout[j] = qn;
+            kb = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
         }
+        const uint32_t r = bin_rank(kb, active, counts);  // whole wavefronts take part
+        if (active) kr[j] = uint2{kb, r};
     } else {
-        for (long long j = blockIdx.x * 256LL + tid; j < n; j += (long long)gridDim.x * 256) {
+        const long long j = blockIdx.x * 256LL + tid;
+        if (j < n) {
             const uint4 q = pin[j];
             const uint32_t id = q.w >> 1;
             T f[3] = {0, 0, 0};
@@ -1102,7 +1109,7 @@ size_t plane_lds_bytes(const Launch& L) {
 
 size_t z_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols + 1) + (size_t)(L.d.mx + L.d.my + L.d.mz)) +
+    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols | 1) + (size_t)(L.d.mx + L.d.my + L.d.mz)) +
            sizeof(ZPlane) * (size_t)L.d.mz + sizeof(ZColumn) * (size_t)L.z_cols;
 }
 
@@ -1160,7 +1167,7 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
 template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
     hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
-                       S.epart, want_energy);
+                       S.epart, want_energy, S.noise_step ? S.noise_part : nullptr, S.n, S.qshift, S.qshift_next);
 }
 
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
@@ -1176,11 +1183,11 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
 
 template <typename T, int P, int MODE>
 static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
-    // at least one block: in MODE 0 block 0 writes the new shift
-    const unsigned g = std::min<unsigned>(blocks_for(S.n > 0 ? S.n : 1, 256), (unsigned)kUpdateBlocks);
+    // one bead per thread, at least one block
+    const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
-                       (const T*)S.fpart, S.qshift, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts,
-                       S.noise_part, 2 * L.d.mz, S.kr, S.counts, S.flag);
+                       (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, S.kr, S.counts,
+                       S.flag);
 }
 
 template <typename T, int MODE>
