@@ -55,13 +55,6 @@ __device__ __forceinline__ void block_sum(V* vals, V* scratch /* [NV][nwaves] */
     __syncthreads();
 }
 
-// Copy the twiddle tables (x, y and z axes, concatenated) into LDS.
-template <typename C>
-__device__ __forceinline__ const C* stage_twiddles(C* dst, const C* __restrict__ tw, const Dims d, int tid, int nthr) {
-    for (int i = tid; i < d.mx + d.my + d.mz; i += nthr) dst[i] = tw[i];
-    return dst;
-}
-
 // ------------------------------------------------------------ bins
 
 // Bin key of a bead: (species, first stencil plane in z, first stencil row in y).
@@ -216,18 +209,14 @@ __device__ __forceinline__ void fold_ghosts(A* acc, const Dims d, int tid, int n
     __syncthreads();
 }
 
-// Scale of the fixed-point spread of plane z: the largest 2^k (k <= 24) for
-// which no cell can overflow int32.  A cell of row y is reached only by beads
-// of the P slabs z-P+1 .. z and the P row bins y-P+1 .. y, each contributing at
-// most wmax, so their number times wmax bounds its count.  The P row bins of
-// one slab are consecutive (modulo the row wrap), so each slab's share is a
-// difference of two bin starts.
+// Bound on the count of any cell of row y of plane z: a cell of row y is
+// reached only by beads of the P slabs z-P+1 .. z and the P row bins
+// y-P+1 .. y.  The P row bins of one slab are consecutive (modulo the row
+// wrap), so each slab's share is a difference of two bin starts.  Returns
+// the largest such bead count over the rows this thread visits.
 template <int P>
-__device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K,
-                                              double wmax, uint32_t* __restrict__ flag, uint32_t* smax, int tid,
-                                              int nthr) {
-    if (tid == 0) *smax = 0u;
-    __syncthreads();
+__device__ __forceinline__ uint32_t stencil_count_max(const uint32_t* __restrict__ bin_start, const Dims d, int z,
+                                                      int K, int tid, int nthr) {
     uint32_t mine = 0;
     for (int y = tid; y < d.my; y += nthr) {
         uint32_t lo[P], hi[P], lo2[P], hi2[P];
@@ -253,9 +242,14 @@ __device__ __forceinline__ float spread_scale(const uint32_t* __restrict__ bin_s
         for (int c = 0; c < P; ++c) sum += (hi[c] - lo[c]) + (hi2[c] - lo2[c]);
         mine = mine > sum ? mine : sum;
     }
-    atomicMax(smax, mine);
-    __syncthreads();
-    const double bound = (double)(*smax) * wmax + 1.0;
+    return mine;
+}
+
+// Scale of the fixed-point spread of a plane: the largest 2^k (k <= 24) for
+// which no cell can overflow int32, each bead contributing at most wmax to a
+// cell whose count of reaching beads is at most maxcount.
+__device__ __forceinline__ float spread_scale(uint32_t maxcount, double wmax, uint32_t* __restrict__ flag, int tid) {
+    const double bound = (double)maxcount * wmax + 1.0;
     int k = 24;
     while (k > 8 && bound * (double)(1 << k) >= 2147483647.0) --k;
     if (bound * (double)(1 << k) >= 2147483647.0 && tid == 0) atomicOr(flag, 4u);
@@ -278,7 +272,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     using C = cplx<T>;
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, T>::type;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t smax;
+    __shared__ uint32_t smax[BLOCK / 64];
     __shared__ double nred[3 * (BLOCK / 64)];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
@@ -287,12 +281,36 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     const int z = t % d.mz, K = t / d.mz;
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
-    const C* twl = stage_twiddles(S + d.npg * zp, tw, d, tid, BLOCK);
     constexpr bool kFixed = sizeof(T) == 4;
-    T scale = (T)1;
-    if constexpr (kFixed) scale = spread_scale<P>(bin_start, d, z, K, ph.wmax, flag, &smax, tid, BLOCK);
+    // Prologue: issue the global loads (twiddles, bin starts) before zeroing
+    // the plane, then one barrier.
+    C* twl = S + d.npg * zp;
+    const int ntw = d.mx + d.my + d.mz;
+    C twv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
+    uint32_t mine = 0;
+    if constexpr (kFixed) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
     for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+        if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+    if constexpr (kFixed) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const uint32_t other = __shfl_xor(mine, o, 64);
+            mine = mine > other ? mine : other;
+        }
+        if ((tid & 63) == 0) smax[tid >> 6] = mine;
+    }
     __syncthreads();
+    T scale = (T)1;
+    if constexpr (kFixed) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < BLOCK / 64; ++w) m = m > smax[w] ? m : smax[w];
+        scale = spread_scale(m, ph.wmax, flag, tid);
+    }
     double nsum[3] = {0, 0, 0};
     spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK);
     if (noise) {
@@ -463,11 +481,15 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     const int a = t % 3, z = (t / 3) % d.mz, K = t / (3 * d.mz);
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
-    const C* twl = stage_twiddles(S + d.npg * zp, tw, d, tid, BLOCK);
+    C* twl = S + d.npg * zp;
+    const int ntw = d.mx + d.my + d.mz;
     {
-        // the plane's half spectrum, sixteen loads in flight per thread
+        C twv[3];  // twiddles, loaded with the plane and stored after it
+#pragma unroll
+        for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
+        // the plane's half spectrum, eighteen loads in flight per thread
         const C* src = zout + ((long long)(a < 2 ? K : 2 + K) * d.mz + z) * d.hplane;
-        constexpr int LB = 16;
+        constexpr int LB = 18;
         const int tot = my * hx;
         Walk2 w(tid, hx, BLOCK);
         for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
@@ -495,6 +517,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
                 w.next();
             }
         }
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
         __syncthreads();
         // For even mx the columns kx = 0 and kx = mx/2 transform back to real
         // rows; one y transform of Z = G_0 + i G_N gives both.
@@ -631,15 +656,19 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     const int tid = threadIdx.x;
     const int mz = d.mz, my = d.my, mx = d.mx, hx = d.hx;
     const int cbp = cb | 1;
-    const C* twl = stage_twiddles(b0 + 4 * mz * cbp, tw, d, tid, BLOCK);
+    C* twl = b0 + 4 * mz * cbp;
+    const int ntw = d.mx + d.my + d.mz;
+    C twv[2];  // twiddles, loaded with the spectra and stored after them
+#pragma unroll
+    for (int u = 0; u < 2; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
     ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + d.mx + d.my + d.mz);
     ZColumn* ct = reinterpret_cast<ZColumn*>(zt + mz);
     const int cn = (int)d.hplane;
     const int c0 = blockIdx.x * cb;
     const double kfx = kTwoPi / ph.lx, kfy = kTwoPi / ph.ly, kfz = kTwoPi / ph.lz;
     {
-        // both spectra of the block's columns, eight loads in flight per thread
-        constexpr int LB = 8;
+        // both spectra of the block's columns, nine loads in flight per thread
+        constexpr int LB = 9;
         const int tot = 2 * mz * cb;
         Walk2 w(tid, cb, BLOCK);
         for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
@@ -672,6 +701,9 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
             const double u = c < cn ? ::exp(-ph.a2 * (kxv * kxv + kyv * kyv)) : 0.0;
             ct[j] = ZColumn{u, kxv, kyv, (kx == 0 || 2 * kx == mx) ? 1.0 : 2.0};
         }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
     }
     __syncthreads();
     fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
