@@ -15,9 +15,12 @@ recorded on the library's stream) and the FP64 oracle timed on the host.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -29,6 +32,38 @@ if ROOT not in sys.path:
 
 METRIC = "TILD bead-steps/s at 648k beads, 128^3 grid; HBM GB/s vs peak; fwd+adj ms"
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_648k_beads_128cubed.md")
+
+
+def kernel_source_sha256() -> str:
+    """Digest of the kernel sources and the ABI header, in a fixed order."""
+    h = hashlib.sha256()
+    pkg = os.path.join(ROOT, "paper_2302_02474_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(pkg, "*.hip")) + glob.glob(os.path.join(pkg, "*.h")))
+    files.append(os.path.join(ROOT, "include", "tild.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when that summary was taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    v = rec.get("hbm_bytes_per_launch", {}).get(kernel)
+    return None if v is None else float(v)
 
 
 def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
@@ -52,7 +87,7 @@ def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
     }
 
 
-def cpu_baseline(melt, steps: int = 1) -> dict:
+def cpu_baseline(melt, steps: int = 5) -> dict:
     """The FP64 oracle, as written, on the same workload: `steps` full steps."""
     from oracle import tild_ref as R
 
@@ -126,6 +161,7 @@ def main() -> int:
                    "GBps": round(abytes[k] / (v * 1e-3) / 1e9, 1) if v > 0 else None}
                for k, v in kms.items()}
     step_bytes = sum(abytes.values())
+    traffic = measured_traffic(dom)
     t.close()
 
     # Achievable copy bandwidth with the library's own streaming kernel.
@@ -155,7 +191,9 @@ def main() -> int:
                    "beads": melt.n, "grid": [int(v) for v in melt.grid], "order": melt.order,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "traffic_unit": "bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": abytes[dom]},
         "step_algorithmic_GBps": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "step_algorithmic_MB": round(step_bytes / 1e6, 2),
         "stream_copy_GBps": round(stream_gbps, 1),
