@@ -90,6 +90,14 @@ extern "C" {
 
 /* tild_params.flags */
 #define TILD_COM_CORRECT 1u /* subtract the mean displacement of every step (centre-of-mass drift correction) */
+#define TILD_POTENTIAL_SAMPLED 2u /* kernel u^ = dV x DFT of the smearing Gaussian u_G sampled at the
+                                     minimum-image node separations (the potential built by FFT and stored,
+                                     Sec. "Long-range interactions"), instead of the analytic exp(-a^2 k^2);
+                                     needs smear_a > 0.  Energies use it (including the k = 0 constant
+                                     chi N_A N_B u^(0) / N); the virial keeps the analytic kernel. */
+#define TILD_DETERMINISTIC 4u /* accepted for compatibility: every result is already bitwise reproducible
+                                 run to run (the spread accumulates fixed-point integers in both precisions,
+                                 every reduction has a fixed order) */
 
 /* tild_forces parts */
 #define TILD_PART_NONBONDED 1u
@@ -119,22 +127,37 @@ typedef struct tild_params {
 } tild_params;
 
 /*
+ * Device bytes a context for these parameters and bonds needs: the size of a
+ * caller workspace for tild_create.  bonds as for tild_create (the partner
+ * table is as wide as the largest bead degree).  Touches no device.  Returns
+ * 0 when the arguments are invalid (the reason is in tild_last_error(NULL)).
+ */
+size_t tild_workspace_bytes(const tild_params* params, int64_t n_beads, int64_t n_bonds, const int32_t* bonds);
+
+/*
  * Create a context for n_beads beads.
  *   types:  host array [n_beads] of int32, 0 = species A, 1 = species B.
  *   bonds:  host array [2 * n_bonds] of int32 pairs (i, j), 0-based ABI
  *           indices, i != j; may be NULL when n_bonds == 0.
+ *   workspace, workspace_bytes: NULL, or device memory on the current device,
+ *           256-byte aligned, of at least tild_workspace_bytes(...) bytes,
+ *           owned by the caller and kept alive until tild_destroy; the
+ *           context then takes all its device buffers from it and allocates
+ *           no device memory (TILD_ENOMEM when it is too small).  NULL: the
+ *           library allocates and frees its own.
  *   hip_stream: a hipStream_t on the current device, or NULL.
  * Positions must be set with tild_set_positions before the first step,
  * force or energy call.  The step counter starts at 0.
  * Returns TILD_EINVAL for invalid parameters (grid not 2,3,5-smooth or out
  * of range, order out of range, non-positive box/dt/gamma, NULL arrays, bond
  * index out of range, types other than 0/1, a grid plane too large for one
- * workgroup's local memory in the chosen precision), TILD_ENOMEM or
- * TILD_EHIP.  On failure *out is set to NULL and the message is available
- * from tild_last_error(NULL) on the same thread.
+ * workgroup's local memory in the chosen precision, a workspace not 256-byte
+ * aligned), TILD_ENOMEM or TILD_EHIP.  On failure *out is set to NULL and
+ * the message is available from tild_last_error(NULL) on the same thread.
  */
 int tild_create(const tild_params* params, int64_t n_beads, const int32_t* types,
-                int64_t n_bonds, const int32_t* bonds, void* hip_stream, tild_ctx** out);
+                int64_t n_bonds, const int32_t* bonds, void* workspace, size_t workspace_bytes,
+                void* hip_stream, tild_ctx** out);
 
 /*
  * Set all positions.  xyz: [n_beads][3] in ABI order, element type dtype

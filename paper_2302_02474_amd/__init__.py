@@ -15,7 +15,7 @@ import numpy as np
 
 from . import _lib as _L
 from ._lib import (  # noqa: F401
-    TILD_COM_CORRECT, TILD_EHIP, TILD_EINVAL, TILD_ENOMEM, TILD_ENONFINITE, TILD_ESTATE,
+    TILD_COM_CORRECT, TILD_POTENTIAL_SAMPLED, TILD_DETERMINISTIC, TILD_EHIP, TILD_EINVAL, TILD_ENOMEM, TILD_ENONFINITE, TILD_ESTATE,
     TILD_FP32, TILD_FP64, TILD_OK, TILD_PART_BOND, TILD_PART_NONBONDED, TILD_PART_TOTAL,
     TildParams,
 )
@@ -32,7 +32,10 @@ def lib():
 
 
 def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0,
-                seed=0, precision=TILD_FP32, com_correct=True) -> TildParams:
+                seed=0, precision=TILD_FP32, com_correct=True, potential="analytic") -> TildParams:
+    """tild_params; potential is "analytic" (exp(-a^2 k^2)) or "sampled" (DFT of the node-sampled Gaussian)."""
+    if potential not in ("analytic", "sampled"):
+        raise ValueError(f"potential must be 'analytic' or 'sampled', got {potential!r}")
     p = TildParams()
     for a in range(3):
         p.box[a] = float(box[a])
@@ -47,7 +50,7 @@ def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gam
     p.kT = float(kT)
     p.seed = int(seed)
     p.precision = int(precision)
-    p.flags = TILD_COM_CORRECT if com_correct else 0
+    p.flags = (TILD_COM_CORRECT if com_correct else 0) | (TILD_POTENTIAL_SAMPLED if potential == "sampled" else 0)
     return p
 
 
@@ -75,19 +78,35 @@ def _ptr(x):
     return ctypes.c_void_p(x.ctypes.data), 0
 
 
+def workspace_bytes(params: TildParams, n_beads: int, bonds=None) -> int:
+    """Device bytes a context needs (tild_workspace_bytes); 0 for invalid arguments."""
+    bonds = np.zeros((0, 2), np.int32) if bonds is None else np.ascontiguousarray(np.asarray(bonds, dtype=np.int32))
+    return int(lib().tild_workspace_bytes(ctypes.byref(params), int(n_beads), int(bonds.shape[0]),
+                                          bonds.ctypes.data if bonds.size else None))
+
+
 class Tild:
     """One TILD system on one GPU.
 
     ``types`` (n,) int and ``bonds`` (n_bonds, 2) int are host arrays in ABI
     order.  ``stream``: a torch.cuda.Stream, an integer hipStream_t, or None
-    for torch's current stream.
+    for torch's current stream.  ``workspace``: None (the library allocates)
+    or a contiguous CUDA tensor of at least ``workspace_bytes(...)`` bytes,
+    256-byte aligned, kept alive by this object.
     """
 
-    def __init__(self, params: TildParams, types, bonds=None, stream=None):
+    def __init__(self, params: TildParams, types, bonds=None, stream=None, workspace=None):
         self._lib = lib()
         self._ctx = ctypes.c_void_p(None)
         types = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
         bonds = np.zeros((0, 2), np.int32) if bonds is None else np.ascontiguousarray(np.asarray(bonds, dtype=np.int32))
+        self._workspace = workspace
+        ws_ptr, ws_bytes = ctypes.c_void_p(None), 0
+        if workspace is not None:
+            if not (_is_torch(workspace) and workspace.is_cuda and workspace.is_contiguous()):
+                raise ValueError("workspace must be a contiguous CUDA tensor")
+            ws_ptr = ctypes.c_void_p(workspace.data_ptr())
+            ws_bytes = workspace.numel() * workspace.element_size()
         self.n = int(types.shape[0])
         self.params = params
         if stream is None:
@@ -97,7 +116,8 @@ class Tild:
         handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
         self._stream = ctypes.c_void_p(int(handle) if handle else None)
         rc = self._lib.tild_create(ctypes.byref(params), self.n, types.ctypes.data, int(bonds.shape[0]),
-                                   bonds.ctypes.data if bonds.size else None, self._stream, ctypes.byref(self._ctx))
+                                   bonds.ctypes.data if bonds.size else None, ws_ptr, ws_bytes, self._stream,
+                                   ctypes.byref(self._ctx))
         if rc != TILD_OK:
             raise TildError(rc, self._lib.tild_last_error(None).decode())
 
@@ -194,10 +214,10 @@ def stream_copy_ms(dst, src, nbytes: int, iters: int = 20, stream=None) -> float
     return float(ms.value)
 
 
-def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None) -> Tild:
+def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None, potential="analytic") -> Tild:
     """Context for a synth.Melt workload (positions are set too)."""
     p = make_params(melt.box, melt.grid, melt.order, melt.smear_a, melt.chi, melt.kappa, melt.bond_k, melt.dt,
-                    melt.gamma, melt.kT, melt.seed, precision, com_correct)
+                    melt.gamma, melt.kT, melt.seed, precision, com_correct, potential)
     t = Tild(p, melt.types, melt.bonds, stream=stream)
     t.set_positions(np.ascontiguousarray(melt.x, dtype=np.float64))
     return t

@@ -17,13 +17,15 @@ TILD_ESTATE = -5
 TILD_FP32 = 0
 TILD_FP64 = 1
 TILD_COM_CORRECT = 1
+TILD_POTENTIAL_SAMPLED = 2
+TILD_DETERMINISTIC = 4
 TILD_PART_NONBONDED = 1
 TILD_PART_BOND = 2
 TILD_PART_TOTAL = 3
 TILD_NUM_KERNELS = 6
 
 EXPORTS = [
-    "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",
+    "tild_workspace_bytes", "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",
     "tild_energy", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
 ]
@@ -62,7 +64,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     P = ctypes.POINTER
-    lib.tild_create.argtypes = [P(TildParams), i64, vp, i64, vp, vp, P(vp)]
+    lib.tild_workspace_bytes.argtypes = [P(TildParams), i64, i64, vp]
+    lib.tild_workspace_bytes.restype = ctypes.c_size_t
+    lib.tild_create.argtypes = [P(TildParams), i64, vp, i64, vp, vp, ctypes.c_size_t, vp, P(vp)]
     lib.tild_create.restype = ctypes.c_int
     lib.tild_set_positions.argtypes = [vp, vp, i32, i32]
     lib.tild_set_positions.restype = ctypes.c_int

@@ -99,8 +99,20 @@ struct tild_ctx {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return TILD_EHIP;
     }
+    // Device memory: hipMalloc, carved from a caller workspace, or (measure)
+    // only counted.  Every buffer starts on a 256-byte boundary.
+    char* ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    bool measure = false;
     hipError_t alloc(void** p, size_t bytes) {
         if (bytes == 0) bytes = 16;
+        if (measure || ws_base) {
+            const size_t off = (ws_used + 255) / 256 * 256;
+            if (!measure && off + bytes > ws_size) return hipErrorOutOfMemory;
+            *p = measure ? nullptr : ws_base + off;
+            ws_used = off + bytes;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(p, bytes);
         if (e == hipSuccess) allocs.push_back(*p);
         return e;
@@ -126,7 +138,10 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
     if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return why = "gamma must be finite and > 0", TILD_EINVAL;
     if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return why = "kT must be finite and >= 0", TILD_EINVAL;
     if (p->precision != TILD_FP32 && p->precision != TILD_FP64) return why = "precision must be TILD_FP32 or TILD_FP64", TILD_EINVAL;
-    if (p->flags & ~TILD_COM_CORRECT) return why = "unknown flag bits", TILD_EINVAL;
+    if (p->flags & ~(TILD_COM_CORRECT | TILD_POTENTIAL_SAMPLED | TILD_DETERMINISTIC))
+        return why = "unknown flag bits", TILD_EINVAL;
+    if ((p->flags & TILD_POTENTIAL_SAMPLED) && !(p->smear_a > 0.0))
+        return why = "TILD_POTENTIAL_SAMPLED needs smear_a > 0", TILD_EINVAL;
     return TILD_OK;
 }
 
@@ -267,20 +282,29 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
 
 }  // namespace
 
-TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32_t* types, int64_t n_bonds,
-                         const int32_t* bonds, void* hip_stream, tild_ctx** out) {
-    if (!out) {
+namespace {
+
+// tild_create, or with `measure` the device bytes it would need (types may
+// then be NULL; nothing touches the device).
+int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types, int64_t n_bonds,
+                const int32_t* bonds, void* workspace, size_t workspace_bytes, void* hip_stream, tild_ctx** out,
+                size_t* measure) {
+    if (!out && !measure) {
         g_create_error = "out is NULL";
         return TILD_EINVAL;
     }
-    *out = nullptr;
+    if (out) *out = nullptr;
+    if (workspace && (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)) {
+        g_create_error = "workspace must be 256-byte aligned";
+        return TILD_EINVAL;
+    }
     std::string why;
     int rc = validate(params, n_beads, why);
     if (rc != TILD_OK) {
         g_create_error = why;
         return rc;
     }
-    if (n_beads > 0 && !types) {
+    if (n_beads > 0 && !types && !measure) {
         g_create_error = "types is NULL";
         return TILD_EINVAL;
     }
@@ -290,7 +314,7 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     }
     // Host-side checks and bond CSR (both ends of every bond).
     int64_t n_a = 0, n_b = 0;
-    for (int64_t i = 0; i < n_beads; ++i) {
+    for (int64_t i = 0; types && i < n_beads; ++i) {
         if (types[i] == 0) ++n_a;
         else if (types[i] == 1) ++n_b;
         else {
@@ -337,6 +361,9 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     }
     c->p = *params;
     c->n_bonds = n_bonds;
+    c->measure = measure != nullptr;
+    c->ws_base = static_cast<char*>(workspace);
+    c->ws_size = workspace_bytes;
     Launch& L = c->L;
     L.stream = (hipStream_t)hip_stream;
     L.precision = params->precision;
@@ -376,7 +403,7 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
         delete c;
         return TILD_EINVAL;
     }
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (!measure && hipGetDevice(&c->device) != hipSuccess) {
         g_create_error = "no HIP device";
         delete c;
         return TILD_EHIP;
@@ -436,14 +463,24 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     A(&S.zout, 4 * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.fpart, 3 * (size_t)params->order * npos * real_sz);
     A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
+    const bool sampled = (params->flags & TILD_POTENTIAL_SAMPLED) != 0;
+    A((void**)&S.utab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
+    if (sampled) A((void**)&S.vtab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
     A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
-    A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(double));
-    A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(double));
+    A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(long long));
+    A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.flag, sizeof(uint32_t));
     A((void**)&S.eout, 8 * sizeof(double));
     A(&c->staging, npos * 3 * sizeof(double));
+    if (measure) {
+        *measure = c->ws_used;
+        delete c;
+        return TILD_OK;
+    }
     if (e != hipSuccess) {
-        g_create_error = std::string("device allocation: ") + hipGetErrorString(e);
+        g_create_error = c->ws_base && e == hipErrorOutOfMemory
+                             ? "workspace smaller than tild_workspace_bytes"
+                             : std::string("device allocation: ") + hipGetErrorString(e);
         tild_destroy(c);
         return e == hipErrorOutOfMemory ? TILD_ENOMEM : TILD_EHIP;
     }
@@ -458,6 +495,30 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
         }
     }
     std::vector<float> twf(tw.begin(), tw.end());
+    // Per-axis kernel factors: u^(n) = t_x(n_x) t_y(n_y) t_z(n_z).  Analytic:
+    // t(n) = exp(-a^2 k_n^2), k_n = 2 pi n' / L with n' the signed index.
+    // Sampled: t(n) = h sum_g g(d_g) cos(2 pi n g / M), g the 1-D factor of the
+    // Gaussian u_G (variance 2 a^2) at the minimum-image separation d_g of node g.
+    std::vector<double> vt, ut;
+    for (int a = 0; a < 3; ++a) {
+        const int m = a == 0 ? d.mx : (a == 1 ? d.my : d.mz);
+        const double len = params->box[a], h = len / m, s2 = 2.0 * params->smear_a * params->smear_a;
+        for (int nn = 0; nn < m; ++nn) {
+            const double k = 2.0 * M_PI * (double)(nn > m / 2 ? nn - m : nn) / len;
+            vt.push_back(std::exp(-params->smear_a * params->smear_a * k * k));
+            if (sampled) {
+                double acc = 0.0;
+                for (int g = 0; g < m; ++g) {
+                    const double dg = (double)(g > m / 2 ? g - m : g) * h;
+                    acc += std::exp(-dg * dg / (2.0 * s2)) * std::cos(2.0 * M_PI * (double)nn * g / m);
+                }
+                ut.push_back(h * acc / std::sqrt(2.0 * M_PI * s2));
+            }
+        }
+    }
+    if (!sampled) ut = vt;
+    ph.u0 = ut[0] * ut[(size_t)d.mx] * ut[(size_t)(d.mx + d.my)];
+
     std::vector<uint32_t> types_u((size_t)npos, 0u);
     for (int64_t i = 0; i < n_beads; ++i) types_u[(size_t)i] = (uint32_t)types[i];
     std::vector<uint32_t> zero_bins(((size_t)S.nbins + 32) / 32 * 32 + 32, 0u);
@@ -475,6 +536,9 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     }
     H2D(S.qshift, zeros4, sizeof(zeros4));
     H2D(S.qshift_next, zeros4, sizeof(zeros4));
+    H2D(S.utab, ut.data(), ut.size() * sizeof(double));
+    if (sampled) H2D(S.vtab, vt.data(), vt.size() * sizeof(double));
+    else S.vtab = S.utab;
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
     else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
     H2D(S.flag, zeros4, sizeof(uint32_t));
@@ -486,6 +550,22 @@ TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32
     }
     *out = c;
     return TILD_OK;
+}
+
+}  // namespace
+
+TILD_API int tild_create(const tild_params* params, int64_t n_beads, const int32_t* types, int64_t n_bonds,
+                         const int32_t* bonds, void* workspace, size_t workspace_bytes, void* hip_stream,
+                         tild_ctx** out) {
+    return create_impl(params, n_beads, types, n_bonds, bonds, workspace, workspace_bytes, hip_stream, out, nullptr);
+}
+
+TILD_API size_t tild_workspace_bytes(const tild_params* params, int64_t n_beads, int64_t n_bonds,
+                                     const int32_t* bonds) {
+    size_t bytes = 0;
+    if (create_impl(params, n_beads, nullptr, n_bonds, bonds, nullptr, 0, nullptr, nullptr, &bytes) != TILD_OK)
+        return 0;
+    return bytes;
 }
 
 TILD_API void tild_destroy(tild_ctx* c) {

@@ -24,6 +24,7 @@ struct Phys {
     double noise_amp;   // sqrt(2 kT dt / gamma)
     double mean_a, mean_b;  // N_A / M, N_B / M: subtracted from the counts
     double wmax;            // largest single-bead weight of one grid point, (max B_P)^3
+    double u0;              // kernel at k = 0 (1 for the analytic kernel)
     uint64_t seed;
     int com_correct;
 };
@@ -59,9 +60,11 @@ struct DeviceState {
     void* zout;           // complex [4][mz][my][hx]: z-inverted Phi_A, Phi_B, then ik_z Phi_A, ik_z Phi_B
     void* fpart;          // real [3][P][n] non-bonded force partials: axis, stencil plane offset, sorted bead
     void* tw;             // complex twiddle tables
+    double* utab;         // [mx + my + mz] per-axis factors of the kernel u^ (index n along each axis)
+    double* vtab;         // [mx + my + mz] per-axis factors of exp(-a^2 k^2) (virial); utab's array when equal
     double* epart;        // [n_zblocks][5] energy partials of the k-space pass
-    double* bpart;        // [n_bblocks][4] bond energy / virial partials
-    double* noise_part;   // [2 mz][3] per-plane sums of the Gaussian increments of the step being taken
+    long long* bpart;     // [n_bblocks][4] bond energy / virial partials (32.32 fixed point)
+    long long* noise_part;  // [2 mz][3] per-plane sums of the step's Gaussian increments (32.32 fixed point)
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
     double* eout;         // [8] reduced energies
     long long n;

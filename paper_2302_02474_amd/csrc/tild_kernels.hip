@@ -119,20 +119,21 @@ struct Walk2 {
 
 // Accumulate the counts of every species-K bead whose stencil reaches plane z
 // (the beads of the P slabs z-P+1 .. z) into the extended LDS plane (ghost
-// cells included).  Single precision accumulates fixed-point integers (each
-// contribution rounded to a multiple of 1/scale): integer LDS atomics are
-// order-independent, and far faster than float ones on this hardware.
-// Double precision accumulates doubles.
+// cells included) as fixed-point integers, each contribution rounded to a
+// multiple of 1/scale: int32 cells in single precision, int64 cells in double
+// precision.  Integer LDS atomics are order-independent, so every run gives
+// the same bits, and far faster than float ones on this hardware.
 //
 // With `noise`, every bead of the plane's own slab (c = 0, so each bead once
-// over the grid) also adds its Gaussian increment of step `step` to nsum.
+// over the grid) also adds its Gaussian increment of step `step` to nsum, in
+// 32.32 fixed point (exact for float increments, order-independent).
 template <typename T, int P>
 __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
                                              const uint32_t* __restrict__ bin_start,
                                              const uint32_t* __restrict__ qs, const Dims d, int z, int K, T scale,
-                                             bool noise, uint64_t step, uint64_t seed, double nsum[3], int tid,
+                                             bool noise, uint64_t step, uint64_t seed, long long nsum[3], int tid,
                                              int nthr) {
-    using A = typename std::conditional<sizeof(T) == 4, uint32_t, T>::type;
+    using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     A* acc = reinterpret_cast<A*>(lds);
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
     const int pr = 4 * d.hxp;
@@ -157,9 +158,9 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
                 if (c == 0 && noise) {
                     T xi[3];
                     Noise<T>::draw(q.w >> 1, step, seed, xi);
-                    nsum[0] += (double)xi[0];
-                    nsum[1] += (double)xi[1];
-                    nsum[2] += (double)xi[2];
+                    nsum[0] += llrint((double)xi[0] * kTwo32);
+                    nsum[1] += llrint((double)xi[1] * kTwo32);
+                    nsum[2] += llrint((double)xi[2] * kTwo32);
                 }
                 int gx, gy;
                 T wx[P], wy[P];
@@ -178,7 +179,7 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
 #pragma unroll
                     for (int a = 0; a < P; ++a) {
                         if constexpr (sizeof(T) == 4) atomicAdd(row + 2 * a, (uint32_t)__float2int_rn(wyz * wx[a]));
-                        else atomicAdd(row + 2 * a, wyz * wx[a]);
+                        else atomicAdd(row + 2 * a, (unsigned long long)__double2ll_rn(wyz * wx[a]));
                     }
                 }
             }
@@ -187,8 +188,8 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
 }
 
 // Add the ghost cells of the extended plane into the cells they alias
-// (columns first, over real and ghost rows, then rows).  A: uint32_t (fixed
-// point, wrapping integer sums) or double.  Ends with a barrier.
+// (columns first, over real and ghost rows, then rows).  A: uint32_t or
+// unsigned long long (fixed point, wrapping integer sums).  Ends with a barrier.
 template <typename A, int P>
 __device__ __forceinline__ void fold_ghosts(A* acc, const Dims d, int tid, int nthr) {
     if constexpr (P > 1) {
@@ -245,15 +246,19 @@ __device__ __forceinline__ uint32_t stencil_count_max(const uint32_t* __restrict
     return mine;
 }
 
-// Scale of the fixed-point spread of a plane: the largest 2^k (k <= 24) for
-// which no cell can overflow int32, each bead contributing at most wmax to a
-// cell whose count of reaching beads is at most maxcount.
-__device__ __forceinline__ float spread_scale(uint32_t maxcount, double wmax, uint32_t* __restrict__ flag, int tid) {
+// Scale of the fixed-point spread of a plane: the largest 2^k for which no
+// cell can overflow the accumulator, each bead contributing at most wmax to a
+// cell whose count of reaching beads is at most maxcount.  Single precision:
+// int32 cells, k <= 24; double precision: int64 cells (below 2^62), k <= 50.
+template <typename T>
+__device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32_t* __restrict__ flag, int tid) {
+    constexpr int kMax = sizeof(T) == 4 ? 24 : 50, kMin = 8;
+    const double limit = sizeof(T) == 4 ? 2147483647.0 : 4611686018427387904.0;
     const double bound = (double)maxcount * wmax + 1.0;
-    int k = 24;
-    while (k > 8 && bound * (double)(1 << k) >= 2147483647.0) --k;
-    if (bound * (double)(1 << k) >= 2147483647.0 && tid == 0) atomicOr(flag, 4u);
-    return (float)(1 << k);
+    int k = kMax;
+    while (k > kMin && bound * ldexp(1.0, k) >= limit) --k;
+    if (bound * ldexp(1.0, k) >= limit && tid == 0) atomicOr(flag, 4u);
+    return (T)ldexp(1.0, k);
 }
 
 // Plane z of species K: counts minus their mean N_K/M, then the forward
@@ -268,12 +273,13 @@ template <typename T, int BLOCK, int P>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
-                uint32_t* __restrict__ flag, int noise, uint64_t step, double* __restrict__ noise_part) {
+                uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part) {
     using C = cplx<T>;
-    using A = typename std::conditional<sizeof(T) == 4, uint32_t, T>::type;
+    using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
+    using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax[BLOCK / 64];
-    __shared__ double nred[3 * (BLOCK / 64)];
+    __shared__ long long nred[3 * (BLOCK / 64)];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
@@ -281,7 +287,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     const int z = t % d.mz, K = t / d.mz;
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
-    constexpr bool kFixed = sizeof(T) == 4;
     // Prologue: issue the global loads (twiddles, bin starts) before zeroing
     // the plane, then one barrier.
     C* twl = S + d.npg * zp;
@@ -289,32 +294,29 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     C twv[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
-    uint32_t mine = 0;
-    if constexpr (kFixed) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
+    uint32_t mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
     for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
 #pragma unroll
     for (int u = 0; u < 3; ++u)
         if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
-    if constexpr (kFixed) {
 #pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            const uint32_t other = __shfl_xor(mine, o, 64);
-            mine = mine > other ? mine : other;
-        }
-        if ((tid & 63) == 0) smax[tid >> 6] = mine;
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t other = __shfl_xor(mine, o, 64);
+        mine = mine > other ? mine : other;
     }
+    if ((tid & 63) == 0) smax[tid >> 6] = mine;
     __syncthreads();
-    T scale = (T)1;
-    if constexpr (kFixed) {
+    T scale;
+    {
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < BLOCK / 64; ++w) m = m > smax[w] ? m : smax[w];
-        scale = spread_scale(m, ph.wmax, flag, tid);
+        scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
-    double nsum[3] = {0, 0, 0};
+    long long nsum[3] = {0, 0, 0};
     spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK);
     if (noise) {
-        block_sum<double, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
+        block_sum<long long, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
         if (tid == 0)
             for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
     } else {
@@ -330,13 +332,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
             const A re = Si[2 * i], im = Si[2 * i + 1];
             T vr = 0, vi = 0;
             if (w.x < mx) {
-                if constexpr (kFixed) {
-                    vr = (T)(int32_t)re * inv - mean;
-                    if (2 * w.p + 1 < my) vi = (T)(int32_t)im * inv - mean;
-                } else {
-                    vr = re - mean;
-                    if (2 * w.p + 1 < my) vi = im - mean;
-                }
+                vr = (T)(SA)re * inv - mean;
+                if (2 * w.p + 1 < my) vi = (T)(SA)im * inv - mean;
             }
             S[i] = C{vr, vi};
         }
@@ -603,23 +600,25 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 // Column block c0 .. c0+cb-1 of the flattened (ky, kx) half-spectrum plane,
 // all z.  After the forward z FFT the spectra c^_A, c^_B become
 //   Phi^_K = (u^/N) sum_L eps_KL c^_L,  eps_AA = eps_BB = kappa, eps_AB = chi + kappa,
-// with u^ = exp(-a^2 k^2) (zero at k = 0: the k = 0 field has no gradient),
-// and both Phi^_K and ik_z Phi^_K are transformed back along z.  u^ factors
-// into exp(-a^2 (kx^2 + ky^2)) per column and exp(-a^2 kz^2) per plane, both
-// tabulated in LDS once per block.  With `want_energy` the block also
-// accumulates, in float64 over the half spectrum (weight 2 for kx strictly
-// between 0 and mx/2):
+// (the k = 0 field has no gradient), and both Phi^_K and ik_z Phi^_K are
+// transformed back along z.  The kernel u^ is separable: u^ = t_x(kx) t_y(ky)
+// t_z(kz) with per-axis float64 tables utab (exp(-a^2 k^2) factors, or the
+// transforms of the node-sampled Gaussian), combined in LDS once per block.
+// With `want_energy` the block also accumulates, in float64 over the half
+// spectrum (weight 2 for kx strictly between 0 and mx/2):
 //   sum u^ Re(c^_A* c^_B), sum_{k!=0} u^ |c^_A + c^_B|^2 and, per axis,
-//   sum k_a^2 u^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2].
+//   sum k_a^2 v^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2],
+// v^ = exp(-a^2 k^2) (tables vtab) for the virial.
 //
 // LDS: [4 mz][cbp] complex with the odd pitch cbp = cb | 1 (the radix-8
 // outputs of a line, eight rows apart, then spread over four LDS bank
 // groups), twiddles, then the tables (z_lds_bytes).
 struct ZColumn {
-    double uxy, kx, ky, w;  // exp(-a^2 (kx^2+ky^2)) (0 past the last column), wavenumbers, energy weight
+    double uxy, vxy, kx, ky, w;  // kernel and analytic factors of (kx, ky) (0 past the last column),
+                                 // wavenumbers, energy weight
 };
 struct ZPlane {
-    double uz, kz;  // exp(-a^2 kz^2), wavenumber
+    double uz, vz, kz;  // kernel and analytic factors of kz, wavenumber
 };
 
 //
@@ -632,21 +631,23 @@ template <typename T, int BLOCK, int ENERGY_ONLY>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
                                                   double* __restrict__ epart, int want_energy,
-                                                  const double* __restrict__ noise_part, long long n,
-                                                  const uint32_t* __restrict__ qs, uint32_t* __restrict__ qs_next) {
+                                                  const long long* __restrict__ noise_part, long long n,
+                                                  const uint32_t* __restrict__ qs, uint32_t* __restrict__ qs_next,
+                                                  const double* __restrict__ utab, const double* __restrict__ vtab) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[5 * (BLOCK / 64)];
     if (noise_part && blockIdx.x == gridDim.x - 1) {
-        double v[3] = {0, 0, 0};
+        __shared__ long long nred[3 * (BLOCK / 64)];
+        long long v[3] = {0, 0, 0};
         for (int i = threadIdx.x; i < 2 * d.mz; i += BLOCK)
             for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
-        block_sum<double, 3>(v, red, threadIdx.x, BLOCK);
+        block_sum<long long, 3>(v, nred, threadIdx.x, BLOCK);
         if (threadIdx.x == 0) {
             const double L[3] = {ph.lx, ph.ly, ph.lz};
             for (int a = 0; a < 3; ++a) {
                 long long shift = 0;
-                if (ph.com_correct && n > 0) shift = llround(ph.noise_amp * v[a] / (double)n * (kTwo32 / L[a]));
+                if (ph.com_correct && n > 0) shift = llround(ph.noise_amp * ((double)v[a] * kInvTwo32) / (double)n * (kTwo32 / L[a]));
                 qs_next[a] = qs[a] + (uint32_t)shift;
             }
             qs_next[3] = 0u;
@@ -692,14 +693,15 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
         }
         for (int z = tid; z < mz; z += BLOCK) {
             const double kz = kfz * (double)(z > mz / 2 ? z - mz : z);
-            zt[z] = ZPlane{::exp(-ph.a2 * kz * kz), kz};
+            zt[z] = ZPlane{utab[mx + my + z], vtab[mx + my + z], kz};
         }
         for (int j = tid; j < cb; j += BLOCK) {
             const int c = c0 + j;
             const int ky = c / hx, kx = c - ky * hx;
             const double kxv = kfx * (double)kx, kyv = kfy * (double)(ky > my / 2 ? ky - my : ky);
-            const double u = c < cn ? ::exp(-ph.a2 * (kxv * kxv + kyv * kyv)) : 0.0;
-            ct[j] = ZColumn{u, kxv, kyv, (kx == 0 || 2 * kx == mx) ? 1.0 : 2.0};
+            const bool in = c < cn;
+            ct[j] = ZColumn{in ? utab[kx] * utab[mx + ky] : 0.0, in ? vtab[kx] * vtab[mx + ky] : 0.0, kxv, kyv,
+                            (kx == 0 || 2 * kx == mx) ? 1.0 : 2.0};
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u)
@@ -719,7 +721,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
             const ZColumn col = ct[j];
             const ZPlane pl = zt[z];
             C PA{0, 0}, PB{0, 0}, QA{0, 0}, QB{0, 0};
-            if (col.uxy != 0.0 && (c0 + j != 0 || z != 0)) {
+            if (c0 + j < cn && (c0 + j != 0 || z != 0)) {
                 const T f = (T)col.uxy * (T)pl.uz * inv_n;
                 PA = C{f * (kap * A.x + cpk * B.x), f * (kap * A.y + cpk * B.y)};
                 PB = C{f * (cpk * A.x + kap * B.x), f * (cpk * A.y + kap * B.y)};
@@ -728,10 +730,11 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
                 QB = C{-kzd * PB.y, kzd * PB.x};
                 if (want_energy) {
                     const double uh = col.w * col.uxy * pl.uz;
+                    const double vh = col.w * col.vxy * pl.vz;
                     const double cross = (double)A.x * B.x + (double)A.y * B.y;
                     const double sx = (double)A.x + B.x, sy = (double)A.y + B.y;
                     const double plus = sx * sx + sy * sy;
-                    const double core = uh * (ph.chi * ph.inv_n * cross + 0.5 * ph.kappa * ph.inv_n * plus);
+                    const double core = vh * (ph.chi * ph.inv_n * cross + 0.5 * ph.kappa * ph.inv_n * plus);
                     acc[0] += uh * cross;
                     acc[1] += uh * plus;
                     acc[2] += col.kx * col.kx * core;
@@ -1029,8 +1032,8 @@ __global__ void __launch_bounds__(256)
 // bond is visited from both ends, hence the factor 1/2).
 __global__ void __launch_bounds__(256) k_bond_energy(const uint4* __restrict__ pin, long long n,
                                                      const int32_t* __restrict__ nbr, int deg, Phys ph,
-                                                     double* __restrict__ bpart) {
-    __shared__ double red[4 * 4];
+                                                     long long* __restrict__ bpart) {
+    __shared__ long long red[4 * 4];
     const int tid = threadIdx.x;
     const long long j = blockIdx.x * 256LL + tid;
     double acc[4] = {0, 0, 0, 0};
@@ -1049,32 +1052,41 @@ __global__ void __launch_bounds__(256) k_bond_energy(const uint4* __restrict__ p
             acc[3] -= ph.bond_k * dz * dz;
         }
     }
-    block_sum<double, 4>(acc, red, tid, 256);
+    // 32.32 fixed point: the total does not depend on the order of the beads
+    long long fx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fx[q] = llrint(acc[q] * kTwo32);
+    block_sum<long long, 4>(fx, red, tid, 256);
     if (tid == 0)
-        for (int q = 0; q < 4; ++q) bpart[blockIdx.x * 4 + q] = acc[q];
+        for (int q = 0; q < 4; ++q) bpart[blockIdx.x * 4 + q] = fx[q];
 }
 
 // Deterministic final sum (fixed order) of the energy partials.
 __global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict__ epart, int nz,
-                                                       const double* __restrict__ bpart, int nb, Phys ph,
+                                                       const long long* __restrict__ bpart, int nb, Phys ph,
                                                        double n_a, double n_b, double* __restrict__ eout) {
-    __shared__ double red[9 * 4];
+    __shared__ double red[5 * 4];
+    __shared__ long long bred[4 * 4];
     const int tid = threadIdx.x;
-    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[5] = {0, 0, 0, 0, 0};
     for (int i = tid; i < nz; i += 256)
         for (int q = 0; q < 5; ++q) acc[q] += epart[i * 5 + q];
+    long long bacc[4] = {0, 0, 0, 0};
     for (int i = tid; i < nb; i += 256)
-        for (int q = 0; q < 4; ++q) acc[5 + q] += bpart[i * 4 + q];
-    block_sum<double, 9>(acc, red, tid, 256);
+        for (int q = 0; q < 4; ++q) bacc[q] += bpart[i * 4 + q];
+    block_sum<long long, 4>(bacc, bred, tid, 256);
+    block_sum<double, 5>(acc, red, tid, 256);
     if (tid == 0) {
-        const double e_chi = ph.chi * ph.inv_n * acc[0] + ph.chi * n_a * n_b * ph.inv_n;
+        const double e_chi = ph.chi * ph.inv_n * acc[0] + ph.chi * n_a * n_b * ph.inv_n * ph.u0;
         const double e_kap = 0.5 * ph.kappa * ph.inv_n * acc[1];
-        const double e_b = acc[5];
+        double wb[3];
+        for (int a = 0; a < 3; ++a) wb[a] = (double)bacc[1 + a] * kInvTwo32;
+        const double e_b = (double)bacc[0] * kInvTwo32;
         eout[0] = e_b;
         eout[1] = e_chi;
         eout[2] = e_kap;
         eout[3] = e_b + e_chi + e_kap;
-        for (int a = 0; a < 3; ++a) eout[4 + a] = -2.0 * ph.a2 * acc[2 + a] + acc[6 + a];
+        for (int a = 0; a < 3; ++a) eout[4 + a] = -2.0 * ph.a2 * acc[2 + a] + wb[a];
         eout[7] = 0.0;
     }
 }
@@ -1199,7 +1211,8 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
 template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
     hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
-                       S.epart, want_energy, S.noise_step ? S.noise_part : nullptr, S.n, S.qshift, S.qshift_next);
+                       S.epart, want_energy, S.noise_step ? S.noise_part : nullptr, S.n, S.qshift, S.qshift_next,
+                       S.utab, S.vtab);
 }
 
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {

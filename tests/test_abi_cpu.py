@@ -54,7 +54,7 @@ def _create(lib, params, n=4, types=None, bonds=None):
     bonds = np.zeros((0, 2), np.int32) if bonds is None else np.asarray(bonds, np.int32)
     ctx = ctypes.c_void_p(None)
     rc = lib.tild_create(ctypes.byref(params), int(types.shape[0]), types.ctypes.data, int(bonds.shape[0]),
-                         bonds.ctypes.data if bonds.size else None, None, ctypes.byref(ctx))
+                         bonds.ctypes.data if bonds.size else None, None, 0, None, ctypes.byref(ctx))
     return rc, ctx, lib.tild_last_error(None).decode()
 
 
@@ -76,6 +76,7 @@ def good():
     (lambda p: setattr(p, "precision", 3), "precision"),
     (lambda p: setattr(p, "flags", 8), "flag"),
     (lambda p: setattr(p, "smear_a", float("inf")), "smear_a"),
+    (lambda p: (setattr(p, "smear_a", 0.0), setattr(p, "flags", _lib.TILD_POTENTIAL_SAMPLED)), "smear_a"),
 ])
 def test_create_rejects_bad_params(lib, mutate, needle):
     p = good()
@@ -109,4 +110,31 @@ def test_null_context_calls(lib):
     assert lib.tild_step_count(None) == -1
     lib.tild_destroy(None)
     out = ctypes.c_void_p(None)
-    assert lib.tild_create(None, 4, None, 0, None, None, ctypes.byref(out)) == _lib.TILD_EINVAL
+    assert lib.tild_create(None, 4, None, 0, None, None, 0, None, ctypes.byref(out)) == _lib.TILD_EINVAL
+
+
+def test_create_rejects_misaligned_workspace(lib):
+    types = np.zeros(4, np.int32)
+    ctx = ctypes.c_void_p(None)
+    rc = lib.tild_create(ctypes.byref(good()), 4, types.ctypes.data, 0, None, ctypes.c_void_p(0x1000 + 16), 1 << 30,
+                         None, ctypes.byref(ctx))
+    assert rc == _lib.TILD_EINVAL and "aligned" in lib.tild_last_error(None).decode()
+    assert ctx.value is None
+
+
+def test_workspace_bytes(lib):
+    # no device needed: the layout is computed on the host
+    p = good()
+    b0 = T.workspace_bytes(p, 1000)
+    assert b0 > 0
+    chain = np.stack([np.arange(999), np.arange(1, 1000)], axis=1)
+    b1 = T.workspace_bytes(p, 1000, chain)
+    assert b1 > b0  # partner tables
+    assert T.workspace_bytes(p, 2000, chain) > b1
+    p64 = T.make_params((5, 5, 5), (16, 16, 16), 4, 0.5, 0.5, 5.0, precision=T.TILD_FP64)
+    assert T.workspace_bytes(p64, 1000, chain) > b1
+    bad = good()
+    bad.order = 0
+    assert T.workspace_bytes(bad, 1000) == 0
+    assert "order" in lib.tild_last_error(None).decode()
+    assert T.workspace_bytes(p, 1000, np.array([[0, 1000]])) == 0

@@ -1,0 +1,109 @@
+"""GPU checks of the ABI's options: the node-sampled kernel (against the
+oracle's sampled variant), caller workspaces, and run-to-run reproducibility."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2302_02474_amd as T
+from oracle import tild_ref as R
+from synth import make_custom, make_melt, snap_to_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel_rms(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def params_for(m, precision, potential="analytic"):
+    return T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                         precision, True, potential)
+
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-9), (T.TILD_FP32, 1e-5)])
+@pytest.mark.parametrize("case", [
+    (30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0),
+    (30, 5, 5, (8.0, 8.0, 8.0), (15, 25, 9), 5, 0.5, 5.0),
+    (20, 5, 5, (4.0, 4.0, 4.0), (32, 32, 32), 4, 0.8, 3.0),  # h = 0.125 < a: aliasing small
+])
+def test_sampled_kernel_matches_oracle(precision, tol, case):
+    nc, na, nb, box, grid, P, chi, kap = case
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=41)
+    x = snap_to_lattice(m.x, m.box)
+    say(f"[sampled] grid={grid} P={P} precision={precision}")
+    t = T.Tild(params_for(m, precision, "sampled"), m.types, m.bonds)
+    t.set_positions(x)
+    f_nb = t.forces(T.TILD_PART_NONBONDED)
+    e = t.energy()
+    t.close()
+    p = R.Params(box=tuple(m.box), grid=tuple(grid), order=P, smear_a=m.smear_a, chi=chi, kappa=kap,
+                 bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed, potential="sampled")
+    ev = R.evaluate(x, m.types, m.bonds, p)
+    pa = R.Params(**{**p.__dict__, "potential": "analytic"})
+    ea = R.evaluate(x, m.types, m.bonds, pa)
+    err = rel_rms(f_nb, ev["F_nb"])
+    say("   F_nb rel-RMS", err, " sampled vs analytic kernel (oracle):", rel_rms(ev["F_nb"], ea["F_nb"]))
+    assert err <= tol
+    for k in ("E_chi", "E_kappa", "E"):
+        assert abs(e[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e[k], ev[k])
+    np.testing.assert_allclose(e["W"], ev["W"], rtol=tol, atol=tol * np.abs(ev["W"]).max())
+
+
+def test_workspace_context_is_identical_and_checked():
+    import torch
+    m = make_melt(0)
+    x = snap_to_lattice(m.x, m.box)
+    p = params_for(m, T.TILD_FP32)
+    need = T.workspace_bytes(p, m.n, m.bonds)
+    say("[workspace] bytes", need)
+    assert need > 0
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    view = ws[off:off + need]
+    a = T.Tild(p, m.types, m.bonds, workspace=view)
+    b = T.Tild(p, m.types, m.bonds)
+    for t in (a, b):
+        t.set_positions(x)
+        t.step(20)
+    xa, xb = a.get_positions(), b.get_positions()
+    fa, fb = a.forces(T.TILD_PART_TOTAL), b.forces(T.TILD_PART_TOTAL)
+    ea, eb = a.energy(), b.energy()
+    a.close()
+    b.close()
+    assert np.array_equal(xa, xb) and np.array_equal(fa, fb)
+    assert all(ea[k] == eb[k] for k in ("E_chi", "E_kappa", "E_bond"))
+    with pytest.raises(T.TildError) as err:
+        T.Tild(p, m.types, m.bonds, workspace=ws[:need // 2])
+    assert err.value.code == T.TILD_ENOMEM
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP32, T.TILD_FP64])
+def test_runs_are_bitwise_reproducible(precision):
+    m = make_melt(0)
+    x = snap_to_lattice(m.x, m.box)
+    out = []
+    for _ in range(2):
+        t = T.Tild(params_for(m, precision), m.types, m.bonds)
+        t.set_positions(x)
+        t.step(25)
+        out.append((t.get_positions(), t.forces(T.TILD_PART_TOTAL), t.energy()["E"]))
+        t.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
