@@ -164,6 +164,19 @@ def main() -> int:
     traffic = measured_traffic(dom)
     t.close()
 
+    # The same workload on the exact-gradient route (TILD_FORCE_AD: two inverse
+    # transforms instead of six), reported beside the headline ik route.
+    ta = T.from_melt(melt, precision=T.TILD_FP32, stream=stream, force="ad")
+    ta.step(args.warmup)
+    ta.synchronize()
+    t0 = time.perf_counter()
+    ta.step(args.steps)
+    ta.synchronize()
+    ad_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    ad_kms = ta.profile_steps(max(1, args.profile_steps // 2))
+    ta.close()
+    print(f"[bench] exact-gradient route: {ad_ms:.4f} ms/step", file=sys.stderr, flush=True)
+
     # Achievable copy bandwidth with the library's own streaming kernel.
     nbytes = 1 << 30
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -198,6 +211,9 @@ def main() -> int:
         "step_algorithmic_MB": round(step_bytes / 1e6, 2),
         "stream_copy_GBps": round(stream_gbps, 1),
         "kernels": kernels,
+        "variants": {"exact_gradient_force": {
+            "ms_per_step": round(ad_ms, 5), "bead_steps_per_s": melt.n / (ad_ms * 1e-3),
+            "kernels_ms": {k: round(v, 5) for k, v in ad_kms.items()}}},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host ...", file=sys.stderr, flush=True)

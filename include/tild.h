@@ -31,8 +31,9 @@
  *     of grid points per dimension touched by a bead (P = 2 is the paper's
  *     "two nearest grid points" first-order scheme); weights are the
  *     centred cardinal B-spline of order P.
- *   - Non-bonded force: ik route; the derivative wavenumber is zero on the
- *     Nyquist plane of an even grid axis, so the net non-bonded force is zero.
+ *   - Non-bonded force: ik route (default); the derivative wavenumber is zero
+ *     on the Nyquist plane of an even grid axis, so the net non-bonded force
+ *     is zero.  TILD_FORCE_AD selects the exact gradient of the mesh energy.
  *   - Noise: Philox4x32-10 (Salmon et al., SC'11) with key (seed mod 2^32,
  *     seed >> 32) and counter (bead id, step mod 2^32, step >> 32, 0); the
  *     four words map to uniforms (w + 1/2) 2^-32 and Box-Muller gives the
@@ -95,6 +96,11 @@ extern "C" {
                                      Sec. "Long-range interactions"), instead of the analytic exp(-a^2 k^2);
                                      needs smear_a > 0.  Energies use it (including the k = 0 constant
                                      chi N_A N_B u^(0) / N); the virial keeps the analytic kernel. */
+#define TILD_FORCE_AD 8u /* non-bonded force by the exact gradient of the mesh energy,
+                           F_i = -sum_g grad_i W_i(g) phi_{s_i}(g) with the potential fields phi_K
+                           (2 inverse transforms instead of 6), instead of the ik route of Eq. PMM;
+                           needs order >= 2.  Its net force is not exactly zero: with
+                           TILD_COM_CORRECT the mean force enters the mean displacement. */
 #define TILD_DETERMINISTIC 4u /* accepted for compatibility: every result is already bitwise reproducible
                                  run to run (the spread accumulates fixed-point integers in both precisions,
                                  every reduction has a fixed order) */
@@ -221,7 +227,8 @@ const char* tild_last_error(const tild_ctx* ctx);
  * every kernel launch, then synchronises and writes the mean duration in
  * milliseconds of each kernel slot to kernel_ms[0 .. n_slots-1] (n_slots <=
  * TILD_NUM_KERNELS) and the launches per step of each slot to
- * launches_per_step (may be NULL).  Slot names: tild_kernel_name(slot).
+ * launches_per_step (may be NULL; the update slot holds two launches on the
+ * exact-gradient route, the shift reduction and the update).  Slot names: tild_kernel_name(slot).
  */
 int tild_profile_steps(tild_ctx* ctx, int64_t n_steps, double* kernel_ms,
                        int32_t* launches_per_step, int32_t n_slots);

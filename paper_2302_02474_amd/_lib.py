@@ -19,6 +19,7 @@ TILD_FP64 = 1
 TILD_COM_CORRECT = 1
 TILD_POTENTIAL_SAMPLED = 2
 TILD_DETERMINISTIC = 4
+TILD_FORCE_AD = 8
 TILD_PART_NONBONDED = 1
 TILD_PART_BOND = 2
 TILD_PART_TOTAL = 3

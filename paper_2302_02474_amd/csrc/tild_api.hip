@@ -138,8 +138,9 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
     if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return why = "gamma must be finite and > 0", TILD_EINVAL;
     if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return why = "kT must be finite and >= 0", TILD_EINVAL;
     if (p->precision != TILD_FP32 && p->precision != TILD_FP64) return why = "precision must be TILD_FP32 or TILD_FP64", TILD_EINVAL;
-    if (p->flags & ~(TILD_COM_CORRECT | TILD_POTENTIAL_SAMPLED | TILD_DETERMINISTIC))
+    if (p->flags & ~(TILD_COM_CORRECT | TILD_POTENTIAL_SAMPLED | TILD_DETERMINISTIC | TILD_FORCE_AD))
         return why = "unknown flag bits", TILD_EINVAL;
+    if ((p->flags & TILD_FORCE_AD) && p->order < 2) return why = "TILD_FORCE_AD needs order >= 2", TILD_EINVAL;
     if ((p->flags & TILD_POTENTIAL_SAMPLED) && !(p->smear_a > 0.0))
         return why = "TILD_POTENTIAL_SAMPLED needs smear_a > 0", TILD_EINVAL;
     return TILD_OK;
@@ -368,6 +369,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     L.stream = (hipStream_t)hip_stream;
     L.precision = params->precision;
     L.order = params->order;
+    L.force_ad = (params->flags & TILD_FORCE_AD) ? 1 : 0;
     Dims& d = L.d;
     d.mx = params->grid[0];
     d.my = params->grid[1];
@@ -460,7 +462,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A((void**)&S.qshift, 4 * sizeof(uint32_t));
     A((void**)&S.qshift_next, 4 * sizeof(uint32_t));
     A(&S.spec, 2 * (size_t)d.mz * d.hplane * cplx_sz);
-    A(&S.zout, 4 * (size_t)d.mz * d.hplane * cplx_sz);
+    A(&S.zout, (L.force_ad ? 2 : 4) * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.fpart, 3 * (size_t)params->order * npos * real_sz);
     A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
     const bool sampled = (params->flags & TILD_POTENTIAL_SAMPLED) != 0;
@@ -469,6 +471,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
     A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(long long));
     A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(long long));
+    A((void**)&S.fsum_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.flag, sizeof(uint32_t));
     A((void**)&S.eout, 8 * sizeof(double));
     A(&c->staging, npos * 3 * sizeof(double));
@@ -703,7 +706,7 @@ TILD_API int tild_profile_steps(tild_ctx* c, int64_t n_steps, double* kernel_ms,
     if (e != hipSuccess) return c->hip_fail(e, "profile_steps");
     for (int k = 0; k < n_slots; ++k) {
         kernel_ms[k] = sum[(size_t)k] / (double)n_steps;
-        if (launches_per_step) launches_per_step[k] = 1;
+        if (launches_per_step) launches_per_step[k] = (k == kUpdate && c->L.force_ad) ? 2 : 1;
     }
     return check_flag(c);
 }

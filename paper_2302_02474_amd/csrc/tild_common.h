@@ -109,6 +109,24 @@ template <typename T, int P, int J = 0> __device__ __forceinline__ void spline_w
     }
 }
 
+// Derivative dw_j/df of the weight of node j (P >= 2): the derivative of the
+// same polynomial piece, with compile-time coefficients k c[i][k].
+template <typename T, int P, int J> __device__ __forceinline__ T spline_dweight(T f) {
+    constexpr SplinePieces<P> sp = spline_pieces<P>();
+    constexpr int i = P - 1 - J;
+    T v = (T)((P - 1) * sp.c[i][P - 1]);
+#pragma unroll
+    for (int k = P - 2; k >= 1; --k) v = v * f + (T)(k * sp.c[i][k]);
+    return v;
+}
+
+template <typename T, int P, int J = 0> __device__ __forceinline__ void spline_dweights(T f, T dw[P]) {
+    if constexpr (J < P) {
+        dw[J] = spline_dweight<T, P, J>(f);
+        spline_dweights<T, P, J + 1>(f, dw);
+    }
+}
+
 // (u - P/2) * 2^32 for fixed-point q on an axis of m points.
 __device__ __forceinline__ int64_t stencil_fixed(uint32_t q, int m, int P) {
     return (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m) - ((int64_t)P << 31);

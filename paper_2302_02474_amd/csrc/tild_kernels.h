@@ -65,6 +65,7 @@ struct DeviceState {
     double* epart;        // [n_zblocks][5] energy partials of the k-space pass
     long long* bpart;     // [n_bblocks][4] bond energy / virial partials (32.32 fixed point)
     long long* noise_part;  // [2 mz][3] per-plane sums of the step's Gaussian increments (32.32 fixed point)
+    long long* fsum_part;   // [2 mz][3] per-plane sums of the non-bonded forces (exact-gradient route)
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
     double* eout;         // [8] reduced energies
     long long n;
@@ -83,6 +84,7 @@ struct Launch {
     Dims d;
     FftPlan px, py, pz;
     int plane_block;  // threads per workgroup of the inverse plane pass
+    int force_ad;     // exact-gradient route: potential planes, weight derivatives (else the ik route)
     int spread_block; // threads per workgroup of the fused spread + forward plane pass
     int z_cols;       // columns per workgroup of the z pass
     int z_block;

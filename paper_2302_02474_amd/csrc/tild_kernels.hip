@@ -456,6 +456,77 @@ __device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4
     }
 }
 
+// Exact-gradient route (the mesh energy's derivative): the potential plane
+// phi_K(z) in LDS gives every bead of the P slabs z-P+1 .. z all three
+// components of its plane-c term,
+//   fpart[a][c][j] = -sum_{b,a'} d/dx_a [w_x[a'] w_y[b] w_z[c]] phi_K(g0y + b, g0x + a'),
+// with dw/dx = (dw/df) / h.  Returns this thread's sum of the values it wrote,
+// per axis, in 32.32 fixed point (the mean force enters the centre-of-mass shift).
+template <typename T, int P>
+__device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const uint4* __restrict__ pos,
+                                              const uint32_t* __restrict__ bin_start,
+                                              const uint32_t* __restrict__ qs, const Dims d, int z, int K,
+                                              long long n, T* __restrict__ fpart, long long fsum[3], int tid,
+                                              int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
+    const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        constexpr int U = 4;  // beads in flight per thread
+        for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
+            uint4 qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                if (j >= j1) break;
+                const uint4 q = qv[u];
+                int gx, gy;
+                T wx[P], wy[P], dwx[P], dwy[P];
+                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                spline_dweights<T, P>(stencil_fraction<T>(q.x - sx, d.mx, P), dwx);
+                spline_dweights<T, P>(stencil_fraction<T>(q.y - sy, d.my, P), dwy);
+                const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+                T wzs[P], dwzs[P];  // only entry c survives unrolling
+                spline_weights<T, P>(fz, wzs);
+                spline_dweights<T, P>(fz, dwzs);
+                const RowOffsets<P> ro(gy, pr);
+                T ax = 0, ay = 0, az = 0;
+#pragma unroll
+                for (int b = 0; b < P; ++b) {
+                    const T* row = Sr + ro.o[b] + 2 * gx;
+                    T r = 0, rx = 0;
+#pragma unroll
+                    for (int a2 = 0; a2 < P; ++a2) {
+                        const T v = row[2 * a2];
+                        r += wx[a2] * v;
+                        rx += dwx[a2] * v;
+                    }
+                    ax += wy[b] * rx;
+                    ay += dwy[b] * r;
+                    az += wy[b] * r;
+                }
+                const T f[3] = {-ihx * wzs[c] * ax, -ihy * wzs[c] * ay, -ihz * dwzs[c] * az};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    fpart[((long long)a * P + c) * n + j] = f[a];
+                    fsum[a] += llrint((double)f[a] * kTwo32);
+                }
+            }
+        }
+    }
+}
+
 // Inverse (one workgroup per plane z, species K and axis a = x, y, z): build
 // the half spectrum of d_a phi_K on plane z (row pitch hxp), inverse FFT
 // along y, then complex-to-real along x with rows 2p and 2p+1 carried as the
@@ -463,19 +534,26 @@ __device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4
 // offset p * zp by the lanes that then transform it; the ghost columns and
 // rows are filled in, and the finished plane d_a phi_K(z) is interpolated
 // onto the beads that reach it.
-template <typename T, int BLOCK, int P>
+//
+// AD: exact-gradient route instead: one workgroup per plane z and species K
+// transforms phi_K itself and interpolates all three components with the
+// weight derivatives (push_plane_ad); fsum_part receives the workgroup's
+// force sums (32.32 fixed point).
+template <typename T, int BLOCK, int P, bool AD>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
-             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n) {
+             const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
+             long long* __restrict__ fsum_part) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes the three axes of a run of consecutive planes of one
     // species: all of them read the same bead slabs
-    const int t = xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
-    const int a = t % 3, z = (t / 3) % d.mz, K = t / (3 * d.mz);
+    const int t = AD ? xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz)
+                     : xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
+    const int a = AD ? 2 : t % 3, z = AD ? t % d.mz : (t / 3) % d.mz, K = AD ? t / d.mz : t / (3 * d.mz);
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     C* twl = S + d.npg * zp;
@@ -485,7 +563,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 #pragma unroll
         for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
         // the plane's half spectrum, eighteen loads in flight per thread
-        const C* src = zout + ((long long)(a < 2 ? K : 2 + K) * d.mz + z) * d.hplane;
+        const C* src = zout + ((long long)(a < 2 || AD ? K : 2 + K) * d.mz + z) * d.hplane;
         constexpr int LB = 18;
         const int tot = my * hx;
         Walk2 w(tid, hx, BLOCK);
@@ -591,7 +669,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
             }
             __syncthreads();
         }
-        push_plane<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK);
+        if constexpr (AD) {
+            __shared__ long long fred[3 * (BLOCK / 64)];
+            long long fsum[3] = {0, 0, 0};
+            push_plane_ad<T, P>(Sr, pos, bin_start, qs, d, z, K, n, fpart, fsum, tid, BLOCK);
+            block_sum<long long, 3>(fsum, fred, tid, BLOCK);
+            if (tid == 0)
+                for (int q = 0; q < 3; ++q) fsum_part[(K * d.mz + z) * 3 + q] = fsum[q];
+        } else {
+            push_plane<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK);
+        }
     }
 }
 
@@ -633,7 +720,8 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
                                                   double* __restrict__ epart, int want_energy,
                                                   const long long* __restrict__ noise_part, long long n,
                                                   const uint32_t* __restrict__ qs, uint32_t* __restrict__ qs_next,
-                                                  const double* __restrict__ utab, const double* __restrict__ vtab) {
+                                                  const double* __restrict__ utab, const double* __restrict__ vtab,
+                                                  int nout) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[5 * (BLOCK / 64)];
@@ -747,8 +835,10 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
             if (!ENERGY_ONLY) {
                 b0[z * cbp + j] = PA;
                 b0[(mz + z) * cbp + j] = PB;
-                b0[(2 * mz + z) * cbp + j] = QA;
-                b0[(3 * mz + z) * cbp + j] = QB;
+                if (nout == 4) {
+                    b0[(2 * mz + z) * cbp + j] = QA;
+                    b0[(3 * mz + z) * cbp + j] = QB;
+                }
             }
         }
     }
@@ -759,11 +849,11 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     }
     if (ENERGY_ONLY) return;
     __syncthreads();
-    fft_lines<C, 1>(b0, LineMap{4 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
+    fft_lines<C, 1>(b0, LineMap{nout * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
     __syncthreads();
     {
         Walk2 w(tid, cb, BLOCK);
-        for (int i = tid; i < 4 * mz * cb; i += BLOCK, w.next()) {
+        for (int i = tid; i < nout * mz * cb; i += BLOCK, w.next()) {
             const int c = c0 + w.x;
             if (c < cn) zout[(long long)w.p * cn + c] = b0[w.p * cbp + w.x];
         }
@@ -790,15 +880,49 @@ __device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t*
     return base + (uint32_t)(lane - hl);
 }
 
+// Exact-gradient route: the non-bonded forces do not sum to zero, so the
+// step's centre-of-mass shift comes from the per-plane noise and force sums
+// (32.32 fixed point, so the total is order-independent): the mean
+// displacement is (sqrt(2 kT dt/gamma) sum xi + (dt/gamma) sum F) / N.
+__global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict__ noise_part,
+                                                    const long long* __restrict__ fsum_part, int nplanes, long long n,
+                                                    Phys ph, const uint32_t* __restrict__ qs,
+                                                    uint32_t* __restrict__ qs_next) {
+    __shared__ long long red[6 * 4];
+    const int tid = threadIdx.x;
+    long long v[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = tid; i < nplanes; i += 256)
+        for (int a = 0; a < 3; ++a) {
+            v[a] += noise_part[3 * i + a];
+            v[3 + a] += fsum_part[3 * i + a];
+        }
+    block_sum<long long, 6>(v, red, tid, 256);
+    if (tid == 0) {
+        const double L[3] = {ph.lx, ph.ly, ph.lz};
+        for (int a = 0; a < 3; ++a) {
+            long long shift = 0;
+            if (ph.com_correct && n > 0) {
+                const double mean =
+                    (ph.noise_amp * ((double)v[a] * kInvTwo32) + ph.mob_dt * ((double)v[3 + a] * kInvTwo32)) /
+                    (double)n;
+                shift = llround(mean * (kTwo32 / L[a]));
+            }
+            qs_next[a] = qs[a] + (uint32_t)shift;
+        }
+        qs_next[3] = 0u;
+    }
+}
+
 // Beads in sorted order, one per thread: F = sum of the P plane partials of each
 // component (non-bonded, ik route) + the stored bond force.
 // MODE 0: Euler-Maruyama step.  The centre-of-mass correction subtracts the
 //         mean displacement; the forces sum to zero exactly (pairwise bonds;
 //         the ik route with the Nyquist derivative zeroed conserves momentum),
 //         so that mean is sqrt(2 kT dt/gamma) times the mean noise, from which
-//         the k-space pass has already formed the new integer shift (qs_new).
-//         Each moved bead goes to pout[j] with its exact new bin key and its
-//         rank in that bin.
+//         the k-space pass has already formed the new integer shift (qs_new;
+//         on the exact-gradient route k_form_shift, from the noise and force
+//         sums).  Each moved bead goes to pout[j] with its exact new bin key
+//         and its rank in that bin.
 // MODE 1: forces only, written to out[abi id] ([n][3], float or double).
 template <typename T, int P, int MODE>
 __global__ void __launch_bounds__(256)
@@ -828,7 +952,7 @@ __global__ void __launch_bounds__(256)
                 f[a] += sa;
             }
         }
-        const uint32_t nsh[3] = {qs_new[0], qs_new[1], qs_new[2]};  // formed by the k-space pass
+        const uint32_t nsh[3] = {qs_new[0], qs_new[1], qs_new[2]};  // formed before this kernel
         uint32_t kb = 0xffffffffu;
         if (active) {
             const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
@@ -1179,9 +1303,15 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
     with_order(L.order, [&](auto Pc) {
-        hipLaunchKernelGGL((k_xy_c2r<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
-                           L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
-                           L.ph, S.pos, S.bin_start, S.qshift, S.n);
+        constexpr int P = decltype(Pc)::value;
+        if (L.force_ad)
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
+                               (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part);
+        else
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, false>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
+                               L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
+                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part);
     });
 }
 
@@ -1211,8 +1341,8 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
 template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
     hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
-                       S.epart, want_energy, S.noise_step ? S.noise_part : nullptr, S.n, S.qshift, S.qshift_next,
-                       S.utab, S.vtab);
+                       S.epart, want_energy, S.noise_step && !L.force_ad ? S.noise_part : nullptr, S.n, S.qshift,
+                       S.qshift_next, S.utab, S.vtab, L.force_ad ? 2 : 4);
 }
 
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
@@ -1250,6 +1380,9 @@ static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, 
 
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts) {
+    if (mode == 0 && L.force_ad)
+        hipLaunchKernelGGL(k_form_shift, dim3(1), dim3(256), 0, L.stream, S.noise_part, S.fsum_part, 2 * L.d.mz,
+                           S.n, L.ph, S.qshift, S.qshift_next);
     if (L.precision == 0) {
         if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts);
         else update_t<float, 1>(L, S, step, out, out_dtype, parts);
@@ -1332,8 +1465,13 @@ template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) 
         else if constexpr (sizeof(T) == 8) set((const void*)k_spread_xy<T, 512, P>);
         else if (L.spread_block == 512) set((const void*)k_spread_xy<T, 512, P>);
         else set((const void*)k_spread_xy<T, 1024, P>);
-        if (L.plane_block == 256) set((const void*)k_xy_c2r<T, 256, P>);
-        else set((const void*)k_xy_c2r<T, 512, P>);
+        if (L.plane_block == 256) {
+            set((const void*)k_xy_c2r<T, 256, P, false>);
+            set((const void*)k_xy_c2r<T, 256, P, true>);
+        } else {
+            set((const void*)k_xy_c2r<T, 512, P, false>);
+            set((const void*)k_xy_c2r<T, 512, P, true>);
+        }
     });
     return e;
 }

@@ -74,9 +74,10 @@ def good():
     (lambda p: setattr(p, "gamma", 0.0), "gamma"),
     (lambda p: setattr(p, "kT", -1.0), "kT"),
     (lambda p: setattr(p, "precision", 3), "precision"),
-    (lambda p: setattr(p, "flags", 8), "flag"),
+    (lambda p: setattr(p, "flags", 16), "flag"),
     (lambda p: setattr(p, "smear_a", float("inf")), "smear_a"),
     (lambda p: (setattr(p, "smear_a", 0.0), setattr(p, "flags", _lib.TILD_POTENTIAL_SAMPLED)), "smear_a"),
+    (lambda p: (setattr(p, "order", 1), setattr(p, "flags", _lib.TILD_FORCE_AD)), "order"),
 ])
 def test_create_rejects_bad_params(lib, mutate, needle):
     p = good()

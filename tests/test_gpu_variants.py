@@ -107,3 +107,66 @@ def test_runs_are_bitwise_reproducible(precision):
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert out[0][2] == out[1][2]
+
+
+# --------------------------------------------------------------------------
+# Exact-gradient route (TILD_FORCE_AD) against the oracle's F_nb_ad, which the
+# oracle pins to central finite differences of its mesh energy.
+# --------------------------------------------------------------------------
+
+AD_CASES = [
+    (30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0),
+    (25, 5, 5, (5.0, 6.0, 7.5), (10, 12, 18), 3, 0.8, 3.0),
+    (40, 4, 4, (7.0, 7.0, 7.0), (20, 24, 30), 5, 0.3, 8.0),
+    (20, 3, 3, (4.0, 3.0, 5.0), (8, 6, 10), 2, 1.0, 2.0),
+    (30, 5, 5, (8.0, 8.0, 8.0), (15, 25, 9), 6, 0.5, 5.0),
+]
+
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-9), (T.TILD_FP32, 1e-5)])
+@pytest.mark.parametrize("case", range(len(AD_CASES)))
+def test_exact_gradient_forces_match_oracle(precision, tol, case):
+    nc, na, nb, box, grid, P, chi, kap = AD_CASES[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=200 + case)
+    x = snap_to_lattice(m.x, m.box)
+    say(f"[ad] grid={grid} P={P} precision={precision}")
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      precision, True, "analytic", "ad")
+    t = T.Tild(p, m.types, m.bonds)
+    t.set_positions(x)
+    f_nb = t.forces(T.TILD_PART_NONBONDED)
+    e = t.energy()
+    t.close()
+    po = R.Params(box=tuple(m.box), grid=tuple(grid), order=P, smear_a=m.smear_a, chi=chi, kappa=kap,
+                  bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed)
+    ev = R.evaluate(x, m.types, m.bonds, po, want_ad=True)
+    err = rel_rms(f_nb, ev["F_nb_ad"])
+    say("   F_nb(ad) rel-RMS", err, " ad vs ik (oracle):", rel_rms(ev["F_nb_ad"], ev["F_nb"]),
+        " net ad force", np.abs(ev["F_nb_ad"].sum(axis=0)).max())
+    assert err <= tol
+    assert abs(e["E"] - ev["E"]) <= tol * max(1.0, abs(ev["E"]))
+
+
+def test_exact_gradient_trajectory_fp64():
+    """20 steps with the centre-of-mass correction, which on this route must
+    include the (non-zero) mean non-bonded force."""
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      T.TILD_FP64, True, "analytic", "ad")
+    t = T.Tild(p, m.types, m.bonds)
+    t.set_positions(x0)
+    t.step(20)
+    xg = t.get_positions()
+    t.close()
+    po = R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
+                  chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed)
+    x = x0.copy()
+    ids = np.arange(m.n)
+    for s in range(20):
+        ev = R.evaluate(x, m.types, m.bonds, po, want_ad=True)
+        x = R.em_update(x, ev["F_nb_ad"] + ev["F_bond"], ids, s, po)
+    d = R.min_image(xg - x, m.box)
+    err = np.sqrt((d ** 2).mean()) / np.sqrt((R.min_image(x - x0, m.box) ** 2).mean())
+    say("[ad] trajectory displacement rel-RMS", err)
+    assert err < 1e-7
