@@ -46,7 +46,7 @@ __all__ = [
     "Params", "bspline", "bspline_deriv", "stencil", "spread", "dft_matrix", "dft3",
     "idft3", "wavenumbers", "kgrid", "uhat_analytic", "uhat_sampled", "field_spectra",
     "gradient_fields", "potential_fields", "gather", "gather_gradient_weights",
-    "nonbonded_energy", "nonbonded_virial", "bond_terms", "evaluate", "em_update",
+    "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
     "trajectory", "structure_factor_exact", "min_image",
 ]
 
@@ -344,6 +344,26 @@ def nonbonded_virial(chat: np.ndarray, a: float, L, M, chi: float, kappa: float,
     plus2[0, 0, 0] = 0.0
     core = uhat * (chi / n_beads * cross + kappa / (2.0 * n_beads) * plus2)
     return np.array([-2.0 * a * a * float(np.sum(ks[ax] ** 2 * core)) for ax in range(3)])
+
+
+def energy_parameter_gradients(chat: np.ndarray, a: float, L, M, chi: float, kappa: float,
+                               n_beads: int) -> np.ndarray:
+    """(dE/dchi, dE/dkappa, dE/da) of the non-bonded energy (analytic kernel) at
+    fixed positions, from the energy written as k-space sums (Eqs. fh, HelfandP
+    with u^ = exp(-a^2 k^2)):
+      dE/dchi   = (1/N) sum_n u^ Re(c^_A* c^_B)          (n = 0 included),
+      dE/dkappa = (1/2N) sum_{n != 0} u^ |c^_A + c^_B|^2,
+      dE/da     = sum_n (-2 a k^2) u^ [(chi/N) Re(c^_A* c^_B) + (kappa/2N) |c^_+|^2 (n != 0)]."""
+    ks, _ = kgrid(L, M)
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    uhat = np.exp(-a * a * k2)
+    cross = np.real(np.conj(chat[0]) * chat[1])
+    plus2 = np.abs(chat[0] + chat[1]) ** 2
+    plus2[0, 0, 0] = 0.0
+    d_chi = float(np.sum(uhat * cross)) / n_beads
+    d_kappa = float(np.sum(uhat * plus2)) / (2.0 * n_beads)
+    d_a = float(np.sum(-2.0 * a * k2 * uhat * (chi / n_beads * cross + kappa / (2.0 * n_beads) * plus2)))
+    return np.array([d_chi, d_kappa, d_a])
 
 
 # --------------------------------------------------------------------------

@@ -317,6 +317,21 @@ def test_virial_by_affine_box_scaling():
         assert abs(w_b - ev["W_bond"][a]) < 1e-5 * max(1, abs(w_b))
 
 
+def test_energy_parameter_gradients_by_finite_differences():
+    p = small_params()
+    x, t, b = random_system(30, p, seed=5)
+    ev = R.evaluate(x, t, b, p)
+    g = R.energy_parameter_gradients(ev["chat"], p.smear_a, p.L, p.M, p.chi, p.kappa, x.shape[0])
+    for i, name in enumerate(("chi", "kappa", "smear_a")):
+        h = 1e-5 * max(1.0, abs(getattr(p, name)))
+        Es = []
+        for sgn in (+1, -1):
+            q = R.Params(**{**p.__dict__, name: getattr(p, name) + sgn * h})
+            Es.append(R.evaluate(x, t, b, q)["E"])
+        fd = (Es[0] - Es[1]) / (2 * h)
+        assert abs(fd - g[i]) < 1e-6 * max(1.0, abs(fd)), (name, fd, g[i])
+
+
 def test_sampled_kernel_approaches_analytic_on_fine_grids():
     a = 0.5
     for M, tol in ((16, 0.05), (48, 1e-6)):
