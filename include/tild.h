@@ -205,6 +205,26 @@ int tild_forces(tild_ctx* ctx, void* out, int32_t dtype, int32_t on_device, uint
  */
 int tild_energy(tild_ctx* ctx, double out[8]);
 
+/*
+ * Energy and its gradients at the current positions (the differentiable
+ * form of Eqs. fh, HelfandP and bonds).  Synchronises.
+ *   out[0] E_total; out[1] dE/dchi = (1/N) sum_n u^ Re(c^_A* c^_B);
+ *   out[2] dE/dkappa = (1/2N) sum_{n!=0} u^ |c^_A + c^_B|^2;
+ *   out[3] dE/da = sum_n -2 a k^2 u^ [...] (analytic kernel; NaN with
+ *   TILD_POTENTIAL_SAMPLED), all at fixed positions.
+ *   grad_x: NULL, or [n_beads][3] (ABI order, dtype, host or device) that
+ *   receives dE/dx = -(F_nb + F_bond) with F_nb the exact gradient of the
+ *   mesh energy (whatever route tild_step uses); needs order >= 2.
+ */
+int tild_energy_grad(tild_ctx* ctx, double out[4], void* grad_x, int32_t dtype, int32_t on_device);
+
+/*
+ * Change chi, kappa and the smearing width a of an existing context (for
+ * differentiating through them); smear_a >= 0, > 0 with
+ * TILD_POTENTIAL_SAMPLED.  Waits for the context's queued work first.
+ */
+int tild_set_interaction(tild_ctx* ctx, double chi, double kappa, double smear_a);
+
 /* Number of steps taken since creation (or since tild_set_step_count). */
 int64_t tild_step_count(const tild_ctx* ctx);
 

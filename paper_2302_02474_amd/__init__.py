@@ -179,6 +179,26 @@ class Tild:
         v = list(buf)
         return dict(E_bond=v[0], E_chi=v[1], E_kappa=v[2], E=v[3], W=np.array(v[4:7]))
 
+    def energy_grad(self, grad_x=True, dtype=np.float64):
+        """(E, dE/dchi, dE/dkappa, dE/da) and, with grad_x (True for a new host
+        array, or an output array / CUDA tensor), dE/dx = -(F_nb exact gradient + F_bond)."""
+        out = None
+        if grad_x is True:
+            out = np.empty((self.n, 3), dtype=dtype)
+        elif grad_x is not None and grad_x is not False:
+            out = grad_x
+        buf = (ctypes.c_double * 4)()
+        if out is None:
+            self._check(self._lib.tild_energy_grad(self._ctx, buf, None, TILD_FP64, 0))
+        else:
+            ptr, dev = _ptr(out)
+            self._check(self._lib.tild_energy_grad(self._ctx, buf, ptr, _dtype_code(out), dev))
+        v = list(buf)
+        return dict(E=v[0], dE_dchi=v[1], dE_dkappa=v[2], dE_da=v[3]), out
+
+    def set_interaction(self, chi: float, kappa: float, smear_a: float):
+        self._check(self._lib.tild_set_interaction(self._ctx, float(chi), float(kappa), float(smear_a)))
+
     @property
     def step_count(self) -> int:
         return int(self._lib.tild_step_count(self._ctx))

@@ -27,7 +27,7 @@ TILD_NUM_KERNELS = 6
 
 EXPORTS = [
     "tild_workspace_bytes", "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",
-    "tild_energy", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
+    "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
 ]
 
@@ -79,6 +79,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_forces.restype = ctypes.c_int
     lib.tild_energy.argtypes = [vp, P(ctypes.c_double)]
     lib.tild_energy.restype = ctypes.c_int
+    lib.tild_energy_grad.argtypes = [vp, P(ctypes.c_double), vp, i32, i32]
+    lib.tild_energy_grad.restype = ctypes.c_int
+    lib.tild_set_interaction.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.tild_set_interaction.restype = ctypes.c_int
     lib.tild_step_count.argtypes = [vp]
     lib.tild_step_count.restype = ctypes.c_int64
     lib.tild_set_step_count.argtypes = [vp, i64]

@@ -285,6 +285,34 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
 
 namespace {
 
+// Per-axis kernel factors, index n along each axis: u^(n) = t_x(n_x) t_y(n_y)
+// t_z(n_z).  vt: t(n) = exp(-a^2 k_n^2), k_n = 2 pi n' / L with n' the signed
+// index.  ut: the kernel's factors, vt itself, or with TILD_POTENTIAL_SAMPLED
+// t(n) = h sum_g g(d_g) cos(2 pi n g / M), g the 1-D factor of the Gaussian u_G
+// (variance 2 a^2) at the minimum-image separation d_g of node g.
+void kernel_tables(const tild_params& p, const Dims& d, std::vector<double>& ut, std::vector<double>& vt) {
+    const bool sampled = (p.flags & TILD_POTENTIAL_SAMPLED) != 0;
+    ut.clear();
+    vt.clear();
+    for (int a = 0; a < 3; ++a) {
+        const int m = a == 0 ? d.mx : (a == 1 ? d.my : d.mz);
+        const double len = p.box[a], h = len / m, s2 = 2.0 * p.smear_a * p.smear_a;
+        for (int nn = 0; nn < m; ++nn) {
+            const double k = 2.0 * M_PI * (double)(nn > m / 2 ? nn - m : nn) / len;
+            vt.push_back(std::exp(-p.smear_a * p.smear_a * k * k));
+            if (sampled) {
+                double acc = 0.0;
+                for (int g = 0; g < m; ++g) {
+                    const double dg = (double)(g > m / 2 ? g - m : g) * h;
+                    acc += std::exp(-dg * dg / (2.0 * s2)) * std::cos(2.0 * M_PI * (double)nn * g / m);
+                }
+                ut.push_back(h * acc / std::sqrt(2.0 * M_PI * s2));
+            }
+        }
+    }
+    if (!sampled) ut = vt;
+}
+
 // tild_create, or with `measure` the device bytes it would need (types may
 // then be NULL; nothing touches the device).
 int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types, int64_t n_bonds,
@@ -473,7 +501,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.fsum_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.flag, sizeof(uint32_t));
-    A((void**)&S.eout, 8 * sizeof(double));
+    A((void**)&S.eout, 16 * sizeof(double));
     A(&c->staging, npos * 3 * sizeof(double));
     if (measure) {
         *measure = c->ws_used;
@@ -498,29 +526,10 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
         }
     }
     std::vector<float> twf(tw.begin(), tw.end());
-    // Per-axis kernel factors: u^(n) = t_x(n_x) t_y(n_y) t_z(n_z).  Analytic:
-    // t(n) = exp(-a^2 k_n^2), k_n = 2 pi n' / L with n' the signed index.
-    // Sampled: t(n) = h sum_g g(d_g) cos(2 pi n g / M), g the 1-D factor of the
-    // Gaussian u_G (variance 2 a^2) at the minimum-image separation d_g of node g.
-    std::vector<double> vt, ut;
-    for (int a = 0; a < 3; ++a) {
-        const int m = a == 0 ? d.mx : (a == 1 ? d.my : d.mz);
-        const double len = params->box[a], h = len / m, s2 = 2.0 * params->smear_a * params->smear_a;
-        for (int nn = 0; nn < m; ++nn) {
-            const double k = 2.0 * M_PI * (double)(nn > m / 2 ? nn - m : nn) / len;
-            vt.push_back(std::exp(-params->smear_a * params->smear_a * k * k));
-            if (sampled) {
-                double acc = 0.0;
-                for (int g = 0; g < m; ++g) {
-                    const double dg = (double)(g > m / 2 ? g - m : g) * h;
-                    acc += std::exp(-dg * dg / (2.0 * s2)) * std::cos(2.0 * M_PI * (double)nn * g / m);
-                }
-                ut.push_back(h * acc / std::sqrt(2.0 * M_PI * s2));
-            }
-        }
-    }
-    if (!sampled) ut = vt;
+    std::vector<double> ut, vt;
+    kernel_tables(*params, d, ut, vt);
     ph.u0 = ut[0] * ut[(size_t)d.mx] * ut[(size_t)(d.mx + d.my)];
+    ph.sampled = sampled ? 1 : 0;
 
     std::vector<uint32_t> types_u((size_t)npos, 0u);
     for (int64_t i = 0; i < n_beads; ++i) types_u[(size_t)i] = (uint32_t)types[i];
@@ -660,6 +669,65 @@ TILD_API int tild_energy(tild_ctx* c, double out[8]) {
     if (e == hipSuccess) e = launch_reduce_energy(c->L, c->S);
     if (e == hipSuccess) e = hipMemcpyAsync(out, c->S.eout, 8 * sizeof(double), hipMemcpyDeviceToHost, c->L.stream);
     if (e != hipSuccess) return c->hip_fail(e, "energy");
+    return check_flag(c);
+}
+
+TILD_API int tild_set_interaction(tild_ctx* c, double chi, double kappa, double smear_a) {
+    if (!c) return TILD_EINVAL;
+    if (!std::isfinite(chi) || !std::isfinite(kappa) || !std::isfinite(smear_a) || smear_a < 0.0)
+        return c->fail(TILD_EINVAL, "set_interaction: chi, kappa must be finite and smear_a finite and >= 0");
+    if ((c->p.flags & TILD_POTENTIAL_SAMPLED) && !(smear_a > 0.0))
+        return c->fail(TILD_EINVAL, "set_interaction: TILD_POTENTIAL_SAMPLED needs smear_a > 0");
+    DeviceGuard g(c->device);
+    // the tables may still be read by queued work
+    hipError_t e = hipStreamSynchronize(c->L.stream);
+    tild_params p = c->p;
+    p.chi = chi;
+    p.kappa = kappa;
+    p.smear_a = smear_a;
+    std::vector<double> ut, vt;
+    kernel_tables(p, c->L.d, ut, vt);
+    if (e == hipSuccess) e = hipMemcpy(c->S.utab, ut.data(), ut.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess && c->S.vtab != c->S.utab)
+        e = hipMemcpy(c->S.vtab, vt.data(), vt.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return c->hip_fail(e, "set_interaction");
+    c->p = p;
+    Phys& ph = c->L.ph;
+    ph.chi = chi;
+    ph.kappa = kappa;
+    ph.a2 = smear_a * smear_a;
+    ph.u0 = ut[0] * ut[(size_t)c->L.d.mx] * ut[(size_t)(c->L.d.mx + c->L.d.my)];
+    return TILD_OK;
+}
+
+TILD_API int tild_energy_grad(tild_ctx* c, double out[4], void* grad_x, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if (!out || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "energy_grad: NULL out or bad dtype");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    if (grad_x && c->L.order < 2) return c->fail(TILD_EINVAL, "energy_grad: dE/dx needs order >= 2");
+    DeviceGuard g(c->device);
+    hipError_t e = launch_spread_xy(c->L, c->S);
+    if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, grad_x == nullptr, true);
+    if (e == hipSuccess) e = launch_bond_energy(c->L, c->S);
+    if (e == hipSuccess) e = launch_reduce_energy(c->L, c->S);
+    double eo[16];
+    if (e == hipSuccess) e = hipMemcpyAsync(eo, c->S.eout, sizeof(eo), hipMemcpyDeviceToHost, c->L.stream);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    if (grad_x) {
+        // dE/dx = -(F_nb by the exact gradient + F_bond), whatever the context's route
+        if (e == hipSuccess) e = launch_xy_c2r(c->L, c->S, 1);
+        void* dst = on_device ? grad_x : c->staging;
+        if (e == hipSuccess) e = launch_update(c->L, c->S, 1, (uint64_t)c->step, dst, dtype, TILD_PART_TOTAL, -1.0);
+        if (e == hipSuccess && !on_device && bytes)
+            e = hipMemcpyAsync(grad_x, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "energy_grad");
+    out[0] = eo[3];
+    out[1] = eo[8];
+    out[2] = eo[9];
+    out[3] = eo[10];
     return check_flag(c);
 }
 

@@ -25,6 +25,7 @@ struct Phys {
     double mean_a, mean_b;  // N_A / M, N_B / M: subtracted from the counts
     double wmax;            // largest single-bead weight of one grid point, (max B_P)^3
     double u0;              // kernel at k = 0 (1 for the analytic kernel)
+    int sampled;            // the kernel is the node-sampled one
     uint64_t seed;
     int com_correct;
 };
@@ -67,7 +68,7 @@ struct DeviceState {
     long long* noise_part;  // [2 mz][3] per-plane sums of the step's Gaussian increments (32.32 fixed point)
     long long* fsum_part;   // [2 mz][3] per-plane sums of the non-bonded forces (exact-gradient route)
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
-    double* eout;         // [8] reduced energies
+    double* eout;         // [16] reduced energies, virial, parameter gradients
     long long n;
     long long n_a, n_b;
     int deg;              // bond slots per bead (maximum degree)
@@ -96,13 +97,16 @@ struct Launch {
 
 // Launch helpers; each returns the hipError_t of the launch.
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S);
-hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only);
-hipError_t launch_xy_c2r(const Launch& L, DeviceState& S);
+// energy_only: energy partials only; with_energy: energy partials and the
+// inverse spectra
+hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool with_energy = false);
+// route: -1 the context's, 0 ik, 1 exact gradient
+hipError_t launch_xy_c2r(const Launch& L, DeviceState& S, int route = -1);
 // mode 0: Euler-Maruyama step with the shift the k-space pass formed in qshift_next
 // (writes pos_tmp, kr, counts);
-// mode 1: write forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
+// mode 1: write out_sign * forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
-                         unsigned parts);
+                         unsigned parts, double out_sign = 1.0);
 hipError_t launch_bin_scan(const Launch& L, DeviceState& S);
 hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src);
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S);

@@ -923,12 +923,14 @@ __global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict_
 //         on the exact-gradient route k_form_shift, from the noise and force
 //         sums).  Each moved bead goes to pout[j] with its exact new bin key
 //         and its rank in that bin.
-// MODE 1: forces only, written to out[abi id] ([n][3], float or double).
+// MODE 1: forces only, times out_sign, written to out[abi id] ([n][3], float
+//         or double).
 template <typename T, int P, int MODE>
 __global__ void __launch_bounds__(256)
     k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
              const T* __restrict__ fpart, const uint32_t* __restrict__ qs_new,
-             long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts, uint2* __restrict__ kr,
+             long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts, double out_sign,
+             uint2* __restrict__ kr,
              uint32_t* __restrict__ counts, uint32_t* __restrict__ flag) {
     const int tid = threadIdx.x;
     const bool need_field = MODE == 0 || (parts & 1u);
@@ -998,16 +1000,17 @@ __global__ void __launch_bounds__(256)
                     f[a] += sa;
                 }
             }
+            const T sg = (T)out_sign;
             if (out_dtype == 0) {
                 float* o = reinterpret_cast<float*>(out) + 3 * (long long)id;
-                o[0] = (float)f[0];
-                o[1] = (float)f[1];
-                o[2] = (float)f[2];
+                o[0] = (float)(sg * f[0]);
+                o[1] = (float)(sg * f[1]);
+                o[2] = (float)(sg * f[2]);
             } else {
                 double* o = reinterpret_cast<double*>(out) + 3 * (long long)id;
-                o[0] = (double)f[0];
-                o[1] = (double)f[1];
-                o[2] = (double)f[2];
+                o[0] = (double)(sg * f[0]);
+                o[1] = (double)(sg * f[1]);
+                o[2] = (double)(sg * f[2]);
             }
         }
     }
@@ -1212,6 +1215,10 @@ __global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict_
         eout[3] = e_b + e_chi + e_kap;
         for (int a = 0; a < 3; ++a) eout[4 + a] = -2.0 * ph.a2 * acc[2 + a] + wb[a];
         eout[7] = 0.0;
+        // parameter gradients of the non-bonded energy at fixed positions
+        eout[8] = ph.inv_n * (acc[0] + n_a * n_b * ph.u0);                       // dE/dchi
+        eout[9] = 0.5 * ph.inv_n * acc[1];                                       // dE/dkappa
+        eout[10] = ph.sampled ? __builtin_nan("") : -2.0 * sqrt(ph.a2) * (acc[2] + acc[3] + acc[4]);  // dE/da
     }
 }
 
@@ -1301,10 +1308,10 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
                            (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part);
     });
 }
-template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S) {
+template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S, bool ad) {
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
-        if (L.force_ad)
+        if (ad)
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
                                S.pos, S.bin_start, S.qshift, S.n, S.fsum_part);
@@ -1327,13 +1334,14 @@ hipError_t launch_spread_xy(const Launch& L, DeviceState& S) {
     return hipGetLastError();
 }
 
-hipError_t launch_xy_c2r(const Launch& L, DeviceState& S) {
+hipError_t launch_xy_c2r(const Launch& L, DeviceState& S, int route) {
+    const bool ad = route < 0 ? L.force_ad != 0 : route == 1;
     if (L.precision == 0) {
-        if (L.plane_block == 256) xy_c2r_b<float, 256>(L, S);
-        else xy_c2r_b<float, 512>(L, S);
+        if (L.plane_block == 256) xy_c2r_b<float, 256>(L, S, ad);
+        else xy_c2r_b<float, 512>(L, S, ad);
     } else {
-        if (L.plane_block == 256) xy_c2r_b<double, 256>(L, S);
-        else xy_c2r_b<double, 512>(L, S);
+        if (L.plane_block == 256) xy_c2r_b<double, 256>(L, S, ad);
+        else xy_c2r_b<double, 512>(L, S, ad);
     }
     return hipGetLastError();
 }
@@ -1345,50 +1353,52 @@ template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, i
                        S.qshift_next, S.utab, S.vtab, L.force_ad ? 2 : 4);
 }
 
-hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only) {
+hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool with_energy) {
+    const int we = (energy_only || with_energy) ? 1 : 0;
     if (L.precision == 0) {
         if (energy_only) z_t<float, 1>(L, S, 1);
-        else z_t<float, 0>(L, S, 0);
+        else z_t<float, 0>(L, S, we);
     } else {
         if (energy_only) z_t<double, 1>(L, S, 1);
-        else z_t<double, 0>(L, S, 0);
+        else z_t<double, 0>(L, S, we);
     }
     return hipGetLastError();
 }
 
 template <typename T, int P, int MODE>
-static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts) {
+static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts,
+                     double out_sign) {
     // one bead per thread, at least one block
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
-                       (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, S.kr, S.counts,
-                       S.flag);
+                       (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, out_sign, S.kr,
+                       S.counts, S.flag);
 }
 
 template <typename T, int MODE>
-static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int od, unsigned parts) {
+static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, int od, unsigned parts, double sg) {
     switch (L.order) {
-        case 1: update_p<T, 1, MODE>(L, S, step, out, od, parts); break;
-        case 2: update_p<T, 2, MODE>(L, S, step, out, od, parts); break;
-        case 3: update_p<T, 3, MODE>(L, S, step, out, od, parts); break;
-        case 4: update_p<T, 4, MODE>(L, S, step, out, od, parts); break;
-        case 5: update_p<T, 5, MODE>(L, S, step, out, od, parts); break;
-        case 6: update_p<T, 6, MODE>(L, S, step, out, od, parts); break;
-        default: update_p<T, 7, MODE>(L, S, step, out, od, parts); break;
+        case 1: update_p<T, 1, MODE>(L, S, step, out, od, parts, sg); break;
+        case 2: update_p<T, 2, MODE>(L, S, step, out, od, parts, sg); break;
+        case 3: update_p<T, 3, MODE>(L, S, step, out, od, parts, sg); break;
+        case 4: update_p<T, 4, MODE>(L, S, step, out, od, parts, sg); break;
+        case 5: update_p<T, 5, MODE>(L, S, step, out, od, parts, sg); break;
+        case 6: update_p<T, 6, MODE>(L, S, step, out, od, parts, sg); break;
+        default: update_p<T, 7, MODE>(L, S, step, out, od, parts, sg); break;
     }
 }
 
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
-                         unsigned parts) {
+                         unsigned parts, double out_sign) {
     if (mode == 0 && L.force_ad)
         hipLaunchKernelGGL(k_form_shift, dim3(1), dim3(256), 0, L.stream, S.noise_part, S.fsum_part, 2 * L.d.mz,
                            S.n, L.ph, S.qshift, S.qshift_next);
     if (L.precision == 0) {
-        if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts);
-        else update_t<float, 1>(L, S, step, out, out_dtype, parts);
+        if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts, out_sign);
+        else update_t<float, 1>(L, S, step, out, out_dtype, parts, out_sign);
     } else {
-        if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts);
-        else update_t<double, 1>(L, S, step, out, out_dtype, parts);
+        if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts, out_sign);
+        else update_t<double, 1>(L, S, step, out, out_dtype, parts, out_sign);
     }
     return hipGetLastError();
 }

@@ -170,3 +170,97 @@ def test_exact_gradient_trajectory_fp64():
     err = np.sqrt((d ** 2).mean()) / np.sqrt((R.min_image(x - x0, m.box) ** 2).mean())
     say("[ad] trajectory displacement rel-RMS", err)
     assert err < 1e-7
+
+
+# --------------------------------------------------------------------------
+# Differentiable energy: tild_energy_grad and the torch.autograd wrapper
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-9), (T.TILD_FP32, 1e-5)])
+@pytest.mark.parametrize("case", [0, 2, 4])
+def test_energy_gradients_match_oracle(precision, tol, case):
+    nc, na, nb, box, grid, P, chi, kap = AD_CASES[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=300 + case)
+    x = snap_to_lattice(m.x, m.box)
+    t = T.Tild(params_for(m, precision), m.types, m.bonds)  # ik context: dE/dx still exact
+    t.set_positions(x)
+    vals, gx = t.energy_grad()
+    t.close()
+    po = R.Params(box=tuple(m.box), grid=tuple(grid), order=P, smear_a=m.smear_a, chi=chi, kappa=kap,
+                  bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed)
+    ev = R.evaluate(x, m.types, m.bonds, po, want_ad=True)
+    g = R.energy_parameter_gradients(ev["chat"], po.smear_a, po.L, po.M, chi, kap, m.n)
+    say(f"[grad] case={case} precision={precision}", vals, "oracle", g)
+    assert abs(vals["E"] - ev["E"]) <= tol * max(1.0, abs(ev["E"]))
+    for got, ref in zip((vals["dE_dchi"], vals["dE_dkappa"], vals["dE_da"]), g):
+        assert abs(got - ref) <= tol * max(1.0, abs(ref)), (got, ref)
+    assert rel_rms(gx, -(ev["F_nb_ad"] + ev["F_bond"])) <= tol
+
+
+def test_set_interaction_matches_a_fresh_context():
+    m = make_melt(0)
+    x = snap_to_lattice(m.x, m.box)
+    t = T.Tild(params_for(m, T.TILD_FP64), m.types, m.bonds)
+    t.set_positions(x)
+    t.set_interaction(0.9, 7.0, 0.6)
+    e1 = t.energy()
+    t.close()
+    p2 = T.make_params(m.box, m.grid, m.order, 0.6, 0.9, 7.0, m.bond_k, m.dt, m.gamma, m.kT, m.seed, T.TILD_FP64)
+    t2 = T.Tild(p2, m.types, m.bonds)
+    t2.set_positions(x)
+    e2 = t2.energy()
+    t2.close()
+    for k in ("E_chi", "E_kappa", "E"):
+        assert abs(e1[k] - e2[k]) <= 1e-12 * max(1.0, abs(e2[k])), (k, e1[k], e2[k])
+
+
+def test_autograd_energy_and_finite_differences():
+    import torch
+    from paper_2302_02474_amd.autograd import tild_energy
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    t = T.Tild(params_for(m, T.TILD_FP64), m.types, m.bonds)
+    x = torch.tensor(x0, dtype=torch.float64, device="cuda", requires_grad=True)
+    chi = torch.tensor(m.chi, dtype=torch.float64, requires_grad=True)
+    kap = torch.tensor(m.kappa, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(m.smear_a, dtype=torch.float64, requires_grad=True)
+    E = tild_energy(x, chi, kap, a, t)
+    E.backward()
+    vals, gx = t.energy_grad()
+    assert np.allclose(x.grad.cpu().numpy(), gx, rtol=0, atol=1e-12 * np.abs(gx).max())
+    assert chi.grad.item() == pytest.approx(vals["dE_dchi"], rel=1e-14)
+    # central differences of the GPU energy in each parameter (FP64)
+    for name, d, val in (("chi", chi.grad.item(), m.chi), ("kappa", kap.grad.item(), m.kappa),
+                         ("a", a.grad.item(), m.smear_a)):
+        h = 1e-5 * max(1.0, abs(val))
+        es = []
+        for sgn in (+1, -1):
+            args = {"chi": m.chi, "kappa": m.kappa, "a": m.smear_a}
+            args[name] = val + sgn * h
+            t.set_interaction(args["chi"], args["kappa"], args["a"])
+            es.append(t.energy()["E"])
+        fd = (es[0] - es[1]) / (2 * h)
+        say(f"[autograd] dE/d{name}: {d} fd {fd}")
+        assert abs(fd - d) <= 1e-6 * max(1.0, abs(fd))
+    # one bead moved: central difference of E against the position gradient
+    t.set_interaction(m.chi, m.kappa, m.smear_a)
+    i, ax, h = 17, 1, 1e-4
+    es = []
+    for sgn in (+1, -1):
+        xp = x0.copy()
+        xp[i, ax] += sgn * h
+        t.set_positions(snap_to_lattice(xp, m.box))
+        es.append(t.energy()["E"])
+    fd = (es[0] - es[1]) / (2 * h)
+    say(f"[autograd] dE/dx[{i},{ax}]: {gx[i, ax]} fd {fd}")
+    assert abs(fd - gx[i, ax]) <= 1e-5 * max(1.0, abs(fd))
+    t.close()
+
+
+def test_sampled_kernel_has_no_smearing_gradient():
+    m = make_melt(0)
+    t = T.Tild(params_for(m, T.TILD_FP32, "sampled"), m.types, m.bonds)
+    t.set_positions(snap_to_lattice(m.x, m.box))
+    vals, _ = t.energy_grad(grad_x=None)
+    t.close()
+    assert np.isnan(vals["dE_da"]) and np.isfinite(vals["dE_dchi"])
