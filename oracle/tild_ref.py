@@ -31,6 +31,10 @@ Conventions (the paper leaves them open; these are the readings used):
     separation; k_b = 3/(2 b^2) (Eq. bonds).
   * Overdamped Euler-Maruyama: x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta),
     Delta the mean displacement when centre-of-mass correction is on.
+  * The GJF integrator the paper lists (Sec. "Integrator Class") is the
+    Gronbech-Jensen--Farago Langevin scheme (Mol. Phys. 111, 983 (2013)) in
+    its published velocity form; its noise beta_n = sqrt(2 gamma kT dt) xi is
+    drawn from the same Philox stream, keyed by the step index n.
 """
 
 from __future__ import annotations
@@ -47,7 +51,8 @@ __all__ = [
     "idft3", "wavenumbers", "kgrid", "uhat_analytic", "uhat_sampled", "field_spectra",
     "gradient_fields", "potential_fields", "gather", "gather_gradient_weights",
     "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
-    "trajectory", "structure_factor_exact", "min_image",
+    "trajectory", "structure_factor_exact", "min_image", "gjf_coefficients", "gjf_trajectory",
+    "half_step_velocity",
 ]
 
 
@@ -65,6 +70,7 @@ class Params:
     kT: float = 1.0
     seed: int = 0
     com_correct: bool = True
+    mass: float = 1.0  # bead mass (GJF only)
     potential: str = "analytic"  # or "sampled"
     transform: str = "dense"  # "dense" separable DFT matrices, or "numpy" FFT
 
@@ -442,6 +448,61 @@ def trajectory(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, 
             record(t, x, ev)
         x = em_update(x, ev["F"], ids, t, p)
     return x
+
+
+# --------------------------------------------------------------------------
+# GJF Langevin integrator (listed in Sec. "Integrator Class")
+# --------------------------------------------------------------------------
+
+def gjf_coefficients(p: Params):
+    """(a, b) of the GJF scheme: with c = gamma dt / (2 m), b = 1/(1 + c) and a = (1 - c)/(1 + c)."""
+    c = p.gamma * p.dt / (2.0 * p.mass)
+    return (1.0 - c) / (1.0 + c), 1.0 / (1.0 + c)
+
+
+def half_step_velocity(dx: np.ndarray, p: Params) -> np.ndarray:
+    """Half-step velocity u_{n+1/2} = (x_{n+1} - x_n) / (sqrt(b) dt) (Gronbech-Jensen, Jensen and Farago,
+    Mol. Phys. 118, e1662506 (2020)); its variance is exactly kT/m for a free particle at any dt."""
+    _, b = gjf_coefficients(p)
+    return dx / (np.sqrt(b) * p.dt)
+
+
+def gjf_trajectory(x0: np.ndarray, v0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, steps: int,
+                   t0: int = 0, record=None):
+    """Run ``steps`` GJF steps from step index t0, on-site velocities v0.
+
+    One step, with F_n the force at x_n and beta_{n+1} = sqrt(2 gamma kT dt) xi(step n+1):
+        x_{n+1} = x_n + b dt v_n + (b dt^2 / 2m) F_n + (b dt / 2m) beta_{n+1}
+        v_{n+1} = a v_n + (dt / 2m) (a F_n + F_{n+1}) + (b / m) beta_{n+1}
+    With centre-of-mass correction the mean displacement and the mean velocity are removed.
+    Returns (x, v, dx): final positions, on-site velocities and the last displacement (minimum image free:
+    dx is the unwrapped x_{n+1} - x_n).  ``record(t, x, v, ev)`` is called before each step.
+    """
+    a, b = gjf_coefficients(p)
+    m, dt = p.mass, p.dt
+    sigma = np.sqrt(2.0 * p.gamma * p.kT * dt)
+    x = np.array(x0, dtype=np.float64)
+    v = np.array(v0, dtype=np.float64)
+    ids = np.arange(x.shape[0])
+    ev = evaluate(x, types, bonds, p)
+    dx = np.zeros_like(x)
+    L = p.L
+    for t in range(t0, t0 + steps):
+        if record is not None:
+            record(t, x, v, ev)
+        beta = sigma * gaussian_noise(ids, t + 1, p.seed)
+        F = ev["F"]
+        dx = b * dt * v + (b * dt * dt / (2.0 * m)) * F + (b * dt / (2.0 * m)) * beta
+        if p.com_correct:
+            dx = dx - dx.mean(axis=0)
+        y = np.mod(x + dx, L)
+        x = np.where(y >= L, y - L, y)
+        ev_next = evaluate(x, types, bonds, p)
+        v = a * v + (dt / (2.0 * m)) * (a * F + ev_next["F"]) + (b / m) * beta
+        if p.com_correct:
+            v = v - v.mean(axis=0)
+        ev = ev_next
+    return x, v, dx
 
 
 # --------------------------------------------------------------------------

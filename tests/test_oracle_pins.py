@@ -426,6 +426,101 @@ def test_com_correction_removes_mean_displacement():
     assert np.all(np.abs(d.mean(axis=0)) < 1e-13)
 
 
+# ----------------------------------------------------------------- GJF integrator
+
+def _dimers(nd, L, d0, seed):
+    g = np.random.default_rng(seed)
+    a = g.uniform(0.2 * L, 0.8 * L, size=(nd, 3))
+    x = np.empty((2 * nd, 3))
+    x[0::2], x[1::2] = a, a + d0
+    bonds = np.stack([np.arange(0, 2 * nd, 2), np.arange(1, 2 * nd, 2)], 1).astype(np.int32)
+    return x, np.zeros(2 * nd, np.int32), bonds
+
+
+def test_gjf_verlet_limit_harmonic_dimer_closed_form():
+    """gamma = 0, kT = 0: GJF is velocity Verlet.  The bond vector d of a dimer with U = k_b |d|^2 then obeys
+    d_{n+1} = (2 - (Omega dt)^2) d_n - d_{n-1}, Omega^2 = 4 k_b / m, whose solution is
+    d_n = d_0 cos(n theta) + (d_1 - d_0 cos theta) / sin(theta) sin(n theta), cos theta = 1 - (Omega dt)^2 / 2,
+    with d_1 = d_0 + dt w_0 - (Omega dt)^2 d_0 / 2 (w_0 the relative velocity)."""
+    kb, m, dt = 1.5, 2.0, 0.4
+    p = R.Params(box=(50.0,) * 3, grid=(4,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0, bond_k=kb,
+                 dt=dt, gamma=0.0, kT=0.0, mass=m, com_correct=False)
+    d0 = np.array([0.8, -0.3, 0.5])
+    x, types, bonds = _dimers(1, 50.0, d0, 0)
+    v = np.zeros_like(x)
+    v[0] = [0.2, 0.1, -0.4]
+    v[1] = [-0.1, 0.3, 0.2]
+    w0 = v[1] - v[0]
+    om2 = 4 * kb / m
+    ct = 1 - om2 * dt * dt / 2
+    th = np.arccos(ct)
+    d1 = d0 + dt * w0 - om2 * dt * dt * d0 / 2
+    seen = []
+    R.gjf_trajectory(x, v, types, bonds, p, 25, record=lambda t, xx, vv, ev: seen.append(xx[1] - xx[0]))
+    for n, d in enumerate(seen):
+        expect = d0 * np.cos(n * th) + (d1 - d0 * ct) / np.sin(th) * np.sin(n * th)
+        np.testing.assert_allclose(d, expect, atol=1e-12)
+
+
+def test_gjf_damped_free_particle_closed_form():
+    """kT = 0, no forces: v_n = a^n v_0 and x_n = x_0 + b dt v_0 (1 - a^n) / (1 - a)."""
+    p = R.Params(box=(40.0,) * 3, grid=(4,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0, dt=0.3,
+                 gamma=1.3, kT=0.0, mass=1.7, com_correct=False)
+    g = np.random.default_rng(4)
+    x0 = g.uniform(15, 25, size=(6, 3))
+    v0 = g.normal(size=(6, 3))
+    a, b = R.gjf_coefficients(p)
+    n = 9
+    x, v, _ = R.gjf_trajectory(x0, v0, np.zeros(6, np.int32), np.zeros((0, 2), np.int32), p, n)
+    np.testing.assert_allclose(v, a ** n * v0, atol=1e-13)
+    np.testing.assert_allclose(x, x0 + b * p.dt * v0 * (1 - a ** n) / (1 - a), atol=1e-12)
+
+
+def test_gjf_free_particle_velocities_have_kt_over_m_variance_at_large_dt():
+    """Free particles: the on-site velocity and the half-step velocity (x_{n+1} - x_n)/(sqrt(b) dt) both have
+    variance exactly kT/m in the stationary state, whatever dt (gamma dt / m = 0.53 here)."""
+    kT, m = 1.2, 1.5
+    p = R.Params(box=(100.0,) * 3, grid=(4,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0, dt=0.8,
+                 gamma=1.0, kT=kT, mass=m, seed=21, com_correct=False)
+    n = 20000
+    g = np.random.default_rng(5)
+    x0 = g.uniform(0, 100, size=(n, 3))
+    v0 = g.normal(0, np.sqrt(kT / m), size=(n, 3))
+    _, v, dx = R.gjf_trajectory(x0, v0, np.zeros(n, np.int32), np.zeros((0, 2), np.int32), p, 12)
+    u = R.half_step_velocity(dx, p)
+    assert abs(np.var(v) / (kT / m) - 1) < 0.03
+    assert abs(np.var(u) / (kT / m) - 1) < 0.03
+
+
+def test_gjf_harmonic_dimer_bond_length_exact_at_large_dt():
+    """GJF samples a harmonic potential's configurations exactly at any stable dt: for dimers with
+    U = k_b |d|^2, <|d|^2> = 3 kT / (2 k_b) at Omega dt = 0.73 (EM-type schemes are biased by O(dt))."""
+    kb, kT = 1.5, 1.0
+    p = R.Params(box=(400.0,) * 3, grid=(4,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0, bond_k=kb,
+                 dt=0.3, gamma=1.0, kT=kT, mass=1.0, seed=17, com_correct=False)
+    nd = 2000
+    g = np.random.default_rng(6)
+    x, types, bonds = _dimers(nd, 400.0, g.normal(0, np.sqrt(1 / 3), size=(nd, 3)), 7)
+    v = g.normal(0, np.sqrt(kT / p.mass), size=x.shape)
+    acc = []
+
+    def rec(t, xx, vv, ev):
+        if t >= 40:
+            d = R.min_image(xx[1::2] - xx[0::2], p.L)
+            acc.append(np.mean(np.sum(d * d, axis=1)))
+    R.gjf_trajectory(x, v, types, bonds, p, 160, record=rec)
+    assert abs(np.mean(acc) / (3 * kT / (2 * kb)) - 1) < 0.02
+
+
+def test_gjf_com_correction_removes_mean_displacement_and_velocity():
+    p = small_params(dt=0.05, mass=1.3)
+    x, t, b = random_system(50, p, seed=10)
+    v0 = np.random.default_rng(2).normal(size=x.shape)
+    _, v, dx = R.gjf_trajectory(x, v0, t, b, p, 3)
+    assert np.all(np.abs(dx.mean(axis=0)) < 1e-14)
+    assert np.all(np.abs(v.mean(axis=0)) < 1e-13)
+
+
 def test_structure_factor_ideal_gas_is_one():
     L = np.array([20.0, 20.0, 20.0])
     x = rng.uniform(0, 1, size=(4000, 3)) * L
