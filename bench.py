@@ -164,18 +164,26 @@ def main() -> int:
     traffic = measured_traffic(dom)
     t.close()
 
+    def time_variant(**kw):
+        tv = T.from_melt(melt, precision=T.TILD_FP32, stream=stream, **kw)
+        tv.step(args.warmup)
+        tv.synchronize()
+        t0 = time.perf_counter()
+        tv.step(args.steps)
+        tv.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / args.steps
+        kv = tv.profile_steps(max(1, args.profile_steps // 2))
+        tv.close()
+        return {"ms_per_step": round(ms, 5), "bead_steps_per_s": melt.n / (ms * 1e-3),
+                "kernels_ms": {k: round(v, 5) for k, v in kv.items()}}
+
     # The same workload on the exact-gradient route (TILD_FORCE_AD: two inverse
-    # transforms instead of six), reported beside the headline ik route.
-    ta = T.from_melt(melt, precision=T.TILD_FP32, stream=stream, force="ad")
-    ta.step(args.warmup)
-    ta.synchronize()
-    t0 = time.perf_counter()
-    ta.step(args.steps)
-    ta.synchronize()
-    ad_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    ad_kms = ta.profile_steps(max(1, args.profile_steps // 2))
-    ta.close()
-    print(f"[bench] exact-gradient route: {ad_ms:.4f} ms/step", file=sys.stderr, flush=True)
+    # transforms instead of six) and with the GJF integrator, reported beside
+    # the headline (ik route, Euler-Maruyama).
+    variants = {"exact_gradient_force": time_variant(force="ad"),
+                "gjf_integrator": time_variant(integrator="gjf")}
+    for k, v in variants.items():
+        print(f"[bench] variant {k}: {v['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
 
     # Differentiable energy, fwd+adj: E and dE/dx, dE/dchi, dE/dkappa, dE/da
     # at the current positions (one tild_energy_grad call, outputs on the
@@ -230,9 +238,7 @@ def main() -> int:
         "kernels": kernels,
         "fwd_adj_ms": round(fwd_adj_ms, 4),
         "fwd_adj_workload": f"{m4.name}: E, dE/dx, dE/dchi, dE/dkappa, dE/da per call (synchronising), FP32",
-        "variants": {"exact_gradient_force": {
-            "ms_per_step": round(ad_ms, 5), "bead_steps_per_s": melt.n / (ad_ms * 1e-3),
-            "kernels_ms": {k: round(v, 5) for k, v in ad_kms.items()}}},
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host ...", file=sys.stderr, flush=True)

@@ -18,8 +18,9 @@
  * assigned to a periodic grid with order-P B-spline weights, the species
  * densities are Fourier transformed, multiplied by the kernel and by i k,
  * transformed back to field gradients and interpolated to the beads with the
- * same weights.  Integrator: Euler-Maruyama with internally generated noise
- * (Sec. "Integrator Class"), in the overdamped form of Eq. EM.
+ * same weights.  Integrators (Sec. "Integrator Class"): Euler-Maruyama with
+ * internally generated noise, in the overdamped form of Eq. EM (default), or
+ * the Gronbech-Jensen--Farago (GJF) Langevin scheme (TILD_INTEGRATOR_GJF).
  *
  * Conventions shared by every call:
  *   - Units: kT, bead mass and the segment length b are the reduced units of
@@ -101,6 +102,16 @@ extern "C" {
                            (2 inverse transforms instead of 6), instead of the ik route of Eq. PMM;
                            needs order >= 2.  Its net force is not exactly zero: with
                            TILD_COM_CORRECT the mean force enters the mean displacement. */
+#define TILD_INTEGRATOR_GJF 16u /* GJF Langevin integrator (Gronbech-Jensen and Farago, Mol. Phys. 111, 983
+                                   (2013)) with bead mass `mass`, friction gamma and noise
+                                   beta_n = sqrt(2 gamma kT dt) xi(step n).  Each step applies
+                                     D_{n+1} = a D_n + (b dt^2 / m) F_n + (b dt / 2m) (beta_n + beta_{n+1}),
+                                     x_{n+1} = x_n + D_{n+1},
+                                   c = gamma dt / 2m, a = (1 - c)/(1 + c), b = 1/(1 + c): the velocity
+                                   form of the scheme with the on-site velocity eliminated.  The state
+                                   carried between steps is the half-step velocity
+                                   u = D / (sqrt(b) dt) (tild_set_velocities, tild_get_velocities; zero
+                                   at creation).  With TILD_COM_CORRECT the mean of D is removed. */
 #define TILD_DETERMINISTIC 4u /* accepted for compatibility: every result is already bitwise reproducible
                                  run to run (the spread accumulates fixed-point integers in both precisions,
                                  every reduction has a fixed order) */
@@ -129,7 +140,9 @@ typedef struct tild_params {
     uint64_t seed;     /* Philox key */
     int32_t precision; /* TILD_FP32 (float grids, transforms and forces; float64 energy, virial and
                           centre-of-mass sums) or TILD_FP64 (everything in float64) */
-    uint32_t flags;    /* TILD_COM_CORRECT or 0 */
+    uint32_t flags;    /* TILD_COM_CORRECT, TILD_POTENTIAL_SAMPLED, TILD_FORCE_AD, TILD_INTEGRATOR_GJF,
+                          TILD_DETERMINISTIC, or 0 */
+    double mass;       /* bead mass for TILD_INTEGRATOR_GJF (> 0; 0 is read as 1); unused by Euler-Maruyama */
 } tild_params;
 
 /*
@@ -179,11 +192,25 @@ int tild_set_positions(tild_ctx* ctx, const void* xyz, int32_t dtype, int32_t on
 int tild_get_positions(tild_ctx* ctx, void* xyz, int32_t dtype, int32_t on_device);
 
 /*
+ * Half-step velocities of a TILD_INTEGRATOR_GJF context: u = (x_n - x_{n-1}) /
+ * (sqrt(b) dt) of the last step (Gronbech-Jensen, Jensen and Farago, Mol.
+ * Phys. 118, e1662506 (2020): for a free particle its variance is exactly
+ * kT/m at any dt), which the next step uses as D_n = sqrt(b) dt u.
+ * v: [n_beads][3] in ABI order, dtype element type, host or device memory.
+ * Positions must have been set (TILD_ESTATE otherwise); a context without
+ * TILD_INTEGRATOR_GJF gives TILD_EINVAL.  tild_set_positions keeps every
+ * bead's velocity.  Non-finite host input gives TILD_EINVAL.
+ */
+int tild_set_velocities(tild_ctx* ctx, const void* v, int32_t dtype, int32_t on_device);
+int tild_get_velocities(tild_ctx* ctx, void* v, int32_t dtype, int32_t on_device);
+
+/*
  * Enqueue n_steps >= 0 steps.  Each step evaluates the forces at the current
  * positions (non-bonded + bonds) and applies
  *   x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta),
  * Delta being the mean displacement when TILD_COM_CORRECT is set, xi the
- * Philox noise of the current step index; the step counter then advances.
+ * Philox noise of the current step index (with TILD_INTEGRATOR_GJF the GJF
+ * update given with that flag instead); the step counter then advances.
  * Asynchronous: returns after enqueueing.
  */
 int tild_step(tild_ctx* ctx, int64_t n_steps);

@@ -468,7 +468,7 @@ def half_step_velocity(dx: np.ndarray, p: Params) -> np.ndarray:
 
 
 def gjf_trajectory(x0: np.ndarray, v0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, steps: int,
-                   t0: int = 0, record=None):
+                   t0: int = 0, record=None, force: str = "ik"):
     """Run ``steps`` GJF steps from step index t0, on-site velocities v0.
 
     One step, with F_n the force at x_n and beta_{n+1} = sqrt(2 gamma kT dt) xi(step n+1):
@@ -476,15 +476,22 @@ def gjf_trajectory(x0: np.ndarray, v0: np.ndarray, types: np.ndarray, bonds: np.
         v_{n+1} = a v_n + (dt / 2m) (a F_n + F_{n+1}) + (b / m) beta_{n+1}
     With centre-of-mass correction the mean displacement and the mean velocity are removed.
     Returns (x, v, dx): final positions, on-site velocities and the last displacement (minimum image free:
-    dx is the unwrapped x_{n+1} - x_n).  ``record(t, x, v, ev)`` is called before each step.
+    dx is the unwrapped x_{n+1} - x_n).  ``record(t, x, v, ev)`` is called before each step.  force: "ik"
+    (Eq. PMM) or "ad" (the exact gradient of the mesh energy) for the non-bonded part.
     """
+    def forces(xx):
+        e = evaluate(xx, types, bonds, p, want_ad=force == "ad")
+        if force == "ad":
+            e["F"] = e["F_nb_ad"] + e["F_bond"]
+        return e
+
     a, b = gjf_coefficients(p)
     m, dt = p.mass, p.dt
     sigma = np.sqrt(2.0 * p.gamma * p.kT * dt)
     x = np.array(x0, dtype=np.float64)
     v = np.array(v0, dtype=np.float64)
     ids = np.arange(x.shape[0])
-    ev = evaluate(x, types, bonds, p)
+    ev = forces(x)
     dx = np.zeros_like(x)
     L = p.L
     for t in range(t0, t0 + steps):
@@ -497,7 +504,7 @@ def gjf_trajectory(x0: np.ndarray, v0: np.ndarray, types: np.ndarray, bonds: np.
             dx = dx - dx.mean(axis=0)
         y = np.mod(x + dx, L)
         x = np.where(y >= L, y - L, y)
-        ev_next = evaluate(x, types, bonds, p)
+        ev_next = forces(x)
         v = a * v + (dt / (2.0 * m)) * (a * F + ev_next["F"]) + (b / m) * beta
         if p.com_correct:
             v = v - v.mean(axis=0)

@@ -15,7 +15,7 @@ import numpy as np
 
 from . import _lib as _L
 from ._lib import (  # noqa: F401
-    TILD_COM_CORRECT, TILD_POTENTIAL_SAMPLED, TILD_DETERMINISTIC, TILD_FORCE_AD, TILD_EHIP, TILD_EINVAL, TILD_ENOMEM, TILD_ENONFINITE, TILD_ESTATE,
+    TILD_COM_CORRECT, TILD_POTENTIAL_SAMPLED, TILD_DETERMINISTIC, TILD_FORCE_AD, TILD_INTEGRATOR_GJF, TILD_EHIP, TILD_EINVAL, TILD_ENOMEM, TILD_ENONFINITE, TILD_ESTATE,
     TILD_FP32, TILD_FP64, TILD_OK, TILD_PART_BOND, TILD_PART_NONBONDED, TILD_PART_TOTAL,
     TildParams,
 )
@@ -32,11 +32,15 @@ def lib():
 
 
 def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0,
-                seed=0, precision=TILD_FP32, com_correct=True, potential="analytic", force="ik") -> TildParams:
+                seed=0, precision=TILD_FP32, com_correct=True, potential="analytic", force="ik",
+                integrator="em", mass=1.0) -> TildParams:
     """tild_params; potential is "analytic" (exp(-a^2 k^2)) or "sampled" (DFT of the node-sampled Gaussian);
-    force is "ik" (the paper's route) or "ad" (exact gradient of the mesh energy)."""
+    force is "ik" (the paper's route) or "ad" (exact gradient of the mesh energy); integrator is "em"
+    (overdamped Euler-Maruyama) or "gjf" (Gronbech-Jensen--Farago Langevin, bead mass ``mass``)."""
     if force not in ("ik", "ad"):
         raise ValueError(f"force must be 'ik' or 'ad', got {force!r}")
+    if integrator not in ("em", "gjf"):
+        raise ValueError(f"integrator must be 'em' or 'gjf', got {integrator!r}")
     if potential not in ("analytic", "sampled"):
         raise ValueError(f"potential must be 'analytic' or 'sampled', got {potential!r}")
     p = TildParams()
@@ -54,7 +58,8 @@ def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gam
     p.seed = int(seed)
     p.precision = int(precision)
     p.flags = ((TILD_COM_CORRECT if com_correct else 0) | (TILD_POTENTIAL_SAMPLED if potential == "sampled" else 0)
-               | (TILD_FORCE_AD if force == "ad" else 0))
+               | (TILD_FORCE_AD if force == "ad" else 0) | (TILD_INTEGRATOR_GJF if integrator == "gjf" else 0))
+    p.mass = float(mass)
     return p
 
 
@@ -163,6 +168,20 @@ class Tild:
         self._check(self._lib.tild_get_positions(self._ctx, ptr, _dtype_code(out), dev))
         return out
 
+    def set_velocities(self, v):
+        """GJF half-step velocities [n][3] (ABI order)."""
+        if not _is_torch(v):
+            v = np.ascontiguousarray(v)
+        ptr, dev = _ptr(v)
+        self._check(self._lib.tild_set_velocities(self._ctx, ptr, _dtype_code(v), dev))
+
+    def get_velocities(self, out=None, dtype=np.float64):
+        if out is None:
+            out = np.empty((self.n, 3), dtype=dtype)
+        ptr, dev = _ptr(out)
+        self._check(self._lib.tild_get_velocities(self._ctx, ptr, _dtype_code(out), dev))
+        return out
+
     def step(self, n_steps: int = 1):
         self._check(self._lib.tild_step(self._ctx, int(n_steps)))
 
@@ -238,10 +257,11 @@ def stream_copy_ms(dst, src, nbytes: int, iters: int = 20, stream=None) -> float
     return float(ms.value)
 
 
-def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None, potential="analytic", force="ik") -> Tild:
+def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None, potential="analytic", force="ik",
+              integrator="em", mass=1.0) -> Tild:
     """Context for a synth.Melt workload (positions are set too)."""
     p = make_params(melt.box, melt.grid, melt.order, melt.smear_a, melt.chi, melt.kappa, melt.bond_k, melt.dt,
-                    melt.gamma, melt.kT, melt.seed, precision, com_correct, potential, force)
+                    melt.gamma, melt.kT, melt.seed, precision, com_correct, potential, force, integrator, mass)
     t = Tild(p, melt.types, melt.bonds, stream=stream)
     t.set_positions(np.ascontiguousarray(melt.x, dtype=np.float64))
     return t

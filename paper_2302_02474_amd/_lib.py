@@ -20,13 +20,15 @@ TILD_COM_CORRECT = 1
 TILD_POTENTIAL_SAMPLED = 2
 TILD_DETERMINISTIC = 4
 TILD_FORCE_AD = 8
+TILD_INTEGRATOR_GJF = 16
 TILD_PART_NONBONDED = 1
 TILD_PART_BOND = 2
 TILD_PART_TOTAL = 3
 TILD_NUM_KERNELS = 6
 
 EXPORTS = [
-    "tild_workspace_bytes", "tild_create", "tild_set_positions", "tild_get_positions", "tild_step", "tild_forces",
+    "tild_workspace_bytes", "tild_create", "tild_set_positions", "tild_get_positions", "tild_set_velocities",
+    "tild_get_velocities", "tild_step", "tild_forces",
     "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
 ]
@@ -47,6 +49,7 @@ class TildParams(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
+        ("mass", ctypes.c_double),
     ]
 
 
@@ -73,6 +76,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_set_positions.restype = ctypes.c_int
     lib.tild_get_positions.argtypes = [vp, vp, i32, i32]
     lib.tild_get_positions.restype = ctypes.c_int
+    lib.tild_set_velocities.argtypes = [vp, vp, i32, i32]
+    lib.tild_set_velocities.restype = ctypes.c_int
+    lib.tild_get_velocities.argtypes = [vp, vp, i32, i32]
+    lib.tild_get_velocities.restype = ctypes.c_int
     lib.tild_step.argtypes = [vp, i64]
     lib.tild_step.restype = ctypes.c_int
     lib.tild_forces.argtypes = [vp, vp, i32, i32, u32]

@@ -138,9 +138,12 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
     if (!(p->gamma > 0.0) || !std::isfinite(p->gamma)) return why = "gamma must be finite and > 0", TILD_EINVAL;
     if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return why = "kT must be finite and >= 0", TILD_EINVAL;
     if (p->precision != TILD_FP32 && p->precision != TILD_FP64) return why = "precision must be TILD_FP32 or TILD_FP64", TILD_EINVAL;
-    if (p->flags & ~(TILD_COM_CORRECT | TILD_POTENTIAL_SAMPLED | TILD_DETERMINISTIC | TILD_FORCE_AD))
+    if (p->flags & ~(TILD_COM_CORRECT | TILD_POTENTIAL_SAMPLED | TILD_DETERMINISTIC | TILD_FORCE_AD |
+                     TILD_INTEGRATOR_GJF))
         return why = "unknown flag bits", TILD_EINVAL;
     if ((p->flags & TILD_FORCE_AD) && p->order < 2) return why = "TILD_FORCE_AD needs order >= 2", TILD_EINVAL;
+    if ((p->flags & TILD_INTEGRATOR_GJF) && !(p->mass >= 0.0 && std::isfinite(p->mass)))
+        return why = "mass must be finite and > 0 (0 reads as 1)", TILD_EINVAL;
     if ((p->flags & TILD_POTENTIAL_SAMPLED) && !(p->smear_a > 0.0))
         return why = "TILD_POTENTIAL_SAMPLED needs smear_a > 0", TILD_EINVAL;
     return TILD_OK;
@@ -453,6 +456,16 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     ph.noise_amp = std::sqrt(2.0 * params->kT * params->dt / params->gamma);
     ph.seed = params->seed;
     ph.com_correct = (params->flags & TILD_COM_CORRECT) ? 1 : 0;
+    ph.gjf = (params->flags & TILD_INTEGRATOR_GJF) ? 1 : 0;
+    if (ph.gjf) {
+        // GJF: c = gamma dt / 2m, a = (1 - c)/(1 + c), b = 1/(1 + c)
+        const double m = params->mass > 0.0 ? params->mass : 1.0, dt = params->dt;
+        const double cf = params->gamma * dt / (2.0 * m), b = 1.0 / (1.0 + cf);
+        ph.gjf_a = (1.0 - cf) / (1.0 + cf);
+        ph.gjf_vs = std::sqrt(b) * dt;
+        ph.mob_dt = b * dt * dt / m;
+        ph.noise_amp = b * dt / (2.0 * m) * std::sqrt(2.0 * params->gamma * params->kT * dt);
+    }
 
     DeviceState& S = c->S;
     S.n = n_beads;
@@ -478,6 +491,10 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A((void**)&S.pos_tmp, npos * sizeof(uint4));
     A((void**)&S.kr, npos * sizeof(uint2));
     A(&S.fbond, npos * 4 * real_sz);
+    if (ph.gjf) {
+        A(&S.vel, npos * 4 * real_sz);
+        A(&S.vel_tmp, npos * 4 * real_sz);
+    }
     const size_t nbins_pad = ((size_t)S.nbins + 32) / 32 * 32 + 32;  // vector scan reads whole 32-bin groups
     A((void**)&S.counts, nbins_pad * sizeof(uint32_t));
     A((void**)&S.bin_start, nbins_pad * sizeof(uint32_t));
@@ -554,6 +571,11 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     if (L.precision == 0) H2D(S.tw, twf.data(), twf.size() * sizeof(float));
     else H2D(S.tw, tw.data(), tw.size() * sizeof(double));
     H2D(S.flag, zeros4, sizeof(uint32_t));
+    if (ph.gjf && e == hipSuccess) {
+        // velocities start at zero; the first placement moves vel_tmp into vel
+        e = hipMemset(S.vel, 0, npos * 4 * real_sz);
+        if (e == hipSuccess) e = hipMemset(S.vel_tmp, 0, npos * 4 * real_sz);
+    }
     if (e == hipSuccess) e = configure_kernel_attributes(L);
     if (e != hipSuccess) {
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
@@ -611,6 +633,8 @@ TILD_API int tild_set_positions(tild_ctx* c, const void* xyz, int32_t dtype, int
         e = hipMemcpyAsync(c->staging, xyz, bytes, hipMemcpyHostToDevice, c->L.stream);
         src = c->staging;
     }
+    // GJF: each bead keeps its velocity; move them to ABI order, the order the placement gives
+    if (e == hipSuccess && c->have_pos && c->L.ph.gjf) e = launch_velocities(c->L, c->S, 2, nullptr, 0);
     if (e == hipSuccess) e = launch_place(c->L, c->S, src, dtype);
     if (e == hipSuccess) e = sort_beads(c, c->S.nbr_abi);
     if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->L.stream);
@@ -630,6 +654,46 @@ TILD_API int tild_get_positions(tild_ctx* c, void* xyz, int32_t dtype, int32_t o
     hipError_t e = launch_get_positions(c->L, c->S, dst, dtype);
     if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(xyz, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
     if (e != hipSuccess) return c->hip_fail(e, "get_positions");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
+TILD_API int tild_set_velocities(tild_ctx* c, const void* v, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if ((!v && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "set_velocities: NULL array or bad dtype");
+    if (!c->L.ph.gjf) return c->fail(TILD_EINVAL, "set_velocities: the context has no velocities (needs TILD_INTEGRATOR_GJF)");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    const void* src = v;
+    hipError_t e = hipSuccess;
+    if (!on_device && c->S.n > 0) {
+        for (int64_t i = 0; i < c->S.n * 3; ++i) {
+            const double x = dtype == TILD_FP32 ? (double)((const float*)v)[i] : ((const double*)v)[i];
+            if (!std::isfinite(x)) return c->fail(TILD_EINVAL, "set_velocities: non-finite value");
+        }
+        e = hipMemcpyAsync(c->staging, v, bytes, hipMemcpyHostToDevice, c->L.stream);
+        src = c->staging;
+    }
+    if (e == hipSuccess) e = launch_velocities(c->L, c->S, 0, const_cast<void*>(src), dtype);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "set_velocities");
+    return TILD_OK;
+}
+
+TILD_API int tild_get_velocities(tild_ctx* c, void* v, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if ((!v && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "get_velocities: NULL array or bad dtype");
+    if (!c->L.ph.gjf) return c->fail(TILD_EINVAL, "get_velocities: the context has no velocities (needs TILD_INTEGRATOR_GJF)");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    void* dst = on_device ? v : c->staging;
+    hipError_t e = launch_velocities(c->L, c->S, 1, dst, dtype);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(v, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "get_velocities");
     if (!on_device) return check_flag(c);
     return TILD_OK;
 }

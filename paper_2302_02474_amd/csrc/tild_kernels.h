@@ -20,8 +20,12 @@ struct Phys {
     double chi, kappa;  // interaction parameters
     double inv_n;       // 1 / N
     double bond_k;
-    double mob_dt;      // dt / gamma
-    double noise_amp;   // sqrt(2 kT dt / gamma)
+    double mob_dt;      // coefficient of F in a step's displacement: dt / gamma (EM) or b dt^2 / m (GJF)
+    double noise_amp;   // coefficient of the unit noise: sqrt(2 kT dt / gamma) (EM) or
+                        // (b dt / 2m) sqrt(2 gamma kT dt) (GJF, times xi_n + xi_{n+1})
+    int gjf;            // GJF integrator: D_{n+1} = a D_n + mob_dt F + noise_amp (xi_n + xi_{n+1})
+    double gjf_a;       // a = (1 - c)/(1 + c), c = gamma dt / 2m
+    double gjf_vs;      // sqrt(b) dt: D = gjf_vs u for the half-step velocity u
     double mean_a, mean_b;  // N_A / M, N_B / M: subtracted from the counts
     double wmax;            // largest single-bead weight of one grid point, (max B_P)^3
     double u0;              // kernel at k = 0 (1 for the analytic kernel)
@@ -48,6 +52,8 @@ struct DeviceState {
     uint4* pos_tmp;       // [n] beads in the previous order (new positions or ABI input)
     uint2* kr;            // [n] {bin key, rank within the bin} of pos_tmp[j]
     void* fbond;          // [n][4] harmonic bond force of sorted bead j {Fx, Fy, Fz, 0} (working precision)
+    void* vel;            // GJF only: [n][4] half-step velocity of sorted bead j {ux, uy, uz, 0}
+    void* vel_tmp;        // GJF only: the same in the order of pos_tmp
     uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
     uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
     unsigned long long* scan_status;  // [ntiles + 1] look-back status words of the bin scan, then its ticket
@@ -102,8 +108,9 @@ hipError_t launch_spread_xy(const Launch& L, DeviceState& S);
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool with_energy = false);
 // route: -1 the context's, 0 ik, 1 exact gradient
 hipError_t launch_xy_c2r(const Launch& L, DeviceState& S, int route = -1);
-// mode 0: Euler-Maruyama step with the shift the k-space pass formed in qshift_next
-// (writes pos_tmp, kr, counts);
+// mode 0: one step of the context's integrator (Euler-Maruyama, or GJF when
+// ph.gjf, which also writes vel_tmp) with the shift the k-space pass formed in
+// qshift_next (writes pos_tmp, kr, counts);
 // mode 1: write out_sign * forces (parts) to out[abi id] (out_dtype 0 float / 1 double)
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts, double out_sign = 1.0);
@@ -114,6 +121,10 @@ hipError_t launch_reduce_energy(const Launch& L, DeviceState& S);
 // ABI-order input -> pos_tmp, key, rank (qshift reset to 0)
 hipError_t launch_place(const Launch& L, DeviceState& S, const void* xyz, int dtype);
 hipError_t launch_get_positions(const Launch& L, DeviceState& S, void* xyz, int dtype);
+// GJF velocities, ABI order [n][3] of dtype: op 0 set (v -> vel), op 1 get
+// (vel -> v), op 2 vel (sorted) -> vel_tmp in ABI order (v unused), before a
+// re-placement of the beads
+hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, int dtype);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 // Dynamic LDS a plane / z workgroup needs (bytes), used for validation.

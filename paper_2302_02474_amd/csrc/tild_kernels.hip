@@ -131,8 +131,8 @@ template <typename T, int P>
 __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
                                              const uint32_t* __restrict__ bin_start,
                                              const uint32_t* __restrict__ qs, const Dims d, int z, int K, T scale,
-                                             bool noise, uint64_t step, uint64_t seed, long long nsum[3], int tid,
-                                             int nthr) {
+                                             bool noise, bool two, uint64_t step, uint64_t seed, long long nsum[3],
+                                             int tid, int nthr) {
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     A* acc = reinterpret_cast<A*>(lds);
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
@@ -156,11 +156,14 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
                 if (jb + (uint32_t)(u * nthr) >= j1) break;
                 const uint4 q = qv[u];
                 if (c == 0 && noise) {
-                    T xi[3];
-                    Noise<T>::draw(q.w >> 1, step, seed, xi);
-                    nsum[0] += llrint((double)xi[0] * kTwo32);
-                    nsum[1] += llrint((double)xi[1] * kTwo32);
-                    nsum[2] += llrint((double)xi[2] * kTwo32);
+                    // the step's noise; with `two` (GJF) also that of the next step
+                    for (int k = 0; k < (two ? 2 : 1); ++k) {
+                        T xi[3];
+                        Noise<T>::draw(q.w >> 1, step + (uint64_t)k, seed, xi);
+                        nsum[0] += llrint((double)xi[0] * kTwo32);
+                        nsum[1] += llrint((double)xi[1] * kTwo32);
+                        nsum[2] += llrint((double)xi[2] * kTwo32);
+                    }
                 }
                 int gx, gy;
                 T wx[P], wy[P];
@@ -314,7 +317,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
     long long nsum[3] = {0, 0, 0};
-    spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, step, ph.seed, nsum, tid, BLOCK);
+    spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, ph.gjf != 0, step, ph.seed, nsum, tid, BLOCK);
     if (noise) {
         block_sum<long long, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
         if (tid == 0)
@@ -923,6 +926,11 @@ __global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict_
 //         on the exact-gradient route k_form_shift, from the noise and force
 //         sums).  Each moved bead goes to pout[j] with its exact new bin key
 //         and its rank in that bin.
+// MODE 2: GJF step, D_{n+1} = a D_n + mob_dt F + noise_amp (xi_n + xi_{n+1})
+//         with D_n = gjf_vs u from the half-step velocity u (vin, sorted
+//         order); the same shift, key and rank as MODE 0, and the realised
+//         displacement (new minus old position, net of the shift) written
+//         back as the new half-step velocity to vout[j].
 // MODE 1: forces only, times out_sign, written to out[abi id] ([n][3], float
 //         or double).
 template <typename T, int P, int MODE>
@@ -931,21 +939,28 @@ __global__ void __launch_bounds__(256)
              const T* __restrict__ fpart, const uint32_t* __restrict__ qs_new,
              long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts, double out_sign,
              uint2* __restrict__ kr,
-             uint32_t* __restrict__ counts, uint32_t* __restrict__ flag) {
+             uint32_t* __restrict__ counts, uint32_t* __restrict__ flag, const uint32_t* __restrict__ qs_old,
+             const T* __restrict__ vin, T* __restrict__ vout) {
     const int tid = threadIdx.x;
-    const bool need_field = MODE == 0 || (parts & 1u);
-    const bool need_bond = MODE == 0 || (parts & 2u);
-    if (MODE == 0) {
+    const bool need_field = MODE != 1 || (parts & 1u);
+    const bool need_bond = MODE != 1 || (parts & 2u);
+    if constexpr (MODE != 1) {
         // one bead per thread; its loads are issued before the shift is formed
         const long long j = blockIdx.x * 256LL + tid;
         const bool active = j < n;
         uint4 q = uint4{0u, 0u, 0u, 0u};
         T f[3] = {0, 0, 0};
+        T u[3] = {0, 0, 0};
         if (active) {
             q = pin[j];
             f[0] = fbond[4 * j + 0];
             f[1] = fbond[4 * j + 1];
             f[2] = fbond[4 * j + 2];
+            if constexpr (MODE == 2) {
+                u[0] = vin[4 * j + 0];
+                u[1] = vin[4 * j + 1];
+                u[2] = vin[4 * j + 2];
+            }
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 T sa = 0;
@@ -961,11 +976,19 @@ __global__ void __launch_bounds__(256)
             const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
             T xi[3];
             Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
+            if constexpr (MODE == 2) {
+                T xi1[3];
+                Noise<T>::draw(q.w >> 1, step + 1, ph.seed, xi1);
+                xi[0] += xi1[0];
+                xi[1] += xi1[1];
+                xi[2] += xi1[2];
+            }
             long long dq[3] = {0, 0, 0};
             bool bad = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                const T disp = mob * f[a] + amp * xi[a];
+                T disp = mob * f[a] + amp * xi[a];
+                if constexpr (MODE == 2) disp += (T)ph.gjf_a * ((T)ph.gjf_vs * u[a]);
                 const double sd = (double)disp * inv_l[a];
                 if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
                 else dq[a] = llrint(sd);
@@ -976,6 +999,17 @@ __global__ void __launch_bounds__(256)
             }
             const uint4 qn = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
             pout[j] = qn;
+            if constexpr (MODE == 2) {
+                // realised displacement: dq minus the step's shift (a small integer)
+                const double L[3] = {ph.lx, ph.ly, ph.lz};
+                const double inv_vs = 1.0 / ph.gjf_vs;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const long long sh = (long long)(int32_t)(nsh[a] - qs_old[a]);
+                    vout[4 * j + a] = (T)((double)(dq[a] - sh) * (L[a] * kInvTwo32) * inv_vs);
+                }
+                vout[4 * j + 3] = (T)0;
+            }
             kb = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
         }
         const uint32_t r = bin_rank(kb, active, counts);  // whole wavefronts take part
@@ -1120,12 +1154,13 @@ __global__ void __launch_bounds__(256)
 // Move every bead of the previous order to its sorted slot, translate its
 // bond partners (slots of the previous order) into sorted slots, and store
 // its harmonic bond force F = -2 k_b sum_partners d (d the minimum-image bond
-// vector, shift-free in fixed point) as {Fx, Fy, Fz, 0}.
+// vector, shift-free in fixed point) as {Fx, Fy, Fz, 0}.  With GJF (vdst not
+// null) the half-step velocity moves with the bead.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
-              T* __restrict__ fbond, long long n, int deg, Phys ph) {
+              T* __restrict__ fbond, long long n, int deg, Phys ph, const T* __restrict__ vsrc, T* __restrict__ vdst) {
     // contiguous bead ranges per XCD: bond partners are near in the order
     const long long j = xcd_contiguous(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
     if (j >= n) return;
@@ -1133,6 +1168,10 @@ __global__ void __launch_bounds__(256)
     const long long nw = (long long)bin_start[kj.x] + kj.y;
     const uint4 q = pos_tmp[j];
     pos[nw] = q;
+    if (vdst) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) vdst[4 * nw + a] = vsrc[4 * j + a];
+    }
     const T c = (T)(-2.0 * ph.bond_k);
     const T sx = (T)(ph.lx * kInvTwo32), sy = (T)(ph.ly * kInvTwo32), sz = (T)(ph.lz * kInvTwo32);
     T f[3] = {0, 0, 0};
@@ -1251,6 +1290,25 @@ __global__ void __launch_bounds__(256)
     pos_tmp[i] = uint4{q[0], q[1], q[2], ((uint32_t)i << 1) | K};
     const uint32_t kb = bin_key(q[1], q[2], K, d, P);
     kr[i] = uint2{kb, atomicAdd(&counts[kb], 1u)};
+}
+
+// GJF half-step velocities between ABI order ([n][3], TA) and sorted order
+// ([n][4], T): OP 0 sorted <- ABI, OP 1 ABI <- sorted, OP 2 vtmp[4 id] <-
+// sorted (the order k_place gives pos_tmp).
+template <typename T, typename TA, int OP>
+__global__ void __launch_bounds__(256) k_velocities(const uint4* __restrict__ pos, T* __restrict__ vel,
+                                                    T* __restrict__ vtmp, TA* __restrict__ abi, long long n) {
+    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    if (j >= n) return;
+    const long long id = (long long)(pos[j].w >> 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (OP == 0) vel[4 * j + a] = (T)abi[3 * id + a];
+        else if constexpr (OP == 1) abi[3 * id + a] = (TA)vel[4 * j + a];
+        else vtmp[4 * id + a] = vel[4 * j + a];
+    }
+    if constexpr (OP == 0) vel[4 * j + 3] = (T)0;
+    if constexpr (OP == 2) vtmp[4 * id + 3] = (T)0;
 }
 
 template <typename TO>
@@ -1372,7 +1430,7 @@ static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, 
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
                        (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, out_sign, S.kr,
-                       S.counts, S.flag);
+                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp);
 }
 
 template <typename T, int MODE>
@@ -1393,11 +1451,14 @@ hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t ste
     if (mode == 0 && L.force_ad)
         hipLaunchKernelGGL(k_form_shift, dim3(1), dim3(256), 0, L.stream, S.noise_part, S.fsum_part, 2 * L.d.mz,
                            S.n, L.ph, S.qshift, S.qshift_next);
+    const bool gjf = mode == 0 && L.ph.gjf;
     if (L.precision == 0) {
-        if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts, out_sign);
+        if (gjf) update_t<float, 2>(L, S, step, out, out_dtype, parts, out_sign);
+        else if (mode == 0) update_t<float, 0>(L, S, step, out, out_dtype, parts, out_sign);
         else update_t<float, 1>(L, S, step, out, out_dtype, parts, out_sign);
     } else {
-        if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts, out_sign);
+        if (gjf) update_t<double, 2>(L, S, step, out, out_dtype, parts, out_sign);
+        else if (mode == 0) update_t<double, 0>(L, S, step, out, out_dtype, parts, out_sign);
         else update_t<double, 1>(L, S, step, out, out_dtype, parts, out_sign);
     }
     return hipGetLastError();
@@ -1414,10 +1475,12 @@ hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_sr
     if (S.n == 0) return hipSuccess;
     if (L.precision == 0)
         hipLaunchKernelGGL(k_scatter<float>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
-                           S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph);
+                           S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph,
+                           (const float*)S.vel_tmp, (float*)S.vel);
     else
         hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
-                           S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph);
+                           S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph,
+                           (const double*)S.vel_tmp, (double*)S.vel);
     return hipGetLastError();
 }
 
@@ -1441,6 +1504,37 @@ hipError_t launch_place(const Launch& L, DeviceState& S, const void* xyz, int dt
     else
         hipLaunchKernelGGL(k_place<double>, dim3(g), dim3(256), 0, L.stream, (const double*)xyz, S.types_abi,
                            S.pos_tmp, S.kr, S.counts, S.qshift, S.n, L.d, L.order, S.flag);
+    return hipGetLastError();
+}
+
+template <typename T>
+static void velocities_t(const Launch& L, DeviceState& S, int op, void* v, int dtype) {
+    const unsigned g = blocks_for(S.n, 256);
+    T* vel = (T*)S.vel;
+    T* vt = (T*)S.vel_tmp;
+    if (op == 2)
+        hipLaunchKernelGGL((k_velocities<T, T, 2>), dim3(g), dim3(256), 0, L.stream, S.pos, vel, vt, (T*)nullptr, S.n);
+    else if (dtype == 0) {
+        if (op == 0)
+            hipLaunchKernelGGL((k_velocities<T, float, 0>), dim3(g), dim3(256), 0, L.stream, S.pos, vel, vt, (float*)v,
+                               S.n);
+        else
+            hipLaunchKernelGGL((k_velocities<T, float, 1>), dim3(g), dim3(256), 0, L.stream, S.pos, vel, vt, (float*)v,
+                               S.n);
+    } else {
+        if (op == 0)
+            hipLaunchKernelGGL((k_velocities<T, double, 0>), dim3(g), dim3(256), 0, L.stream, S.pos, vel, vt,
+                               (double*)v, S.n);
+        else
+            hipLaunchKernelGGL((k_velocities<T, double, 1>), dim3(g), dim3(256), 0, L.stream, S.pos, vel, vt,
+                               (double*)v, S.n);
+    }
+}
+
+hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, int dtype) {
+    if (S.n == 0 || !S.vel) return hipSuccess;
+    if (L.precision == 0) velocities_t<float>(L, S, op, v, dtype);
+    else velocities_t<double>(L, S, op, v, dtype);
     return hipGetLastError();
 }
 

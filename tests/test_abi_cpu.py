@@ -5,6 +5,7 @@ before touching a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import numpy as np
 import pytest
@@ -44,9 +45,19 @@ def test_kernel_slot_names(lib):
     assert lib.tild_kernel_name(-1) is None
 
 
-def test_params_struct_layout():
-    # double box[3], int32 grid[3], int32 order, 7 doubles, uint64, int32, uint32
-    assert ctypes.sizeof(_lib.TildParams) == 24 + 12 + 4 + 56 + 8 + 4 + 4
+def test_params_struct_layout(tmp_path):
+    """The ctypes mirror of tild_params matches the header's layout, as a C compiler lays it out."""
+    fields = [f for f, _ in _lib.TildParams._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"tild.h\"\nint main(void) {\n"
+                   '  printf("%zu\\n", sizeof(tild_params));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(tild_params, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(_lib.TildParams)
+    assert got[1:] == [getattr(_lib.TildParams, f).offset for f in fields]
 
 
 def _create(lib, params, n=4, types=None, bonds=None):
@@ -74,7 +85,9 @@ def good():
     (lambda p: setattr(p, "gamma", 0.0), "gamma"),
     (lambda p: setattr(p, "kT", -1.0), "kT"),
     (lambda p: setattr(p, "precision", 3), "precision"),
-    (lambda p: setattr(p, "flags", 16), "flag"),
+    (lambda p: setattr(p, "flags", 32), "flag"),
+    (lambda p: (setattr(p, "flags", _lib.TILD_INTEGRATOR_GJF), setattr(p, "mass", -1.0)), "mass"),
+    (lambda p: (setattr(p, "flags", _lib.TILD_INTEGRATOR_GJF), setattr(p, "mass", float("nan"))), "mass"),
     (lambda p: setattr(p, "smear_a", float("inf")), "smear_a"),
     (lambda p: (setattr(p, "smear_a", 0.0), setattr(p, "flags", _lib.TILD_POTENTIAL_SAMPLED)), "smear_a"),
     (lambda p: (setattr(p, "order", 1), setattr(p, "flags", _lib.TILD_FORCE_AD)), "order"),

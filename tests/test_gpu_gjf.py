@@ -1,0 +1,155 @@
+"""GPU checks of the GJF integrator (TILD_INTEGRATOR_GJF): trajectories and
+half-step velocities against the oracle's velocity form of the scheme, the
+velocity calls, and two properties that hold at any size (kT/m velocity
+variance of free particles and exact harmonic bond statistics at large dt)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2302_02474_amd as T
+from oracle import tild_ref as R
+from synth import make_melt, snap_to_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel_rms(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gjf_params(m, precision, force="ik", dt=0.05, gamma=1.0, mass=1.3, com=True):
+    return T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, dt, gamma, m.kT, m.seed,
+                         precision, com, "analytic", force, "gjf", mass)
+
+
+@pytest.mark.parametrize("precision,xtol,utol", [(T.TILD_FP64, 1e-7, 1e-6), (T.TILD_FP32, 1e-5, 1e-5)])
+@pytest.mark.parametrize("force", ["ik", "ad"])
+def test_gjf_trajectory_matches_oracle(precision, xtol, utol, force):
+    """The GPU carries the half-step velocity and applies the two-step form of
+    GJF; the oracle runs the published velocity form.  Both start from the
+    oracle's state after one step (the two forms agree from there on)."""
+    m = make_melt(0)
+    x0 = snap_to_lattice(m.x, m.box)
+    po = R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
+                  chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=0.05, gamma=1.0, kT=m.kT, seed=m.seed,
+                  com_correct=True, mass=1.3)
+    v0 = np.random.default_rng(11).normal(0, np.sqrt(po.kT / po.mass), size=x0.shape)
+    x1, v1, dx1 = R.gjf_trajectory(x0, v0, m.types, m.bonds, po, 1, force=force)
+    K = 12
+    xk, _, dxk = R.gjf_trajectory(x1, v1, m.types, m.bonds, po, K, t0=1, force=force)
+    say(f"[gjf] force={force} precision={precision} n={m.n} K={K}")
+    t = T.Tild(gjf_params(m, precision, force), m.types, m.bonds)
+    t.set_positions(x1)
+    t.set_velocities(R.half_step_velocity(dx1, po))
+    t.step_count = 1
+    t.step(K)
+    xg = t.get_positions()
+    ug = t.get_velocities()
+    t.close()
+    d = R.min_image(xg - xk, m.box)
+    err_x = np.sqrt((d ** 2).mean()) / np.sqrt((R.min_image(xk - x1, m.box) ** 2).mean())
+    err_u = rel_rms(ug, R.half_step_velocity(dxk, po))
+    say(f"[gjf] displacement rel-RMS {err_x:.3e}, half-step velocity rel-RMS {err_u:.3e}")
+    assert err_x < xtol
+    assert err_u < utol
+    assert np.all(np.abs(ug.mean(axis=0)) < 1e-5 * np.sqrt(po.kT / po.mass))
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+def test_gjf_velocities_follow_beads(precision):
+    """Velocities round-trip, move with the beads through the per-step sort,
+    and survive a re-placement of the positions."""
+    m = make_melt(0)
+    t = T.Tild(gjf_params(m, precision), m.types, m.bonds)
+    t.set_positions(m.x)
+    assert np.all(t.get_velocities() == 0.0)
+    u = np.random.default_rng(3).normal(size=(m.n, 3))
+    t.set_velocities(u)
+    ref = u if precision == T.TILD_FP64 else u.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(t.get_velocities(), ref)
+    t.step(3)
+    u3, x3 = t.get_velocities(), t.get_positions()
+    t.set_positions(x3 + np.array([0.37, -1.2, 2.9]))  # another bead order
+    np.testing.assert_array_equal(t.get_velocities(), u3)
+    t.close()
+
+
+def test_velocity_calls_check_their_state():
+    m = make_melt(0)
+    t = T.Tild(gjf_params(m, T.TILD_FP32), m.types, m.bonds)
+    with pytest.raises(T.TildError) as e:
+        t.get_velocities()
+    assert e.value.code == T.TILD_ESTATE
+    t.set_positions(m.x)
+    bad = np.zeros((m.n, 3))
+    bad[5, 1] = np.nan
+    with pytest.raises(T.TildError) as e:
+        t.set_velocities(bad)
+    assert e.value.code == T.TILD_EINVAL
+    t.close()
+    em = T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa), m.types, m.bonds)
+    em.set_positions(m.x)
+    with pytest.raises(T.TildError) as e:
+        em.get_velocities()
+    assert e.value.code == T.TILD_EINVAL
+    em.close()
+
+
+def test_gjf_free_particles_have_kt_over_m_velocity_variance():
+    """No forces, gamma dt / m = 0.53: the half-step velocity keeps variance
+    kT/m exactly at this dt (300,000 beads, 10 steps)."""
+    n, L, kT, mass = 300_000, 60.0, 1.2, 1.5
+    p = T.make_params((L, L, L), (32, 32, 32), 4, 0.5, 0.0, 0.0, 1.5, 0.8, 1.0, kT, 77, T.TILD_FP32, False,
+                      "analytic", "ik", "gjf", mass)
+    g = np.random.default_rng(8)
+    t = T.Tild(p, np.zeros(n, np.int32))
+    t.set_positions(g.uniform(0, L, size=(n, 3)))
+    t.set_velocities(g.normal(0, np.sqrt(kT / mass), size=(n, 3)))
+    t.step(10)
+    u = t.get_velocities()
+    t.close()
+    ratio = u.var() / (kT / mass)
+    say(f"[gjf] free-particle <u^2> / (kT/m) = {ratio:.4f}")
+    assert abs(ratio - 1) < 0.01
+
+
+def test_gjf_dimer_bond_statistics_exact_at_large_dt():
+    """Dimers with U = k_b |d|^2 at Omega dt = 0.73: <|d|^2> = 3 kT / (2 k_b)."""
+    nd, L, kb = 20_000, 200.0, 1.5
+    p = T.make_params((L, L, L), (32, 32, 32), 2, 0.5, 0.0, 0.0, kb, 0.3, 1.0, 1.0, 5, T.TILD_FP32, False,
+                      "analytic", "ik", "gjf", 1.0)
+    g = np.random.default_rng(9)
+    a = g.uniform(0, L, size=(nd, 3))
+    x = np.empty((2 * nd, 3))
+    x[0::2], x[1::2] = a, a + g.normal(0, np.sqrt(1 / 3), size=(nd, 3))
+    bonds = np.stack([np.arange(0, 2 * nd, 2), np.arange(1, 2 * nd, 2)], 1).astype(np.int32)
+    t = T.Tild(p, np.zeros(2 * nd, np.int32), bonds)
+    t.set_positions(x)
+    t.set_velocities(g.normal(size=x.shape))
+    t.step(40)
+    acc = []
+    for _ in range(24):
+        t.step(5)
+        y = t.get_positions()
+        d = R.min_image(y[1::2] - y[0::2], p.box[:])
+        acc.append(np.mean(np.sum(d * d, axis=1)))
+    t.close()
+    ratio = np.mean(acc) / (3 * 1.0 / (2 * kb))
+    say(f"[gjf] dimer <|d|^2> / (3kT/2k_b) = {ratio:.4f}")
+    assert abs(ratio - 1) < 0.015
