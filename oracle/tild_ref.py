@@ -31,6 +31,16 @@ Conventions (the paper leaves them open; these are the readings used):
     separation; k_b = 3/(2 b^2) (Eq. bonds).
   * Overdamped Euler-Maruyama: x <- wrap(x + (dt/gamma) F + sqrt(2 kT dt/gamma) xi - Delta),
     Delta the mean displacement when centre-of-mass correction is on.
+  * Electrostatics (long-range forces between charged monomers, Sec.
+    "Long-range interactions"; Bjerrum length and one charge spreading length
+    for the whole system, Sec. "Input Script"): every bead of species K carries the
+    charge q_K, and charges are smeared like the mass density, with a
+    Gaussian h_e of width a_e (h_e^ = exp(-a_e^2 k^2 / 2)).  The energy is
+    E_e = (l_B / 2) int int rho_e~(r) rho_e~(r') / |r - r'|, i.e.
+    E_e = (1/2) sum_{n != 0} W_e(n) |q_A c^_A + q_B c^_B|^2 with
+    W_e = (4 pi l_B / V) exp(-a_e^2 k^2) / k^2; k = 0 is left out (a
+    neutralising background), and W_e adds q_K q_L W_e to the pair kernel of
+    species K and L.
   * The GJF integrator the paper lists (Sec. "Integrator Class") is the
     Gronbech-Jensen--Farago Langevin scheme (Mol. Phys. 111, 983 (2013)) in
     its published velocity form; its noise beta_n = sqrt(2 gamma kT dt) xi is
@@ -52,7 +62,7 @@ __all__ = [
     "gradient_fields", "potential_fields", "gather", "gather_gradient_weights",
     "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
     "trajectory", "structure_factor_exact", "min_image", "gjf_coefficients", "gjf_trajectory",
-    "half_step_velocity",
+    "half_step_velocity", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
 ]
 
 
@@ -71,6 +81,9 @@ class Params:
     seed: int = 0
     com_correct: bool = True
     mass: float = 1.0  # bead mass (GJF only)
+    charges: Sequence[float] = (0.0, 0.0)  # charge of an A and of a B bead (elementary charges)
+    bjerrum: float = 0.0  # Bjerrum length l_B
+    charge_smear: float = 0.0  # charge spreading length a_e
     potential: str = "analytic"  # or "sampled"
     transform: str = "dense"  # "dense" separable DFT matrices, or "numpy" FFT
 
@@ -256,13 +269,35 @@ def _uhat(p: Params) -> np.ndarray:
     return uhat_analytic(p.smear_a, p.L, p.M)
 
 
-def field_spectra(chat: np.ndarray, uhat: np.ndarray, chi: float, kappa: float, n_beads: int) -> np.ndarray:
-    """Phi^_K(n) = (u^/N) sum_L eps_KL c^_L(n); n = 0: (chi/N) c^_{other}(0)."""
+def coulomb_kernel(L, M, bjerrum: float, ae: float) -> np.ndarray:
+    """W_e(n) = (4 pi l_B / V) exp(-a_e^2 |k|^2) / |k|^2 for n != 0, and 0 at n = 0."""
+    ks, _ = kgrid(L, M)
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    V = float(np.prod(np.asarray(L, dtype=np.float64)))
+    W = np.zeros_like(k2)
+    nz = k2 > 0
+    W[nz] = 4.0 * np.pi * bjerrum / V * np.exp(-ae * ae * k2[nz]) / k2[nz]
+    return W
+
+
+def charge_spectrum(chat: np.ndarray, charges) -> np.ndarray:
+    """rho^_e(n) = q_A c^_A(n) + q_B c^_B(n)."""
+    return charges[0] * chat[0] + charges[1] * chat[1]
+
+
+def field_spectra(chat: np.ndarray, uhat: np.ndarray, chi: float, kappa: float, n_beads: int,
+                  welec: Optional[np.ndarray] = None, charges=(0.0, 0.0)) -> np.ndarray:
+    """Phi^_K(n) = (u^/N) sum_L eps_KL c^_L(n); n = 0: (chi/N) c^_{other}(0).  With a Coulomb kernel
+    welec, plus q_K W_e(n) rho^_e(n)."""
     eps = np.array([[kappa, chi + kappa], [chi + kappa, kappa]])
     Phi = np.empty_like(chat, dtype=np.complex128)
     for K in (0, 1):
         Phi[K] = uhat / n_beads * (eps[K, 0] * chat[0] + eps[K, 1] * chat[1])
         Phi[K][0, 0, 0] = chi / n_beads * chat[1 - K][0, 0, 0]
+    if welec is not None:
+        rho = charge_spectrum(chat, charges)
+        for K in (0, 1):
+            Phi[K] = Phi[K] + charges[K] * welec * rho
     return Phi
 
 
@@ -352,6 +387,23 @@ def nonbonded_virial(chat: np.ndarray, a: float, L, M, chi: float, kappa: float,
     return np.array([-2.0 * a * a * float(np.sum(ks[ax] ** 2 * core)) for ax in range(3)])
 
 
+def electrostatic_energy(chat: np.ndarray, welec: np.ndarray, charges) -> float:
+    """E_e = (1/2) sum_n W_e(n) |rho^_e(n)|^2 (W_e(0) = 0)."""
+    return 0.5 * float(np.sum(welec * np.abs(charge_spectrum(chat, charges)) ** 2))
+
+
+def electrostatic_virial(chat: np.ndarray, L, M, charges, bjerrum: float, ae: float) -> np.ndarray:
+    """W_aa = -L_a dE_e/dL_a at fixed scaled coordinates: with V = L_x L_y L_z and k_a = 2 pi n'_a / L_a,
+    each mode contributes (1/2) W_e |rho^_e|^2 [1 - 2 k_a^2 (1/k^2 + a_e^2)]."""
+    ks, _ = kgrid(L, M)
+    k2 = ks[0] ** 2 + ks[1] ** 2 + ks[2] ** 2
+    W = coulomb_kernel(L, M, bjerrum, ae)
+    e = 0.5 * W * np.abs(charge_spectrum(chat, charges)) ** 2
+    inv = np.zeros_like(k2)
+    inv[k2 > 0] = 1.0 / k2[k2 > 0]
+    return np.array([float(np.sum(e * (1.0 - 2.0 * ks[ax] ** 2 * (inv + ae * ae)))) for ax in range(3)])
+
+
 def energy_parameter_gradients(chat: np.ndarray, a: float, L, M, chi: float, kappa: float,
                                n_beads: int) -> np.ndarray:
     """(dE/dchi, dE/dkappa, dE/da) of the non-bonded energy (analytic kernel) at
@@ -409,14 +461,20 @@ def evaluate(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params,
     c = spread(x, types, L, M, p.order)
     chat = dft3(c, p.transform)
     uhat = _uhat(p)
-    Phi = field_spectra(chat, uhat, p.chi, p.kappa, n)
+    charged = p.bjerrum != 0.0 and any(q != 0.0 for q in p.charges)
+    welec = coulomb_kernel(L, M, p.bjerrum, p.charge_smear) if charged else None
+    Phi = field_spectra(chat, uhat, p.chi, p.kappa, n, welec, p.charges)
     grad = gradient_fields(Phi, L, M, p.transform)
     F_nb = gather(x, types, grad, L, M, p.order)
     e_chi, e_kappa = nonbonded_energy(chat, uhat, p.chi, p.kappa, n)
     e_b, F_b, W_b = bond_terms(x, bonds, L, p.bond_k)
     W_nb = nonbonded_virial(chat, p.smear_a, L, M, p.chi, p.kappa, n)
-    out = dict(F_nb=F_nb, F_bond=F_b, F=F_nb + F_b, E_bond=e_b, E_chi=e_chi, E_kappa=e_kappa,
-               E=e_b + e_chi + e_kappa, W_nb=W_nb, W_bond=W_b, W=W_nb + W_b,
+    e_el = 0.0
+    if charged:
+        e_el = electrostatic_energy(chat, welec, p.charges)
+        W_nb = W_nb + electrostatic_virial(chat, L, M, p.charges, p.bjerrum, p.charge_smear)
+    out = dict(F_nb=F_nb, F_bond=F_b, F=F_nb + F_b, E_bond=e_b, E_chi=e_chi, E_kappa=e_kappa, E_elec=e_el,
+               E=e_b + e_chi + e_kappa + e_el, W_nb=W_nb, W_bond=W_b, W=W_nb + W_b,
                counts=c, chat=chat, grad=grad)
     if want_ad:
         phi = potential_fields(Phi, p.transform)

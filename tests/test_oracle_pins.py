@@ -190,12 +190,18 @@ def test_energy_matches_real_space_double_sum_with_sampled_kernel():
     assert abs(ev["E_kappa"] - e_kap) < 1e-10 * max(1, abs(e_kap))
 
 
-def test_parseval_energy_equals_half_sum_c_phi():
-    p = small_params()
+CHARGED = dict(charges=(1.0, -0.7), bjerrum=2.0, charge_smear=0.4)
+
+
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+def test_parseval_energy_equals_half_sum_c_phi(extra):
+    p = small_params(**extra)
     x, t, b = random_system(40, p, seed=5)
     ev = R.evaluate(x, t, b, p, want_ad=True)
     half = 0.5 * float(np.sum(ev["counts"] * ev["phi"]))
-    assert abs(half - (ev["E_chi"] + ev["E_kappa"])) < 1e-10 * abs(half)
+    assert abs(half - (ev["E_chi"] + ev["E_kappa"] + ev["E_elec"])) < 1e-10 * abs(half)
+    if extra:
+        assert abs(ev["E_elec"]) > 1e-3 * abs(half)
 
 
 def _two_bead_energy(h, L=8.0, a=0.5, r=np.array([1.3, 0.7, -0.4])):
@@ -243,11 +249,86 @@ def test_two_beads_on_nodes_closed_form():
     assert abs(ev["E_chi"] - p.chi / 2 * total) < 1e-12 * abs(total)
 
 
+# ---------------------------------------------------------- electrostatics
+
+def _coulomb_continuum(x, q, L, lb, ae, nmax):
+    """(l_B / 2V) sum_{k != 0} (4 pi / k^2) exp(-a_e^2 k^2) |sum_i q_i exp(-i k.r_i)|^2 over |n_a| <= nmax,
+    with the exact particle phases (no grid)."""
+    n = np.arange(-nmax, nmax + 1)
+    nv = np.array(np.meshgrid(n, n, n, indexing="ij")).reshape(3, -1).T
+    nv = nv[np.any(nv != 0, axis=1)]
+    k = 2 * np.pi * nv / np.asarray(L)[None, :]
+    k2 = np.sum(k * k, axis=1)
+    rho = np.exp(-1j * (k @ x.T)) @ q
+    return lb / (2 * np.prod(L)) * float(np.sum(4 * np.pi / k2 * np.exp(-ae * ae * k2) * np.abs(rho) ** 2))
+
+
+def test_coulomb_continuum_sum_is_smeared_coulomb_law():
+    """The reference sum itself: for a +q/-q pair far from its images it is l_B q1 q2 erf(r/2a_e)/r plus the
+    two self-energies l_B q^2 / (2 a_e sqrt(pi)) of Gaussian charges, less the tin-foil dipole term
+    2 pi l_B |M|^2 / (3V) of a cubic lattice."""
+    from math import erf, pi, sqrt
+    L, lb, ae = 30.0, 1.7, 0.5
+    x = np.array([[10.0, 11.0, 12.0], [11.1, 11.6, 12.8]])
+    q = np.array([1.0, -1.0])
+    r = np.linalg.norm(x[1] - x[0])
+    dip = q @ x
+    exact = lb * (q[0] * q[1] * erf(r / (2 * ae)) / r + (q @ q) / (2 * ae * sqrt(pi))) \
+        - 2 * pi * lb * (dip @ dip) / (3 * L ** 3)
+    got = _coulomb_continuum(x, q, (L,) * 3, lb, ae, 40)
+    assert abs(got - exact) < 2e-5 * abs(exact)
+
+
+def test_coulomb_beads_on_nodes_closed_form():
+    """Charged beads on nodes: rho_e^ = sum_i q_i S(n) exp(-i k.r_i) with S the separable transform of the
+    B_4 node values, so E_e is a closed sum over modes."""
+    L = np.array([5.0, 6.0, 4.0])
+    M = np.array([10, 12, 8])
+    h = L / M
+    p = R.Params(box=tuple(L), grid=tuple(M), order=4, smear_a=0.4, chi=0.0, kappa=0.0,
+                 charges=(1.3, -0.6), bjerrum=1.9, charge_smear=0.35)
+    g = np.array([[1, 2, 3], [4, 9, 7], [6, 0, 2]])
+    types = np.array([0, 1, 1])
+    x = g * h
+    ev = R.evaluate(x, types, np.zeros((0, 2), np.int32), p)
+    q = np.array(p.charges)[types]
+    node = {-1: 1 / 6, 0: 2 / 3, 1: 1 / 6}
+    ks = [R.wavenumbers(L[a], M[a])[0] for a in range(3)]
+    total = 0.0
+    for n in np.ndindex(*M):
+        if n == (0, 0, 0):
+            continue
+        k = np.array([ks[a][n[a]] for a in range(3)])
+        S = 1.0
+        for a in range(3):
+            S *= sum(node[j] * np.cos(k[a] * h[a] * j) for j in (-1, 0, 1))
+        rho = S * np.sum(q * np.exp(-1j * (x @ k)))
+        total += 4 * np.pi * p.bjerrum / np.prod(L) * np.exp(-p.charge_smear ** 2 * (k @ k)) / (k @ k) * abs(rho) ** 2
+    assert abs(ev["E_elec"] - total / 2) < 1e-12 * abs(total)
+
+
+def test_coulomb_grid_energy_converges_to_continuum():
+    """An off-node +1/-1 pair: the mesh energy approaches the particle sum as h -> 0 (second order)."""
+    L, lb, ae = 8.0, 1.0, 0.5
+    x = np.array([[3.1, 2.9, 4.05], [4.4, 3.6, 3.65]])
+    exact = _coulomb_continuum(x, np.array([1.0, -1.0]), (L,) * 3, lb, ae, 24)
+    errs = []
+    for h in (0.25, 0.125, 0.0625):
+        M = int(round(L / h))
+        p = R.Params(box=(L,) * 3, grid=(M,) * 3, order=4, smear_a=0.5, chi=0.0, kappa=0.0,
+                     charges=(1.0, -1.0), bjerrum=lb, charge_smear=ae, transform="numpy")
+        ev = R.evaluate(x, np.array([0, 1]), np.zeros((0, 2), np.int32), p)
+        errs.append(abs(ev["E_elec"] - exact) / abs(exact))
+    assert errs[-1] < 0.01
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
 # ------------------------------------------------------------------ forces
 
-def test_nonbonded_momentum_conservation():
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+def test_nonbonded_momentum_conservation(extra):
     for grid in [(8, 10, 6), (7, 9, 5)]:
-        p = small_params(grid=grid)
+        p = small_params(grid=grid, **extra)
         x, t, b = random_system(60, p, seed=7)
         ev = R.evaluate(x, t, b, p)
         scale = np.abs(ev["F_nb"]).max()
@@ -255,8 +336,9 @@ def test_nonbonded_momentum_conservation():
         assert np.all(np.abs(ev["F_bond"].sum(axis=0)) < 1e-11)
 
 
-def test_energy_gradient_force_is_exact_finite_difference():
-    p = small_params()
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+def test_energy_gradient_force_is_exact_finite_difference(extra):
+    p = small_params(**extra)
     x, t, b = random_system(20, p, seed=11)
     ev = R.evaluate(x, t, b, p, want_ad=True)
     e = 1e-6
@@ -267,7 +349,7 @@ def test_energy_gradient_force_is_exact_finite_difference():
             xm[i, a] -= e
             ep = R.evaluate(xp, t, b, p)
             em = R.evaluate(xm, t, b, p)
-            fd = -((ep["E_chi"] + ep["E_kappa"]) - (em["E_chi"] + em["E_kappa"])) / (2 * e)
+            fd = -((ep["E_chi"] + ep["E_kappa"] + ep["E_elec"]) - (em["E_chi"] + em["E_kappa"] + em["E_elec"])) / (2 * e)
             assert abs(fd - ev["F_nb_ad"][i, a]) < 1e-6 * max(1.0, abs(fd))
             fdb = -(ep["E_bond"] - em["E_bond"]) / (2 * e)
             assert abs(fdb - ev["F_bond"][i, a]) < 1e-6 * max(1.0, abs(fdb))
@@ -297,8 +379,9 @@ def test_bond_closed_form_across_boundary():
     np.testing.assert_allclose(W, -3.0 * d * d, atol=1e-12)
 
 
-def test_virial_by_affine_box_scaling():
-    p = small_params()
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+def test_virial_by_affine_box_scaling(extra):
+    p = small_params(**extra)
     x, t, b = random_system(30, p, seed=4)
     ev = R.evaluate(x, t, b, p)
     s = x / p.L
@@ -310,7 +393,7 @@ def test_virial_by_affine_box_scaling():
             L2[a] *= 1 + sgn * e
             q = R.Params(**{**p.__dict__, "box": tuple(L2)})
             v = R.evaluate(s * L2, t, b, q)
-            Es.append((v["E_chi"] + v["E_kappa"], v["E_bond"]))
+            Es.append((v["E_chi"] + v["E_kappa"] + v["E_elec"], v["E_bond"]))
         w_nb = -(Es[0][0] - Es[1][0]) / (2 * e)
         w_b = -(Es[0][1] - Es[1][1]) / (2 * e)
         assert abs(w_nb - ev["W_nb"][a]) < 1e-5 * max(1, abs(w_nb))
