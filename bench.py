@@ -178,10 +178,12 @@ def main() -> int:
                 "kernels_ms": {k: round(v, 5) for k, v in kv.items()}}
 
     # The same workload on the exact-gradient route (TILD_FORCE_AD: two inverse
-    # transforms instead of six) and with the GJF integrator, reported beside
-    # the headline (ik route, Euler-Maruyama).
+    # transforms instead of six), with the GJF integrator, and with A = +1 and
+    # B = -1 charges (l_B = 1, a_e = 0.5), reported beside the headline (ik
+    # route, Euler-Maruyama, neutral).
     variants = {"exact_gradient_force": time_variant(force="ad"),
-                "gjf_integrator": time_variant(integrator="gjf")}
+                "gjf_integrator": time_variant(integrator="gjf"),
+                "charged_species": time_variant(charges=(1.0, -1.0), bjerrum=1.0, charge_smear=0.5)}
     for k, v in variants.items():
         print(f"[bench] variant {k}: {v['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
 

@@ -14,6 +14,13 @@
  *     Eq. HelfandP, with rho_0 = N/V and u_G a unit Gaussian of variance
  *     sigma^2 = 2 a^2, i.e. u_G = h * h for the smearing h of width a
  *     (Eqs. smearRho, fhF, HelfandF); its transform is exp(-a^2 k^2).
+ * Electrostatics (Sec. "Long-range interactions": the same mesh carries the
+ * forces between charged monomers; Sec. "Input Script": one Bjerrum length
+ * and one charge spreading length): with per-species charges q_K the pair
+ * kernel of species K and L gains q_K q_L (4 pi l_B / V) exp(-a_e^2 k^2) / k^2
+ * (k = 0 left out: a neutralising background), i.e. the energy
+ * E_e = (l_B / 2) int int rho_e~ rho_e~ / |r - r'| of the smeared charge
+ * density, so it rides through the same spread, transforms and gather.
  * Method (Sec. "Long-range interactions", Eq. PMM, Fig. pmm): beads are
  * assigned to a periodic grid with order-P B-spline weights, the species
  * densities are Fourier transformed, multiplied by the kernel and by i k,
@@ -143,6 +150,11 @@ typedef struct tild_params {
     uint32_t flags;    /* TILD_COM_CORRECT, TILD_POTENTIAL_SAMPLED, TILD_FORCE_AD, TILD_INTEGRATOR_GJF,
                           TILD_DETERMINISTIC, or 0 */
     double mass;       /* bead mass for TILD_INTEGRATOR_GJF (> 0; 0 is read as 1); unused by Euler-Maruyama */
+    double charge[2];  /* charge of an A and of a B bead (elementary charges); electrostatics is on when
+                          bjerrum != 0 and a charge is non-zero */
+    double bjerrum;    /* Bjerrum length l_B >= 0 (Coulomb energy l_B / r kT between unit point charges) */
+    double charge_smear; /* charge spreading length a_e >= 0: charges are Gaussian clouds of width a_e, as
+                            the mass density is smeared with width a (Eq. smearRho) */
 } tild_params;
 
 /*
@@ -226,7 +238,8 @@ int tild_forces(tild_ctx* ctx, void* out, int32_t dtype, int32_t on_device, uint
  * Energies (kT) and virial at the current positions, accumulated in float64:
  *   out[0] E_bond, out[1] E_chi, out[2] E_kappa, out[3] E_total,
  *   out[4..6] W_xx, W_yy, W_zz with W_aa = -L_a dE/dL_a at fixed scaled
- *   coordinates (bonded + non-bonded), out[7] = 0.
+ *   coordinates (bonded + non-bonded), out[7] E_elec (0 without charges;
+ *   included in E_total).
  * E_chi includes the constant k = 0 term chi N_A N_B / N; both non-bonded
  * terms include the grid-dependent bead self-interaction.  Synchronises.
  */

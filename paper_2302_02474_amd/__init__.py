@@ -33,10 +33,11 @@ def lib():
 
 def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0,
                 seed=0, precision=TILD_FP32, com_correct=True, potential="analytic", force="ik",
-                integrator="em", mass=1.0) -> TildParams:
+                integrator="em", mass=1.0, charges=(0.0, 0.0), bjerrum=0.0, charge_smear=0.0) -> TildParams:
     """tild_params; potential is "analytic" (exp(-a^2 k^2)) or "sampled" (DFT of the node-sampled Gaussian);
     force is "ik" (the paper's route) or "ad" (exact gradient of the mesh energy); integrator is "em"
-    (overdamped Euler-Maruyama) or "gjf" (Gronbech-Jensen--Farago Langevin, bead mass ``mass``)."""
+    (overdamped Euler-Maruyama) or "gjf" (Gronbech-Jensen--Farago Langevin, bead mass ``mass``); charges
+    (q_A, q_B), bjerrum and charge_smear switch on smeared electrostatics."""
     if force not in ("ik", "ad"):
         raise ValueError(f"force must be 'ik' or 'ad', got {force!r}")
     if integrator not in ("em", "gjf"):
@@ -60,6 +61,9 @@ def make_params(box, grid, order, smear_a, chi, kappa, bond_k=1.5, dt=0.005, gam
     p.flags = ((TILD_COM_CORRECT if com_correct else 0) | (TILD_POTENTIAL_SAMPLED if potential == "sampled" else 0)
                | (TILD_FORCE_AD if force == "ad" else 0) | (TILD_INTEGRATOR_GJF if integrator == "gjf" else 0))
     p.mass = float(mass)
+    p.charge[0], p.charge[1] = float(charges[0]), float(charges[1])
+    p.bjerrum = float(bjerrum)
+    p.charge_smear = float(charge_smear)
     return p
 
 
@@ -196,7 +200,7 @@ class Tild:
         buf = (ctypes.c_double * 8)()
         self._check(self._lib.tild_energy(self._ctx, buf))
         v = list(buf)
-        return dict(E_bond=v[0], E_chi=v[1], E_kappa=v[2], E=v[3], W=np.array(v[4:7]))
+        return dict(E_bond=v[0], E_chi=v[1], E_kappa=v[2], E_elec=v[7], E=v[3], W=np.array(v[4:7]))
 
     def energy_grad(self, grad_x=True, dtype=np.float64):
         """(E, dE/dchi, dE/dkappa, dE/da) and, with grad_x (True for a new host
@@ -258,10 +262,11 @@ def stream_copy_ms(dst, src, nbytes: int, iters: int = 20, stream=None) -> float
 
 
 def from_melt(melt, precision=TILD_FP32, com_correct=True, stream=None, potential="analytic", force="ik",
-              integrator="em", mass=1.0) -> Tild:
+              integrator="em", mass=1.0, charges=(0.0, 0.0), bjerrum=0.0, charge_smear=0.0) -> Tild:
     """Context for a synth.Melt workload (positions are set too)."""
     p = make_params(melt.box, melt.grid, melt.order, melt.smear_a, melt.chi, melt.kappa, melt.bond_k, melt.dt,
-                    melt.gamma, melt.kT, melt.seed, precision, com_correct, potential, force, integrator, mass)
+                    melt.gamma, melt.kT, melt.seed, precision, com_correct, potential, force, integrator, mass,
+                    charges, bjerrum, charge_smear)
     t = Tild(p, melt.types, melt.bonds, stream=stream)
     t.set_positions(np.ascontiguousarray(melt.x, dtype=np.float64))
     return t

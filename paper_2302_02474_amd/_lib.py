@@ -50,6 +50,9 @@ class TildParams(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("mass", ctypes.c_double),
+        ("charge", ctypes.c_double * 2),
+        ("bjerrum", ctypes.c_double),
+        ("charge_smear", ctypes.c_double),
     ]
 
 

@@ -144,6 +144,9 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
     if ((p->flags & TILD_FORCE_AD) && p->order < 2) return why = "TILD_FORCE_AD needs order >= 2", TILD_EINVAL;
     if ((p->flags & TILD_INTEGRATOR_GJF) && !(p->mass >= 0.0 && std::isfinite(p->mass)))
         return why = "mass must be finite and > 0 (0 reads as 1)", TILD_EINVAL;
+    if (!std::isfinite(p->charge[0]) || !std::isfinite(p->charge[1]) || !(p->bjerrum >= 0.0) ||
+        !std::isfinite(p->bjerrum) || !(p->charge_smear >= 0.0) || !std::isfinite(p->charge_smear))
+        return why = "charge must be finite, bjerrum and charge_smear finite and >= 0", TILD_EINVAL;
     if ((p->flags & TILD_POTENTIAL_SAMPLED) && !(p->smear_a > 0.0))
         return why = "TILD_POTENTIAL_SAMPLED needs smear_a > 0", TILD_EINVAL;
     return TILD_OK;
@@ -456,6 +459,11 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     ph.noise_amp = std::sqrt(2.0 * params->kT * params->dt / params->gamma);
     ph.seed = params->seed;
     ph.com_correct = (params->flags & TILD_COM_CORRECT) ? 1 : 0;
+    ph.elec = (params->bjerrum != 0.0 && (params->charge[0] != 0.0 || params->charge[1] != 0.0)) ? 1 : 0;
+    ph.qa = params->charge[0];
+    ph.qb = params->charge[1];
+    ph.lb4v = 4.0 * M_PI * params->bjerrum / (d.lx * d.ly * d.lz);
+    ph.ae2 = params->charge_smear * params->charge_smear;
     ph.gjf = (params->flags & TILD_INTEGRATOR_GJF) ? 1 : 0;
     if (ph.gjf) {
         // GJF: c = gamma dt / 2m, a = (1 - c)/(1 + c), b = 1/(1 + c)
@@ -513,7 +521,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     const bool sampled = (params->flags & TILD_POTENTIAL_SAMPLED) != 0;
     A((void**)&S.utab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
     if (sampled) A((void**)&S.vtab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
-    A((void**)&S.epart, (size_t)L.n_zblocks * 5 * sizeof(double));
+    A((void**)&S.epart, (size_t)L.n_zblocks * kEpart * sizeof(double));
     A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(long long));
     A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.fsum_part, (size_t)2 * d.mz * 3 * sizeof(long long));

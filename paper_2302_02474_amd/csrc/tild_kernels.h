@@ -11,6 +11,7 @@
 namespace tild {
 
 constexpr int kZBlock = 512;         // threads per workgroup of the z pass
+constexpr int kEpart = 9;            // energy partials per z-pass workgroup
 constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
 
 // Physical constants of one context, passed by value to kernels.
@@ -26,6 +27,10 @@ struct Phys {
     int gjf;            // GJF integrator: D_{n+1} = a D_n + mob_dt F + noise_amp (xi_n + xi_{n+1})
     double gjf_a;       // a = (1 - c)/(1 + c), c = gamma dt / 2m
     double gjf_vs;      // sqrt(b) dt: D = gjf_vs u for the half-step velocity u
+    int elec;           // per-species charges with a Coulomb kernel
+    double qa, qb;      // charges of A and B beads
+    double lb4v;        // 4 pi l_B / V
+    double ae2;         // a_e^2, charge smearing
     double mean_a, mean_b;  // N_A / M, N_B / M: subtracted from the counts
     double wmax;            // largest single-bead weight of one grid point, (max B_P)^3
     double u0;              // kernel at k = 0 (1 for the analytic kernel)

@@ -717,7 +717,11 @@ struct ZPlane {
 // zero exactly (pairwise bonds; the ik route with the Nyquist derivative
 // zeroed), so the mean displacement is sqrt(2 kT dt/gamma) times the mean
 // Gaussian increment, which the spread pass summed per plane.
-template <typename T, int BLOCK, int ENERGY_ONLY>
+// ELEC: the Coulomb kernel of Gaussian-smeared per-species charges joins the
+// pair kernel: Phi^_K += q_K W_e rho^_e with W_e = (4 pi l_B / V)
+// exp(-a_e^2 k^2) / k^2 and rho^_e = q_A c^_A + q_B c^_B (k = 0 left out),
+// and the energy partials gain sum W_e |rho^_e|^2 and its virial terms.
+template <typename T, int BLOCK, int ENERGY_ONLY, bool ELEC>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
                                                   double* __restrict__ epart, int want_energy,
@@ -727,7 +731,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
                                                   int nout) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[5 * (BLOCK / 64)];
+    __shared__ double red[(ELEC ? 9 : 5) * (BLOCK / 64)];
     if (noise_part && blockIdx.x == gridDim.x - 1) {
         __shared__ long long nred[3 * (BLOCK / 64)];
         long long v[3] = {0, 0, 0};
@@ -802,7 +806,10 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
     __syncthreads();
 
-    double acc[5] = {0, 0, 0, 0, 0};
+    constexpr int NACC = ELEC ? 9 : 5;
+    double acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = 0.0;
     const T inv_n = (T)ph.inv_n, kap = (T)ph.kappa, cpk = (T)(ph.chi + ph.kappa);
     {
         Walk2 w(tid, cb, BLOCK);
@@ -816,6 +823,27 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
                 const T f = (T)col.uxy * (T)pl.uz * inv_n;
                 PA = C{f * (kap * A.x + cpk * B.x), f * (kap * A.y + cpk * B.y)};
                 PB = C{f * (cpk * A.x + kap * B.x), f * (cpk * A.y + kap * B.y)};
+                if constexpr (ELEC) {
+                    // k^2 > 0: the k = 0 mode is excluded above
+                    const double k2 = col.kx * col.kx + col.ky * col.ky + pl.kz * pl.kz;
+                    const double we = ph.lb4v * exp(-ph.ae2 * k2) / k2;
+                    const T rx = (T)ph.qa * A.x + (T)ph.qb * B.x, ry = (T)ph.qa * A.y + (T)ph.qb * B.y;
+                    const T wa = (T)(we * ph.qa), wb = (T)(we * ph.qb);
+                    PA.x += wa * rx;
+                    PA.y += wa * ry;
+                    PB.x += wb * rx;
+                    PB.y += wb * ry;
+                    if (want_energy) {
+                        const double dx = ph.qa * (double)A.x + ph.qb * (double)B.x;
+                        const double dy = ph.qa * (double)A.y + ph.qb * (double)B.y;
+                        const double e = col.w * we * (dx * dx + dy * dy);
+                        const double t = 1.0 / k2 + ph.ae2;
+                        acc[5] += e;
+                        acc[6] += e * col.kx * col.kx * t;
+                        acc[7] += e * col.ky * col.ky * t;
+                        acc[8] += e * pl.kz * pl.kz * t;
+                    }
+                }
                 const T kzd = (2 * z == mz) ? (T)0 : (T)pl.kz;
                 QA = C{-kzd * PA.y, kzd * PA.x};
                 QB = C{-kzd * PB.y, kzd * PB.x};
@@ -846,9 +874,9 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
         }
     }
     if (want_energy) {
-        block_sum<double, 5>(acc, red, tid, BLOCK);
+        block_sum<double, NACC>(acc, red, tid, BLOCK);
         if (tid == 0)
-            for (int q = 0; q < 5; ++q) epart[blockIdx.x * 5 + q] = acc[q];
+            for (int q = 0; q < kEpart; ++q) epart[blockIdx.x * kEpart + q] = q < NACC ? acc[q] : 0.0;
     }
     if (ENERGY_ONLY) return;
     __syncthreads();
@@ -1231,29 +1259,33 @@ __global__ void __launch_bounds__(256) k_bond_energy(const uint4* __restrict__ p
 __global__ void __launch_bounds__(256) k_reduce_energy(const double* __restrict__ epart, int nz,
                                                        const long long* __restrict__ bpart, int nb, Phys ph,
                                                        double n_a, double n_b, double* __restrict__ eout) {
-    __shared__ double red[5 * 4];
+    __shared__ double red[kEpart * 4];
     __shared__ long long bred[4 * 4];
     const int tid = threadIdx.x;
-    double acc[5] = {0, 0, 0, 0, 0};
+    double acc[kEpart];
+    for (int q = 0; q < kEpart; ++q) acc[q] = 0.0;
     for (int i = tid; i < nz; i += 256)
-        for (int q = 0; q < 5; ++q) acc[q] += epart[i * 5 + q];
+        for (int q = 0; q < kEpart; ++q) acc[q] += epart[i * kEpart + q];
     long long bacc[4] = {0, 0, 0, 0};
     for (int i = tid; i < nb; i += 256)
         for (int q = 0; q < 4; ++q) bacc[q] += bpart[i * 4 + q];
     block_sum<long long, 4>(bacc, bred, tid, 256);
-    block_sum<double, 5>(acc, red, tid, 256);
+    block_sum<double, kEpart>(acc, red, tid, 256);
     if (tid == 0) {
         const double e_chi = ph.chi * ph.inv_n * acc[0] + ph.chi * n_a * n_b * ph.inv_n * ph.u0;
         const double e_kap = 0.5 * ph.kappa * ph.inv_n * acc[1];
+        // electrostatics: E_e = (1/2) sum W_e |rho_e|^2; W_aa gets
+        // (1/2) sum W_e |rho_e|^2 [1 - 2 k_a^2 (1/k^2 + a_e^2)]
+        const double e_el = 0.5 * acc[5];
         double wb[3];
         for (int a = 0; a < 3; ++a) wb[a] = (double)bacc[1 + a] * kInvTwo32;
         const double e_b = (double)bacc[0] * kInvTwo32;
         eout[0] = e_b;
         eout[1] = e_chi;
         eout[2] = e_kap;
-        eout[3] = e_b + e_chi + e_kap;
-        for (int a = 0; a < 3; ++a) eout[4 + a] = -2.0 * ph.a2 * acc[2 + a] + wb[a];
-        eout[7] = 0.0;
+        eout[3] = e_b + e_chi + e_kap + e_el;
+        for (int a = 0; a < 3; ++a) eout[4 + a] = -2.0 * ph.a2 * acc[2 + a] + wb[a] + e_el - acc[6 + a];
+        eout[7] = e_el;
         // parameter gradients of the non-bonded energy at fixed positions
         eout[8] = ph.inv_n * (acc[0] + n_a * n_b * ph.u0);                       // dE/dchi
         eout[9] = 0.5 * ph.inv_n * acc[1];                                       // dE/dkappa
@@ -1404,11 +1436,16 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S, int route) {
     return hipGetLastError();
 }
 
-template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
-    hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
+template <typename T, int EO, bool EL> static void z_te(const Launch& L, DeviceState& S, int want_energy) {
+    hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO, EL>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
                        S.epart, want_energy, S.noise_step && !L.force_ad ? S.noise_part : nullptr, S.n, S.qshift,
                        S.qshift_next, S.utab, S.vtab, L.force_ad ? 2 : 4);
+}
+
+template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
+    if (L.ph.elec) z_te<T, EO, true>(L, S, want_energy);
+    else z_te<T, EO, false>(L, S, want_energy);
 }
 
 hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool with_energy) {
@@ -1581,11 +1618,13 @@ template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) 
 }
 
 template <typename T> static hipError_t attr_z(size_t lds) {
-    hipError_t e =
-        hipFuncSetAttribute((const void*)k_z_kmul<T, kZBlock, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_z_kmul<T, kZBlock, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
+    const void* fns[4] = {(const void*)k_z_kmul<T, kZBlock, 0, false>, (const void*)k_z_kmul<T, kZBlock, 1, false>,
+                          (const void*)k_z_kmul<T, kZBlock, 0, true>, (const void*)k_z_kmul<T, kZBlock, 1, true>};
+    for (const void* f : fns) {
+        const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t configure_kernel_attributes(const Launch& L) {

@@ -88,6 +88,9 @@ def good():
     (lambda p: setattr(p, "flags", 32), "flag"),
     (lambda p: (setattr(p, "flags", _lib.TILD_INTEGRATOR_GJF), setattr(p, "mass", -1.0)), "mass"),
     (lambda p: (setattr(p, "flags", _lib.TILD_INTEGRATOR_GJF), setattr(p, "mass", float("nan"))), "mass"),
+    (lambda p: setattr(p, "bjerrum", -1.0), "bjerrum"),
+    (lambda p: setattr(p, "charge_smear", float("inf")), "charge_smear"),
+    (lambda p: p.charge.__setitem__(1, float("nan")), "charge"),
     (lambda p: setattr(p, "smear_a", float("inf")), "smear_a"),
     (lambda p: (setattr(p, "smear_a", 0.0), setattr(p, "flags", _lib.TILD_POTENTIAL_SAMPLED)), "smear_a"),
     (lambda p: (setattr(p, "order", 1), setattr(p, "flags", _lib.TILD_FORCE_AD)), "order"),
