@@ -305,6 +305,37 @@ const char* tild_kernel_name(int32_t slot);
 int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t iters,
                      void* hip_stream, double* ms_per_copy);
 
+/*
+ * Batches: independent contexts (replicas of uneven box, grid and bead
+ * count: the multiple boxes of replica exchange, parallel tempering or Gibbs
+ * ensemble sampling the paper plans, Sec. "Planned future developments")
+ * stepped together, one launch per
+ * kernel for all members instead of one per member.
+ *   ctxs: n_ctx >= 1 distinct contexts on the current device, all with the
+ *         same precision, order and flags, all charged or all neutral, on
+ *         the ik route with Euler-Maruyama (no TILD_FORCE_AD, no
+ *         TILD_INTEGRATOR_GJF); at most 16,776,960 beads each.  The batch
+ *         borrows them: they must outlive it.
+ *   hip_stream: the stream the batch's work is enqueued on (NULL = null stream).
+ * tild_batch_step advances every member by n_steps (< 2^31) steps, exactly as
+ * tild_step on each member would (same noise stream, same step counters), and
+ * returns after enqueueing.  The batch's stream first waits for the work
+ * queued on each member's stream, and each member's stream then waits for
+ * the batch, so calls on a member (positions, forces, energy) stay ordered
+ * with the batch.  It also waits on the host until the previous call's
+ * descriptor upload (a few hundred bytes per member) has been read.
+ * TILD_ESTATE if a member's positions were never set.
+ * tild_batch_synchronize waits for the batch's stream and reports the first
+ * member's latched error (as tild_synchronize).  Errors of a batch call are
+ * described by tild_batch_last_error (creation errors: tild_batch_last_error(NULL)).
+ */
+typedef struct tild_batch tild_batch;
+int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_stream, tild_batch** out);
+int tild_batch_step(tild_batch* batch, int64_t n_steps);
+int tild_batch_synchronize(tild_batch* batch);
+void tild_batch_destroy(tild_batch* batch);
+const char* tild_batch_last_error(const tild_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

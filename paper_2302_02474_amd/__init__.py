@@ -241,6 +241,54 @@ class Tild:
         return {self._lib.tild_kernel_name(i).decode(): float(ms[i]) for i in range(k)}
 
 
+class Batch:
+    """Several Tild contexts stepped together, one launch per kernel for all of
+    them (tild_batch_*).  The contexts are borrowed and must stay open while
+    the batch lives; ``stream`` as for Tild."""
+
+    def __init__(self, members: Sequence[Tild], stream=None):
+        self._lib = lib()
+        self._b = ctypes.c_void_p(None)
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[m._ctx.value for m in self.members])
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self._stream_obj = stream
+        handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
+        self._stream = ctypes.c_void_p(int(handle) if handle else None)
+        rc = self._lib.tild_batch_create(arr, len(self.members), self._stream, ctypes.byref(self._b))
+        if rc != TILD_OK:
+            raise TildError(rc, self._lib.tild_batch_last_error(None).decode())
+
+    def _check(self, rc: int):
+        if rc != TILD_OK:
+            raise TildError(rc, self._lib.tild_batch_last_error(self._b).decode())
+
+    def step(self, n_steps: int = 1):
+        self._check(self._lib.tild_batch_step(self._b, int(n_steps)))
+
+    def synchronize(self):
+        self._check(self._lib.tild_batch_synchronize(self._b))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.tild_batch_destroy(self._b)
+            self._b = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 def kernel_names() -> Sequence[str]:
     L = lib()
     return [L.tild_kernel_name(i).decode() for i in range(_L.TILD_NUM_KERNELS)]

@@ -31,6 +31,7 @@ EXPORTS = [
     "tild_get_velocities", "tild_step", "tild_forces",
     "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
+    "tild_batch_create", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
 ]
 
 
@@ -109,5 +110,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_kernel_name.restype = ctypes.c_char_p
     lib.tild_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, vp, P(ctypes.c_double)]
     lib.tild_stream_copy.restype = ctypes.c_int
+    lib.tild_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
+    lib.tild_batch_create.restype = ctypes.c_int
+    lib.tild_batch_step.argtypes = [vp, i64]
+    lib.tild_batch_step.restype = ctypes.c_int
+    lib.tild_batch_synchronize.argtypes = [vp]
+    lib.tild_batch_synchronize.restype = ctypes.c_int
+    lib.tild_batch_destroy.argtypes = [vp]
+    lib.tild_batch_destroy.restype = None
+    lib.tild_batch_last_error.argtypes = [vp]
+    lib.tild_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib

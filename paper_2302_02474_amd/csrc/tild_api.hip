@@ -881,3 +881,206 @@ TILD_API int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t 
     *ms_per_copy = ms / iters;
     return TILD_OK;
 }
+
+// ---------------------------------------------------------------- batches
+
+struct tild_batch {
+    std::vector<tild_ctx*> ctx;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Launch L{};
+    RepDesc* h_desc = nullptr;  // pinned host copy of the descriptors
+    RepDesc* d_desc = nullptr;
+    uint32_t* maps = nullptr;
+    unsigned long long* status = nullptr;  // every member's scan status words, then the ticket
+    std::vector<size_t> status_off;
+    BatchMaps B{};
+    size_t lds_plane = 0, lds_z = 0;
+    std::vector<hipEvent_t> member_ev;
+    hipEvent_t copy_ev = nullptr, done_ev = nullptr;
+    bool copy_pending = false;
+    std::string err;
+
+    int fail(int code, const std::string& msg) {
+        err = msg;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return TILD_EHIP;
+    }
+};
+
+TILD_API void tild_batch_destroy(tild_batch* b) {
+    if (!b) return;
+    {
+        DeviceGuard g(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        if (b->h_desc) (void)hipHostFree(b->h_desc);
+        if (b->d_desc) (void)hipFree(b->d_desc);
+        if (b->maps) (void)hipFree(b->maps);
+        if (b->status) (void)hipFree(b->status);
+        for (hipEvent_t e : b->member_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (b->copy_ev) (void)hipEventDestroy(b->copy_ev);
+        if (b->done_ev) (void)hipEventDestroy(b->done_ev);
+    }
+    delete b;
+}
+
+TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_stream, tild_batch** out) {
+    if (!out) return TILD_EINVAL;
+    *out = nullptr;
+    auto bad = [&](const std::string& why) {
+        g_create_error = "batch: " + why;
+        return TILD_EINVAL;
+    };
+    if (!ctxs || n_ctx < 1 || n_ctx > 65535) return bad("needs 1..65535 contexts");
+    const tild_ctx* c0 = ctxs[0];
+    if (!c0) return bad("NULL context");
+    for (int32_t i = 0; i < n_ctx; ++i) {
+        const tild_ctx* c = ctxs[i];
+        if (!c) return bad("NULL context");
+        for (int32_t k = 0; k < i; ++k)
+            if (ctxs[k] == c) return bad("a context appears twice");
+        if (c->device != c0->device) return bad("contexts on different devices");
+        if (c->L.precision != c0->L.precision || c->L.order != c0->L.order || c->p.flags != c0->p.flags ||
+            c->L.ph.elec != c0->L.ph.elec)
+            return bad("contexts differ in precision, order, flags or the presence of charges");
+        if (c->L.force_ad || c->L.ph.gjf) return bad("batched steps use the ik route and Euler-Maruyama");
+        if ((c->S.n + 255) / 256 > 65535) return bad("a member has more than 16,776,960 beads");
+    }
+    tild_batch* b = new (std::nothrow) tild_batch();
+    if (!b) {
+        g_create_error = "out of host memory";
+        return TILD_ENOMEM;
+    }
+    b->device = c0->device;
+    b->stream = (hipStream_t)hip_stream;
+    b->ctx.assign(ctxs, ctxs + n_ctx);
+    b->L = c0->L;
+    b->L.stream = b->stream;
+    DeviceGuard g(b->device);
+    // unit maps, member by member; every member's scan keeps its own status words
+    std::vector<uint32_t> plane, c2r, zcol, bead, tile;
+    size_t nstatus = 0;
+    for (int32_t r = 0; r < n_ctx; ++r) {
+        const tild_ctx* c = ctxs[r];
+        const Dims& d = c->L.d;
+        const uint32_t hi = (uint32_t)r << 16;
+        for (int u = 0; u < 2 * d.mz; ++u) plane.push_back(hi | (uint32_t)u);
+        for (int u = 0; u < 6 * d.mz; ++u) c2r.push_back(hi | (uint32_t)u);
+        for (int u = 0; u < c->L.n_zblocks; ++u) zcol.push_back(hi | (uint32_t)u);
+        for (long long u = 0; u < (c->S.n + 255) / 256; ++u) bead.push_back(hi | (uint32_t)u);
+        const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
+        for (int u = 0; u < ntiles; ++u) tile.push_back(hi | (uint32_t)u);
+        b->status_off.push_back(nstatus);
+        nstatus += (size_t)ntiles;
+        b->lds_plane = std::max(b->lds_plane, plane_lds_bytes(c->L));
+        b->lds_z = std::max(b->lds_z, z_lds_bytes(c->L));
+    }
+    const size_t nmap = plane.size() + c2r.size() + zcol.size() + bead.size() + tile.size();
+    std::vector<uint32_t> all;
+    all.reserve(nmap);
+    for (const auto* v : {&plane, &c2r, &zcol, &bead, &tile}) all.insert(all.end(), v->begin(), v->end());
+    hipError_t e = hipMalloc((void**)&b->maps, nmap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(b->maps, all.data(), nmap * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->status, (nstatus + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(b->status, 0, (nstatus + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_desc, (size_t)n_ctx * sizeof(RepDesc));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_desc, (size_t)n_ctx * sizeof(RepDesc), hipHostMallocDefault);
+    b->member_ev.assign((size_t)n_ctx, nullptr);
+    for (int32_t r = 0; e == hipSuccess && r < n_ctx; ++r)
+        e = hipEventCreateWithFlags(&b->member_ev[(size_t)r], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copy_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = configure_batch_attributes(b->L, b->lds_plane, b->lds_z);
+    if (e != hipSuccess) {
+        g_create_error = std::string("batch: device setup: ") + hipGetErrorString(e);
+        tild_batch_destroy(b);
+        return TILD_EHIP;
+    }
+    BatchMaps& B = b->B;
+    B.reps = b->d_desc;
+    B.plane = b->maps;
+    B.c2r = B.plane + plane.size();
+    B.zcol = B.c2r + c2r.size();
+    B.bead = B.zcol + zcol.size();
+    B.tile = B.bead + bead.size();
+    B.n_plane = (int)plane.size();
+    B.n_c2r = (int)c2r.size();
+    B.n_zcol = (int)zcol.size();
+    B.n_bead = (int)bead.size();
+    B.n_tile = (int)tile.size();
+    B.ticket = b->status + nstatus;
+    *out = b;
+    return TILD_OK;
+}
+
+TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
+    if (!b) return TILD_EINVAL;
+    if (n_steps < 0 || n_steps > 0x7fffffffLL) return b->fail(TILD_EINVAL, "n_steps must be in [0, 2^31)");
+    for (tild_ctx* c : b->ctx)
+        if (!c->have_pos) return b->fail(TILD_ESTATE, "a member's positions were never set");
+    if (n_steps == 0) return TILD_OK;
+    DeviceGuard g(b->device);
+    hipError_t e = hipSuccess;
+    // the batch's stream waits for the work already queued on every member's stream
+    for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) {
+        e = hipEventRecord(b->member_ev[r], b->ctx[r]->L.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->member_ev[r], 0);
+    }
+    // the previous call's descriptor upload must have left the pinned buffer
+    if (e == hipSuccess && b->copy_pending) e = hipEventSynchronize(b->copy_ev);
+    for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) {
+        const tild_ctx* c = b->ctx[r];
+        RepDesc& R = b->h_desc[r];
+        R.d = c->L.d;
+        R.px = c->L.px;
+        R.py = c->L.py;
+        R.pz = c->L.pz;
+        R.ph = c->L.ph;
+        R.S = c->S;
+        R.S.scan_status = b->status + b->status_off[r];
+        R.z_cols = c->L.z_cols;
+        R.n_zblocks = c->L.n_zblocks;
+        R.ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
+        R.step0 = (uint64_t)c->step;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_desc, b->h_desc, b->ctx.size() * sizeof(RepDesc), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->copy_ev, b->stream);
+    if (e == hipSuccess) b->copy_pending = true;
+    for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
+        e = launch_batch_step(b->L, b->B, (int)s, b->lds_plane, b->lds_z);
+    if (e != hipSuccess) return b->hip_fail(e, "batch step");
+    // the members' pointer pairs swap once per step; their step counters advance
+    for (tild_ctx* c : b->ctx) {
+        if (n_steps & 1) {
+            std::swap(c->S.qshift, c->S.qshift_next);
+            std::swap(c->S.nbr, c->S.nbr_old);
+        }
+        c->step += n_steps;
+    }
+    // later work on a member's stream waits for the batch
+    e = hipEventRecord(b->done_ev, b->stream);
+    for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) e = hipStreamWaitEvent(b->ctx[r]->L.stream, b->done_ev, 0);
+    if (e != hipSuccess) return b->hip_fail(e, "batch step");
+    return TILD_OK;
+}
+
+TILD_API int tild_batch_synchronize(tild_batch* b) {
+    if (!b) return TILD_EINVAL;
+    DeviceGuard g(b->device);
+    const hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "batch synchronize");
+    for (tild_ctx* c : b->ctx) {
+        const int rc = check_flag(c);
+        if (rc != TILD_OK) return b->fail(rc, c->err);
+    }
+    return TILD_OK;
+}
+
+TILD_API const char* tild_batch_last_error(const tild_batch* b) {
+    return b ? b->err.c_str() : g_create_error.c_str();
+}

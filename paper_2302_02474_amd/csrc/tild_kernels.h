@@ -89,6 +89,33 @@ struct DeviceState {
     int nbins;            // 2 * mz * my
 };
 
+// One member of a batch of independent contexts stepped together: what the
+// batched kernels read from its context.  The pointer pairs (qshift,
+// qshift_next) and (nbr, nbr_old) are those at the start of a batch call;
+// at step s of the call the kernels take them swapped when s is odd.
+struct RepDesc {
+    Dims d;
+    FftPlan px, py, pz;
+    Phys ph;
+    DeviceState S;   // S.scan_status points at the batch's own status words for this member
+    int z_cols;
+    int n_zblocks;
+    int ntiles;      // bin scan tiles
+    uint64_t step0;  // the member's step counter at the start of the call
+};
+
+// Work-unit maps of a batched launch: entry g = (member << 16) | local unit.
+struct BatchMaps {
+    const RepDesc* reps;
+    const uint32_t* plane;  // spread units: (z, species) planes, 2 mz per member
+    const uint32_t* c2r;    // inverse plane units: (z, species, axis), 6 mz per member
+    const uint32_t* zcol;   // z-pass column blocks, n_zblocks per member
+    const uint32_t* bead;   // 256-bead blocks, ceil(n / 256) per member
+    const uint32_t* tile;   // bin scan tiles, ntiles per member
+    int n_plane, n_c2r, n_zcol, n_bead, n_tile;
+    unsigned long long* ticket;  // the batch's scan ticket
+};
+
 struct Launch {
     hipStream_t stream;
     int precision;   // 0 float, 1 double
@@ -131,6 +158,13 @@ hipError_t launch_get_positions(const Launch& L, DeviceState& S, void* xyz, int 
 // re-placement of the beads
 hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, int dtype);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+// One step of every member of a batch (ik route, Euler-Maruyama, all members
+// of the same precision, order and flags as L), one launch per kernel; s is
+// the step's index within the call (its parity selects the pointer pairs).
+// lds_plane / lds_z: the largest dynamic LDS any member needs.
+hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z);
+hipError_t configure_batch_attributes(const Launch& L, size_t lds_plane, size_t lds_z);
 
 // Dynamic LDS a plane / z workgroup needs (bytes), used for validation.
 size_t plane_lds_bytes(const Launch& L);

@@ -272,11 +272,16 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
 // row 2p+1 at p * zp + hxp, i.e. H has row pitch hxp.
 // At least four waves per SIMD (128 VGPRs): two 512-thread or one
 // 1024-thread workgroup per CU, as the plane's LDS allows.
-template <typename T, int BLOCK, int P>
+//
+// BATCH: one launch for all members of a batch; the unit map names each
+// workgroup's member and plane, and the member's descriptor replaces the
+// per-context arguments.
+template <typename T, int BLOCK, int P, bool BATCH = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
-                uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part) {
+                uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part,
+                const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity) {
     using C = cplx<T>;
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
@@ -286,7 +291,26 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
-    const int t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
+    int t;
+    if constexpr (BATCH) {
+        const uint32_t e = umap[xcd_contiguous(blockIdx.x, gridDim.x)];
+        const RepDesc& R = reps[e >> 16];
+        pos = R.S.pos;
+        bin_start = R.S.bin_start;
+        qs = parity ? R.S.qshift_next : R.S.qshift;
+        spec = (C*)R.S.spec;
+        d = R.d;
+        px = R.px;
+        py = R.py;
+        tw = (const C*)R.S.tw;
+        ph = R.ph;
+        flag = R.S.flag;
+        step += R.step0;  // step: the step's index within the batch call
+        noise_part = R.S.noise_part;
+        t = (int)(e & 0xffffu);
+    } else {
+        t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
+    }
     const int z = t % d.mz, K = t / d.mz;
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T mean = (T)(K ? ph.mean_b : ph.mean_a);
@@ -542,20 +566,43 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
 // transforms phi_K itself and interpolates all three components with the
 // weight derivatives (push_plane_ad); fsum_part receives the workgroup's
 // force sums (32.32 fixed point).
-template <typename T, int BLOCK, int P, bool AD>
+//
+// BATCH (ik route only): one launch for all members of a batch, as for the
+// spread.
+template <typename T, int BLOCK, int P, bool AD, bool BATCH = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
-             long long* __restrict__ fsum_part) {
+             long long* __restrict__ fsum_part, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
+             int parity) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes the three axes of a run of consecutive planes of one
     // species: all of them read the same bead slabs
-    const int t = AD ? xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz)
-                     : xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
+    int t;
+    if constexpr (BATCH) {
+        static_assert(!AD, "batched steps use the ik route");
+        const uint32_t e = umap[xcd_contiguous(blockIdx.x, gridDim.x)];
+        const RepDesc& R = reps[e >> 16];
+        zout = (const C*)R.S.zout;
+        fpart = (T*)R.S.fpart;
+        d = R.d;
+        px = R.px;
+        py = R.py;
+        tw = (const C*)R.S.tw;
+        ph = R.ph;
+        pos = R.S.pos;
+        bin_start = R.S.bin_start;
+        qs = parity ? R.S.qshift_next : R.S.qshift;
+        n = R.S.n;
+        t = (int)(e & 0xffffu);
+    } else {
+        t = AD ? xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz)
+               : xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
+    }
     const int a = AD ? 2 : t % 3, z = AD ? t % d.mz : (t / 3) % d.mz, K = AD ? t / d.mz : t / (3 * d.mz);
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
@@ -721,18 +768,45 @@ struct ZPlane {
 // pair kernel: Phi^_K += q_K W_e rho^_e with W_e = (4 pi l_B / V)
 // exp(-a_e^2 k^2) / k^2 and rho^_e = q_A c^_A + q_B c^_B (k = 0 left out),
 // and the energy partials gain sum W_e |rho^_e|^2 and its virial terms.
-template <typename T, int BLOCK, int ENERGY_ONLY, bool ELEC>
+// BATCH: one launch for all members of a batch (stepping only: noise sums
+// given, four outputs); each member's last column block forms its shift.
+template <typename T, int BLOCK, int ENERGY_ONLY, bool ELEC, bool BATCH = false>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
                                                   double* __restrict__ epart, int want_energy,
                                                   const long long* __restrict__ noise_part, long long n,
                                                   const uint32_t* __restrict__ qs, uint32_t* __restrict__ qs_next,
                                                   const double* __restrict__ utab, const double* __restrict__ vtab,
-                                                  int nout) {
+                                                  int nout, const RepDesc* __restrict__ reps,
+                                                  const uint32_t* __restrict__ umap, int parity) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[(ELEC ? 9 : 5) * (BLOCK / 64)];
-    if (noise_part && blockIdx.x == gridDim.x - 1) {
+    int blk, nblk;
+    if constexpr (BATCH) {
+        const uint32_t e = umap[blockIdx.x];
+        const RepDesc& R = reps[e >> 16];
+        spec = (const C*)R.S.spec;
+        zout = (C*)R.S.zout;
+        d = R.d;
+        pz = R.pz;
+        tw = (const C*)R.S.tw;
+        ph = R.ph;
+        cb = R.z_cols;
+        epart = R.S.epart;
+        noise_part = R.S.noise_part;
+        n = R.S.n;
+        qs = parity ? R.S.qshift_next : R.S.qshift;
+        qs_next = parity ? R.S.qshift : R.S.qshift_next;
+        utab = R.S.utab;
+        vtab = R.S.vtab;
+        blk = (int)(e & 0xffffu);
+        nblk = R.n_zblocks;
+    } else {
+        blk = blockIdx.x;
+        nblk = gridDim.x;
+    }
+    if (noise_part && blk == nblk - 1) {
         __shared__ long long nred[3 * (BLOCK / 64)];
         long long v[3] = {0, 0, 0};
         for (int i = threadIdx.x; i < 2 * d.mz; i += BLOCK)
@@ -760,7 +834,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + d.mx + d.my + d.mz);
     ZColumn* ct = reinterpret_cast<ZColumn*>(zt + mz);
     const int cn = (int)d.hplane;
-    const int c0 = blockIdx.x * cb;
+    const int c0 = blk * cb;
     const double kfx = kTwoPi / ph.lx, kfy = kTwoPi / ph.ly, kfz = kTwoPi / ph.lz;
     {
         // both spectra of the block's columns, nine loads in flight per thread
@@ -876,7 +950,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     if (want_energy) {
         block_sum<double, NACC>(acc, red, tid, BLOCK);
         if (tid == 0)
-            for (int q = 0; q < kEpart; ++q) epart[blockIdx.x * kEpart + q] = q < NACC ? acc[q] : 0.0;
+            for (int q = 0; q < kEpart; ++q) epart[blk * kEpart + q] = q < NACC ? acc[q] : 0.0;
     }
     if (ENERGY_ONLY) return;
     __syncthreads();
@@ -961,20 +1035,43 @@ __global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict_
 //         back as the new half-step velocity to vout[j].
 // MODE 1: forces only, times out_sign, written to out[abi id] ([n][3], float
 //         or double).
-template <typename T, int P, int MODE>
+// BATCH (MODE 0): one launch for all members of a batch, 256-bead blocks
+// named by the unit map.
+template <typename T, int P, int MODE, bool BATCH = false>
 __global__ void __launch_bounds__(256)
     k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
              const T* __restrict__ fpart, const uint32_t* __restrict__ qs_new,
              long long n, Dims d, Phys ph, uint64_t step, void* out, int out_dtype, unsigned parts, double out_sign,
              uint2* __restrict__ kr,
              uint32_t* __restrict__ counts, uint32_t* __restrict__ flag, const uint32_t* __restrict__ qs_old,
-             const T* __restrict__ vin, T* __restrict__ vout) {
+             const T* __restrict__ vin, T* __restrict__ vout, const RepDesc* __restrict__ reps,
+             const uint32_t* __restrict__ umap, int parity) {
     const int tid = threadIdx.x;
     const bool need_field = MODE != 1 || (parts & 1u);
     const bool need_bond = MODE != 1 || (parts & 2u);
+    long long blk = blockIdx.x;
+    if constexpr (BATCH) {
+        static_assert(MODE == 0, "batched steps use Euler-Maruyama");
+        const uint32_t e = umap[blockIdx.x];
+        const RepDesc& R = reps[e >> 16];
+        pin = R.S.pos;
+        pout = R.S.pos_tmp;
+        fbond = (const T*)R.S.fbond;
+        fpart = (const T*)R.S.fpart;
+        qs_new = parity ? R.S.qshift : R.S.qshift_next;
+        qs_old = parity ? R.S.qshift_next : R.S.qshift;
+        n = R.S.n;
+        d = R.d;
+        ph = R.ph;
+        step += R.step0;
+        kr = R.S.kr;
+        counts = R.S.counts;
+        flag = R.S.flag;
+        blk = (long long)(e & 0xffffu);
+    }
     if constexpr (MODE != 1) {
         // one bead per thread; its loads are issued before the shift is formed
-        const long long j = blockIdx.x * 256LL + tid;
+        const long long j = blk * 256LL + tid;
         const bool active = j < n;
         uint4 q = uint4{0u, 0u, 0u, 0u};
         T f[3] = {0, 0, 0};
@@ -1096,21 +1193,42 @@ __device__ __forceinline__ unsigned long long scan_status(uint32_t epoch, uint32
     return ((unsigned long long)((epoch << 2) | flag) << 32) | value;
 }
 
+//
+// BATCH: one launch for all members of a batch; the ticket orders the tiles
+// of all members (each member's tiles consecutively in the unit map), so a
+// tile still only waits on tiles claimed before it, of its own member.
+template <bool BATCH = false>
 __global__ void __launch_bounds__(256)
     k_bin_scan(uint32_t* __restrict__ counts, uint32_t* __restrict__ bin_start, int nbins,
                unsigned long long* __restrict__ status, unsigned long long* __restrict__ ticket,
-               uint32_t* __restrict__ flag) {
-    __shared__ uint32_t s_tile, s_excl;
+               uint32_t* __restrict__ flag, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap) {
+    __shared__ uint32_t s_tile, s_excl, s_rep;
     __shared__ uint32_t wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const unsigned ntiles = gridDim.x;
+    unsigned ntiles = gridDim.x;
     if (tid == 0) {
         const unsigned long long t = atomicAdd(ticket, 1ull);
-        s_tile = (uint32_t)(t % ntiles);
-        s_excl = (uint32_t)((t / ntiles) & 0x3fffffffull);  // epoch, until the prefix is known
+        const uint32_t g = (uint32_t)(t % gridDim.x);
+        s_excl = (uint32_t)((t / gridDim.x) & 0x3fffffffull);  // epoch, until the prefix is known
+        if constexpr (BATCH) {
+            const uint32_t e = umap[g];
+            s_rep = e >> 16;
+            s_tile = e & 0xffffu;
+        } else {
+            s_tile = g;
+        }
     }
     __syncthreads();
     const uint32_t tile = s_tile, epoch = s_excl;
+    if constexpr (BATCH) {
+        const RepDesc& R = reps[s_rep];
+        counts = R.S.counts;
+        bin_start = R.S.bin_start;
+        nbins = R.S.nbins;
+        status = R.S.scan_status;
+        flag = R.S.flag;
+        ntiles = (unsigned)R.ntiles;
+    }
     const int lo = (int)tile * kScanBins + 4 * tid;
     uint4 v = uint4{0u, 0u, 0u, 0u};
     if (lo < nbins) v = *reinterpret_cast<const uint4*>(counts + lo);
@@ -1184,13 +1302,32 @@ __global__ void __launch_bounds__(256)
 // its harmonic bond force F = -2 k_b sum_partners d (d the minimum-image bond
 // vector, shift-free in fixed point) as {Fx, Fy, Fz, 0}.  With GJF (vdst not
 // null) the half-step velocity moves with the bead.
-template <typename T>
+template <typename T, bool BATCH = false>
 __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
-              T* __restrict__ fbond, long long n, int deg, Phys ph, const T* __restrict__ vsrc, T* __restrict__ vdst) {
+              T* __restrict__ fbond, long long n, int deg, Phys ph, const T* __restrict__ vsrc, T* __restrict__ vdst,
+              const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity) {
     // contiguous bead ranges per XCD: bond partners are near in the order
-    const long long j = xcd_contiguous(blockIdx.x, gridDim.x) * 256LL + threadIdx.x;
+    long long blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    if constexpr (BATCH) {
+        const uint32_t e = umap[blk];
+        const RepDesc& R = reps[e >> 16];
+        pos_tmp = R.S.pos_tmp;
+        kr = R.S.kr;
+        bin_start = R.S.bin_start;
+        nbr_src = parity ? R.S.nbr_old : R.S.nbr;
+        pos = R.S.pos;
+        nbr_dst = parity ? R.S.nbr : R.S.nbr_old;
+        fbond = (T*)R.S.fbond;
+        n = R.S.n;
+        deg = R.S.deg;
+        ph = R.ph;
+        vsrc = nullptr;
+        vdst = nullptr;
+        blk = (long long)(e & 0xffffu);
+    }
+    const long long j = blk * 256LL + threadIdx.x;
     if (j >= n) return;
     const uint2 kj = kr[j];
     const long long nw = (long long)bin_start[kj.x] + kj.y;
@@ -1395,7 +1532,8 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
     with_order(L.order, [&](auto Pc) {
         hipLaunchKernelGGL((k_spread_xy<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                            L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
-                           (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part);
+                           (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part,
+                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
     });
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S, bool ad) {
@@ -1404,11 +1542,11 @@ template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& 
         if (ad)
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
-                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part);
+                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
         else
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, false>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
-                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part);
+                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
     });
 }
 
@@ -1440,7 +1578,7 @@ template <typename T, int EO, bool EL> static void z_te(const Launch& L, DeviceS
     hipLaunchKernelGGL((k_z_kmul<T, kZBlock, EO, EL>), dim3(L.n_zblocks), dim3(kZBlock), z_lds_bytes(L), L.stream,
                        (const cplx<T>*)S.spec, (cplx<T>*)S.zout, L.d, L.pz, (const cplx<T>*)S.tw, L.ph, L.z_cols,
                        S.epart, want_energy, S.noise_step && !L.force_ad ? S.noise_part : nullptr, S.n, S.qshift,
-                       S.qshift_next, S.utab, S.vtab, L.force_ad ? 2 : 4);
+                       S.qshift_next, S.utab, S.vtab, L.force_ad ? 2 : 4, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
 }
 
 template <typename T, int EO> static void z_t(const Launch& L, DeviceState& S, int want_energy) {
@@ -1467,7 +1605,7 @@ static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, 
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
                        (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, out_sign, S.kr,
-                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp);
+                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
 }
 
 template <typename T, int MODE>
@@ -1503,22 +1641,87 @@ hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t ste
 
 hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
     const unsigned ntiles = (unsigned)((S.nbins + kScanBins - 1) / kScanBins);
-    hipLaunchKernelGGL(k_bin_scan, dim3(ntiles), dim3(256), 0, L.stream, S.counts, S.bin_start, S.nbins, S.scan_status,
-                       S.scan_status + ntiles, S.flag);
+    hipLaunchKernelGGL(k_bin_scan<false>, dim3(ntiles), dim3(256), 0, L.stream, S.counts, S.bin_start, S.nbins,
+                       S.scan_status, S.scan_status + ntiles, S.flag, (const RepDesc*)nullptr, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src) {
     if (S.n == 0) return hipSuccess;
     if (L.precision == 0)
-        hipLaunchKernelGGL(k_scatter<float>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
+        hipLaunchKernelGGL((k_scatter<float, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph,
-                           (const float*)S.vel_tmp, (float*)S.vel);
+                           (const float*)S.vel_tmp, (float*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
     else
-        hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
+        hipLaunchKernelGGL((k_scatter<double, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph,
-                           (const double*)S.vel_tmp, (double*)S.vel);
+                           (const double*)S.vel_tmp, (double*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batched step
+
+template <typename T> static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, size_t lz) {
+    const RepDesc* R = B.reps;
+    const uint64_t so = (uint64_t)s;
+    const int par = s & 1;
+    constexpr int PB = 512;  // plane workgroups of every member
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
+                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
+                           (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, 1, so, (long long*)nullptr, R, B.plane,
+                           par);
+        if (L.ph.elec)
+            hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
+                               (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
+                               (double*)nullptr, 0, (const long long*)nullptr, 0LL, (const uint32_t*)nullptr,
+                               (uint32_t*)nullptr, (const double*)nullptr, (const double*)nullptr, 4, R, B.zcol, par);
+        else
+            hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, false, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
+                               (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
+                               (double*)nullptr, 0, (const long long*)nullptr, 0LL, (const uint32_t*)nullptr,
+                               (uint32_t*)nullptr, (const double*)nullptr, (const double*)nullptr, 4, R, B.zcol, par);
+        hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
+                           (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
+                           (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
+                           (long long*)nullptr, R, B.c2r, par);
+        hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
+                           (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
+                           L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,
+                           (uint32_t*)nullptr, (const uint32_t*)nullptr, (const T*)nullptr, (T*)nullptr, R, B.bead,
+                           par);
+    });
+    hipLaunchKernelGGL(k_bin_scan<true>, dim3(B.n_tile), dim3(256), 0, L.stream, (uint32_t*)nullptr,
+                       (uint32_t*)nullptr, 0, (unsigned long long*)nullptr, B.ticket, (uint32_t*)nullptr, R, B.tile);
+    hipLaunchKernelGGL((k_scatter<T, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
+                       (const uint2*)nullptr, (const uint32_t*)nullptr, (const int32_t*)nullptr, (uint4*)nullptr,
+                       (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph, (const T*)nullptr, (T*)nullptr, R, B.bead, par);
+}
+
+hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z) {
+    if (L.precision == 0) batch_step_t<float>(L, B, s, lds_plane, lds_z);
+    else batch_step_t<double>(L, B, s, lds_plane, lds_z);
+    return hipGetLastError();
+}
+
+template <typename T> static hipError_t attr_batch(const Launch& L, size_t lp, size_t lz) {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f, size_t b) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    };
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        set((const void*)k_spread_xy<T, 512, P, true>, lp);
+        set((const void*)k_xy_c2r<T, 512, P, false, true>, lp);
+    });
+    set((const void*)k_z_kmul<T, kZBlock, 0, false, true>, lz);
+    set((const void*)k_z_kmul<T, kZBlock, 0, true, true>, lz);
+    return e;
+}
+
+hipError_t configure_batch_attributes(const Launch& L, size_t lds_plane, size_t lds_z) {
+    return L.precision == 0 ? attr_batch<float>(L, lds_plane, lds_z) : attr_batch<double>(L, lds_plane, lds_z);
 }
 
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S) {

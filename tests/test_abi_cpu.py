@@ -155,3 +155,15 @@ def test_workspace_bytes(lib):
     assert T.workspace_bytes(bad, 1000) == 0
     assert "order" in lib.tild_last_error(None).decode()
     assert T.workspace_bytes(p, 1000, np.array([[0, 1000]])) == 0
+
+
+def test_batch_create_rejects_bad_arguments(lib):
+    out = ctypes.c_void_p(None)
+    assert lib.tild_batch_create(None, 1, None, ctypes.byref(out)) == _lib.TILD_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.tild_batch_create(arr, 1, None, ctypes.byref(out)) == _lib.TILD_EINVAL
+    assert "NULL" in lib.tild_batch_last_error(None).decode()
+    assert lib.tild_batch_create(arr, 0, None, ctypes.byref(out)) == _lib.TILD_EINVAL
+    assert out.value is None
+    assert lib.tild_batch_step(None, 1) == _lib.TILD_EINVAL
+    lib.tild_batch_destroy(None)
