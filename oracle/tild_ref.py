@@ -62,7 +62,8 @@ __all__ = [
     "gradient_fields", "potential_fields", "gather", "gather_gradient_weights",
     "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
     "trajectory", "structure_factor_exact", "min_image", "gjf_coefficients", "gjf_trajectory",
-    "half_step_velocity", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
+    "half_step_velocity", "bspline_deriv2", "spread_directional", "gather_hessian_weights",
+    "bond_hessian_vector", "hessian_vector_product", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
 ]
 
 
@@ -121,11 +122,20 @@ def bspline_deriv(P: int, t) -> np.ndarray:
     return bspline(P - 1, t + 0.5) - bspline(P - 1, t - 0.5)
 
 
-def stencil(x: np.ndarray, L: np.ndarray, M: np.ndarray, P: int, deriv: bool = False):
+def bspline_deriv2(P: int, t) -> np.ndarray:
+    """d^2 B_P/dt^2 = B_{P-2}(t + 1) - 2 B_{P-2}(t) + B_{P-2}(t - 1)  (the derivative rule applied twice; P >= 3)."""
+    if P < 3:
+        raise ValueError("second derivatives need P >= 3")
+    t = np.asarray(t, dtype=np.float64)
+    return bspline(P - 2, t + 1.0) - 2.0 * bspline(P - 2, t) + bspline(P - 2, t - 1.0)
+
+
+def stencil(x: np.ndarray, L: np.ndarray, M: np.ndarray, P: int, deriv: bool = False, deriv2: bool = False):
     """Per-bead grid indices and 1D weights.
 
     Returns idx (n, 3, P) int64 (already reduced mod M), w (n, 3, P) and, with
-    ``deriv``, dw (n, 3, P) = d w / d x_a (units 1/length).
+    ``deriv``, dw (n, 3, P) = d w / d x_a (units 1/length); with ``deriv2``
+    also d2w = d^2 w / d x_a^2.
     """
     x = np.asarray(x, dtype=np.float64)
     h = L / M
@@ -139,7 +149,9 @@ def stencil(x: np.ndarray, L: np.ndarray, M: np.ndarray, P: int, deriv: bool = F
     if not deriv:
         return idx, w
     dw = bspline_deriv(P, t) / h[None, :, None]
-    return idx, w, dw
+    if not deriv2:
+        return idx, w, dw
+    return idx, w, dw, bspline_deriv2(P, t) / (h * h)[None, :, None]
 
 
 def _chunks(n: int, size: int):
@@ -357,6 +369,99 @@ def gather_gradient_weights(x: np.ndarray, types: np.ndarray, phi: np.ndarray, L
         for a in range(3):
             F[s:e, a] = -np.sum(comps[a].reshape(e - s, -1) * vals, axis=1)
     return F
+
+
+# --------------------------------------------------------------------------
+# Second order: Hessian-vector products of the mesh energy (for adjoints)
+# --------------------------------------------------------------------------
+
+def spread_directional(x: np.ndarray, types: np.ndarray, v: np.ndarray, L, M, P: int,
+                       chunk: int = 200000) -> np.ndarray:
+    """delta c_K(g) = sum_{j in K} grad W_j(g) . v_j: the first-order change of the counts when every bead j
+    moves along v_j.  Returns (2, Mx, My, Mz)."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    out = np.zeros((2, int(np.prod(M))))
+    types = np.asarray(types)
+    for s, e in _chunks(x.shape[0], chunk):
+        idx, w, dw = stencil(x[s:e], L, M, P, deriv=True)
+        vv = v[s:e]
+        dW = (vv[:, 0, None, None, None] * dw[:, 0, :, None, None] * w[:, 1, None, :, None] * w[:, 2, None, None, :]
+              + vv[:, 1, None, None, None] * w[:, 0, :, None, None] * dw[:, 1, None, :, None] * w[:, 2, None, None, :]
+              + vv[:, 2, None, None, None] * w[:, 0, :, None, None] * w[:, 1, None, :, None] * dw[:, 2, None, None, :])
+        lin = _flat_index(idx, M).reshape(e - s, -1)
+        for K in (0, 1):
+            sel = types[s:e] == K
+            out[K] += np.bincount(lin[sel].ravel(), weights=dW.reshape(e - s, -1)[sel].ravel(),
+                                  minlength=out.shape[1])
+    return out.reshape((2,) + tuple(int(m) for m in M))
+
+
+def gather_hessian_weights(x: np.ndarray, types: np.ndarray, phi: np.ndarray, v: np.ndarray, L, M, P: int,
+                           chunk: int = 200000) -> np.ndarray:
+    """sum_g (grad grad W_i(g)) v_i phi_{s_i}(g) for every bead i: the derivative of
+    sum_g grad W_i(g) phi(g) along v_i at fixed phi."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    n = x.shape[0]
+    out = np.zeros((n, 3))
+    flat = phi.reshape(2, -1)
+    types = np.asarray(types)
+    for s, e in _chunks(n, chunk):
+        idx, w, dw, d2w = stencil(x[s:e], L, M, P, deriv=True, deriv2=True)
+        lin = _flat_index(idx, M).reshape(e - s, -1)
+        vals = flat[types[s:e][:, None], lin]
+        f = [[None] * 3 for _ in range(3)]  # f[a][b] = 1D factors of d^2 W / dx_a dx_b per axis
+        for a in range(3):
+            for b in range(3):
+                fac = [w[:, ax] for ax in range(3)]
+                if a == b:
+                    fac[a] = d2w[:, a]
+                else:
+                    fac[a] = dw[:, a]
+                    fac[b] = dw[:, b]
+                f[a][b] = (fac[0][:, :, None, None] * fac[1][:, None, :, None] * fac[2][:, None, None, :]).reshape(e - s, -1)
+        vv = v[s:e]
+        for a in range(3):
+            acc = np.zeros(e - s)
+            for b in range(3):
+                acc += vv[:, b] * np.sum(f[a][b] * vals, axis=1)
+            out[s:e, a] = acc
+    return out
+
+
+def bond_hessian_vector(bonds: np.ndarray, v: np.ndarray, k_b: float) -> np.ndarray:
+    """H_b v for U = k_b sum |d|^2: each bond (i, j) adds 2 k_b (v_i - v_j) to bead i and the opposite to j."""
+    out = np.zeros_like(v, dtype=np.float64)
+    b = np.asarray(bonds, dtype=np.int64).reshape(-1, 2)
+    if b.size:
+        dv = v[b[:, 0]] - v[b[:, 1]]
+        np.add.at(out, b[:, 0], 2.0 * k_b * dv)
+        np.add.at(out, b[:, 1], -2.0 * k_b * dv)
+    return out
+
+
+def hessian_vector_product(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params,
+                           v: np.ndarray) -> np.ndarray:
+    """H v, H the Hessian of the total energy (mesh energy of Eqs. fh, HelfandP and electrostatics, plus
+    bonds) in the bead coordinates.  With F = -grad E (the exact-gradient force), -H v is the force's
+    Jacobian applied to v, and also its transpose (H is symmetric):
+      H v|_i = sum_g (grad grad W_i(g)) v_i phi_{s_i}(g) + sum_g grad W_i(g) delta phi_{s_i}(g) + (H_b v)_i,
+    delta phi the field of the directional counts delta c = spread_directional(v).  Needs P >= 3."""
+    L, M = p.L, p.M
+    n = x.shape[0]
+    c = spread(x, types, L, M, p.order)
+    chat = dft3(c, p.transform)
+    uhat = _uhat(p)
+    charged = p.bjerrum != 0.0 and any(q != 0.0 for q in p.charges)
+    welec = coulomb_kernel(L, M, p.bjerrum, p.charge_smear) if charged else None
+    phi = potential_fields(field_spectra(chat, uhat, p.chi, p.kappa, n, welec, p.charges), p.transform)
+    dc = spread_directional(x, types, v, L, M, p.order)
+    dchat = dft3(dc, p.transform)
+    dphi = potential_fields(field_spectra(dchat, uhat, p.chi, p.kappa, n, welec, p.charges), p.transform)
+    g1 = -gather_gradient_weights(x, types, dphi, L, M, p.order)
+    g2 = gather_hessian_weights(x, types, phi, v, L, M, p.order)
+    return g1 + g2 + bond_hessian_vector(bonds, v, p.bond_k)
 
 
 # --------------------------------------------------------------------------

@@ -368,6 +368,69 @@ def test_ik_force_converges_to_energy_gradient():
     assert errs[0] / errs[1] > 4 and errs[1] / errs[2] > 4
 
 
+# ------------------------------------------------------- Hessian-vector products
+
+@pytest.mark.parametrize("P", [3, 4, 5])
+def test_bspline_second_derivative_by_finite_differences(P):
+    t = np.linspace(-P / 2 + 0.013, P / 2 - 0.013, 301)
+    e = 1e-5
+    fd = (R.bspline_deriv(P, t + e) - R.bspline_deriv(P, t - e)) / (2 * e)
+    # away from the knots, where the second derivative jumps (P = 3)
+    ok = np.abs(((t + P / 2) % 1.0) - 0.5) < 0.5 - 2 * e
+    np.testing.assert_allclose(R.bspline_deriv2(P, t)[ok], fd[ok], atol=1e-7)
+
+
+def test_directional_spread_is_the_derivative_of_the_counts():
+    p = small_params()
+    x, t, _ = random_system(30, p, seed=21)
+    v = np.random.default_rng(3).normal(size=x.shape)
+    e = 1e-6
+    fd = (R.spread(x + e * v, t, p.L, p.M, p.order) - R.spread(x - e * v, t, p.L, p.M, p.order)) / (2 * e)
+    dc = R.spread_directional(x, t, v, p.L, p.M, p.order)
+    assert np.max(np.abs(dc - fd)) < 1e-7 * max(1.0, np.max(np.abs(fd)))
+    assert abs(dc.sum()) < 1e-11  # the counts' total does not change
+
+
+def test_hessian_gather_is_the_derivative_of_the_gradient_gather():
+    p = small_params(order=5)
+    x, t, _ = random_system(25, p, seed=22)
+    phi = np.random.default_rng(4).normal(size=(2,) + tuple(p.grid))
+    v = np.random.default_rng(5).normal(size=x.shape)
+    e = 1e-6
+    g = lambda y: -R.gather_gradient_weights(y, t, phi, p.L, p.M, p.order)
+    fd = (g(x + e * v) - g(x - e * v)) / (2 * e)
+    h = R.gather_hessian_weights(x, t, phi, v, p.L, p.M, p.order)
+    np.testing.assert_allclose(h, fd, atol=1e-6 * np.abs(fd).max())
+
+
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+@pytest.mark.parametrize("P", [3, 4])
+def test_hessian_vector_product_is_the_derivative_of_the_exact_force(P, extra):
+    p = small_params(order=P, **extra)
+    x, t, b = random_system(24, p, seed=23)
+    v = np.random.default_rng(6).normal(size=x.shape)
+    hv = R.hessian_vector_product(x, t, b, p, v)
+    e = 1e-5
+
+    def force(y):
+        ev = R.evaluate(y, t, b, p, want_ad=True)
+        return ev["F_nb_ad"] + ev["F_bond"]
+    fd = -(force(x + e * v) - force(x - e * v)) / (2 * e)
+    assert np.linalg.norm(hv - fd) < 1e-6 * np.linalg.norm(fd)
+    # symmetric: u . H v = v . H u
+    u = np.random.default_rng(7).normal(size=x.shape)
+    hu = R.hessian_vector_product(x, t, b, p, u)
+    assert abs(np.sum(u * hv) - np.sum(v * hu)) < 1e-10 * np.linalg.norm(hv) * np.linalg.norm(u)
+
+
+def test_bond_hessian_closed_form():
+    v = np.array([[1.0, 0.0, 2.0], [0.5, -1.0, 0.0], [0.0, 0.0, 1.0]])
+    hb = R.bond_hessian_vector(np.array([[0, 1], [1, 2]]), v, 1.5)
+    np.testing.assert_allclose(hb[0], 3.0 * (v[0] - v[1]))
+    np.testing.assert_allclose(hb[1], 3.0 * (v[1] - v[0]) + 3.0 * (v[1] - v[2]))
+    np.testing.assert_allclose(hb[2], 3.0 * (v[2] - v[1]))
+
+
 def test_bond_closed_form_across_boundary():
     L = np.array([10.0, 10.0, 10.0])
     x = np.array([[9.8, 5.0, 5.0], [0.3, 5.4, 4.5]])
