@@ -306,6 +306,21 @@ int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t iters,
                      void* hip_stream, double* ms_per_copy);
 
 /*
+ * Hessian-vector product of the total energy (mesh energy of Eqs. fh,
+ * HelfandP and electrostatics, plus bonds) at the current positions:
+ *   out_i = sum_j (d^2 E / dx_i dx_j) v_j
+ *         = sum_g (grad grad W_i(g)) v_i phi_{s_i}(g) + sum_g grad W_i(g) delta phi_{s_i}(g) + (H_b v)_i,
+ * delta phi the potential of the directional counts sum_j grad W_j . v_j,
+ * H_b v the bond term 2 bond_k sum_partners (v_i - v_j).  -H v is the
+ * Jacobian of the exact-gradient force applied to v, and also its transpose
+ * (H is symmetric), the building block of adjoints through time steps.
+ * v, out: [n_beads][3] in ABI order, dtype, both host or both device
+ * memory (on_device).  Needs order >= 3 (TILD_EINVAL otherwise).  Host
+ * calls synchronise.
+ */
+int tild_hvp(tild_ctx* ctx, const void* v, void* out, int32_t dtype, int32_t on_device);
+
+/*
  * Batches: independent contexts (replicas of uneven box, grid and bead
  * count: the multiple boxes of replica exchange, parallel tempering or Gibbs
  * ensemble sampling the paper plans, Sec. "Planned future developments")

@@ -219,6 +219,25 @@ class Tild:
         v = list(buf)
         return dict(E=v[0], dE_dchi=v[1], dE_dkappa=v[2], dE_da=v[3]), out
 
+    def hvp(self, v, out=None):
+        """Hessian-vector product H v of the total energy at the current positions ([n][3], ABI order);
+        v and out both host arrays or both CUDA tensors (out defaults to a new array of v's dtype)."""
+        if _is_torch(v):
+            import torch
+            v = v.contiguous()
+            if out is None:
+                out = torch.empty_like(v)
+        else:
+            v = np.ascontiguousarray(v)
+            if out is None:
+                out = np.empty_like(v)
+        pv, dv = _ptr(v)
+        po, do = _ptr(out)
+        if dv != do:
+            raise ValueError("v and out must both be host arrays or both device tensors")
+        self._check(self._lib.tild_hvp(self._ctx, pv, po, _dtype_code(v), dv))
+        return out
+
     def set_interaction(self, chi: float, kappa: float, smear_a: float):
         self._check(self._lib.tild_set_interaction(self._ctx, float(chi), float(kappa), float(smear_a)))
 

@@ -127,6 +127,23 @@ template <typename T, int P, int J = 0> __device__ __forceinline__ void spline_d
     }
 }
 
+// Second derivative d^2 w_j/df^2 (P >= 3): coefficients k (k - 1) c[i][k].
+template <typename T, int P, int J> __device__ __forceinline__ T spline_d2weight(T f) {
+    constexpr SplinePieces<P> sp = spline_pieces<P>();
+    constexpr int i = P - 1 - J;
+    T v = (T)((P - 1) * (P - 2) * sp.c[i][P - 1]);
+#pragma unroll
+    for (int k = P - 2; k >= 2; --k) v = v * f + (T)(k * (k - 1) * sp.c[i][k]);
+    return v;
+}
+
+template <typename T, int P, int J = 0> __device__ __forceinline__ void spline_d2weights(T f, T d2w[P]) {
+    if constexpr (J < P) {
+        d2w[J] = P >= 3 ? spline_d2weight<T, P, J>(f) : (T)0;
+        spline_d2weights<T, P, J + 1>(f, d2w);
+    }
+}
+
 // (u - P/2) * 2^32 for fixed-point q on an axis of m points.
 __device__ __forceinline__ int64_t stencil_fixed(uint32_t q, int m, int P) {
     return (int64_t)((uint64_t)q * (uint64_t)(uint32_t)m) - ((int64_t)P << 31);

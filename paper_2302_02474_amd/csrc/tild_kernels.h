@@ -59,6 +59,8 @@ struct DeviceState {
     void* fbond;          // [n][4] harmonic bond force of sorted bead j {Fx, Fy, Fz, 0} (working precision)
     void* vel;            // GJF only: [n][4] half-step velocity of sorted bead j {ux, uy, uz, 0}
     void* vel_tmp;        // GJF only: the same in the order of pos_tmp
+    void* vdir;           // [n][4] direction v of a Hessian-vector product, sorted order
+    void* hacc;           // [n][4] accumulated H v, sorted order
     uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
     uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
     unsigned long long* scan_status;  // [ntiles + 1] look-back status words of the bin scan, then its ticket
@@ -114,6 +116,7 @@ struct BatchMaps {
     const uint32_t* tile;   // bin scan tiles, ntiles per member
     int n_plane, n_c2r, n_zcol, n_bead, n_tile;
     unsigned long long* ticket;  // the batch's scan ticket
+    int plane_block;  // threads per plane workgroup (256 or 512) for every member
 };
 
 struct Launch {
@@ -157,6 +160,11 @@ hipError_t launch_get_positions(const Launch& L, DeviceState& S, void* xyz, int 
 // (vel -> v), op 2 vel (sorted) -> vel_tmp in ABI order (v unused), before a
 // re-placement of the beads
 hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, int dtype);
+
+// Hessian-vector product of the total energy at the current positions:
+// v ([n][3] ABI order, dtype) -> out ([n][3] ABI order, dtype), through vdir
+// and hacc (order >= 3).
+hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 // One step of every member of a batch (ik route, Euler-Maruyama, all members

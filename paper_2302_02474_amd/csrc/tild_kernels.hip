@@ -190,6 +190,50 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
     }
 }
 
+// Directional counts (adjoint and Hessian-vector products): every bead j of
+// the P slabs z-P+1 .. z adds grad W_j(g) . v_j to the node g of plane z it
+// reaches, accumulated in floating point (T atomics in LDS).  vdir: [n][4]
+// per sorted bead.
+template <typename T, int P>
+__device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint4* __restrict__ pos,
+                                                 const uint32_t* __restrict__ bin_start,
+                                                 const uint32_t* __restrict__ qs, const Dims d, int z, int K,
+                                                 const T* __restrict__ vdir, int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
+    const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const uint4 q = pos[j];
+            const T vx = vdir[4 * (long long)j] * ihx, vy = vdir[4 * (long long)j + 1] * ihy;
+            const T vz = vdir[4 * (long long)j + 2] * ihz;
+            int gx, gy;
+            T wx[P], wy[P], dwx[P], dwy[P];
+            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+            spline_dweights<T, P>(stencil_fraction<T>(q.x - sx, d.mx, P), dwx);
+            spline_dweights<T, P>(stencil_fraction<T>(q.y - sy, d.my, P), dwy);
+            const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+            T wzs[P], dwzs[P];  // only entry c survives unrolling
+            spline_weights<T, P>(fz, wzs);
+            spline_dweights<T, P>(fz, dwzs);
+            const RowOffsets<P> ro(gy, pr);
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                T* row = acc + ro.o[b] + 2 * gx;
+                const T cy = wy[b] * wzs[c] * vx, cr = dwy[b] * wzs[c] * vy + wy[b] * dwzs[c] * vz;
+#pragma unroll
+                for (int a = 0; a < P; ++a) atomicAdd(row + 2 * a, dwx[a] * cy + wx[a] * cr);
+            }
+        }
+    }
+}
+
 // Add the ghost cells of the extended plane into the cells they alias
 // (columns first, over real and ghost rows, then rows).  A: uint32_t or
 // unsigned long long (fixed point, wrapping integer sums).  Ends with a barrier.
@@ -276,12 +320,16 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
 // BATCH: one launch for all members of a batch; the unit map names each
 // workgroup's member and plane, and the member's descriptor replaces the
 // per-context arguments.
-template <typename T, int BLOCK, int P, bool BATCH = false>
+//
+// DIR: the directional counts sum_j grad W_j . v_j (vdir) instead of the
+// counts, accumulated in floating point, with no mean to subtract and no noise.
+template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
                 uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part,
-                const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity) {
+                const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
+                const T* __restrict__ vdir) {
     using C = cplx<T>;
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
@@ -313,7 +361,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     }
     const int z = t % d.mz, K = t / d.mz;
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
-    const T mean = (T)(K ? ph.mean_b : ph.mean_a);
+    const T mean = DIR ? (T)0 : (T)(K ? ph.mean_b : ph.mean_a);
     // Prologue: issue the global loads (twiddles, bin starts) before zeroing
     // the plane, then one barrier.
     C* twl = S + d.npg * zp;
@@ -321,46 +369,65 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     C twv[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
-    uint32_t mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
+    uint32_t mine = 0;
+    if constexpr (!DIR) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
     for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
 #pragma unroll
     for (int u = 0; u < 3; ++u)
         if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+    if constexpr (!DIR) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint32_t other = __shfl_xor(mine, o, 64);
-        mine = mine > other ? mine : other;
+        for (int o = 32; o >= 1; o >>= 1) {
+            const uint32_t other = __shfl_xor(mine, o, 64);
+            mine = mine > other ? mine : other;
+        }
+        if ((tid & 63) == 0) smax[tid >> 6] = mine;
     }
-    if ((tid & 63) == 0) smax[tid >> 6] = mine;
     __syncthreads();
-    T scale;
-    {
+    T scale = (T)1;
+    if constexpr (!DIR) {
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < BLOCK / 64; ++w) m = m > smax[w] ? m : smax[w];
         scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
-    long long nsum[3] = {0, 0, 0};
-    spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, ph.gjf != 0, step, ph.seed, nsum, tid, BLOCK);
-    if (noise) {
-        block_sum<long long, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
-        if (tid == 0)
-            for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
-    } else {
+    if constexpr (DIR) {
+        spread_plane_dir<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, tid, BLOCK);
         __syncthreads();
+        fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
+    } else {
+        long long nsum[3] = {0, 0, 0};
+        spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, ph.gjf != 0, step, ph.seed, nsum, tid,
+                           BLOCK);
+        if (noise) {
+            block_sum<long long, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
+            if (tid == 0)
+                for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
+        } else {
+            __syncthreads();
+        }
+        fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     }
-    fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     {
         // counts (minus their mean) of the real cells; zero elsewhere
         const T inv = (T)1 / scale;
-        const A* Si = reinterpret_cast<const A*>(smem);
         Walk2 w(tid, zp, BLOCK);
         for (int i = tid; i < np * zp; i += BLOCK, w.next()) {
-            const A re = Si[2 * i], im = Si[2 * i + 1];
             T vr = 0, vi = 0;
-            if (w.x < mx) {
-                vr = (T)(SA)re * inv - mean;
-                if (2 * w.p + 1 < my) vi = (T)(SA)im * inv - mean;
+            if constexpr (DIR) {
+                const T* Sf = reinterpret_cast<const T*>(smem);
+                const T re = Sf[2 * i], im = Sf[2 * i + 1];
+                if (w.x < mx) {
+                    vr = re;
+                    if (2 * w.p + 1 < my) vi = im;
+                }
+            } else {
+                const A* Si = reinterpret_cast<const A*>(smem);
+                const A re = Si[2 * i], im = Si[2 * i + 1];
+                if (w.x < mx) {
+                    vr = (T)(SA)re * inv - mean;
+                    if (2 * w.p + 1 < my) vi = (T)(SA)im * inv - mean;
+                }
             }
             S[i] = C{vr, vi};
         }
@@ -554,6 +621,74 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
     }
 }
 
+// Hessian-vector products: with the potential plane phi_K(z) in LDS, every
+// bead j of the P slabs z-P+1 .. z gets its plane-c term of
+//   (H v)_a = sum_b sum_g d^2 W_j(g) / dx_a dx_b v_jb phi_K(g),
+// written (with a plus sign) to fpart[a][c][j]; the weights' second
+// derivatives come from the same compile-time spline pieces (P >= 3).
+template <typename T, int P>
+__device__ __forceinline__ void push_plane_hess(const T* __restrict__ Sr, const uint4* __restrict__ pos,
+                                                const uint32_t* __restrict__ bin_start,
+                                                const uint32_t* __restrict__ qs, const Dims d, int z, int K,
+                                                long long n, const T* __restrict__ vdir, T* __restrict__ fpart,
+                                                int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
+    const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const uint4 q = pos[j];
+            int gx, gy;
+            T wx[P], wy[P], dwx[P], dwy[P], ddx[P], ddy[P];
+            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
+            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+            const T fx = stencil_fraction<T>(q.x - sx, d.mx, P), fy = stencil_fraction<T>(q.y - sy, d.my, P);
+            spline_dweights<T, P>(fx, dwx);
+            spline_dweights<T, P>(fy, dwy);
+            spline_d2weights<T, P>(fx, ddx);
+            spline_d2weights<T, P>(fy, ddy);
+            const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+            T wzs[P], dwzs[P], ddzs[P];  // only entry c survives unrolling
+            spline_weights<T, P>(fz, wzs);
+            spline_dweights<T, P>(fz, dwzs);
+            spline_d2weights<T, P>(fz, ddzs);
+            const RowOffsets<P> ro(gy, pr);
+            // node sums of phi against products of 1-D factors: s_ab = sum w^(a)_x w^(b)_y phi
+            T s00 = 0, s10 = 0, s01 = 0, s20 = 0, s11 = 0, s02 = 0;
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const T* row = Sr + ro.o[b] + 2 * gx;
+                T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+                for (int a2 = 0; a2 < P; ++a2) {
+                    const T v = row[2 * a2];
+                    r0 += wx[a2] * v;
+                    r1 += dwx[a2] * v;
+                    r2 += ddx[a2] * v;
+                }
+                s00 += wy[b] * r0;
+                s10 += wy[b] * r1;
+                s01 += dwy[b] * r0;
+                s20 += wy[b] * r2;
+                s11 += dwy[b] * r1;
+                s02 += ddy[b] * r0;
+            }
+            const T wz = wzs[c], dwz = dwzs[c], ddz = ddzs[c];
+            const T hxx = ihx * ihx * wz * s20, hyy = ihy * ihy * wz * s02, hzz = ihz * ihz * ddz * s00;
+            const T hxy = ihx * ihy * wz * s11, hxz = ihx * ihz * dwz * s10, hyz = ihy * ihz * dwz * s01;
+            const T vx = vdir[4 * (long long)j], vy = vdir[4 * (long long)j + 1], vz = vdir[4 * (long long)j + 2];
+            fpart[((long long)0 * P + c) * n + j] = hxx * vx + hxy * vy + hxz * vz;
+            fpart[((long long)1 * P + c) * n + j] = hxy * vx + hyy * vy + hyz * vz;
+            fpart[((long long)2 * P + c) * n + j] = hxz * vx + hyz * vy + hzz * vz;
+        }
+    }
+}
+
 // Inverse (one workgroup per plane z, species K and axis a = x, y, z): build
 // the half spectrum of d_a phi_K on plane z (row pitch hxp), inverse FFT
 // along y, then complex-to-real along x with rows 2p and 2p+1 carried as the
@@ -569,13 +704,16 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
 //
 // BATCH (ik route only): one launch for all members of a batch, as for the
 // spread.
-template <typename T, int BLOCK, int P, bool AD, bool BATCH = false>
+//
+// HESS (with AD): the potential plane's Hessian-vector terms (push_plane_hess,
+// vdir) instead of the force terms.
+template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
              long long* __restrict__ fsum_part, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
-             int parity) {
+             int parity, const T* __restrict__ vdir) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
@@ -719,7 +857,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
             }
             __syncthreads();
         }
-        if constexpr (AD) {
+        if constexpr (AD && HESS) {
+            push_plane_hess<T, P>(Sr, pos, bin_start, qs, d, z, K, n, vdir, fpart, tid, BLOCK);
+        } else if constexpr (AD) {
             __shared__ long long fred[3 * (BLOCK / 64)];
             long long fsum[3] = {0, 0, 0};
             push_plane_ad<T, P>(Sr, pos, bin_start, qs, d, z, K, n, fpart, fsum, tid, BLOCK);
@@ -1533,7 +1673,7 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
         hipLaunchKernelGGL((k_spread_xy<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                            L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                            (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part,
-                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr);
     });
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S, bool ad) {
@@ -1542,11 +1682,13 @@ template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& 
         if (ad)
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
-                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
         else
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, false>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
-                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
     });
 }
 
@@ -1661,17 +1803,17 @@ hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_sr
 
 // ------------------------------------------------------------ batched step
 
-template <typename T> static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, size_t lz) {
+template <typename T, int PB>
+static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, size_t lz) {
     const RepDesc* R = B.reps;
     const uint64_t so = (uint64_t)s;
     const int par = s & 1;
-    constexpr int PB = 512;  // plane workgroups of every member
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
         hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
                            (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, 1, so, (long long*)nullptr, R, B.plane,
-                           par);
+                           par, (const T*)nullptr);
         if (L.ph.elec)
             hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
@@ -1685,7 +1827,7 @@ template <typename T> static void batch_step_t(const Launch& L, const BatchMaps&
         hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
                            (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
                            (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
-                           (long long*)nullptr, R, B.c2r, par);
+                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr);
         hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                            (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
                            L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,
@@ -1700,8 +1842,13 @@ template <typename T> static void batch_step_t(const Launch& L, const BatchMaps&
 }
 
 hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z) {
-    if (L.precision == 0) batch_step_t<float>(L, B, s, lds_plane, lds_z);
-    else batch_step_t<double>(L, B, s, lds_plane, lds_z);
+    if (L.precision == 0) {
+        if (B.plane_block == 256) batch_step_t<float, 256>(L, B, s, lds_plane, lds_z);
+        else batch_step_t<float, 512>(L, B, s, lds_plane, lds_z);
+    } else {
+        if (B.plane_block == 256) batch_step_t<double, 256>(L, B, s, lds_plane, lds_z);
+        else batch_step_t<double, 512>(L, B, s, lds_plane, lds_z);
+    }
     return hipGetLastError();
 }
 
@@ -1712,6 +1859,8 @@ template <typename T> static hipError_t attr_batch(const Launch& L, size_t lp, s
     };
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
+        set((const void*)k_spread_xy<T, 256, P, true>, lp);
+        set((const void*)k_xy_c2r<T, 256, P, false, true>, lp);
         set((const void*)k_spread_xy<T, 512, P, true>, lp);
         set((const void*)k_xy_c2r<T, 512, P, false, true>, lp);
     });
@@ -1778,6 +1927,121 @@ hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, i
     return hipGetLastError();
 }
 
+// H v accumulation in sorted order: acc = (first ? bond term : acc) + sign * sum of
+// the P plane partials per axis; the bond term of U = k_b sum |d|^2 is
+// 2 k_b sum_partners (v_j - v_p).
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_hvp_accum(const T* __restrict__ fpart, long long n,
+                                                   const T* __restrict__ vdir, const int32_t* __restrict__ nbr,
+                                                   int deg, double bond_k, T* __restrict__ acc, int first, T sign) {
+    const long long j = blockIdx.x * 256LL + threadIdx.x;
+    if (j >= n) return;
+    T r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T sa = 0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
+        r[a] = (first ? (T)0 : acc[4 * j + a]) + sign * sa;
+    }
+    if (first) {
+        const T kb2 = (T)(2.0 * bond_k);
+        for (int b = 0; b < deg; ++b) {
+            const int p = nbr[j * deg + b];
+            if (p < 0) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) r[a] += kb2 * (vdir[4 * j + a] - vdir[4 * (long long)p + a]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) acc[4 * j + a] = r[a];
+    acc[4 * j + 3] = (T)0;
+}
+
+template <typename T>
+static void bead_vectors_t(const Launch& L, DeviceState& S, T* sorted, int op, void* v, int dtype) {
+    const unsigned g = blocks_for(S.n, 256);
+    if (dtype == 0) {
+        if (op == 0)
+            hipLaunchKernelGGL((k_velocities<T, float, 0>), dim3(g), dim3(256), 0, L.stream, S.pos, sorted, (T*)nullptr,
+                               (float*)v, S.n);
+        else
+            hipLaunchKernelGGL((k_velocities<T, float, 1>), dim3(g), dim3(256), 0, L.stream, S.pos, sorted, (T*)nullptr,
+                               (float*)v, S.n);
+    } else {
+        if (op == 0)
+            hipLaunchKernelGGL((k_velocities<T, double, 0>), dim3(g), dim3(256), 0, L.stream, S.pos, sorted,
+                               (T*)nullptr, (double*)v, S.n);
+        else
+            hipLaunchKernelGGL((k_velocities<T, double, 1>), dim3(g), dim3(256), 0, L.stream, S.pos, sorted,
+                               (T*)nullptr, (double*)v, S.n);
+    }
+}
+
+template <typename T, int B> static void hvp_b(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
+    bead_vectors_t<T>(L, S, (T*)S.vdir, 0, const_cast<void*>(v), dtype);
+    const unsigned gb = blocks_for(S.n, 256);
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 3) {
+            // second-derivative terms against the potential planes of the counts
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                               L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
+                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)S.vdir);
+            hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1);
+            // the field of the directional counts, gathered with the weight gradients
+            hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                               L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                               (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir);
+        }
+    });
+}
+
+template <typename T, int B> static void hvp_tail(const Launch& L, DeviceState& S, void* out, int dtype) {
+    const unsigned gb = blocks_for(S.n, 256);
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 3) {
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
+                               (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
+            // those partials are -sum grad W delta phi
+            hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1);
+        }
+    });
+    bead_vectors_t<T>(L, S, (T*)S.hacc, 1, out, dtype);
+}
+
+hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
+    if (S.n == 0 || L.order < 3) return hipSuccess;
+    // the potential planes of the counts: spread, k-space pass (noise off)
+    hipError_t e = launch_spread_xy(L, S);
+    if (e == hipSuccess) e = launch_z_kmul(L, S, false);
+    if (e != hipSuccess) return e;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) hvp_b<float, 256>(L, S, v, out, dtype);
+        else hvp_b<float, 512>(L, S, v, out, dtype);
+    } else {
+        if (L.plane_block == 256) hvp_b<double, 256>(L, S, v, out, dtype);
+        else hvp_b<double, 512>(L, S, v, out, dtype);
+    }
+    e = launch_z_kmul(L, S, false);  // Phi of the directional counts
+    if (e != hipSuccess) return e;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) hvp_tail<float, 256>(L, S, out, dtype);
+        else hvp_tail<float, 512>(L, S, out, dtype);
+    } else {
+        if (L.plane_block == 256) hvp_tail<double, 256>(L, S, out, dtype);
+        else hvp_tail<double, 512>(L, S, out, dtype);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_get_positions(const Launch& L, DeviceState& S, void* xyz, int dtype) {
     if (S.n == 0) return hipSuccess;
     const unsigned g = blocks_for(S.n, 256);
@@ -1812,9 +2076,17 @@ template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) 
         if (L.plane_block == 256) {
             set((const void*)k_xy_c2r<T, 256, P, false>);
             set((const void*)k_xy_c2r<T, 256, P, true>);
+            if constexpr (P >= 3) {
+                set((const void*)k_xy_c2r<T, 256, P, true, false, true>);
+                set((const void*)k_spread_xy<T, 256, P, false, true>);
+            }
         } else {
             set((const void*)k_xy_c2r<T, 512, P, false>);
             set((const void*)k_xy_c2r<T, 512, P, true>);
+            if constexpr (P >= 3) {
+                set((const void*)k_xy_c2r<T, 512, P, true, false, true>);
+                set((const void*)k_spread_xy<T, 512, P, false, true>);
+            }
         }
     });
     return e;
