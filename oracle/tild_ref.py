@@ -63,7 +63,7 @@ __all__ = [
     "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
     "trajectory", "structure_factor_exact", "min_image", "gjf_coefficients", "gjf_trajectory",
     "half_step_velocity", "bspline_deriv2", "spread_directional", "gather_hessian_weights",
-    "bond_hessian_vector", "hessian_vector_product", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
+    "bond_hessian_vector", "hessian_vector_product", "density_mse", "em_adjoint", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
 ]
 
 
@@ -611,6 +611,57 @@ def trajectory(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, 
             record(t, x, ev)
         x = em_update(x, ev["F"], ids, t, p)
     return x
+
+
+# --------------------------------------------------------------------------
+# Adjoint of Euler-Maruyama steps (backpropagation through time, fixed noise)
+# --------------------------------------------------------------------------
+
+def density_mse(x: np.ndarray, types: np.ndarray, p: Params, target_a: np.ndarray):
+    """Loss (1/M) sum_g (rho_A(g) - rho*(g))^2 with rho_A = c_A / dV on the mesh (target indexed [x, y, z]),
+    and its gradient by the bead positions, sum_g grad W_i(g) psi(g) with psi = 2 (rho_A - rho*) / (M dV) on
+    species A and 0 on B."""
+    L, M = p.L, p.M
+    dV = float(np.prod(L / M))
+    Mt = float(np.prod(M))
+    c = spread(x, types, L, M, p.order)
+    diff = c[0] / dV - target_a
+    loss = float(np.mean(diff ** 2))
+    psi = np.zeros_like(c)
+    psi[0] = 2.0 * diff / (Mt * dV)
+    return loss, -gather_gradient_weights(x, types, psi, L, M, p.order)
+
+
+def em_adjoint(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, steps: int, loss_and_grad,
+               t0: int = 0):
+    """Loss after ``steps`` Euler-Maruyama steps from x0 (step indices t0 ..), with the exact-gradient force
+    F = -grad E and the noise held fixed, and its gradients by x0, chi and kappa.
+
+    Forward: x_{t+1} = x_t + Pr[(dt/gamma) F(x_t) + sqrt(2 kT dt/gamma) xi_t], Pr removing the mean over beads
+    when the centre-of-mass correction is on.  Backward, from lambda = dL/dx_K:
+        dL/dtheta += (dt/gamma) (Pr lambda) . dF/dtheta(x_t),
+        lambda    <- lambda - (dt/gamma) H(x_t) Pr lambda,
+    for t = K-1 .. 0, H the energy Hessian (dF/dx = -H, symmetric); dF/dchi and dF/dkappa are the forces of
+    the interaction with (chi, kappa) = (1, 0) and (0, 1) (the energy is linear in both).
+    Returns (loss, dL/dx0, {"chi": ..., "kappa": ...})."""
+    mu = p.dt / p.gamma
+    ids = np.arange(x0.shape[0])
+    xs = [np.array(x0, dtype=np.float64)]
+    for t in range(t0, t0 + steps):
+        ev = evaluate(xs[-1], types, bonds, p, want_ad=True)
+        xs.append(em_update(xs[-1], ev["F_nb_ad"] + ev["F_bond"], ids, t, p))
+    loss, lam = loss_and_grad(xs[-1])
+    proj = (lambda v: v - v.mean(axis=0)) if p.com_correct else (lambda v: v)
+    pure = {k: Params(**{**p.__dict__, "chi": float(k == "chi"), "kappa": float(k == "kappa"), "bjerrum": 0.0,
+                         "bond_k": 0.0}) for k in ("chi", "kappa")}
+    grads = {"chi": 0.0, "kappa": 0.0}
+    for t in range(steps - 1, -1, -1):
+        x = xs[t]
+        pl = proj(lam)
+        for k, q in pure.items():
+            grads[k] += mu * float(np.sum(pl * evaluate(x, types, bonds, q, want_ad=True)["F_nb_ad"]))
+        lam = lam - mu * hessian_vector_product(x, types, bonds, p, pl)
+    return loss, lam, grads
 
 
 # --------------------------------------------------------------------------

@@ -431,6 +431,39 @@ def test_bond_hessian_closed_form():
     np.testing.assert_allclose(hb[2], 3.0 * (v[2] - v[1]))
 
 
+def _lamellar_target(p, n_a, period):
+    xg = np.arange(p.grid[0]) * p.L[0] / p.grid[0]
+    prof = n_a / np.prod(p.L) * (1 + 0.5 * np.sin(2 * np.pi * xg / period))
+    return np.broadcast_to(prof[:, None, None], tuple(p.grid)).copy()
+
+
+@pytest.mark.parametrize("com", [True, False])
+def test_em_adjoint_matches_finite_differences(com):
+    """Gradients of a density loss after 6 EM steps (fixed noise) by chi, kappa and along a direction in x0."""
+    p = small_params(dt=0.02, com_correct=com)
+    x, t, b = random_system(40, p, seed=31)
+    target = _lamellar_target(p, int(np.sum(t == 0)), p.L[0] / 2)
+    lg = lambda y, q=p: R.density_mse(y, t, q, target)
+    loss, gx, g = R.em_adjoint(x, t, b, p, 6, lg, t0=3)
+
+    def run(q, y0):
+        y = y0.copy()
+        for s_ in range(3, 9):
+            ev = R.evaluate(y, t, b, q, want_ad=True)
+            y = R.em_update(y, ev["F_nb_ad"] + ev["F_bond"], np.arange(40), s_, q)
+        return R.density_mse(y, t, q, target)[0]
+    assert abs(run(p, x) - loss) < 1e-14 * max(1.0, loss)
+    for k in ("chi", "kappa"):
+        h = 1e-4
+        fd = (run(R.Params(**{**p.__dict__, k: getattr(p, k) + h}), x)
+              - run(R.Params(**{**p.__dict__, k: getattr(p, k) - h}), x)) / (2 * h)
+        assert abs(fd - g[k]) < 1e-6 * max(abs(fd), 1e-3 * loss), (k, fd, g[k])
+    v = np.random.default_rng(8).normal(size=x.shape)
+    e = 1e-5
+    fd = (run(p, x + e * v) - run(p, x - e * v)) / (2 * e)
+    assert abs(fd - np.sum(gx * v)) < 1e-6 * max(abs(fd), 1e-3 * loss)
+
+
 def test_bond_closed_form_across_boundary():
     L = np.array([10.0, 10.0, 10.0])
     x = np.array([[9.8, 5.0, 5.0], [0.3, 5.4, 4.5]])
