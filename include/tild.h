@@ -306,6 +306,22 @@ int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t iters,
                      void* hip_stream, double* ms_per_copy);
 
 /*
+ * Grid access for losses and external fields (differentiable use).  Grid
+ * arrays are [2][M_z][M_y][M_x] (species, then z, y, x with x fastest) in the
+ * context's working precision (float for TILD_FP32, double for TILD_FP64),
+ * host or device memory (on_device).
+ * tild_counts: the assignment counts c_K(g) = sum_{i in K} W_i(g) at the
+ *   current positions (density c_K / dV, Eq. rhohat on the mesh).
+ * tild_field_forces: the forces -sum_g grad W_i(g) psi_{s_i}(g) of a given
+ *   field psi (the gradient of sum_g c_K(g) psi_K(g), i.e. of any loss whose
+ *   derivative by the counts is psi), out [n_beads][3] ABI order, dtype;
+ *   field and out both host or both device memory.  Needs order >= 2.
+ * Host calls synchronise.
+ */
+int tild_counts(tild_ctx* ctx, void* out, int32_t on_device);
+int tild_field_forces(tild_ctx* ctx, const void* field, void* out, int32_t dtype, int32_t on_device);
+
+/*
  * Hessian-vector product of the total energy (mesh energy of Eqs. fh,
  * HelfandP and electrostatics, plus bonds) at the current positions:
  *   out_i = sum_j (d^2 E / dx_i dx_j) v_j

@@ -219,6 +219,37 @@ class Tild:
         v = list(buf)
         return dict(E=v[0], dE_dchi=v[1], dE_dkappa=v[2], dE_da=v[3]), out
 
+    @property
+    def _grid_dtype(self):
+        return np.float32 if self.params.precision == TILD_FP32 else np.float64
+
+    def counts(self, out=None):
+        """Counts c_K(g) at the current positions, (2, M_z, M_y, M_x) in the working precision; ``out`` may be
+        a CUDA tensor of that shape and dtype."""
+        if out is None:
+            g = self.params.grid
+            out = np.empty((2, g[2], g[1], g[0]), dtype=self._grid_dtype)
+        ptr, dev = _ptr(out)
+        self._check(self._lib.tild_counts(self._ctx, ptr, dev))
+        return out
+
+    def field_forces(self, field, out=None, dtype=np.float64):
+        """Forces -sum_g grad W_i(g) psi_{s_i}(g) of a field psi (2, M_z, M_y, M_x) in the working precision."""
+        if not _is_torch(field):
+            field = np.ascontiguousarray(field, dtype=self._grid_dtype)
+            if out is None:
+                out = np.empty((self.n, 3), dtype=dtype)
+        elif out is None:
+            import torch
+            out = torch.empty((self.n, 3), dtype=torch.float64 if dtype == np.float64 else torch.float32,
+                              device=field.device)
+        pf, df = _ptr(field)
+        po, do = _ptr(out)
+        if df != do:
+            raise ValueError("field and out must both be host arrays or both device tensors")
+        self._check(self._lib.tild_field_forces(self._ctx, pf, po, _dtype_code(out), df))
+        return out
+
     def hvp(self, v, out=None):
         """Hessian-vector product H v of the total energy at the current positions ([n][3], ABI order);
         v and out both host arrays or both CUDA tensors (out defaults to a new array of v's dtype)."""

@@ -748,6 +748,43 @@ TILD_API int tild_energy(tild_ctx* c, double out[8]) {
     return check_flag(c);
 }
 
+TILD_API int tild_counts(tild_ctx* c, void* out, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if (!out) return c->fail(TILD_EINVAL, "counts: out is NULL");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t bytes = 2 * (size_t)c->L.d.m * (c->L.precision == 0 ? 4 : 8);
+    void* dst = on_device ? out : c->S.zout;  // zout holds at least 2 M reals
+    hipError_t e = launch_counts(c->L, c->S, dst);
+    if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, c->S.zout, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "counts");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
+TILD_API int tild_field_forces(tild_ctx* c, const void* field, void* out, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if (!field || (!out && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "field_forces: NULL array or bad dtype");
+    if (c->L.order < 2) return c->fail(TILD_EINVAL, "field_forces: needs order >= 2");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t gbytes = 2 * (size_t)c->L.d.m * (c->L.precision == 0 ? 4 : 8);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    hipError_t e = hipSuccess;
+    const void* src = field;
+    if (!on_device) {
+        e = hipMemcpyAsync(c->S.zout, field, gbytes, hipMemcpyHostToDevice, c->L.stream);
+        src = c->S.zout;
+    }
+    void* dst = on_device ? out : c->staging;
+    if (e == hipSuccess) e = launch_field_forces(c->L, c->S, src, dst, dtype);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(out, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "field_forces");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
 TILD_API int tild_hvp(tild_ctx* c, const void* v, void* out, int32_t dtype, int32_t on_device) {
     if (!c) return TILD_EINVAL;
     if (((!v || !out) && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))

@@ -165,6 +165,11 @@ hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, i
 // v ([n][3] ABI order, dtype) -> out ([n][3] ABI order, dtype), through vdir
 // and hacc (order >= 3).
 hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype);
+// Counts c_K(g) ([2][mz][my][mx], x fastest, working precision) to device memory.
+hipError_t launch_counts(const Launch& L, DeviceState& S, void* out);
+// Forces -sum_g grad W_i(g) psi_{s_i}(g) of a given field psi ([2][mz][my][mx],
+// working precision, device) to out ([n][3] ABI order, dtype); order >= 2.
+hipError_t launch_field_forces(const Launch& L, DeviceState& S, const void* field, void* out, int dtype);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 // One step of every member of a batch (ik route, Euler-Maruyama, all members

@@ -323,13 +323,16 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
 //
 // DIR: the directional counts sum_j grad W_j . v_j (vdir) instead of the
 // counts, accumulated in floating point, with no mean to subtract and no noise.
-template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false>
+//
+// COUNTS: write the counts c_K(z) themselves (real, [2][mz][my][mx], x
+// fastest) to cout and stop before the transforms.
+template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false, bool COUNTS = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
                 uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part,
                 const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
-                const T* __restrict__ vdir) {
+                const T* __restrict__ vdir, T* __restrict__ cout) {
     using C = cplx<T>;
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
@@ -407,6 +410,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
             __syncthreads();
         }
         fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
+    }
+    if constexpr (COUNTS) {
+        const T inv = (T)1 / scale;
+        const A* Si = reinterpret_cast<const A*>(smem);
+        T* dst = cout + ((long long)K * d.mz + z) * (long long)my * mx;
+        for (int i = tid; i < my * mx; i += BLOCK) {
+            const int y = i / mx, x = i - y * mx;
+            dst[i] = (T)(SA)Si[__mul24(y >> 1, 4 * hxp) + (y & 1) + 2 * x] * inv;
+        }
+        return;
     }
     {
         // counts (minus their mean) of the real cells; zero elsewhere
@@ -707,13 +720,17 @@ __device__ __forceinline__ void push_plane_hess(const T* __restrict__ Sr, const 
 //
 // HESS (with AD): the potential plane's Hessian-vector terms (push_plane_hess,
 // vdir) instead of the force terms.
-template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false>
+//
+// FIELD (with AD): interpolate a given real field psi_K ([2][mz][my][mx],
+// x fastest) instead of transforming a spectrum: the forces
+// -sum_g grad W_i(g) psi_{s_i}(g).
+template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false, bool FIELD = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
              long long* __restrict__ fsum_part, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
-             int parity, const T* __restrict__ vdir) {
+             int parity, const T* __restrict__ vdir, const T* __restrict__ field) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
@@ -747,96 +764,105 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     C* twl = S + d.npg * zp;
     const int ntw = d.mx + d.my + d.mz;
     {
-        C twv[3];  // twiddles, loaded with the plane and stored after it
-#pragma unroll
-        for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
-        // the plane's half spectrum, eighteen loads in flight per thread
-        const C* src = zout + ((long long)(a < 2 || AD ? K : 2 + K) * d.mz + z) * d.hplane;
-        constexpr int LB = 18;
-        const int tot = my * hx;
-        Walk2 w(tid, hx, BLOCK);
-        for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
-            C v[LB];
-#pragma unroll
-            for (int u = 0; u < LB; ++u) {
-                const int i = i0 + u * BLOCK;
-                v[u] = i < tot ? src[i] : C{0, 0};
+        if constexpr (FIELD) {
+            T* Sf = reinterpret_cast<T*>(smem);
+            const T* src = field + ((long long)K * d.mz + z) * (long long)my * mx;
+            for (int i = tid; i < my * mx; i += BLOCK) {
+                const int y = i / mx, x = i - y * mx;
+                Sf[__mul24(y >> 1, 4 * hxp) + (y & 1) + 2 * x] = src[i];
             }
+        } else {
+            C twv[3];  // twiddles, loaded with the plane and stored after it
 #pragma unroll
-            for (int u = 0; u < LB; ++u) {
-                if (i0 + u * BLOCK < tot) {
-                    const int ky = w.p, kx = w.x;
-                    C vv = v[u];
-                    if (a == 0) {
-                        const T k = (2 * kx == mx) ? (T)0 : kfx * (T)kx;
-                        vv = C{-k * vv.y, k * vv.x};
-                    } else if (a == 1) {
-                        const int ny = ky > my / 2 ? ky - my : ky;
-                        const T k = (2 * ky == my) ? (T)0 : kfy * (T)ny;
-                        vv = C{-k * vv.y, k * vv.x};
-                    }
-                    S[hidx(d, ky, kx)] = vv;
+            for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
+            // the plane's half spectrum, eighteen loads in flight per thread
+            const C* src = zout + ((long long)(a < 2 || AD ? K : 2 + K) * d.mz + z) * d.hplane;
+            constexpr int LB = 18;
+            const int tot = my * hx;
+            Walk2 w(tid, hx, BLOCK);
+            for (int i0 = tid; i0 < tot; i0 += LB * BLOCK) {
+                C v[LB];
+#pragma unroll
+                for (int u = 0; u < LB; ++u) {
+                    const int i = i0 + u * BLOCK;
+                    v[u] = i < tot ? src[i] : C{0, 0};
                 }
-                w.next();
-            }
-        }
 #pragma unroll
-        for (int u = 0; u < 3; ++u)
-            if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
-        __syncthreads();
-        // For even mx the columns kx = 0 and kx = mx/2 transform back to real
-        // rows; one y transform of Z = G_0 + i G_N gives both.
-        const bool pair_n = (mx & 1) == 0 && hx > 1;
-        if (pair_n) {
-            for (int y = tid; y < my; y += BLOCK) {
-                const C g0 = S[hidx(d, y, 0)], gn = S[hidx(d, y, hx - 1)];
-                S[hidx(d, y, 0)] = C{g0.x - gn.y, g0.y + gn.x};
-            }
-            __syncthreads();
-        }
-        if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
-        else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
-        __syncthreads();
-        if (pair_n) {
-            for (int y = tid; y < my; y += BLOCK) {
-                const C zv = S[hidx(d, y, 0)];
-                S[hidx(d, y, 0)] = C{zv.x, (T)0};
-                S[hidx(d, y, hx - 1)] = C{zv.y, (T)0};
-            }
-            __syncthreads();
-        }
-        {
-            const int G = px.group, lane = tid % G;
-            for (int p = tid / G; p < np; p += BLOCK / G) {
-                const int base = p * zp;
-                const bool odd = 2 * p + 1 < my;
-                C rz[kPairItems];
-#pragma unroll
-                for (int u = 0; u < kPairItems; ++u) {
-                    const int x = lane + u * G;
-                    if (x < mx) {
-                        C A, B;
-                        if (x < hx) {
-                            A = S[hidx(d, 2 * p, x)];
-                            B = odd ? S[hidx(d, 2 * p + 1, x)] : C{0, 0};
-                        } else {
-                            const int xs = mx - x;
-                            const C a0 = S[hidx(d, 2 * p, xs)];
-                            const C b0 = odd ? S[hidx(d, 2 * p + 1, xs)] : C{0, 0};
-                            A = C{a0.x, -a0.y};
-                            B = C{b0.x, -b0.y};
+                for (int u = 0; u < LB; ++u) {
+                    if (i0 + u * BLOCK < tot) {
+                        const int ky = w.p, kx = w.x;
+                        C vv = v[u];
+                        if (a == 0) {
+                            const T k = (2 * kx == mx) ? (T)0 : kfx * (T)kx;
+                            vv = C{-k * vv.y, k * vv.x};
+                        } else if (a == 1) {
+                            const int ny = ky > my / 2 ? ky - my : ky;
+                            const T k = (2 * ky == my) ? (T)0 : kfy * (T)ny;
+                            vv = C{-k * vv.y, k * vv.x};
                         }
-                        rz[u] = C{A.x - B.y, A.y + B.x};
+                        S[hidx(d, ky, kx)] = vv;
                     }
+                    w.next();
                 }
-                wave_sync();
+            }
 #pragma unroll
-                for (int u = 0; u < kPairItems; ++u) {
-                    const int x = lane + u * G;
-                    if (x < mx) S[base + x] = rz[u];
+            for (int u = 0; u < 3; ++u)
+                if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+            __syncthreads();
+            // For even mx the columns kx = 0 and kx = mx/2 transform back to real
+            // rows; one y transform of Z = G_0 + i G_N gives both.
+            const bool pair_n = (mx & 1) == 0 && hx > 1;
+            if (pair_n) {
+                for (int y = tid; y < my; y += BLOCK) {
+                    const C g0 = S[hidx(d, y, 0)], gn = S[hidx(d, y, hx - 1)];
+                    S[hidx(d, y, 0)] = C{g0.x - gn.y, g0.y + gn.x};
                 }
-                wave_sync();
-                fft_line<C, 1>(S, base, 1, px, twl, lane);
+                __syncthreads();
+            }
+            if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
+            else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
+            __syncthreads();
+            if (pair_n) {
+                for (int y = tid; y < my; y += BLOCK) {
+                    const C zv = S[hidx(d, y, 0)];
+                    S[hidx(d, y, 0)] = C{zv.x, (T)0};
+                    S[hidx(d, y, hx - 1)] = C{zv.y, (T)0};
+                }
+                __syncthreads();
+            }
+            {
+                const int G = px.group, lane = tid % G;
+                for (int p = tid / G; p < np; p += BLOCK / G) {
+                    const int base = p * zp;
+                    const bool odd = 2 * p + 1 < my;
+                    C rz[kPairItems];
+#pragma unroll
+                    for (int u = 0; u < kPairItems; ++u) {
+                        const int x = lane + u * G;
+                        if (x < mx) {
+                            C A, B;
+                            if (x < hx) {
+                                A = S[hidx(d, 2 * p, x)];
+                                B = odd ? S[hidx(d, 2 * p + 1, x)] : C{0, 0};
+                            } else {
+                                const int xs = mx - x;
+                                const C a0 = S[hidx(d, 2 * p, xs)];
+                                const C b0 = odd ? S[hidx(d, 2 * p + 1, xs)] : C{0, 0};
+                                A = C{a0.x, -a0.y};
+                                B = C{b0.x, -b0.y};
+                            }
+                            rz[u] = C{A.x - B.y, A.y + B.x};
+                        }
+                    }
+                    wave_sync();
+#pragma unroll
+                    for (int u = 0; u < kPairItems; ++u) {
+                        const int x = lane + u * G;
+                        if (x < mx) S[base + x] = rz[u];
+                    }
+                    wave_sync();
+                    fft_line<C, 1>(S, base, 1, px, twl, lane);
+                }
             }
         }
         __syncthreads();
@@ -1673,7 +1699,7 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
         hipLaunchKernelGGL((k_spread_xy<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                            L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                            (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part,
-                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr);
+                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)nullptr);
     });
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S, bool ad) {
@@ -1683,12 +1709,12 @@ template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& 
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
                                S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
         else
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, false>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
                                L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
     });
 }
 
@@ -1813,7 +1839,7 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
                            (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, 1, so, (long long*)nullptr, R, B.plane,
-                           par, (const T*)nullptr);
+                           par, (const T*)nullptr, (T*)nullptr);
         if (L.ph.elec)
             hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
@@ -1827,7 +1853,7 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
                            (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
                            (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
-                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr);
+                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr);
         hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                            (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
                            L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,
@@ -1988,14 +2014,14 @@ template <typename T, int B> static void hvp_b(const Launch& L, DeviceState& S, 
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
                                L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)S.vdir);
+                               (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr);
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
                                (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1);
             // the field of the directional counts, gathered with the weight gradients
             hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                                L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                                (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
-                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir);
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr);
         }
     });
 }
@@ -2008,13 +2034,60 @@ template <typename T, int B> static void hvp_tail(const Launch& L, DeviceState& 
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
                                S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
             // those partials are -sum grad W delta phi
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
                                (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1);
         }
     });
     bead_vectors_t<T>(L, S, (T*)S.hacc, 1, out, dtype);
+}
+
+template <typename T, int B> static void counts_b(const Launch& L, DeviceState& S, void* out) {
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_spread_xy<T, B, P, false, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                           L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                           (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part, (const RepDesc*)nullptr,
+                           (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)out);
+    });
+}
+
+hipError_t launch_counts(const Launch& L, DeviceState& S, void* out) {
+    if (L.precision == 0) {
+        if (L.plane_block == 256) counts_b<float, 256>(L, S, out);
+        else counts_b<float, 512>(L, S, out);
+    } else {
+        if (L.plane_block == 256) counts_b<double, 256>(L, S, out);
+        else counts_b<double, 512>(L, S, out);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int B> static void field_b(const Launch& L, DeviceState& S, const void* field) {
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 2)
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, false, true>), dim3(L.d.mz, 2), dim3(B),
+                               plane_lds_bytes(L), L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py,
+                               (const cplx<T>*)S.tw, L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part,
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr,
+                               (const T*)field);
+    });
+}
+
+hipError_t launch_field_forces(const Launch& L, DeviceState& S, const void* field, void* out, int dtype) {
+    if (L.order < 2) return hipErrorInvalidValue;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) field_b<float, 256>(L, S, field);
+        else field_b<float, 512>(L, S, field);
+    } else {
+        if (L.plane_block == 256) field_b<double, 256>(L, S, field);
+        else field_b<double, 512>(L, S, field);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_update(L, S, 1, 0, out, dtype, 1u);
+    return e;
 }
 
 hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
@@ -2080,6 +2153,8 @@ template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) 
                 set((const void*)k_xy_c2r<T, 256, P, true, false, true>);
                 set((const void*)k_spread_xy<T, 256, P, false, true>);
             }
+            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 256, P, true, false, false, true>);
+            set((const void*)k_spread_xy<T, 256, P, false, false, true>);
         } else {
             set((const void*)k_xy_c2r<T, 512, P, false>);
             set((const void*)k_xy_c2r<T, 512, P, true>);
@@ -2087,6 +2162,8 @@ template <typename T> static hipError_t attr_plane(const Launch& L, size_t lds) 
                 set((const void*)k_xy_c2r<T, 512, P, true, false, true>);
                 set((const void*)k_spread_xy<T, 512, P, false, true>);
             }
+            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 512, P, true, false, false, true>);
+            set((const void*)k_spread_xy<T, 512, P, false, false, true>);
         }
     });
     return e;

@@ -1,0 +1,119 @@
+"""GPU checks of the differentiable-simulation pieces: mesh counts and
+given-field forces against the oracle, and backpropagation through
+Euler-Maruyama steps (paper_2302_02474_amd.adjoint) against the oracle's
+adjoint and against finite differences with the noise held fixed."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2302_02474_amd as T
+from paper_2302_02474_amd import adjoint as A
+from oracle import tild_ref as R
+from synth import make_custom, make_melt, snap_to_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _oracle_params(m, **kw):
+    return R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
+                    chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed, **kw)
+
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-12), (T.TILD_FP32, 1e-6)])
+def test_counts_and_field_forces_match_oracle(precision, tol):
+    m = make_custom(30, 5, 5, (5.0, 6.0, 7.5), (10, 12, 18), 4, 0.8, 3.0, seed_init=900)
+    x = snap_to_lattice(m.x, m.box)
+    t = T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, precision=precision),
+               m.types, m.bonds)
+    t.set_positions(x)
+    c = t.counts()
+    ref = R.spread(x, m.types, m.box, m.grid, m.order).transpose(0, 3, 2, 1)  # to [K][z][y][x]
+    assert np.abs(c - ref).max() <= tol * max(1.0, np.abs(ref).max())
+    psi = np.random.default_rng(2).normal(size=ref.shape)
+    f = t.field_forces(psi.astype(c.dtype))
+    fr = R.gather_gradient_weights(x, m.types, psi.astype(c.dtype).astype(np.float64).transpose(0, 3, 2, 1),
+                                   m.box, m.grid, m.order)
+    t.close()
+    err = rel(f, fr)
+    say(f"[adj] counts max err {np.abs(c - ref).max():.2e}, field forces rel err {err:.2e}")
+    assert err <= max(tol, 1e-12) * 10
+
+
+def _lamellar(m, period):
+    nz, ny, nx = int(m.grid[2]), int(m.grid[1]), int(m.grid[0])
+    xg = np.arange(nx) * m.box[0] / nx
+    n_a = int(np.sum(m.types == 0))
+    prof = n_a / np.prod(m.box) * (1 + 0.5 * np.sin(2 * np.pi * xg / period))
+    return np.broadcast_to(prof[None, None, :], (nz, ny, nx)).copy()
+
+
+def test_em_adjoint_matches_oracle_fp64():
+    import torch
+    m = make_custom(30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0, seed_init=901, dt=0.02)
+    x0 = snap_to_lattice(m.x, m.box)
+    target = _lamellar(m, 3.0)
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      T.TILD_FP64, True, "analytic", "ad")
+    t = T.Tild(p, m.types, m.bonds)
+    tt = torch.from_numpy(target).cuda()
+    loss, gx, g = A.em_adjoint(t, x0, 6, lambda c: A.density_mse(c, tt), checkpoint=4, t0=3)
+    t.close()
+    po = _oracle_params(m, com_correct=True)
+    to = target.transpose(2, 1, 0)  # oracle grids are [x][y][z]
+    lo, gxo, go = R.em_adjoint(x0, m.types, m.bonds, po, 6, lambda y: R.density_mse(y, m.types, po, to), t0=3)
+    say(f"[adj] loss {loss:.12g} oracle {lo:.12g}; dL/dchi {g['chi']:.8g} oracle {go['chi']:.8g}; "
+        f"dL/dkappa {g['kappa']:.8g} oracle {go['kappa']:.8g}")
+    assert abs(loss - lo) < 1e-9 * abs(lo)
+    for k in ("chi", "kappa"):
+        assert abs(g[k] - go[k]) < 1e-6 * abs(go[k]), k
+    assert rel(gx.cpu().numpy(), gxo) < 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-4), (T.TILD_FP32, 3e-2)])
+def test_em_adjoint_finite_differences_differentiation_workload(precision, tol):
+    """The 80,992-bead A16B16 melt at 64^3: 50 steps with checkpoints every 10, loss against a lamellar
+    target of period 10; dL/dchi against central differences with the same noise."""
+    import torch
+    m = make_melt(4)
+    target = torch.from_numpy(_lamellar(m, 10.0)).cuda()
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      precision, True, "analytic", "ad")
+    t = T.Tild(p, m.types, m.bonds)
+    loss, gx, g = A.em_adjoint(t, m.x, 50, lambda c: A.density_mse(c, target), checkpoint=10, t0=0)
+
+    def run(chi):
+        t.set_interaction(chi, m.kappa, m.smear_a)
+        t.set_positions(m.x)
+        t.step_count = 0
+        t.step(50)
+        return A.density_mse(t, target)[0]
+    # central differences at h and 2h, combined (Richardson) to remove the O(h^2) term.  The positions live
+    # on a 32-bit lattice (L / 2^32), so each run's loss carries rounding of order 1e-9: h is taken large
+    # enough that this stays near 1e-6 of the derivative, and the bound allows 1e-4 (FP64)
+    h = 1e-2 * m.chi
+    d1 = (run(m.chi + h) - run(m.chi - h)) / (2 * h)
+    d2 = (run(m.chi + 2 * h) - run(m.chi - 2 * h)) / (4 * h)
+    fd = (4 * d1 - d2) / 3
+    t.close()
+    say(f"[adj] 80,992 beads, 50 steps: loss {loss:.8g}, dL/dchi adjoint {g['chi']:.10g} "
+        f"FD {fd:.10g} (h: {d1:.10g}, 2h: {d2:.10g})")
+    assert abs(g["chi"] - fd) < tol * abs(fd)
