@@ -969,7 +969,8 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
         blk = (int)(e & 0xffffu);
         nblk = R.n_zblocks;
     } else {
-        blk = blockIdx.x;
+        // neighbouring column blocks share cache lines at their edges: keep them on one XCD (own L2)
+        blk = xcd_contiguous(blockIdx.x, gridDim.x);
         nblk = gridDim.x;
     }
     if (noise_part && blk == nblk - 1) {
