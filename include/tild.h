@@ -235,6 +235,17 @@ int tild_step(tild_ctx* ctx, int64_t n_steps);
 int tild_forces(tild_ctx* ctx, void* out, int32_t dtype, int32_t on_device, uint32_t parts);
 
 /*
+ * Non-bonded forces (the context's route) at the current positions with chi
+ * and kappa replaced by the given values; the smearing, the kernel and the
+ * context's own parameters are unchanged, and with_charges = 0 leaves the
+ * electrostatic part out.  The forces are linear in chi and kappa, so
+ * (1, 0, 0) and (0, 1, 0) give dF/dchi and dF/dkappa (adjoints through time
+ * steps).  out as for tild_forces.
+ */
+int tild_interaction_forces(tild_ctx* ctx, double chi, double kappa, int32_t with_charges, void* out,
+                            int32_t dtype, int32_t on_device);
+
+/*
  * Energies (kT) and virial at the current positions, accumulated in float64:
  *   out[0] E_bond, out[1] E_chi, out[2] E_kappa, out[3] E_total,
  *   out[4..6] W_xx, W_yy, W_zz with W_aa = -L_a dE/dL_a at fixed scaled

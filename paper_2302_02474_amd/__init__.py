@@ -196,6 +196,16 @@ class Tild:
         self._check(self._lib.tild_forces(self._ctx, ptr, _dtype_code(out), dev, int(parts)))
         return out
 
+    def interaction_forces(self, chi: float, kappa: float, with_charges: bool = True, out=None,
+                           dtype=np.float64):
+        """Non-bonded forces with chi and kappa replaced (tild_interaction_forces)."""
+        if out is None:
+            out = np.empty((self.n, 3), dtype=dtype)
+        ptr, dev = _ptr(out)
+        self._check(self._lib.tild_interaction_forces(self._ctx, float(chi), float(kappa), int(bool(with_charges)),
+                                                      ptr, _dtype_code(out), dev))
+        return out
+
     def energy(self) -> Dict[str, object]:
         buf = (ctypes.c_double * 8)()
         self._check(self._lib.tild_energy(self._ctx, buf))

@@ -31,7 +31,7 @@ EXPORTS = [
     "tild_get_velocities", "tild_step", "tild_forces",
     "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
-    "tild_hvp", "tild_counts", "tild_field_forces", "tild_batch_create", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
+    "tild_hvp", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
 ]
 
 
@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_kernel_name.restype = ctypes.c_char_p
     lib.tild_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, vp, P(ctypes.c_double)]
     lib.tild_stream_copy.restype = ctypes.c_int
+    lib.tild_interaction_forces.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, i32, i32]
+    lib.tild_interaction_forces.restype = ctypes.c_int
     lib.tild_counts.argtypes = [vp, vp, i32]
     lib.tild_counts.restype = ctypes.c_int
     lib.tild_field_forces.argtypes = [vp, vp, vp, i32, i32]

@@ -12,8 +12,8 @@ the adjoint of a loss L(x_K) runs backwards as
 for t = K-1 .. 0, from lambda = dL/dx_K.  Positions are kept every
 ``checkpoint`` steps and each segment is recomputed once on the way back.
 The energy is linear in chi and kappa, so dF/dchi and dF/dkappa are the
-forces of the interaction with (chi, kappa) = (1, 0) and (0, 1), less those
-at (0, 0) (which hold any electrostatic part).
+forces of the interaction with (chi, kappa) = (1, 0) and (0, 1) and no
+charges (tild_interaction_forces).
 
 Every array stays on the device (torch CUDA tensors); the library's kernels
 do the spreads, transforms, gathers and Hessian products.
@@ -25,7 +25,7 @@ from typing import Callable, Dict, Tuple
 
 import numpy as np
 
-from . import TILD_COM_CORRECT, TILD_FORCE_AD, TILD_FP32, TILD_PART_NONBONDED, Tild
+from . import TILD_COM_CORRECT, TILD_FORCE_AD, TILD_FP32, Tild
 
 
 def _torch():
@@ -66,7 +66,6 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
         raise ValueError("em_adjoint needs a context on the exact-gradient route (force='ad')")
     mu = p.dt / p.gamma
     com = bool(p.flags & TILD_COM_CORRECT)
-    chi, kappa, a = p.chi, p.kappa, p.smear_a
     t0 = tild.step_count if t0 is None else int(t0)
     x0 = torch.as_tensor(np.asarray(x0) if not hasattr(x0, "is_cuda") else x0, dtype=torch.float64).cuda()
 
@@ -87,7 +86,7 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
         ck[done] = positions()
     loss, lam = loss_grad(tild)
     lam = lam.double()
-    grads = {"chi": 0.0, "kappa": 0.0}
+    acc = {k: torch.zeros((), dtype=torch.float64, device="cuda") for k in ("chi", "kappa")}
     f = torch.empty((tild.n, 3), dtype=torch.float64, device="cuda")
     starts = sorted(ck)[:-1]
     try:
@@ -102,17 +101,11 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
             for t in range(s1 - 1, s0 - 1, -1):
                 tild.set_positions(xs[t - s0])
                 pl = lam - lam.mean(dim=0, keepdim=True) if com else lam
-                fk = {}
-                for name, (cc, kk) in (("chi", (1.0, 0.0)), ("kappa", (0.0, 1.0)), ("none", (0.0, 0.0))):
-                    tild.set_interaction(cc, kk, a)
-                    tild.forces(TILD_PART_NONBONDED, out=f)
-                    fk[name] = f.clone()
-                tild.set_interaction(chi, kappa, a)
-                for name in ("chi", "kappa"):
-                    grads[name] += mu * float((pl * (fk[name] - fk["none"])).sum())
+                for name, (cc, kk) in (("chi", (1.0, 0.0)), ("kappa", (0.0, 1.0))):
+                    tild.interaction_forces(cc, kk, with_charges=False, out=f)
+                    acc[name] += (pl * f).sum()
                 lam = lam - mu * tild.hvp(pl.contiguous())
     finally:
-        tild.set_interaction(chi, kappa, a)
         tild.set_positions(ck[steps])
         tild.step_count = t0 + steps
-    return loss, lam, grads
+    return loss, lam, {k: mu * float(v) for k, v in acc.items()}

@@ -735,6 +735,31 @@ TILD_API int tild_forces(tild_ctx* c, void* out, int32_t dtype, int32_t on_devic
     return TILD_OK;
 }
 
+TILD_API int tild_interaction_forces(tild_ctx* c, double chi, double kappa, int32_t with_charges, void* out,
+                                    int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if ((!out && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64) || !std::isfinite(chi) ||
+        !std::isfinite(kappa))
+        return c->fail(TILD_EINVAL, "interaction_forces: NULL array, bad dtype or non-finite chi/kappa");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    // the kernels take the physics by value: a modified copy needs no table change
+    Launch L = c->L;
+    L.ph.chi = chi;
+    L.ph.kappa = kappa;
+    if (!with_charges) L.ph.elec = 0;
+    hipError_t e = launch_spread_xy(L, c->S);
+    if (e == hipSuccess) e = launch_z_kmul(L, c->S, false);
+    if (e == hipSuccess) e = launch_xy_c2r(L, c->S);
+    void* dst = on_device ? out : c->staging;
+    if (e == hipSuccess) e = launch_update(L, c->S, 1, (uint64_t)c->step, dst, dtype, TILD_PART_NONBONDED);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(out, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "interaction_forces");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
 TILD_API int tild_energy(tild_ctx* c, double out[8]) {
     if (!c) return TILD_EINVAL;
     if (!out) return c->fail(TILD_EINVAL, "energy: out is NULL");

@@ -58,6 +58,23 @@ def test_counts_and_field_forces_match_oracle(precision, tol):
     assert err <= max(tol, 1e-12) * 10
 
 
+@pytest.mark.parametrize("force", ["ik", "ad"])
+def test_interaction_forces_equal_a_context_with_those_parameters(force):
+    m = make_custom(30, 5, 5, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.8, 3.0, seed_init=902)
+    el = dict(charges=(1.0, -1.0), bjerrum=2.0, charge_smear=0.4)
+    mk = lambda chi, kap, **kw: T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, chi, kap, force=force,
+                                                     precision=T.TILD_FP64, **kw), m.types, m.bonds)
+    t = mk(m.chi, m.kappa, **el)
+    ref = mk(1.0, 0.0)
+    for c in (t, ref):
+        c.set_positions(m.x)
+    got = t.interaction_forces(1.0, 0.0, with_charges=False)
+    np.testing.assert_array_equal(got, ref.forces(T.TILD_PART_NONBONDED))
+    np.testing.assert_array_equal(t.interaction_forces(m.chi, m.kappa), t.forces(T.TILD_PART_NONBONDED))
+    for c in (t, ref):
+        c.close()
+
+
 def _lamellar(m, period):
     nz, ny, nx = int(m.grid[2]), int(m.grid[1]), int(m.grid[0])
     xg = np.arange(nx) * m.box[0] / nx
