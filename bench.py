@@ -121,6 +121,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the headline workload (for profiler runs): no variants, batch or adjoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -163,6 +165,11 @@ def main() -> int:
     step_bytes = sum(abytes.values())
     traffic = measured_traffic(dom)
     t.close()
+    if args.main_only:
+        print(json.dumps({"metric": METRIC, "value": value, "unit": "bead-steps/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": ms_per_step, "kernels": kernels,
+                          "note": "headline workload only (--main-only)"}), flush=True)
+        return 0
 
     def time_variant(**kw):
         tv = T.from_melt(melt, precision=T.TILD_FP32, stream=stream, **kw)

@@ -134,3 +134,27 @@ def test_em_adjoint_finite_differences_differentiation_workload(precision, tol):
     say(f"[adj] 80,992 beads, 50 steps: loss {loss:.8g}, dL/dchi adjoint {g['chi']:.10g} "
         f"FD {fd:.10g} (h: {d1:.10g}, 2h: {d2:.10g})")
     assert abs(g["chi"] - fd) < tol * abs(fd)
+
+
+def test_second_order_calls_and_batches_accept_empty_systems():
+    """A context with no beads: counts are zero, field forces, H v and a batch step are no-ops."""
+    p = T.make_params((5.0, 5.0, 5.0), (8, 8, 8), 4, 0.5, 0.5, 5.0, precision=T.TILD_FP64)
+    t = T.Tild(p, np.zeros(0, np.int32))
+    t.set_positions(np.zeros((0, 3)))
+    assert np.all(t.counts() == 0.0)
+    assert t.field_forces(np.ones((2, 8, 8, 8))).shape == (0, 3)
+    assert t.hvp(np.zeros((0, 3))).shape == (0, 3)
+    m = make_custom(10, 3, 3, (5.0, 5.0, 5.0), (8, 8, 8), 4, 0.5, 5.0, seed_init=903)
+    u = T.Tild(T.make_params(m.box, m.grid, 4, m.smear_a, m.chi, m.kappa, precision=T.TILD_FP64), m.types, m.bonds)
+    alone = T.Tild(T.make_params(m.box, m.grid, 4, m.smear_a, m.chi, m.kappa, precision=T.TILD_FP64), m.types,
+                   m.bonds)
+    u.set_positions(m.x)
+    alone.set_positions(m.x)
+    with T.Batch([t, u]) as b:
+        b.step(3)
+        b.synchronize()
+    alone.step(3)
+    np.testing.assert_array_equal(u.get_positions(), alone.get_positions())
+    assert t.step_count == 3
+    for c in (t, u, alone):
+        c.close()
