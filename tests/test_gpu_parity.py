@@ -88,6 +88,32 @@ SMALL = [
 ]
 
 
+# The largest planes each precision accepts (one workgroup's LDS holds a plane): 135^2 in FP64 (odd, so
+# no Nyquist column), 192^2 in FP32, and the longest axes (256) against short ones.
+EXTREME = [
+    # (n_chains, nA, nB, box, grid, P, chi, kappa, precision)
+    (12, 5, 5, (13.5, 13.5, 5.0), (135, 135, 10), 4, 0.5, 5.0, T.TILD_FP64),
+    (12, 5, 5, (25.6, 2.0, 3.0), (256, 8, 6), 3, 0.8, 3.0, T.TILD_FP64),
+    (12, 5, 5, (2.0, 25.6, 3.0), (8, 256, 6), 5, 0.3, 8.0, T.TILD_FP32),
+    (12, 5, 5, (19.2, 19.2, 2.5), (192, 192, 5), 4, 0.5, 5.0, T.TILD_FP32),
+]
+
+
+@pytest.mark.parametrize("case", range(len(EXTREME)))
+def test_extreme_grid_shapes(case):
+    nc, na, nb, box, grid, P, chi, kap, precision = EXTREME[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=150 + case)
+    compare_forces(m, precision, TOL64 if precision == T.TILD_FP64 else TOL32, transform="numpy")
+
+
+def test_planes_beyond_local_memory_are_rejected():
+    for grid, precision in (((144, 144, 8), T.TILD_FP64), ((200, 200, 8), T.TILD_FP32)):
+        p = T.make_params((10.0, 10.0, 10.0), grid, 4, 0.5, 0.5, 5.0, precision=precision)
+        with pytest.raises(T.TildError) as e:
+            T.Tild(p, np.zeros(4, np.int32))
+        assert e.value.code == T.TILD_EINVAL
+
+
 @pytest.mark.parametrize("case", range(len(SMALL)))
 def test_small_systems_fp64(case):
     nc, na, nb, box, grid, P, chi, kap = SMALL[case]
