@@ -36,11 +36,11 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_648k_beads_128cube
 
 
 def kernel_source_sha256() -> str:
-    """Digest of the device-code sources (kernels and the headers they include), in a fixed order; the host
-    side of the ABI does not change what a kernel moves."""
+    """Digest of the library sources (kernels, their launchers and the shape choices), in a fixed order; the
+    public header only declares the interface."""
     h = hashlib.sha256()
     pkg = os.path.join(ROOT, "paper_2302_02474_amd", "csrc")
-    files = [os.path.join(pkg, f) for f in ("tild_common.h", "tild_fft.h", "tild_kernels.h", "tild_kernels.hip")]
+    files = sorted(glob.glob(os.path.join(pkg, "*.hip")) + glob.glob(os.path.join(pkg, "*.h")))
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtild.so")
-SOURCES = ["tild_kernels.hip", "tild_api.hip"]
+SOURCES = ["tild_plane.hip", "tild_second.hip", "tild_batch.hip", "tild_kernels.hip", "tild_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -42,15 +42,18 @@ def build_library(verbose: bool = False) -> str:
     """Compile every source for gfx950 and link libtild.so next to this file."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
     cc = hipcc()
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
+    objs = [os.path.join(objdir, src.replace(".hip", ".o")) for src in SOURCES]
+    cmds = [[cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj] for src, obj in zip(SOURCES, objs)]
+    if verbose:
+        for cmd in cmds:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+    # the translation units are independent: compile them side by side
+    procs = [subprocess.Popen(cmd) for cmd in cmds]
+    codes = [p.wait() for p in procs]
+    for cmd, code in zip(cmds, codes):
+        if code != 0:
+            raise subprocess.CalledProcessError(code, cmd)
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

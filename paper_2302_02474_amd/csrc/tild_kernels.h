@@ -183,5 +183,9 @@ hipError_t configure_batch_attributes(const Launch& L, size_t lds_plane, size_t 
 size_t plane_lds_bytes(const Launch& L);
 size_t z_lds_bytes(const Launch& L);
 hipError_t configure_kernel_attributes(const Launch& L);
+hipError_t configure_plane_attributes(const Launch& L, size_t lds);
+hipError_t configure_second_attributes(const Launch& L, size_t lds);
+// [n][4] sorted-order vectors <-> [n][3] ABI-order arrays of dtype: op 0 ABI -> sorted, op 1 sorted -> ABI
+hipError_t launch_bead_vectors(const Launch& L, DeviceState& S, void* sorted, int op, void* v, int dtype);
 
 }  // namespace tild

@@ -1,0 +1,149 @@
+// Launchers of the plane kernels' other modes: mesh counts, forces of a given
+// field, and Hessian-vector products (directional spread, second-derivative
+// interpolation).
+#include "tild_device.h"
+
+namespace tild {
+
+template <typename T, int B> static void hvp_b(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
+    launch_bead_vectors(L, S, S.vdir, 0, const_cast<void*>(v), dtype);
+    const unsigned gb = blocks_for(S.n, 256);
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 3) {
+            // second-derivative terms against the potential planes of the counts
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                               L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
+                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr);
+            hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1);
+            // the field of the directional counts, gathered with the weight gradients
+            hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                               L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                               (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr);
+        }
+    });
+}
+
+template <typename T, int B> static void hvp_tail(const Launch& L, DeviceState& S, void* out, int dtype) {
+    const unsigned gb = blocks_for(S.n, 256);
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 3) {
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
+                               (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
+            // those partials are -sum grad W delta phi
+            hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1);
+        }
+    });
+    launch_bead_vectors(L, S, S.hacc, 1, out, dtype);
+}
+
+template <typename T, int B> static void counts_b(const Launch& L, DeviceState& S, void* out) {
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        hipLaunchKernelGGL((k_spread_xy<T, B, P, false, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
+                           L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                           (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part, (const RepDesc*)nullptr,
+                           (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)out);
+    });
+}
+
+hipError_t launch_counts(const Launch& L, DeviceState& S, void* out) {
+    if (L.precision == 0) {
+        if (L.plane_block == 256) counts_b<float, 256>(L, S, out);
+        else counts_b<float, 512>(L, S, out);
+    } else {
+        if (L.plane_block == 256) counts_b<double, 256>(L, S, out);
+        else counts_b<double, 512>(L, S, out);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int B> static void field_b(const Launch& L, DeviceState& S, const void* field) {
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 2)
+            hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, false, true>), dim3(L.d.mz, 2), dim3(B),
+                               plane_lds_bytes(L), L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py,
+                               (const cplx<T>*)S.tw, L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part,
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr,
+                               (const T*)field);
+    });
+}
+
+hipError_t launch_field_forces(const Launch& L, DeviceState& S, const void* field, void* out, int dtype) {
+    if (L.order < 2) return hipErrorInvalidValue;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) field_b<float, 256>(L, S, field);
+        else field_b<float, 512>(L, S, field);
+    } else {
+        if (L.plane_block == 256) field_b<double, 256>(L, S, field);
+        else field_b<double, 512>(L, S, field);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_update(L, S, 1, 0, out, dtype, 1u);
+    return e;
+}
+
+hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
+    if (S.n == 0 || L.order < 3) return hipSuccess;
+    // the potential planes of the counts: spread, k-space pass (noise off)
+    hipError_t e = launch_spread_xy(L, S);
+    if (e == hipSuccess) e = launch_z_kmul(L, S, false);
+    if (e != hipSuccess) return e;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) hvp_b<float, 256>(L, S, v, out, dtype);
+        else hvp_b<float, 512>(L, S, v, out, dtype);
+    } else {
+        if (L.plane_block == 256) hvp_b<double, 256>(L, S, v, out, dtype);
+        else hvp_b<double, 512>(L, S, v, out, dtype);
+    }
+    e = launch_z_kmul(L, S, false);  // Phi of the directional counts
+    if (e != hipSuccess) return e;
+    if (L.precision == 0) {
+        if (L.plane_block == 256) hvp_tail<float, 256>(L, S, out, dtype);
+        else hvp_tail<float, 512>(L, S, out, dtype);
+    } else {
+        if (L.plane_block == 256) hvp_tail<double, 256>(L, S, out, dtype);
+        else hvp_tail<double, 512>(L, S, out, dtype);
+    }
+    return hipGetLastError();
+}
+
+template <typename T> static hipError_t attr_second(const Launch& L, size_t lds) {
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if (L.plane_block == 256) {
+            if constexpr (P >= 3) {
+                set((const void*)k_xy_c2r<T, 256, P, true, false, true>);
+                set((const void*)k_spread_xy<T, 256, P, false, true>);
+            }
+            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 256, P, true, false, false, true>);
+            set((const void*)k_spread_xy<T, 256, P, false, false, true>);
+        } else {
+            if constexpr (P >= 3) {
+                set((const void*)k_xy_c2r<T, 512, P, true, false, true>);
+                set((const void*)k_spread_xy<T, 512, P, false, true>);
+            }
+            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 512, P, true, false, false, true>);
+            set((const void*)k_spread_xy<T, 512, P, false, false, true>);
+        }
+    });
+    return e;
+}
+
+hipError_t configure_second_attributes(const Launch& L, size_t lds) {
+    return L.precision == 0 ? attr_second<float>(L, lds) : attr_second<double>(L, lds);
+}
+
+}  // namespace tild
