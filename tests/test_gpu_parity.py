@@ -320,3 +320,32 @@ def test_workload2_precision_study_sampled():
     say("   relative errors", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= TOL32, (k, v)
+
+
+def test_long_run_statistics_fp32_match_fp64():
+    """Workload 0 for 10,000 steps in FP32 and in FP64 (same noise): the mean energies and the A-species
+    structure factor at the smallest wavevectors agree within their sampling errors, so FP32 rounding
+    does not bias the long-run statistics (the FP64 path itself follows the oracle step by step)."""
+    m = make_melt(0)
+    nv = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [0, 1, 1]])
+    stats = {}
+    for precision in (T.TILD_FP32, T.TILD_FP64):
+        t = gpu_ctx(m, precision)
+        t.set_positions(m.x)
+        t.step(2000)
+        es, sk = [], []
+        for _ in range(80):
+            t.step(100)
+            es.append(t.energy()["E"])
+            x = t.get_positions()
+            sk.append(R.structure_factor_exact(x[m.types == 0], m.box, nv))
+        t.close()
+        es, sk = np.array(es), np.array(sk)
+        # errors of the means from 8 blocks of 10 samples
+        err = lambda a: a.reshape(8, 10, *a.shape[1:]).mean(axis=1).std(axis=0, ddof=1) / np.sqrt(8)
+        stats[precision] = (es.mean(), err(es), sk.mean(axis=0), err(sk))
+        say(f"[long] precision={precision}: <E> = {es.mean():.3f} +- {err(es):.3f}, "
+            f"<S(k)> = {np.round(sk.mean(axis=0), 3)}")
+    (e32, s32, k32, ks32), (e64, s64, k64, ks64) = stats[T.TILD_FP32], stats[T.TILD_FP64]
+    assert abs(e32 - e64) < 4 * np.hypot(s32, s64) + 1e-6 * abs(e64)
+    assert np.all(np.abs(k32 - k64) < 4 * np.hypot(ks32, ks64) + 1e-3)
