@@ -194,6 +194,18 @@ def main() -> int:
     for k, v in variants.items():
         print(f"[bench] variant {k}: {v['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
 
+    # The small workload (3000-bead A10B10 melt, 16^3): latency-bound, reported as time per step only.
+    m0 = make_melt(0)
+    t0c = T.from_melt(m0, precision=T.TILD_FP32, stream=stream)
+    t0c.step(args.warmup)
+    t0c.synchronize()
+    t0 = time.perf_counter()
+    t0c.step(args.steps)
+    t0c.synchronize()
+    small_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0c.close()
+    print(f"[bench] {m0.name}: {small_ms * 1e3:.1f} us/step", file=sys.stderr, flush=True)
+
     # Batched replicas: 64 A10B10 melts of uneven size (boxes 16^3..40^3,
     # grids 32^3..80^3, ~5.8 million beads) stepped by one batch (one launch
     # per kernel for all 64), against the same 64 contexts stepped one after
@@ -308,6 +320,8 @@ def main() -> int:
         "energy_grad_ms": round(egrad_ms, 4),
         "variants": variants,
         "batched_replicas": replicas,
+        "small_workload": {"workload": m0.name + ", FP32", "ms_per_step": round(small_ms, 5),
+                           "bead_steps_per_s": m0.n / (small_ms * 1e-3)},
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host ...", file=sys.stderr, flush=True)
