@@ -216,6 +216,7 @@ def main() -> int:
     n_rep = sum(r.n for r in reps)
     k_rep = max(10, args.steps // 10)
     bt = T.Batch(members, stream=stream)
+    plane_block = bt.autotune(3)
     bt.step(3)
     bt.synchronize()
     t0 = time.perf_counter()
@@ -241,7 +242,7 @@ def main() -> int:
                 "sequential_ms_per_step": round(seq_ms, 4),
                 "batched_bead_steps_per_s": n_rep / (batched_ms * 1e-3),
                 "sequential_bead_steps_per_s": n_rep / (seq_ms * 1e-3),
-                "speedup": round(seq_ms / batched_ms, 3)}
+                "speedup": round(seq_ms / batched_ms, 3), "plane_block_autotuned": plane_block}
     print(f"[bench] 64 replicas ({n_rep} beads): batched {batched_ms:.4f} ms/step, one by one {seq_ms:.4f} ms/step",
           file=sys.stderr, flush=True)
 

@@ -374,6 +374,16 @@ int tild_hvp(tild_ctx* ctx, const void* v, void* out, int32_t dtype, int32_t on_
 typedef struct tild_batch tild_batch;
 int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_stream, tild_batch** out);
 int tild_batch_step(tild_batch* batch, int64_t n_steps);
+/*
+ * Choose the batch's plane-workgroup size (256 or 512 threads; the default
+ * is set from the largest member plane) by timing trial_steps (1..1000)
+ * batched steps with each, twice, on the members' own systems.  Every
+ * member's positions and step counter are restored after each trial, so the
+ * simulation state is unchanged (bitwise).  Synchronises; needs a temporary
+ * device buffer of 24 bytes per bead.  The choice is stored in
+ * *plane_block when it is not NULL.
+ */
+int tild_batch_autotune(tild_batch* batch, int32_t trial_steps, int32_t* plane_block);
 int tild_batch_synchronize(tild_batch* batch);
 void tild_batch_destroy(tild_batch* batch);
 const char* tild_batch_last_error(const tild_batch* batch);

@@ -331,6 +331,12 @@ class Batch:
     def synchronize(self):
         self._check(self._lib.tild_batch_synchronize(self._b))
 
+    def autotune(self, trial_steps: int = 4) -> int:
+        """Time the plane-workgroup sizes on the members' own systems (state restored) and keep the fastest."""
+        pb = ctypes.c_int32(0)
+        self._check(self._lib.tild_batch_autotune(self._b, int(trial_steps), ctypes.byref(pb)))
+        return pb.value
+
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:
             self._lib.tild_batch_destroy(self._b)

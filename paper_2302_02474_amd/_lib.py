@@ -31,7 +31,8 @@ EXPORTS = [
     "tild_get_velocities", "tild_step", "tild_forces",
     "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
-    "tild_hvp", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
+    "tild_hvp", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create",
+    "tild_batch_autotune", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
 ]
 
 
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_hvp.restype = ctypes.c_int
     lib.tild_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
     lib.tild_batch_create.restype = ctypes.c_int
+    lib.tild_batch_autotune.argtypes = [vp, i32, P(i32)]
+    lib.tild_batch_autotune.restype = ctypes.c_int
     lib.tild_batch_step.argtypes = [vp, i64]
     lib.tild_batch_step.restype = ctypes.c_int
     lib.tild_batch_synchronize.argtypes = [vp]

@@ -1167,6 +1167,69 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
     return TILD_OK;
 }
 
+TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* plane_block) {
+    if (!b) return TILD_EINVAL;
+    if (trial_steps < 1 || trial_steps > 1000) return b->fail(TILD_EINVAL, "autotune: trial_steps must be in [1, 1000]");
+    for (tild_ctx* c : b->ctx)
+        if (!c->have_pos) return b->fail(TILD_ESTATE, "a member's positions were never set");
+    DeviceGuard g(b->device);
+    // snapshot: every member's positions (ABI order, float64) and step counter
+    std::vector<size_t> off;
+    size_t total = 0;
+    for (tild_ctx* c : b->ctx) {
+        off.push_back(total);
+        total += (size_t)c->S.n * 3;
+    }
+    double* snap = nullptr;
+    hipError_t e = hipMalloc((void**)&snap, std::max<size_t>(total, 1) * sizeof(double));
+    if (e != hipSuccess) return b->fail(TILD_ENOMEM, "autotune: no device memory for the snapshot");
+    std::vector<int64_t> step0;
+    for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) {
+        tild_ctx* c = b->ctx[r];
+        step0.push_back(c->step);
+        e = launch_get_positions(c->L, c->S, snap + off[r], 1);  // on the member's own stream
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const int cand[2] = {256, 512};
+    float best_ms[2] = {1e30f, 1e30f};
+    const int keep = b->B.plane_block;
+    int rc = TILD_OK;
+    // each candidate twice, alternating; the state is restored after every trial
+    for (int rep = 0; rep < 4 && e == hipSuccess && rc == TILD_OK; ++rep) {
+        const int k = rep & 1;
+        b->B.plane_block = cand[k];
+        for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) {
+            e = hipEventRecord(b->member_ev[r], b->ctx[r]->L.stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->member_ev[r], 0);
+        }
+        if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+        if (e == hipSuccess) rc = tild_batch_step(b, trial_steps);
+        if (rc == TILD_OK && e == hipSuccess) e = hipEventRecord(t1, b->stream);
+        if (rc == TILD_OK && e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (rc == TILD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (rc == TILD_OK && e == hipSuccess) best_ms[k] = std::min(best_ms[k], ms);
+        for (size_t r = 0; rc == TILD_OK && r < b->ctx.size(); ++r) {
+            rc = tild_set_positions(b->ctx[r], snap + off[r], TILD_FP64, 1);
+            b->ctx[r]->step = step0[r];
+        }
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    (void)hipFree(snap);
+    if (rc != TILD_OK || e != hipSuccess) {
+        b->B.plane_block = keep;
+        if (rc != TILD_OK) return b->fail(rc, "autotune: a trial step or the restore failed");
+        return b->hip_fail(e, "autotune");
+    }
+    b->B.plane_block = best_ms[0] <= best_ms[1] ? cand[0] : cand[1];
+    if (plane_block) *plane_block = b->B.plane_block;
+    return TILD_OK;
+}
+
 TILD_API int tild_batch_synchronize(tild_batch* b) {
     if (!b) return TILD_EINVAL;
     DeviceGuard g(b->device);

@@ -76,6 +76,29 @@ def test_batch_equals_members_stepped_alone(precision, P):
         t.close()
 
 
+def test_autotune_leaves_the_state_unchanged():
+    ms = [_member(i, T.TILD_FP32) for i in range(len(MEMBERS))]
+    alone = [T.Tild(p, m.types, m.bonds) for m, p in ms]
+    batched = [T.Tild(p, m.types, m.bonds) for m, p in ms]
+    for i, ((m, _), a, b) in enumerate(zip(ms, alone, batched)):
+        a.set_positions(m.x)
+        b.set_positions(m.x)
+        a.step_count = b.step_count = 5 * i
+    with T.Batch(batched) as bt:
+        pb = bt.autotune(3)
+        say(f"[batch] autotune chose {pb}-thread plane workgroups")
+        assert pb in (256, 512)
+        for i, b in enumerate(batched):
+            assert b.step_count == 5 * i
+        bt.step(4)
+        bt.synchronize()
+    for a, b in zip(alone, batched):
+        a.step(4)
+        np.testing.assert_array_equal(a.get_positions(), b.get_positions())
+    for t in alone + batched:
+        t.close()
+
+
 def test_batch_member_trajectory_matches_oracle_fp64():
     ms = [_member(i, T.TILD_FP64) for i in range(3)]
     ts = [T.Tild(p, m.types, m.bonds) for m, p in ms]
