@@ -1,8 +1,11 @@
 /*
  * tild.h -- C ABI of libtild, a gfx950 (MI355X) implementation of one
  * theoretically-informed Langevin dynamics (TILD) step: the particle-mesh
- * non-bonded force of a two-species (A/B) bead-spring melt, harmonic bond
- * forces, and an overdamped Euler-Maruyama position update.
+ * non-bonded force of a two-species (A/B) bead-spring melt (optionally with
+ * smeared electrostatics), harmonic bond forces, and an overdamped
+ * Euler-Maruyama (or GJF Langevin) position update; with energy gradients,
+ * Hessian-vector products and mesh access for differentiable use, and
+ * batches of independent systems stepped together.
  *
  * Model (MATILDA.FT paper, Sec. "Structure of theoretically-informed
  * coarse-grained and field-theoretic models"):
