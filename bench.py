@@ -67,7 +67,8 @@ def measured_traffic(kernel: str):
 
 
 def algorithmic_bytes(melt, precision_bytes: int = 4) -> dict:
-    """Bytes each kernel must move at minimum per launch ('Byte model')."""
+    """Bytes each kernel must move at minimum per launch: its inputs read once and its outputs written once
+    (beads 16 B, half spectra hs complex values, force partials 3 P per bead, bond slots 4 B each)."""
     mx, my, mz = (int(v) for v in melt.grid)
     m = mx * my * mz
     hs = (mx // 2 + 1) * my * mz  # complex elements of one half spectrum
@@ -125,8 +126,8 @@ def main() -> int:
                     help="time only the headline workload (for profiler runs): no variants, batch or adjoint")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md, 'Sharding'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent systems shard "
+              "one per GPU; one large box would need a z-slab decomposition); run with --gpus 1", file=sys.stderr)
         return 2
 
     import torch
