@@ -38,7 +38,6 @@ struct FftPlan {
 // into different LDS banks.
 struct LineMap {
     int lines, l1, s1, s2, es, swz;
-    __device__ __forceinline__ int base(int l) const { return (l % l1) * s1 + (l / l1) * s2; }
 };
 
 // LDS index of element e of the line starting at `base`.
@@ -188,6 +187,65 @@ __device__ __forceinline__ void line_pass(C* buf, const int base, const int es, 
     wave_sync();
 }
 
+// The passes of a power-of-two length N with groups of N/8 lanes (the
+// group the host picks for these lengths), starting at the pass whose
+// already-applied radix product is S: radix 8 while at least 8 elements
+// per butterfly remain, then 4 or 2, as the host's plan orders them.  Every
+// length, stride and radix is a compile-time constant here, so the index
+// arithmetic reduces to shifts, masks and immediate LDS offsets; the
+// arithmetic on the elements is that of line_pass.
+template <typename C, int INV, bool SWZ, int N, int S>
+__device__ __forceinline__ void line_passes_fixed(C* buf, const int base, const int es, const int swz,
+                                                  const C* __restrict__ tw, const int lane) {
+    if constexpr (S < N) {
+        constexpr int R = N / S >= 8 ? 8 : N / S;
+        constexpr int G = N / 8, BPL = N / R, NB = BPL / G, TS = N / (S * R);
+        static_assert(NB * G == BPL && NB * R <= kFftRegElems, "fixed pass does not fit the lane budget");
+        // the lane index made opaque to the optimiser: every address and twiddle
+        // derived from it would otherwise be hoisted out of the callers' line
+        // loops and held in registers for the whole kernel
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        C v[NB][R];
+        int ob[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = ln + b * G;
+            const int k = j & (S - 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = buf[line_index<SWZ>(base, j + r * BPL, es, swz)];
+            if constexpr (S > 1) {
+                C w[R];
+                w[1] = tw[k * TS];
+                if (INV) w[1].y = -w[1].y;
+                if constexpr (R > 2) {
+                    w[2] = tw[2 * k * TS];
+                    if (INV) w[2].y = -w[2].y;
+                }
+                if constexpr (R > 3) w[3] = cmul(w[1], w[2]);
+                if constexpr (R > 4) w[4] = cmul(w[2], w[2]);
+                if constexpr (R > 5) {
+                    w[5] = cmul(w[1], w[4]);
+                    w[6] = cmul(w[2], w[4]);
+                    w[7] = cmul(w[3], w[4]);
+                }
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], w[r]);
+            }
+            ob[b] = (j - k) * R + k;
+        }
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            dft_r<R, INV>(v[b]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[line_index<SWZ>(base, ob[b] + r * S, es, swz)] = v[b][r];
+        }
+        wave_sync();
+        line_passes_fixed<C, INV, SWZ, N, S * R>(buf, base, es, swz, tw, lane);
+    }
+}
+
 // Transform the line at `base` (elements `es` apart, swizzled with mask swz
 // when SWZ) in place; called by all G lanes of the owning group.
 template <typename C, int INV, bool SWZ = false>
@@ -195,6 +253,13 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
                                          const C* __restrict__ twiddles, const int lane, const int swz = 0) {
     const C* tw = twiddles + plan.tw;
     const int G = plan.group;
+    if (G * 8 == plan.n) {
+        switch (plan.n) {
+            case 16: line_passes_fixed<C, INV, SWZ, 16, 1>(buf, base, es, swz, tw, lane); return;
+            case 128: line_passes_fixed<C, INV, SWZ, 128, 1>(buf, base, es, swz, tw, lane); return;
+            default: break;
+        }
+    }
     int s = 1;
     for (int st = 0; st < plan.nst; ++st) {
         const int R = plan.radix(st);
@@ -217,8 +282,18 @@ __device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPla
                                           int tid, int nthr) {
     const int G = plan.group;
     const int lane = tid % G, grp = tid / G, ngrp = nthr / G;
-    for (int l = grp; l < lm.lines; l += ngrp)
-        fft_line<C, INV, SWZ>(buf, lm.base(l), lm.es, plan, twiddles, lane, lm.swz);
+    // line l = q l1 + r, stepped by ngrp = dq l1 + dr without a division per line
+    const int dq = ngrp / lm.l1, dr = ngrp % lm.l1;
+    int q = grp / lm.l1, r = grp % lm.l1;
+    for (int l = grp; l < lm.lines; l += ngrp) {
+        fft_line<C, INV, SWZ>(buf, r * lm.s1 + q * lm.s2, lm.es, plan, twiddles, lane, lm.swz);
+        q += dq;
+        r += dr;
+        if (r >= lm.l1) {
+            r -= lm.l1;
+            ++q;
+        }
+    }
 }
 
 }  // namespace tild

@@ -5,8 +5,10 @@
 
 namespace tild {
 
-template <typename T, int B> static void hvp_b(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
-    launch_bead_vectors(L, S, S.vdir, 0, const_cast<void*>(v), dtype);
+template <typename T, int B>
+static hipError_t hvp_b(const Launch& L, DeviceState& S, const void* v, void* out, int dtype) {
+    const hipError_t e = launch_bead_vectors(L, S, S.vdir, 0, const_cast<void*>(v), dtype);
+    if (e != hipSuccess) return e;
     const unsigned gb = blocks_for(S.n, 256);
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
@@ -25,9 +27,10 @@ template <typename T, int B> static void hvp_b(const Launch& L, DeviceState& S, 
                                (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr);
         }
     });
+    return hipGetLastError();
 }
 
-template <typename T, int B> static void hvp_tail(const Launch& L, DeviceState& S, void* out, int dtype) {
+template <typename T, int B> static hipError_t hvp_tail(const Launch& L, DeviceState& S, void* out, int dtype) {
     const unsigned gb = blocks_for(S.n, 256);
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
@@ -41,7 +44,8 @@ template <typename T, int B> static void hvp_tail(const Launch& L, DeviceState& 
                                (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1);
         }
     });
-    launch_bead_vectors(L, S, S.hacc, 1, out, dtype);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_bead_vectors(L, S, S.hacc, 1, out, dtype);
 }
 
 template <typename T, int B> static void counts_b(const Launch& L, DeviceState& S, void* out) {
@@ -97,23 +101,15 @@ hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out,
     hipError_t e = launch_spread_xy(L, S);
     if (e == hipSuccess) e = launch_z_kmul(L, S, false);
     if (e != hipSuccess) return e;
-    if (L.precision == 0) {
-        if (L.plane_block == 256) hvp_b<float, 256>(L, S, v, out, dtype);
-        else hvp_b<float, 512>(L, S, v, out, dtype);
-    } else {
-        if (L.plane_block == 256) hvp_b<double, 256>(L, S, v, out, dtype);
-        else hvp_b<double, 512>(L, S, v, out, dtype);
-    }
-    e = launch_z_kmul(L, S, false);  // Phi of the directional counts
+    if (L.precision == 0) e = L.plane_block == 256 ? hvp_b<float, 256>(L, S, v, out, dtype)
+                                                   : hvp_b<float, 512>(L, S, v, out, dtype);
+    else e = L.plane_block == 256 ? hvp_b<double, 256>(L, S, v, out, dtype)
+                                  : hvp_b<double, 512>(L, S, v, out, dtype);
+    if (e == hipSuccess) e = launch_z_kmul(L, S, false);  // Phi of the directional counts
     if (e != hipSuccess) return e;
-    if (L.precision == 0) {
-        if (L.plane_block == 256) hvp_tail<float, 256>(L, S, out, dtype);
-        else hvp_tail<float, 512>(L, S, out, dtype);
-    } else {
-        if (L.plane_block == 256) hvp_tail<double, 256>(L, S, out, dtype);
-        else hvp_tail<double, 512>(L, S, out, dtype);
-    }
-    return hipGetLastError();
+    if (L.precision == 0) return L.plane_block == 256 ? hvp_tail<float, 256>(L, S, out, dtype)
+                                                      : hvp_tail<float, 512>(L, S, out, dtype);
+    return L.plane_block == 256 ? hvp_tail<double, 256>(L, S, out, dtype) : hvp_tail<double, 512>(L, S, out, dtype);
 }
 
 template <typename T> static hipError_t attr_second(const Launch& L, size_t lds) {
