@@ -256,7 +256,10 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
     if (G * 8 == plan.n) {
         switch (plan.n) {
             case 16: line_passes_fixed<C, INV, SWZ, 16, 1>(buf, base, es, swz, tw, lane); return;
+            case 32: line_passes_fixed<C, INV, SWZ, 32, 1>(buf, base, es, swz, tw, lane); return;
+            case 64: line_passes_fixed<C, INV, SWZ, 64, 1>(buf, base, es, swz, tw, lane); return;
             case 128: line_passes_fixed<C, INV, SWZ, 128, 1>(buf, base, es, swz, tw, lane); return;
+            case 256: line_passes_fixed<C, INV, SWZ, 256, 1>(buf, base, es, swz, tw, lane); return;
             default: break;
         }
     }
