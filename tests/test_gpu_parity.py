@@ -89,13 +89,18 @@ SMALL = [
 
 
 # The largest planes each precision accepts (one workgroup's LDS holds a plane): 135^2 in FP64 (odd, so
-# no Nyquist column), 192^2 in FP32, and the longest axes (256) against short ones.
+# no Nyquist column), 192^2 in FP32, and the longest axes (256) against short ones.  The last two put
+# every power-of-two length from 8 to 256 on each axis (these lengths take the fixed-length FFT passes).
 EXTREME = [
     # (n_chains, nA, nB, box, grid, P, chi, kappa, precision)
     (12, 5, 5, (13.5, 13.5, 5.0), (135, 135, 10), 4, 0.5, 5.0, T.TILD_FP64),
     (12, 5, 5, (25.6, 2.0, 3.0), (256, 8, 6), 3, 0.8, 3.0, T.TILD_FP64),
     (12, 5, 5, (2.0, 25.6, 3.0), (8, 256, 6), 5, 0.3, 8.0, T.TILD_FP32),
     (12, 5, 5, (19.2, 19.2, 2.5), (192, 192, 5), 4, 0.5, 5.0, T.TILD_FP32),
+    (12, 5, 5, (6.4, 2.0, 25.6), (64, 8, 256), 4, 0.5, 5.0, T.TILD_FP32),
+    (12, 5, 5, (3.2, 6.4, 12.8), (32, 64, 128), 3, 0.6, 4.0, T.TILD_FP64),
+    (12, 5, 5, (12.8, 3.2, 6.4), (128, 32, 64), 5, 0.4, 6.0, T.TILD_FP32),
+    (12, 5, 5, (1.6, 12.8, 3.2), (16, 128, 32), 2, 0.5, 5.0, T.TILD_FP64),
 ]
 
 
