@@ -3,6 +3,7 @@ itself (a closed form, a library routine, brute force on a tiny input, an
 invariant or a finite difference), so that a dropped term, a wrong sign or
 index, or a transposed operand fails at least one of them."""
 
+import os
 import numpy as np
 import pytest
 
@@ -540,6 +541,18 @@ def test_philox64_matches_numpy_philox():
                 ctrs.append(list(c))
             ours = oracle.philox4(np.array(ctrs, dtype=np.uint64), key, width=64)
             np.testing.assert_array_equal(ours, raw)
+
+
+def test_philox4x32_10_known_answers():
+    """The W = 32 instance (the one the noise uses) against the generator authors' published known-answer
+    vectors (tests/golden/philox4x32_10_kat.txt): fixes both multipliers and both Weyl increments."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+    rows = [[int(v, 16) for v in line.split()] for line in open(path)
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for w in rows:
+        out = oracle.philox4x32(np.array([w[:4]], dtype=np.uint64), w[4:6])[0]
+        assert [int(v) for v in out] == w[6:], [hex(int(v)) for v in out]
 
 
 def test_noise_statistics():
