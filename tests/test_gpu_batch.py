@@ -160,3 +160,38 @@ def test_batch_of_64_uneven_replicas_equals_members_alone():
         np.testing.assert_array_equal(alone[i].get_positions(), batched[i].get_positions())
     for t in alone + batched:
         t.close()
+
+
+def test_replica_workload_fp32_members_match_oracle():
+    """The batched-replica workload in FP32: all 64 members advanced 20 steps by the batch; the three
+    smallest are compared with 20 FP64 oracle steps from the same snapped positions and noise
+    (displacement and end-of-run forces, relative RMS <= 1e-5)."""
+    reps = make_replicas(64)
+    x0 = [snap_to_lattice(r.x, r.box) for r in reps]
+    ts = [T.from_melt(r, precision=T.TILD_FP32) for r in reps]
+    for t, x in zip(ts, x0):
+        t.set_positions(x)
+    steps = 20
+    with T.Batch(ts) as bt:
+        bt.step(steps)
+        bt.synchronize()
+    picks = sorted(range(64), key=lambda i: reps[i].n)[:3]
+    for k in picks:
+        m = reps[k]
+        po = R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
+                      chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=m.dt, gamma=m.gamma, kT=m.kT, seed=m.seed,
+                      transform="numpy")
+        say(f"[batch] oracle for {m.name} ({m.n} beads), {steps} steps")
+        xo = R.trajectory(x0[k], m.types, m.bonds, po, steps)
+        xg = ts[k].get_positions()
+        d = R.min_image(xg - xo, m.box)
+        err_x = np.sqrt((d ** 2).mean()) / np.sqrt((R.min_image(xo - x0[k], m.box) ** 2).mean())
+        ev = R.evaluate(xo, m.types, m.bonds, po)
+        f = ts[k].forces(T.TILD_PART_TOTAL)
+        fnb = ts[k].forces(T.TILD_PART_NONBONDED)
+        err_f = np.linalg.norm(f - ev["F"]) / np.linalg.norm(ev["F"])
+        err_nb = np.linalg.norm(fnb - ev["F_nb"]) / np.linalg.norm(ev["F_nb"])
+        say(f"   displacement rel-RMS {err_x:.3e}, force {err_f:.3e}, non-bonded {err_nb:.3e}")
+        assert err_x < 1e-5 and err_f < 1e-5 and err_nb < 1e-5
+    for t in ts:
+        t.close()

@@ -354,3 +354,64 @@ def test_long_run_statistics_fp32_match_fp64():
     (e32, s32, k32, ks32), (e64, s64, k64, ks64) = stats[T.TILD_FP32], stats[T.TILD_FP64]
     assert abs(e32 - e64) < 4 * np.hypot(s32, s64) + 1e-6 * abs(e64)
     assert np.all(np.abs(k32 - k64) < 4 * np.hypot(ks32, ks64) + 1e-3)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def test_workload1_trajectory_100_steps_against_stored_oracle():
+    """The 648,000-bead melt at 128^3: 100 FP32 steps on the GPU against 100 FP64 oracle steps from the same
+    snapped positions and noise (stored by tests/golden/make_oracle_references.py, which runs the oracle
+    only).  Compared on 2048 sampled beads: displacement, total and non-bonded force at the end; energies
+    and virial of the whole system."""
+    ref = np.load(os.path.join(GOLDEN, "workload1_trajectory_100.npz"), allow_pickle=False)
+    m = make_melt(1)
+    x0 = snap_to_lattice(m.x, m.box)
+    idx = ref["idx"]
+    say(f"[trajectory] {m.name}, 100 steps, fp32")
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(x0)
+    t.step(100)
+    xg = t.get_positions()
+    f = t.forces(T.TILD_PART_TOTAL)
+    fnb = t.forces(T.TILD_PART_NONBONDED)
+    e = t.energy()
+    t.close()
+    disp_ref = R.min_image(ref["x"] - x0[idx], m.box)
+    disp_gpu = R.min_image(xg[idx] - x0[idx], m.box)
+    errs = dict(x=rel_rms(disp_gpu, disp_ref), F=rel_rms(f[idx], ref["F"]), F_nb=rel_rms(fnb[idx], ref["F_nb"]))
+    say("   rel-RMS", errs)
+    for k, v in errs.items():
+        assert v <= TOL32, (k, v)
+    for k in ("E_bond", "E_chi", "E_kappa"):
+        assert abs(e[k] - float(ref[k])) <= TOL32 * abs(float(ref[k])), (k, e[k], float(ref[k]))
+    np.testing.assert_allclose(e["W"], ref["W"], rtol=TOL32)
+
+
+def test_workload0_long_run_statistics_match_oracle():
+    """Workload 0, FP32 on the GPU, run as the stored FP64 oracle long run was (2000 steps, then 80 samples
+    100 steps apart, same noise): the mean total energy and the mean A-species S(k) (Eq. sk) at the six
+    smallest wavevectors agree within four combined standard errors of the means (8 blocks of 10 samples)."""
+    import json
+    with open(os.path.join(GOLDEN, "workload0_long_run.json")) as fh:
+        ref = json.load(fh)
+    m = make_melt(0)
+    nv = np.array(ref["nvecs"])
+    t = gpu_ctx(m, T.TILD_FP32)
+    t.set_positions(snap_to_lattice(m.x, m.box))
+    t.step(ref["equilibration_steps"])
+    es, sk = [], []
+    for _ in range(ref["samples"]):
+        t.step(ref["steps_between_samples"])
+        es.append(t.energy()["E"])
+        x = t.get_positions()
+        sk.append(R.structure_factor_exact(x[m.types == 0], m.box, nv))
+    t.close()
+    es, sk = np.array(es), np.array(sk)
+    eo, sko = np.array(ref["E"]), np.array(ref["S_A"])
+    err = lambda a: a.reshape(8, -1, *a.shape[1:]).mean(axis=1).std(axis=0, ddof=1) / np.sqrt(8)
+    say(f"[long] GPU <E> = {es.mean():.4f} +- {err(es):.4f}, oracle {eo.mean():.4f} +- {err(eo):.4f}; "
+        f"largest per-sample |dE|/|E| {np.max(np.abs(es - eo) / np.abs(eo)):.2e}")
+    say(f"[long] GPU <S(k)> = {np.round(sk.mean(axis=0), 4)}, oracle {np.round(sko.mean(axis=0), 4)}")
+    assert abs(es.mean() - eo.mean()) < 4 * np.hypot(err(es), err(eo)) + 1e-6 * abs(eo.mean())
+    assert np.all(np.abs(sk.mean(axis=0) - sko.mean(axis=0)) < 4 * np.hypot(err(sk), err(sko)) + 1e-4)
