@@ -52,10 +52,14 @@ bool smooth235(int n) {
 }
 
 // Radix passes for one length: as many 8s as possible, then 4, 2, 3, 5.
-bool make_plan(int n, int tw_offset, FftPlan& pl) {
+// Lengths 64, 128 and 256 also get the two-pass shape (8 x 8, 16 x 8,
+// 16 x 16), whose table starts at tw2_offset.
+bool make_plan(int n, int tw_offset, int tw2_offset, FftPlan& pl) {
     std::memset(&pl, 0, sizeof(pl));
     pl.n = n;
     pl.tw = tw_offset;
+    pl.tw2 = tw2_offset;
+    pl.r1 = n == 64 ? 8 : ((n == 128 || n == 256) ? 16 : 0);
     int r = n, k = 0;
     auto push = [&](int R) {
         if (k >= kMaxRadixStages) return false;
@@ -153,8 +157,13 @@ int validate(const tild_params* p, int64_t n, std::string& why) {
 }
 
 // Smallest power-of-two lane group (<= 64, >= min_g) for which every radix
-// pass of `pl` fits the per-lane register budget of the line transform.
+// pass of `pl` fits the per-lane register budget of the line transform; the
+// two-pass shapes have fixed groups (n/16 lanes for 128 and 256, 8 for 64).
 int choose_group(const FftPlan& pl, int min_g) {
+    if (pl.r1) {
+        const int G = pl.n == 64 ? 8 : pl.n / 16;
+        return G >= min_g ? G : 0;
+    }
     for (int G = 1; G <= 64; G <<= 1) {
         if (G < min_g) continue;
         bool ok = true;
@@ -171,7 +180,7 @@ int choose_group(const FftPlan& pl, int min_g) {
 bool choose_shapes(Launch& L, std::string& why) {
     const Dims& d = L.d;
     const size_t lds_max = 160 * 1024;
-    const int pair_items = 8;  // row-pair (un)packing items per lane in the plane kernels
+    const int pair_items = kPairItems;  // row-pair (un)packing items per lane in the plane kernels
     L.px.group = choose_group(L.px, (d.mx + pair_items - 1) / pair_items);
     L.py.group = choose_group(L.py, 1);
     L.pz.group = choose_group(L.pz, 1);
@@ -182,7 +191,7 @@ bool choose_shapes(Launch& L, std::string& why) {
     const long long need = std::max((long long)d.npair * L.px.group, (long long)d.hx * L.py.group);
     // measured on MI355X at 128^2 planes: the fused spread prefers 1024 threads, the inverse pass 512
     L.plane_block = need <= 256 ? 256 : 512;
-    L.spread_block = need <= 256 ? 256 : (need <= 512 || L.precision == 1 ? 512 : 1024);
+    L.spread_block = need <= 256 ? 256 : (L.precision == 1 ? 512 : 1024);
     if (plane_lds_bytes(L) > lds_max) {
         why = "grid plane does not fit one workgroup's LDS in this precision";
         return false;
@@ -422,7 +431,16 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     d.lx = params->box[0];
     d.ly = params->box[1];
     d.lz = params->box[2];
-    if (!make_plan(d.mx, 0, L.px) || !make_plan(d.my, d.mx, L.py) || !make_plan(d.mz, d.mx + d.my, L.pz)) {
+    // the two-pass tables follow the plain ones, for the lengths that use them
+    int nt = d.mx + d.my + d.mz;
+    bool planned = make_plan(d.mx, 0, nt, L.px);
+    nt += L.px.r1 ? d.mx : 0;
+    planned = planned && make_plan(d.my, d.mx, nt, L.py);
+    nt += L.py.r1 ? d.my : 0;
+    planned = planned && make_plan(d.mz, d.mx + d.my, nt, L.pz);
+    nt += L.pz.r1 ? d.mz : 0;
+    d.ntw2 = nt - (d.mx + d.my + d.mz);
+    if (!planned) {
         g_create_error = "internal: radix plan";
         delete c;
         return TILD_EINVAL;
@@ -498,6 +516,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A((void**)&S.pos, npos * sizeof(uint4));
     A((void**)&S.pos_tmp, npos * sizeof(uint4));
     A((void**)&S.kr, npos * sizeof(uint2));
+    if (L.precision == 0) A((void**)&S.grec, npos * sizeof(uint4));
     A(&S.fbond, npos * 4 * real_sz);
     if (ph.gjf) {
         A(&S.vel, npos * 4 * real_sz);
@@ -521,7 +540,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     A(&S.spec, 2 * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.zout, (L.force_ad ? 2 : 4) * (size_t)d.mz * d.hplane * cplx_sz);
     A(&S.fpart, 3 * (size_t)params->order * npos * real_sz);
-    A(&S.tw, (size_t)(d.mx + d.my + d.mz) * cplx_sz);
+    A(&S.tw, (size_t)d.ntw() * cplx_sz);
     const bool sampled = (params->flags & TILD_POTENTIAL_SAMPLED) != 0;
     A((void**)&S.utab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
     if (sampled) A((void**)&S.vtab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
@@ -550,6 +569,17 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
         const int n = a == 0 ? d.mx : (a == 1 ? d.my : d.mz);
         for (int m = 0; m < n; ++m) {
             const double ang = 2.0 * M_PI * (double)m / (double)n;
+            tw.push_back(std::cos(ang));
+            tw.push_back(-std::sin(ang));
+        }
+    }
+    // two-pass tables: w_n^(l k1) at [l][k1], l < n / r1, k1 < r1, for the lengths that use them
+    for (const FftPlan* pl : {&L.px, &L.py, &L.pz}) {
+        if (!pl->r1) continue;
+        const int n = pl->n;
+        for (int m = 0; m < n; ++m) {
+            const int l = m / pl->r1, k1 = m % pl->r1;
+            const double ang = 2.0 * M_PI * (double)((long long)l * k1 % n) / (double)n;
             tw.push_back(std::cos(ang));
             tw.push_back(-std::sin(ang));
         }
@@ -1245,3 +1275,4 @@ TILD_API int tild_batch_synchronize(tild_batch* b) {
 TILD_API const char* tild_batch_last_error(const tild_batch* b) {
     return b ? b->err.c_str() : g_create_error.c_str();
 }
+

@@ -41,7 +41,8 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
                        (uint32_t*)nullptr, 0, (unsigned long long*)nullptr, B.ticket, (uint32_t*)nullptr, R, B.tile);
     hipLaunchKernelGGL((k_scatter<T, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                        (const uint2*)nullptr, (const uint32_t*)nullptr, (const int32_t*)nullptr, (uint4*)nullptr,
-                       (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph, (const T*)nullptr, (T*)nullptr, R, B.bead, par);
+                       (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph, (const T*)nullptr, (T*)nullptr, R, B.bead, par,
+                       (uint4*)nullptr, (const uint32_t*)nullptr, L.d, L.order);
 }
 
 hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z) {

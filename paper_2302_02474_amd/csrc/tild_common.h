@@ -40,6 +40,9 @@ struct Dims {
     long long m;     // mx*my*mz
     long long hplane;  // my*hx complex per half-spectrum plane
     double lx, ly, lz;
+    int ntw2;        // entries of the two-pass twiddle tables (lengths that use them)
+    // complex twiddle entries: exp(-2 pi i m/n) for each axis, then the two-pass tables
+    __host__ __device__ __forceinline__ int ntw() const { return mx + my + mz + ntw2; }
 };
 
 // The dispatcher hands consecutive workgroups of a launch to the device's 8
@@ -174,6 +177,45 @@ __device__ __forceinline__ void assignment_weights(uint32_t q, int m, int& g0, T
     g0 = wrap_start((int)(s >> 32) + 1, m, P);
     const T f = (T)(uint32_t)(s & 0xffffffffLL) * (T)2.3283064365386963e-10;  // 2^-32
     spline_weights<T, P>(f, w);
+}
+
+// Grid record of one coordinate, formed once per step when the beads are
+// sorted and read by the single-precision spread and interpolation: the
+// wrapped first stencil node g0 (< 256) in the top 8 bits and the fraction
+// f = frac(u - P/2) truncated to 24 bits below (the precision a float
+// fraction holds near 1).
+__device__ __forceinline__ uint32_t grid_record(uint32_t q, int m, int P) {
+    const int64_t s = stencil_fixed(q, m, P);
+    const int g0 = wrap_start((int)(s >> 32) + 1, m, P);
+    return ((uint32_t)g0 << 24) | ((uint32_t)s >> 8);
+}
+
+// First stencil nodes (x, y) and fractions (x, y, z) of a bead: from its grid
+// record when T is float (sx, sy, sz unused), from its fixed-point position
+// minus the shift when T is double.
+template <typename T> struct BeadFrac {
+    int gx, gy;
+    T fx, fy, fz;
+};
+template <typename T, int P>
+__device__ __forceinline__ BeadFrac<T> bead_frac(const uint4 q, uint32_t sx, uint32_t sy, uint32_t sz, int mx, int my,
+                                                 int mz) {
+    BeadFrac<T> b;
+    if constexpr (sizeof(T) == 4) {
+        constexpr float k24 = 5.9604644775390625e-8f;  // 2^-24
+        b.gx = (int)(q.x >> 24);
+        b.gy = (int)(q.y >> 24);
+        b.fx = (float)(q.x & 0xffffffu) * k24;
+        b.fy = (float)(q.y & 0xffffffu) * k24;
+        b.fz = (float)(q.z & 0xffffffu) * k24;
+    } else {
+        b.gx = stencil_start(q.x - sx, mx, P);
+        b.gy = stencil_start(q.y - sy, my, P);
+        b.fx = stencil_fraction<T>(q.x - sx, mx, P);
+        b.fy = stencil_fraction<T>(q.y - sy, my, P);
+        b.fz = stencil_fraction<T>(q.z - sz, mz, P);
+    }
+    return b;
 }
 
 // Minimum-image separation (in box units * 2^32) of two fixed-point coordinates.

@@ -24,7 +24,6 @@
 namespace tild {
 
 
-constexpr int kPairItems = 8;  // row-pair (un)packing items per lane
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kInvTwo32 = 2.3283064365386962890625e-10;
@@ -127,6 +126,9 @@ struct Walk2 {
 // precision.  Integer LDS atomics are order-independent, so every run gives
 // the same bits, and far faster than float ones on this hardware.
 //
+// pos holds the beads' grid records in single precision, their fixed-point
+// positions in double precision (bead_frac).
+//
 // With `noise`, every bead of the plane's own slab (c = 0, so each bead once
 // over the grid) also adds its Gaussian increment of step `step` to nsum, in
 // 32.32 fixed point (exact for float increments, order-independent).
@@ -148,15 +150,17 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
         constexpr int U = 4;  // beads in flight per thread
         for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
+            // every load is issued (clamped to the last bead of the range), so none waits on a branch
             uint4 qv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t j = jb + (uint32_t)(u * nthr);
-                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+                qv[u] = pos[j < j1 ? j : j1 - 1u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (jb + (uint32_t)(u * nthr) >= j1) break;
+                const uint32_t j = jb + (uint32_t)(u * nthr);
+                if (j >= j1) break;
                 const uint4 q = qv[u];
                 if (c == 0 && noise) {
                     // the step's noise; with `two` (GJF) also that of the next step
@@ -167,25 +171,30 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
                         nsum[1] += llrint((double)xi[1] * kTwo32);
                         nsum[2] += llrint((double)xi[2] * kTwo32);
                     }
+
                 }
-                int gx, gy;
+                const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
                 T wx[P], wy[P];
-                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                spline_weights<T, P>(bf.fx, wx);
+                spline_weights<T, P>(bf.fy, wy);
                 // the bead's slab is s: its z weight on plane z = s + c is w_c (c is
                 // a constant after unrolling, so only that weight is evaluated)
                 T wz[P];
-                spline_weights<T, P>(stencil_fraction<T>(q.z - sz, d.mz, P), wz);
+                spline_weights<T, P>(bf.fz, wz);
                 const T w0 = wz[c] * scale;
-                const RowOffsets<P> ro(gy, pr);
+                const RowOffsets<P> ro(bf.gy, pr);
+                const int gx = bf.gx;
 #pragma unroll
                 for (int b = 0; b < P; ++b) {
                     A* row = acc + ro.o[b] + 2 * gx;
                     const T wyz = w0 * wy[b];
+                    // contributions are >= 0: adding 1/2 and truncating rounds to the nearest multiple
 #pragma unroll
                     for (int a = 0; a < P; ++a) {
-                        if constexpr (sizeof(T) == 4) atomicAdd(row + 2 * a, (uint32_t)__float2int_rn(wyz * wx[a]));
-                        else atomicAdd(row + 2 * a, (unsigned long long)__double2ll_rn(wyz * wx[a]));
+                        if constexpr (sizeof(T) == 4)
+                            atomicAdd(row + 2 * a, __float2uint_rz(fmaf(wyz, wx[a], 0.5f)));
+                        else
+                            atomicAdd(row + 2 * a, (unsigned long long)__double2ll_rz(fma(wyz, wx[a], 0.5)));
                     }
                 }
             }
@@ -215,17 +224,18 @@ __device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint
             const uint4 q = pos[j];
             const T vx = vdir[4 * (long long)j] * ihx, vy = vdir[4 * (long long)j + 1] * ihy;
             const T vz = vdir[4 * (long long)j + 2] * ihz;
-            int gx, gy;
+            const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+            const int gx = bf.gx;
             T wx[P], wy[P], dwx[P], dwy[P];
-            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
-            spline_dweights<T, P>(stencil_fraction<T>(q.x - sx, d.mx, P), dwx);
-            spline_dweights<T, P>(stencil_fraction<T>(q.y - sy, d.my, P), dwy);
-            const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+            spline_weights<T, P>(bf.fx, wx);
+            spline_weights<T, P>(bf.fy, wy);
+            spline_dweights<T, P>(bf.fx, dwx);
+            spline_dweights<T, P>(bf.fy, dwy);
+            const T fz = bf.fz;
             T wzs[P], dwzs[P];  // only entry c survives unrolling
             spline_weights<T, P>(fz, wzs);
             spline_dweights<T, P>(fz, dwzs);
-            const RowOffsets<P> ro(gy, pr);
+            const RowOffsets<P> ro(bf.gy, pr);
 #pragma unroll
             for (int b = 0; b < P; ++b) {
                 T* row = acc + ro.o[b] + 2 * gx;
@@ -349,7 +359,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     if constexpr (BATCH) {
         const uint32_t e = umap[xcd_contiguous(blockIdx.x, gridDim.x)];
         const RepDesc& R = reps[e >> 16];
-        pos = R.S.pos;
+        pos = sizeof(T) == 4 ? R.S.grec : R.S.pos;
         bin_start = R.S.bin_start;
         qs = parity ? R.S.qshift_next : R.S.qshift;
         spec = (C*)R.S.spec;
@@ -371,7 +381,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     // Prologue: issue the global loads (twiddles, bin starts) before zeroing
     // the plane, then one barrier.
     C* twl = S + d.npg * zp;
-    const int ntw = d.mx + d.my + d.mz;
+    const int ntw = d.ntw();
     C twv[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
@@ -381,6 +391,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 #pragma unroll
     for (int u = 0; u < 3; ++u)
         if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+    for (int i = tid + 3 * BLOCK; i < ntw; i += BLOCK) twl[i] = tw[i];
     if constexpr (!DIR) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
@@ -536,21 +547,22 @@ __device__ __forceinline__ void push_plane(const T* __restrict__ Sr, const uint4
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t j = jb + (uint32_t)(u * nthr);
-                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+                qv[u] = pos[j < j1 ? j : j1 - 1u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t j = jb + (uint32_t)(u * nthr);
                 if (j >= j1) break;
                 const uint4 q = qv[u];
-                int gx, gy;
+                const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+                const int gx = bf.gx;
                 T wx[P], wy[P];
-                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
+                spline_weights<T, P>(bf.fx, wx);
+                spline_weights<T, P>(bf.fy, wy);
                 T wzs[P];  // only wzs[c] survives unrolling
-                spline_weights<T, P>(stencil_fraction<T>(q.z - sz, d.mz, P), wzs);
+                spline_weights<T, P>(bf.fz, wzs);
                 const T wz = wzs[c];
-                const RowOffsets<P> ro(gy, pr);
+                const RowOffsets<P> ro(bf.gy, pr);
                 T acc = 0;
 #pragma unroll
                 for (int b = 0; b < P; ++b) {
@@ -593,24 +605,25 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t j = jb + (uint32_t)(u * nthr);
-                qv[u] = j < j1 ? pos[j] : uint4{0u, 0u, 0u, 0u};
+                qv[u] = pos[j < j1 ? j : j1 - 1u];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t j = jb + (uint32_t)(u * nthr);
                 if (j >= j1) break;
                 const uint4 q = qv[u];
-                int gx, gy;
+                const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+                const int gx = bf.gx;
                 T wx[P], wy[P], dwx[P], dwy[P];
-                assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-                assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
-                spline_dweights<T, P>(stencil_fraction<T>(q.x - sx, d.mx, P), dwx);
-                spline_dweights<T, P>(stencil_fraction<T>(q.y - sy, d.my, P), dwy);
-                const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+                spline_weights<T, P>(bf.fx, wx);
+                spline_weights<T, P>(bf.fy, wy);
+                spline_dweights<T, P>(bf.fx, dwx);
+                spline_dweights<T, P>(bf.fy, dwy);
+                const T fz = bf.fz;
                 T wzs[P], dwzs[P];  // only entry c survives unrolling
                 spline_weights<T, P>(fz, wzs);
                 spline_dweights<T, P>(fz, dwzs);
-                const RowOffsets<P> ro(gy, pr);
+                const RowOffsets<P> ro(bf.gy, pr);
                 T ax = 0, ay = 0, az = 0;
 #pragma unroll
                 for (int b = 0; b < P; ++b) {
@@ -659,16 +672,17 @@ __device__ __forceinline__ void push_plane_hess(const T* __restrict__ Sr, const 
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
         for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
             const uint4 q = pos[j];
-            int gx, gy;
+            const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+            const int gx = bf.gx, gy = bf.gy;
             T wx[P], wy[P], dwx[P], dwy[P], ddx[P], ddy[P];
-            assignment_weights<T, P>(q.x - sx, d.mx, gx, wx);
-            assignment_weights<T, P>(q.y - sy, d.my, gy, wy);
-            const T fx = stencil_fraction<T>(q.x - sx, d.mx, P), fy = stencil_fraction<T>(q.y - sy, d.my, P);
+            const T fx = bf.fx, fy = bf.fy;
+            spline_weights<T, P>(fx, wx);
+            spline_weights<T, P>(fy, wy);
             spline_dweights<T, P>(fx, dwx);
             spline_dweights<T, P>(fy, dwy);
             spline_d2weights<T, P>(fx, ddx);
             spline_d2weights<T, P>(fy, ddy);
-            const T fz = stencil_fraction<T>(q.z - sz, d.mz, P);
+            const T fz = bf.fz;
             T wzs[P], dwzs[P], ddzs[P];  // only entry c survives unrolling
             spline_weights<T, P>(fz, wzs);
             spline_dweights<T, P>(fz, dwzs);
@@ -703,6 +717,98 @@ __device__ __forceinline__ void push_plane_hess(const T* __restrict__ Sr, const 
             fpart[((long long)2 * P + c) * n + j] = hxz * vx + hyz * vy + hzz * vz;
         }
     }
+}
+
+// Inverse transform of one plane held in LDS as a half spectrum (row pitch
+// hxp, swizzled as hidx): inverse FFT along y, then complex-to-real along x
+// with rows 2p and 2p+1 carried as the real and imaginary parts of one
+// complex row, packed in place at complex offset p * zp by the lanes that
+// then transform it.  Called by nthr threads (tid < nthr) after a barrier;
+// every thread of the block takes part in its barriers, so two halves of a
+// block may transform two planes side by side.  Ends without a barrier.
+template <typename T>
+__device__ __forceinline__ void inverse_xy_transform(cplx<T>* __restrict__ S, const Dims d, const FftPlan px,
+                                                     const FftPlan py, const cplx<T>* __restrict__ twl, int tid,
+                                                     int nthr) {
+    using C = cplx<T>;
+    const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
+    // For even mx the columns kx = 0 and kx = mx/2 transform back to real
+    // rows; one y transform of Z = G_0 + i G_N gives both.
+    const bool pair_n = (mx & 1) == 0 && hx > 1;
+    if (pair_n) {
+        for (int y = tid; y < my; y += nthr) {
+            const C g0 = S[hidx(d, y, 0)], gn = S[hidx(d, y, hx - 1)];
+            S[hidx(d, y, 0)] = C{g0.x - gn.y, g0.y + gn.x};
+        }
+        __syncthreads();
+    }
+    if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, nthr);
+    else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, nthr);
+    __syncthreads();
+    if (pair_n) {
+        for (int y = tid; y < my; y += nthr) {
+            const C zv = S[hidx(d, y, 0)];
+            S[hidx(d, y, 0)] = C{zv.x, (T)0};
+            S[hidx(d, y, hx - 1)] = C{zv.y, (T)0};
+        }
+        __syncthreads();
+    }
+    {
+        const int G = px.group, lane = tid % G;
+        for (int p = tid / G; p < np; p += nthr / G) {
+            const int base = p * zp;
+            const bool odd = 2 * p + 1 < my;
+            C rz[kPairItems];
+#pragma unroll
+            for (int u = 0; u < kPairItems; ++u) {
+                const int x = lane + u * G;
+                if (x < mx) {
+                    C A, B;
+                    if (x < hx) {
+                        A = S[hidx(d, 2 * p, x)];
+                        B = odd ? S[hidx(d, 2 * p + 1, x)] : C{0, 0};
+                    } else {
+                        const int xs = mx - x;
+                        const C a0 = S[hidx(d, 2 * p, xs)];
+                        const C b0 = odd ? S[hidx(d, 2 * p + 1, xs)] : C{0, 0};
+                        A = C{a0.x, -a0.y};
+                        B = C{b0.x, -b0.y};
+                    }
+                    rz[u] = C{A.x - B.y, A.y + B.x};
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < kPairItems; ++u) {
+                const int x = lane + u * G;
+                if (x < mx) S[base + x] = rz[u];
+            }
+            wave_sync();
+            fft_line<C, 1>(S, base, 1, px, twl, lane);
+        }
+    }
+}
+
+// Fill the ghost columns and rows of a real plane in the extended row-pair
+// layout (ghost columns of the real rows, then ghost rows, ghost columns
+// included).  Starts after a barrier and ends with one.
+template <typename T, int P>
+__device__ __forceinline__ void fill_ghosts(T* __restrict__ Sr, const Dims d, int tid, int nthr) {
+    if constexpr (P > 1) {
+        const int pr = 4 * d.hxp, mx = d.mx, my = d.my;
+        for (int i = tid; i < my * (P - 1); i += nthr) {
+            const int y = i / (P - 1), e = i - y * (P - 1);
+            const int o = __mul24(y >> 1, pr) + (y & 1);
+            Sr[o + 2 * (mx + e)] = Sr[o + 2 * e];
+        }
+        __syncthreads();
+        for (int i = tid; i < (P - 1) * (mx + P - 1); i += nthr) {
+            const int e = i / (mx + P - 1), x = i - e * (mx + P - 1);
+            const int yg = my + e;
+            Sr[__mul24(yg >> 1, pr) + (yg & 1) + 2 * x] = Sr[__mul24(e >> 1, pr) + (e & 1) + 2 * x];
+        }
+    }
+    __syncthreads();
 }
 
 // Inverse (one workgroup per plane z, species K and axis a = x, y, z): build
@@ -752,7 +858,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         py = R.py;
         tw = (const C*)R.S.tw;
         ph = R.ph;
-        pos = R.S.pos;
+        pos = sizeof(T) == 4 ? R.S.grec : R.S.pos;
         bin_start = R.S.bin_start;
         qs = parity ? R.S.qshift_next : R.S.qshift;
         n = R.S.n;
@@ -765,7 +871,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     C* twl = S + d.npg * zp;
-    const int ntw = d.mx + d.my + d.mz;
+    const int ntw = d.ntw();
     {
         if constexpr (FIELD) {
             T* Sf = reinterpret_cast<T*>(smem);
@@ -811,81 +917,13 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 #pragma unroll
             for (int u = 0; u < 3; ++u)
                 if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+            for (int i = tid + 3 * BLOCK; i < ntw; i += BLOCK) twl[i] = tw[i];
             __syncthreads();
-            // For even mx the columns kx = 0 and kx = mx/2 transform back to real
-            // rows; one y transform of Z = G_0 + i G_N gives both.
-            const bool pair_n = (mx & 1) == 0 && hx > 1;
-            if (pair_n) {
-                for (int y = tid; y < my; y += BLOCK) {
-                    const C g0 = S[hidx(d, y, 0)], gn = S[hidx(d, y, hx - 1)];
-                    S[hidx(d, y, 0)] = C{g0.x - gn.y, g0.y + gn.x};
-                }
-                __syncthreads();
-            }
-            if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
-            else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
-            __syncthreads();
-            if (pair_n) {
-                for (int y = tid; y < my; y += BLOCK) {
-                    const C zv = S[hidx(d, y, 0)];
-                    S[hidx(d, y, 0)] = C{zv.x, (T)0};
-                    S[hidx(d, y, hx - 1)] = C{zv.y, (T)0};
-                }
-                __syncthreads();
-            }
-            {
-                const int G = px.group, lane = tid % G;
-                for (int p = tid / G; p < np; p += BLOCK / G) {
-                    const int base = p * zp;
-                    const bool odd = 2 * p + 1 < my;
-                    C rz[kPairItems];
-#pragma unroll
-                    for (int u = 0; u < kPairItems; ++u) {
-                        const int x = lane + u * G;
-                        if (x < mx) {
-                            C A, B;
-                            if (x < hx) {
-                                A = S[hidx(d, 2 * p, x)];
-                                B = odd ? S[hidx(d, 2 * p + 1, x)] : C{0, 0};
-                            } else {
-                                const int xs = mx - x;
-                                const C a0 = S[hidx(d, 2 * p, xs)];
-                                const C b0 = odd ? S[hidx(d, 2 * p + 1, xs)] : C{0, 0};
-                                A = C{a0.x, -a0.y};
-                                B = C{b0.x, -b0.y};
-                            }
-                            rz[u] = C{A.x - B.y, A.y + B.x};
-                        }
-                    }
-                    wave_sync();
-#pragma unroll
-                    for (int u = 0; u < kPairItems; ++u) {
-                        const int x = lane + u * G;
-                        if (x < mx) S[base + x] = rz[u];
-                    }
-                    wave_sync();
-                    fft_line<C, 1>(S, base, 1, px, twl, lane);
-                }
-            }
+            inverse_xy_transform<T>(S, d, px, py, twl, tid, BLOCK);
         }
         __syncthreads();
         T* Sr = reinterpret_cast<T*>(smem);
-        if constexpr (P > 1) {
-            // ghost columns of the real rows, then ghost rows (ghost columns included)
-            const int pr = 4 * hxp;
-            for (int i = tid; i < my * (P - 1); i += BLOCK) {
-                const int y = i / (P - 1), e = i - y * (P - 1);
-                const int o = __mul24(y >> 1, pr) + (y & 1);
-                Sr[o + 2 * (mx + e)] = Sr[o + 2 * e];
-            }
-            __syncthreads();
-            for (int i = tid; i < (P - 1) * (mx + P - 1); i += BLOCK) {
-                const int e = i / (mx + P - 1), x = i - e * (mx + P - 1);
-                const int yg = my + e;
-                Sr[__mul24(yg >> 1, pr) + (yg & 1) + 2 * x] = Sr[__mul24(e >> 1, pr) + (e & 1) + 2 * x];
-            }
-            __syncthreads();
-        }
+        fill_ghosts<T, P>(Sr, d, tid, BLOCK);
         if constexpr (AD && HESS) {
             push_plane_hess<T, P>(Sr, pos, bin_start, qs, d, z, K, n, vdir, fpart, tid, BLOCK);
         } else if constexpr (AD) {
@@ -997,11 +1035,11 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     const int mz = d.mz, my = d.my, mx = d.mx, hx = d.hx;
     const int cbp = cb | 1;
     C* twl = b0 + 4 * mz * cbp;
-    const int ntw = d.mx + d.my + d.mz;
+    const int ntw = d.ntw();
     C twv[2];  // twiddles, loaded with the spectra and stored after them
 #pragma unroll
     for (int u = 0; u < 2; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
-    ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + d.mx + d.my + d.mz);
+    ZPlane* zt = reinterpret_cast<ZPlane*>(b0 + 4 * mz * cbp + ntw);
     ZColumn* ct = reinterpret_cast<ZColumn*>(zt + mz);
     const int cn = (int)d.hplane;
     const int c0 = blk * cb;
@@ -1045,6 +1083,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 #pragma unroll
         for (int u = 0; u < 2; ++u)
             if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
+        for (int i = tid + 2 * BLOCK; i < ntw; i += BLOCK) twl[i] = tw[i];
     }
     __syncthreads();
     fft_lines<C, 0>(b0, LineMap{2 * cb, cb, 1, mz * cbp, cbp, 0}, pz, twl, tid, BLOCK);
@@ -1438,13 +1477,16 @@ __global__ void __launch_bounds__(256)
 // bond partners (slots of the previous order) into sorted slots, and store
 // its harmonic bond force F = -2 k_b sum_partners d (d the minimum-image bond
 // vector, shift-free in fixed point) as {Fx, Fy, Fz, 0}.  With GJF (vdst not
-// null) the half-step velocity moves with the bead.
+// null) the half-step velocity moves with the bead.  Single precision: also
+// the bead's grid record {x, y, z, id << 1 | species} (grid_record, with the
+// current shift qs and order P) to grec[slot].
 template <typename T, bool BATCH = false>
 __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
               T* __restrict__ fbond, long long n, int deg, Phys ph, const T* __restrict__ vsrc, T* __restrict__ vdst,
-              const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity) {
+              const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
+              uint4* __restrict__ grec, const uint32_t* __restrict__ qs, Dims d, int P) {
     // contiguous bead ranges per XCD: bond partners are near in the order
     long long blk = xcd_contiguous(blockIdx.x, gridDim.x);
     if constexpr (BATCH) {
@@ -1462,6 +1504,9 @@ __global__ void __launch_bounds__(256)
         ph = R.ph;
         vsrc = nullptr;
         vdst = nullptr;
+        grec = R.S.grec;
+        qs = parity ? R.S.qshift : R.S.qshift_next;  // the shift the update of this step formed
+        d = R.d;
         blk = (long long)(e & 0xffffu);
     }
     const long long j = blk * 256LL + threadIdx.x;
@@ -1470,6 +1515,9 @@ __global__ void __launch_bounds__(256)
     const long long nw = (long long)bin_start[kj.x] + kj.y;
     const uint4 q = pos_tmp[j];
     pos[nw] = q;
+    if constexpr (sizeof(T) == 4)
+        grec[nw] = uint4{grid_record(q.x - qs[0], d.mx, P), grid_record(q.y - qs[1], d.my, P),
+                         grid_record(q.z - qs[2], d.mz, P), q.w};
     if (vdst) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) vdst[4 * nw + a] = vsrc[4 * j + a];

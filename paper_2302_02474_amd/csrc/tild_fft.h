@@ -17,6 +17,7 @@ namespace tild {
 
 constexpr int kMaxRadixStages = 8;  // 4-bit radix codes in one 32-bit word
 constexpr int kFftRegElems = 8;
+constexpr int kPairItems = 16;  // row-pair (un)packing items per lane of an x line
 
 // Factorisation of one transform length, the offset of its twiddle table
 // (exp(-2 pi i m/n), m = 0..n-1) inside the context's twiddle array, and the
@@ -27,6 +28,8 @@ struct FftPlan {
     int tw;
     int group;  // lanes per line: a power of two <= 64
     uint32_t codes;  // radix of pass st in bits 4 st .. 4 st + 3
+    int r1;     // two-pass transform n = r1 r2 (line_fft2) when > 0, else the radix passes
+    int tw2;    // offset of its table w^(l k1), l < r2, k1 < r1, stored [l][k1]
     __host__ __device__ __forceinline__ int radix(int st) const { return (int)((codes >> (4 * st)) & 15u); }
 };
 
@@ -128,11 +131,56 @@ template <int INV, typename C> __device__ __forceinline__ void dft5(C* a) {
     a[3] = csub(t2, iu2);
 }
 
+// 16 points as 4 x 4: transforms of the four residue classes n1 (elements
+// n1, n1 + 4, n1 + 8, n1 + 12), the twiddles w16^(n1 k1), then transforms over
+// n1; output k1 + 4 k2 in natural order.
+template <int INV, typename C> __device__ __forceinline__ void dft16(C* a) {
+    using T = decltype(a[0].x);
+    C b[4][4];
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) {
+        C t[4] = {a[n1], a[n1 + 4], a[n1 + 8], a[n1 + 12]};
+        dft4<INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) b[n1][k1] = t[k1];
+    }
+    const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, r = (T)0.70710678118654752440;
+    // w16^e for e = n1 k1 in {1, 2, 3, 4, 6, 9}: (cos, -+sin)(2 pi e / 16)
+    auto tw = [&](C v, int e) -> C {
+        T wr, wi;
+        switch (e) {
+            case 1: wr = c1; wi = -s1; break;
+            case 2: wr = r; wi = -r; break;
+            case 3: wr = s1; wi = -c1; break;
+            case 6: wr = -r; wi = -r; break;
+            default: wr = -c1; wi = s1; break;  // 9
+        }
+        if (INV) wi = -wi;
+        return C{v.x * wr - v.y * wi, v.x * wi + v.y * wr};
+    };
+#pragma unroll
+    for (int n1 = 1; n1 < 4; ++n1)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) {
+            const int e = n1 * k1;
+            if (e == 4) b[n1][k1] = INV ? mul_pi(b[n1][k1]) : mul_mi(b[n1][k1]);
+            else b[n1][k1] = tw(b[n1][k1], e);
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C t[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+        dft4<INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+    }
+}
+
 template <int R, int INV, typename C> __device__ __forceinline__ void dft_r(C* a) {
     if constexpr (R == 2) dft2<INV>(a);
     else if constexpr (R == 3) dft3<INV>(a);
     else if constexpr (R == 4) dft4<INV>(a);
     else if constexpr (R == 5) dft5<INV>(a);
+    else if constexpr (R == 16) dft16<INV>(a);
     else dft8<INV>(a);
 }
 
@@ -246,6 +294,68 @@ __device__ __forceinline__ void line_passes_fixed(C* buf, const int base, const 
     }
 }
 
+// Two-pass transform of a line of N = R1 R2 points by G lanes (N / G
+// elements each, G dividing R1 and R2), from n = l + R2 m and
+// k = k1 + R1 k2:
+//   X[k1 + R1 k2] = sum_l w_N^(l k1) w_R2^(l k2) sum_m x[l + R2 m] w_R1^(m k1).
+// Pass A: each lane takes R2/G values of l, transforms over m in registers,
+// multiplies by w_N^(l k1) (table tw2[l R1 + k1]) and writes the result to
+// element k1 R2 + l -- the elements it read, so no other lane is disturbed.
+// Pass B: each lane takes R1/G values of k1, reads elements k1 R2 + l,
+// transforms over l and writes element k1 + R1 k2 (natural order).  Two
+// rounds of LDS traffic instead of one per radix pass.
+template <typename C, int INV, bool SWZ, int N, int R1, int R2, int G>
+__device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, const int swz,
+                                          const C* __restrict__ tw2, const int lane) {
+    static_assert(R1 * R2 == N && R1 % G == 0 && R2 % G == 0, "two-pass shape");
+    constexpr int NA = R2 / G, NB = R1 / G;
+    // the lane index made opaque to the optimiser (see line_passes_fixed)
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    {
+        C v[NA][R1];
+#pragma unroll
+        for (int d = 0; d < NA; ++d) {
+            const int l = ln + d * G;
+#pragma unroll
+            for (int m = 0; m < R1; ++m) v[d][m] = buf[line_index<SWZ>(base, l + R2 * m, es, swz)];
+        }
+#pragma unroll
+        for (int d = 0; d < NA; ++d) {
+            const int l = ln + d * G;
+            dft_r<R1, INV>(v[d]);
+            const C* w = tw2 + l * R1;
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) {
+                C wk = w[k1];
+                if (INV) wk.y = -wk.y;
+                v[d][k1] = cmul(v[d][k1], wk);
+            }
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) buf[line_index<SWZ>(base, k1 * R2 + l, es, swz)] = v[d][k1];
+        }
+    }
+    wave_sync();
+    {
+        C v[NB][R2];
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const int k1 = ln + d * G;
+#pragma unroll
+            for (int l = 0; l < R2; ++l) v[d][l] = buf[line_index<SWZ>(base, k1 * R2 + l, es, swz)];
+        }
+        wave_sync();
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+            const int k1 = ln + d * G;
+            dft_r<R2, INV>(v[d]);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) buf[line_index<SWZ>(base, k1 + R1 * k2, es, swz)] = v[d][k2];
+        }
+    }
+    wave_sync();
+}
+
 // Transform the line at `base` (elements `es` apart, swizzled with mask swz
 // when SWZ) in place; called by all G lanes of the owning group.
 template <typename C, int INV, bool SWZ = false>
@@ -253,6 +363,15 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
                                          const C* __restrict__ twiddles, const int lane, const int swz = 0) {
     const C* tw = twiddles + plan.tw;
     const int G = plan.group;
+    if (plan.r1) {
+        const C* tw2 = twiddles + plan.tw2;
+        switch (plan.n) {
+            case 64: line_fft2<C, INV, SWZ, 64, 8, 8, 8>(buf, base, es, swz, tw2, lane); return;
+            case 128: line_fft2<C, INV, SWZ, 128, 16, 8, 8>(buf, base, es, swz, tw2, lane); return;
+            case 256: line_fft2<C, INV, SWZ, 256, 16, 16, 16>(buf, base, es, swz, tw2, lane); return;
+            default: break;
+        }
+    }
     if (G * 8 == plan.n) {
         switch (plan.n) {
             case 16: line_passes_fixed<C, INV, SWZ, 16, 1>(buf, base, es, swz, tw, lane); return;

@@ -55,6 +55,8 @@ struct Phys {
 struct DeviceState {
     uint4* pos;           // [n] sorted beads
     uint4* pos_tmp;       // [n] beads in the previous order (new positions or ABI input)
+    uint4* grec;          // [n] grid records of the sorted beads {x, y, z, id << 1 | species} (grid_record;
+                          // single precision only): first stencil node and 24-bit fraction per axis
     uint2* kr;            // [n] {bin key, rank within the bin} of pos_tmp[j]
     void* fbond;          // [n][4] harmonic bond force of sorted bead j {Fx, Fy, Fz, 0} (working precision)
     void* vel;            // GJF only: [n][4] half-step velocity of sorted bead j {ux, uy, uz, 0}
@@ -135,6 +137,10 @@ struct Launch {
     int cu_count;     // compute units of the device
     Phys ph;
 };
+
+// What the spread and interpolation kernels read per sorted bead: grid
+// records in single precision, fixed-point positions in double precision.
+inline const uint4* bead_src(const Launch& L, const DeviceState& S) { return L.precision == 0 ? S.grec : S.pos; }
 
 // Launch helpers; each returns the hipError_t of the launch.
 hipError_t launch_spread_xy(const Launch& L, DeviceState& S);

@@ -117,12 +117,12 @@ __global__ void __launch_bounds__(256) k_stream_copy(uint4* __restrict__ dst, co
 
 size_t plane_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * ((size_t)L.d.npg * (size_t)(2 * L.d.hxp) + (size_t)(L.d.mx + L.d.my + L.d.mz));
+    return c * ((size_t)L.d.npg * (size_t)(2 * L.d.hxp) + (size_t)L.d.ntw());
 }
 
 size_t z_lds_bytes(const Launch& L) {
     const size_t c = L.precision == 0 ? sizeof(float2) : sizeof(double2);
-    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols | 1) + (size_t)(L.d.mx + L.d.my + L.d.mz)) +
+    return c * (4 * (size_t)L.d.mz * (size_t)(L.z_cols | 1) + (size_t)L.d.ntw()) +
            sizeof(ZPlane) * (size_t)L.d.mz + sizeof(ZColumn) * (size_t)L.z_cols;
 }
 
@@ -157,7 +157,8 @@ static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, 
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
     hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
                        (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, out_sign, S.kr,
-                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp, (const RepDesc*)nullptr,
+                       (const uint32_t*)nullptr, 0);
 }
 
 template <typename T, int MODE>
@@ -203,11 +204,13 @@ hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_sr
     if (L.precision == 0)
         hipLaunchKernelGGL((k_scatter<float, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph,
-                           (const float*)S.vel_tmp, (float*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                           (const float*)S.vel_tmp, (float*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
+                           S.grec, S.qshift, L.d, L.order);
     else
         hipLaunchKernelGGL((k_scatter<double, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph,
-                           (const double*)S.vel_tmp, (double*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
+                           (const double*)S.vel_tmp, (double*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
+                           S.grec, S.qshift, L.d, L.order);
     return hipGetLastError();
 }
 

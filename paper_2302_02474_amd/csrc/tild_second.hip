@@ -16,13 +16,13 @@ static hipError_t hvp_b(const Launch& L, DeviceState& S, const void* v, void* ou
             // second-derivative terms against the potential planes of the counts
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
-                               L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
                                (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr);
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
                                (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1);
             // the field of the directional counts, gathered with the weight gradients
             hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
-                               L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                               L.stream, bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                                (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
                                (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr);
         }
@@ -37,7 +37,7 @@ template <typename T, int B> static hipError_t hvp_tail(const Launch& L, DeviceS
         if constexpr (P >= 3) {
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
-                               S.pos, S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                               bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
                                (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
             // those partials are -sum grad W delta phi
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
@@ -52,7 +52,7 @@ template <typename T, int B> static void counts_b(const Launch& L, DeviceState& 
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
         hipLaunchKernelGGL((k_spread_xy<T, B, P, false, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
-                           L.stream, S.pos, S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                           L.stream, bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                            (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part, (const RepDesc*)nullptr,
                            (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)out);
     });
@@ -75,7 +75,7 @@ template <typename T, int B> static void field_b(const Launch& L, DeviceState& S
         if constexpr (P >= 2)
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, false, true>), dim3(L.d.mz, 2), dim3(B),
                                plane_lds_bytes(L), L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py,
-                               (const cplx<T>*)S.tw, L.ph, S.pos, S.bin_start, S.qshift, S.n, S.fsum_part,
+                               (const cplx<T>*)S.tw, L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part,
                                (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr,
                                (const T*)field);
     });
