@@ -63,7 +63,8 @@ __all__ = [
     "nonbonded_energy", "nonbonded_virial", "energy_parameter_gradients", "bond_terms", "evaluate", "em_update",
     "trajectory", "structure_factor_exact", "min_image", "gjf_coefficients", "gjf_trajectory",
     "half_step_velocity", "bspline_deriv2", "spread_directional", "gather_hessian_weights",
-    "bond_hessian_vector", "hessian_vector_product", "density_mse", "em_adjoint", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
+    "bond_hessian_vector", "hessian_vector_product", "density_mse", "em_adjoint", "spread_weighted",
+    "ik_force_jvp", "ik_force_vjp", "coulomb_kernel", "charge_spectrum", "electrostatic_energy", "electrostatic_virial",
 ]
 
 
@@ -465,6 +466,80 @@ def hessian_vector_product(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, 
 
 
 # --------------------------------------------------------------------------
+# Jacobian of the ik-route force (Eq. PMM) for adjoints through its steps
+# --------------------------------------------------------------------------
+
+def spread_weighted(x: np.ndarray, types: np.ndarray, q: np.ndarray, L, M, P: int,
+                    chunk: int = 200000) -> np.ndarray:
+    """c^q_K(g) = sum_{j in K} q_j W_j(g): the counts with one weight q_j per bead.  (2, Mx, My, Mz)."""
+    L = np.asarray(L, dtype=np.float64)
+    M = np.asarray(M, dtype=np.int64)
+    out = np.zeros((2, int(np.prod(M))))
+    types = np.asarray(types)
+    for s, e in _chunks(x.shape[0], chunk):
+        idx, w = stencil(x[s:e], L, M, P)
+        W = (w[:, 0, :, None, None] * w[:, 1, None, :, None] * w[:, 2, None, None, :]).reshape(e - s, -1)
+        W = W * np.asarray(q[s:e], dtype=np.float64)[:, None]
+        lin = _flat_index(idx, M).reshape(e - s, -1)
+        for K in (0, 1):
+            sel = types[s:e] == K
+            out[K] += np.bincount(lin[sel].ravel(), weights=W[sel].ravel(), minlength=out.shape[1])
+    return out.reshape((2,) + tuple(int(m) for m in M))
+
+
+def _field_operator(p: Params, n: int):
+    """c -> the field spectra Phi^ of counts c (the same kernel as the forces, charges included)."""
+    uhat = _uhat(p)
+    charged = p.bjerrum != 0.0 and any(q != 0.0 for q in p.charges)
+    welec = coulomb_kernel(p.L, p.M, p.bjerrum, p.charge_smear) if charged else None
+    return lambda c: field_spectra(dft3(c, p.transform), uhat, p.chi, p.kappa, n, welec, p.charges)
+
+
+def ik_force_jvp(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, v: np.ndarray) -> np.ndarray:
+    """J v with J = dF/dx, F = F^ik + F_bond the ik-route force (Eq. PMM) and the bond force (Eq. bonds):
+      (J v)_i,a = - sum_b v_i,b sum_g d_b W_i(g) d_a phi_{s_i}(g)   (the weights move with bead i)
+                  - sum_g W_i(g) d_a dphi_{s_i}(g)                  (the field moves with every bead)
+                  - (H_b v)_i,a,
+    dphi the field of the directional counts spread_directional(v); the ik force is not a gradient, so J is
+    not symmetric (ik_force_vjp applies its transpose)."""
+    L, M, P = p.L, p.M, p.order
+    n = x.shape[0]
+    field = _field_operator(p, n)
+    grad = gradient_fields(field(spread(x, types, L, M, P)), L, M, p.transform)
+    out = np.zeros((n, 3))
+    for a in range(3):
+        # sum_g grad W_i(g) d_a phi(g) = -gather_gradient_weights(d_a phi)
+        m_a = -gather_gradient_weights(x, types, grad[:, a], L, M, P)
+        out[:, a] -= np.sum(m_a * v, axis=1)
+    dgrad = gradient_fields(field(spread_directional(x, types, v, L, M, P)), L, M, p.transform)
+    out += gather(x, types, dgrad, L, M, P)
+    return out - bond_hessian_vector(bonds, v, p.bond_k)
+
+
+def ik_force_vjp(x: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, lam: np.ndarray) -> np.ndarray:
+    """J^T lam for the J of ik_force_jvp:
+      (J^T lam)_j,b = - sum_a lam_j,a sum_g d_b W_j(g) d_a phi_{s_j}(g)
+                      + sum_g d_b W_j(g) psi_{s_j}(g) - (H_b lam)_j,b,
+    psi = sum_a [d_a phi^(a)], phi^(a) the field of the lam_a-weighted counts spread_weighted(lam_a).  The
+    field term follows from the derivative operators being antisymmetric (i k^D is odd in k, zero on the
+    Nyquist plane) and the pair kernel symmetric."""
+    L, M, P = p.L, p.M, p.order
+    n = x.shape[0]
+    field = _field_operator(p, n)
+    grad = gradient_fields(field(spread(x, types, L, M, P)), L, M, p.transform)
+    out = np.zeros((n, 3))
+    for a in range(3):
+        m_a = -gather_gradient_weights(x, types, grad[:, a], L, M, P)
+        out -= lam[:, a, None] * m_a
+    psi = np.zeros((2,) + tuple(int(m) for m in M))
+    for a in range(3):
+        ga = gradient_fields(field(spread_weighted(x, types, lam[:, a], L, M, P)), L, M, p.transform)
+        psi += ga[:, a]
+    out -= gather_gradient_weights(x, types, psi, L, M, P)
+    return out - bond_hessian_vector(bonds, lam, p.bond_k)
+
+
+# --------------------------------------------------------------------------
 # Energies and virial (Eqs. fh, HelfandP)
 # --------------------------------------------------------------------------
 
@@ -633,23 +708,26 @@ def density_mse(x: np.ndarray, types: np.ndarray, p: Params, target_a: np.ndarra
 
 
 def em_adjoint(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, steps: int, loss_and_grad,
-               t0: int = 0):
-    """Loss after ``steps`` Euler-Maruyama steps from x0 (step indices t0 ..), with the exact-gradient force
-    F = -grad E and the noise held fixed, and its gradients by x0, chi and kappa.
+               t0: int = 0, force: str = "ad"):
+    """Loss after ``steps`` Euler-Maruyama steps from x0 (step indices t0 ..), with the noise held fixed, and
+    its gradients by x0, chi and kappa.  force: "ad" (the exact gradient F = -grad E) or "ik" (Eq. PMM).
 
     Forward: x_{t+1} = x_t + Pr[(dt/gamma) F(x_t) + sqrt(2 kT dt/gamma) xi_t], Pr removing the mean over beads
     when the centre-of-mass correction is on.  Backward, from lambda = dL/dx_K:
         dL/dtheta += (dt/gamma) (Pr lambda) . dF/dtheta(x_t),
-        lambda    <- lambda - (dt/gamma) H(x_t) Pr lambda,
-    for t = K-1 .. 0, H the energy Hessian (dF/dx = -H, symmetric); dF/dchi and dF/dkappa are the forces of
-    the interaction with (chi, kappa) = (1, 0) and (0, 1) (the energy is linear in both).
-    Returns (loss, dL/dx0, {"chi": ..., "kappa": ...})."""
+        lambda    <- lambda + (dt/gamma) J(x_t)^T Pr lambda,
+    for t = K-1 .. 0, J = dF/dx (-H, H the energy Hessian, on the exact-gradient route; ik_force_vjp on the
+    ik route); dF/dchi and dF/dkappa are the forces of the interaction with (chi, kappa) = (1, 0) and (0, 1)
+    (the force is linear in both).  Returns (loss, dL/dx0, {"chi": ..., "kappa": ...})."""
+    if force not in ("ad", "ik"):
+        raise ValueError("force must be 'ad' or 'ik'")
     mu = p.dt / p.gamma
     ids = np.arange(x0.shape[0])
+    key = "F_nb_ad" if force == "ad" else "F_nb"
     xs = [np.array(x0, dtype=np.float64)]
     for t in range(t0, t0 + steps):
-        ev = evaluate(xs[-1], types, bonds, p, want_ad=True)
-        xs.append(em_update(xs[-1], ev["F_nb_ad"] + ev["F_bond"], ids, t, p))
+        ev = evaluate(xs[-1], types, bonds, p, want_ad=force == "ad")
+        xs.append(em_update(xs[-1], ev[key] + ev["F_bond"], ids, t, p))
     loss, lam = loss_and_grad(xs[-1])
     proj = (lambda v: v - v.mean(axis=0)) if p.com_correct else (lambda v: v)
     pure = {k: Params(**{**p.__dict__, "chi": float(k == "chi"), "kappa": float(k == "kappa"), "bjerrum": 0.0,
@@ -659,8 +737,11 @@ def em_adjoint(x0: np.ndarray, types: np.ndarray, bonds: np.ndarray, p: Params, 
         x = xs[t]
         pl = proj(lam)
         for k, q in pure.items():
-            grads[k] += mu * float(np.sum(pl * evaluate(x, types, bonds, q, want_ad=True)["F_nb_ad"]))
-        lam = lam - mu * hessian_vector_product(x, types, bonds, p, pl)
+            grads[k] += mu * float(np.sum(pl * evaluate(x, types, bonds, q, want_ad=force == "ad")[key]))
+        if force == "ad":
+            lam = lam - mu * hessian_vector_product(x, types, bonds, p, pl)
+        else:
+            lam = lam + mu * ik_force_vjp(x, types, bonds, p, pl)
     return loss, lam, grads
 
 

@@ -465,6 +465,87 @@ def test_em_adjoint_matches_finite_differences(com):
     assert abs(fd - np.sum(gx * v)) < 1e-6 * max(abs(fd), 1e-3 * loss)
 
 
+# ------------------------------------------------- Jacobian of the ik-route force
+
+def test_spread_weighted_brute_force_and_unit_weights():
+    p = small_params()
+    x, t, _ = random_system(12, p, seed=41)
+    q = np.random.default_rng(3).normal(size=12)
+    c = R.spread_weighted(x, t, q, p.L, p.M, p.order)
+    # brute force: every bead's 4x4x4 stencil added node by node
+    ref = np.zeros_like(c)
+    idx, w = R.stencil(x, p.L, p.M, p.order)
+    for i in range(12):
+        for a in range(p.order):
+            for b_ in range(p.order):
+                for c_ in range(p.order):
+                    ref[t[i], idx[i, 0, a], idx[i, 1, b_], idx[i, 2, c_]] += q[i] * w[i, 0, a] * w[i, 1, b_] * w[i, 2, c_]
+    np.testing.assert_allclose(c, ref, atol=1e-14)
+    np.testing.assert_allclose(R.spread_weighted(x, t, np.ones(12), p.L, p.M, p.order),
+                               R.spread(x, t, p.L, p.M, p.order), atol=1e-14)
+
+
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+@pytest.mark.parametrize("P", [3, 4, 5])
+def test_ik_force_jvp_matches_finite_differences(extra, P):
+    """J v of the ik-route force (Eq. PMM plus bonds) against central differences of the force along v;
+    the h^2 error of the differences is removed by combining h and 2h."""
+    p = small_params(order=P, **extra)
+    x, t, b = random_system(30, p, seed=43)
+    v = np.random.default_rng(9).normal(size=x.shape)
+    jv = R.ik_force_jvp(x, t, b, p, v)
+    F = lambda y: R.evaluate(y, t, b, p)["F"]
+    h = 1e-4
+    d1 = (F(x + h * v) - F(x - h * v)) / (2 * h)
+    d2 = (F(x + 2 * h * v) - F(x - 2 * h * v)) / (4 * h)
+    fd = (4 * d1 - d2) / 3
+    assert np.linalg.norm(jv - fd) < 1e-7 * np.linalg.norm(fd), np.linalg.norm(jv - fd) / np.linalg.norm(fd)
+    # the ik force is not a gradient: its Jacobian is not symmetric
+    u = np.random.default_rng(10).normal(size=x.shape)
+    assert abs(np.sum(u * jv) - np.sum(v * R.ik_force_jvp(x, t, b, p, u))) > 1e-6 * abs(np.sum(u * jv))
+
+
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+def test_ik_force_vjp_is_the_transpose_of_the_jvp(extra):
+    """lambda . (J v) = (J^T lambda) . v for random lambda and v (J v pinned by finite differences above)."""
+    p = small_params(**extra)
+    x, t, b = random_system(30, p, seed=44)
+    g = np.random.default_rng(11)
+    for _ in range(3):
+        lam, v = g.normal(size=x.shape), g.normal(size=x.shape)
+        lhs = np.sum(lam * R.ik_force_jvp(x, t, b, p, v))
+        rhs = np.sum(R.ik_force_vjp(x, t, b, p, lam) * v)
+        assert abs(lhs - rhs) < 1e-11 * max(abs(lhs), 1.0), (lhs, rhs)
+
+
+@pytest.mark.parametrize("com", [True, False])
+def test_em_adjoint_ik_route_matches_finite_differences(com):
+    """The adjoint through 6 EM steps with the ik-route force: dL/dchi, dL/dkappa and dL/dx0 along a
+    direction against central differences with the noise held fixed."""
+    p = small_params(dt=0.02, com_correct=com)
+    x, t, b = random_system(40, p, seed=32)
+    target = _lamellar_target(p, int(np.sum(t == 0)), p.L[0] / 2)
+    lg = lambda y, q=p: R.density_mse(y, t, q, target)
+    loss, gx, g = R.em_adjoint(x, t, b, p, 6, lg, t0=3, force="ik")
+
+    def run(q, y0):
+        y = y0.copy()
+        for s_ in range(3, 9):
+            ev = R.evaluate(y, t, b, q)
+            y = R.em_update(y, ev["F"], np.arange(40), s_, q)
+        return R.density_mse(y, t, q, target)[0]
+    assert abs(run(p, x) - loss) < 1e-14 * max(1.0, loss)
+    for k in ("chi", "kappa"):
+        h = 1e-4
+        fd = (run(R.Params(**{**p.__dict__, k: getattr(p, k) + h}), x)
+              - run(R.Params(**{**p.__dict__, k: getattr(p, k) - h}), x)) / (2 * h)
+        assert abs(fd - g[k]) < 1e-6 * max(abs(fd), 1e-3 * loss), (k, fd, g[k])
+    v = np.random.default_rng(8).normal(size=x.shape)
+    e = 1e-5
+    fd = (run(p, x + e * v) - run(p, x - e * v)) / (2 * e)
+    assert abs(fd - np.sum(gx * v)) < 1e-6 * max(abs(fd), 1e-3 * loss)
+
+
 def test_bond_closed_form_across_boundary():
     L = np.array([10.0, 10.0, 10.0])
     x = np.array([[9.8, 5.0, 5.0], [0.3, 5.4, 4.5]])
