@@ -391,6 +391,29 @@ int tild_batch_synchronize(tild_batch* batch);
 void tild_batch_destroy(tild_batch* batch);
 const char* tild_batch_last_error(const tild_batch* batch);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): step
+ * n_ctx contexts as one batch, exactly as tild_batch_create + tild_batch_step
+ * + tild_batch_destroy would (bitwise the same positions), without a batch
+ * object and without allocating anything.  The member descriptors, the
+ * work-unit maps and the bin-scan status words go into a fixed 1 MiB
+ * scratch array that the library holds on each device until the process
+ * ends (its address is taken on the first call on that device); a batch
+ * that needs more (a few hundred bytes per member plus 4 bytes per work
+ * unit: about 280 KB for 64 replicas of 5.8 million beads in all) is
+ * rejected with TILD_EINVAL.
+ *   ctxs: as for tild_batch_create; every member must have been created on
+ *         hip_stream (TILD_EINVAL otherwise), and the work is enqueued there.
+ *   n_steps: 0 .. 2^31 - 1.  TILD_ESTATE if a member's positions were never set.
+ * Returns after enqueueing (the host waits only for the previous call's
+ * upload of the maps to have been read).  Calls on one device share the
+ * scratch array and keep the last call's contents: calls whose work
+ * overlaps on the device (different streams, no ordering) race.  Errors are
+ * described by tild_batch_last_error(NULL).
+ */
+int tild_batch_step_static(tild_ctx* const* ctxs, int32_t n_ctx, int64_t n_steps, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -355,6 +355,20 @@ class Batch:
         self.close()
 
 
+def batch_step_static(members: Sequence[Tild], n_steps: int = 1, stream=None):
+    """Step the contexts as one batch without allocating (tild_batch_step_static); every member must have
+    been created on ``stream`` (default: torch's current stream)."""
+    L = lib()
+    arr = (ctypes.c_void_p * len(members))(*[m._ctx.value for m in members])
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
+    rc = L.tild_batch_step_static(arr, len(members), int(n_steps), ctypes.c_void_p(int(handle) if handle else None))
+    if rc != TILD_OK:
+        raise TildError(rc, L.tild_batch_last_error(None).decode())
+
+
 def kernel_names() -> Sequence[str]:
     L = lib()
     return [L.tild_kernel_name(i).decode() for i in range(_L.TILD_NUM_KERNELS)]

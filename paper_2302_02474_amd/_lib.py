@@ -33,6 +33,7 @@ EXPORTS = [
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
     "tild_hvp", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create",
     "tild_batch_autotune", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
+    "tild_batch_step_static",
 ]
 
 
@@ -131,5 +132,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_batch_destroy.restype = None
     lib.tild_batch_last_error.argtypes = [vp]
     lib.tild_batch_last_error.restype = ctypes.c_char_p
+    lib.tild_batch_step_static.argtypes = [P(vp), i32, i64, vp]
+    lib.tild_batch_step_static.restype = ctypes.c_int
     _lib = lib
     return lib

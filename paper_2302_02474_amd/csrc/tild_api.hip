@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1276,3 +1277,185 @@ TILD_API const char* tild_batch_last_error(const tild_batch* b) {
     return b ? b->err.c_str() : g_create_error.c_str();
 }
 
+// ---------------------------------------------------------------- batches without allocations
+//
+// tild_batch_step_static steps a set of contexts as one batch with no batch
+// object: the member descriptors, the unit maps and the bin-scan status words
+// live in this file's `scratch` array, one copy per device, whose address is
+// taken once per device with hipGetSymbolAddress.  The host side builds them
+// in a fixed static staging buffer of the same size.  Nothing is allocated
+// per call; concurrent calls on one device share the array and race.
+
+static constexpr size_t kStaticScratchBytes = 1u << 20;  // 1 MiB per device
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct StaticSlot {
+    void* ptr = nullptr;         // device address of `scratch` on this device
+    hipEvent_t copied = nullptr;  // recorded after the staging buffer's upload
+    bool copy_pending = false;
+};
+StaticSlot g_static[kMaxDevices];
+std::mutex g_static_mu;
+alignas(256) unsigned char g_static_stage[kStaticScratchBytes];  // host staging (guarded by g_static_mu)
+
+__global__ void __launch_bounds__(256) k_zero_u64(unsigned long long* __restrict__ p, long long n) {
+    const long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// Per-device set-up on first use (the device is current): the scratch array's
+// address and the event that guards the staging buffer.
+hipError_t static_slot(int dev, StaticSlot** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    StaticSlot& s = g_static[dev];
+    if (!s.ptr) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        s.ptr = ptr;
+    }
+    *out = &s;
+    return hipSuccess;
+}
+
+}  // namespace
+
+TILD_API int tild_batch_step_static(tild_ctx* const* ctxs, int32_t n_ctx, int64_t n_steps, void* hip_stream) {
+    auto bad = [&](int code, const std::string& why) {
+        g_create_error = "batch_step_static: " + why;
+        return code;
+    };
+    if (!ctxs || n_ctx < 1 || n_ctx > 65535) return bad(TILD_EINVAL, "needs 1..65535 contexts");
+    if (n_steps < 0 || n_steps > 0x7fffffffLL) return bad(TILD_EINVAL, "n_steps must be in [0, 2^31)");
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    const tild_ctx* c0 = ctxs[0];
+    if (!c0) return bad(TILD_EINVAL, "NULL context");
+    for (int32_t i = 0; i < n_ctx; ++i) {
+        const tild_ctx* c = ctxs[i];
+        if (!c) return bad(TILD_EINVAL, "NULL context");
+        for (int32_t k = 0; k < i; ++k)
+            if (ctxs[k] == c) return bad(TILD_EINVAL, "a context appears twice");
+        if (c->device != c0->device) return bad(TILD_EINVAL, "contexts on different devices");
+        if (c->L.stream != stream) return bad(TILD_EINVAL, "every member must use the stream passed in");
+        if (c->L.precision != c0->L.precision || c->L.order != c0->L.order || c->p.flags != c0->p.flags ||
+            c->L.ph.elec != c0->L.ph.elec)
+            return bad(TILD_EINVAL, "contexts differ in precision, order, flags or the presence of charges");
+        if (c->L.force_ad || c->L.ph.gjf) return bad(TILD_EINVAL, "batched steps use the ik route and Euler-Maruyama");
+        if ((c->S.n + 255) / 256 > 65535) return bad(TILD_EINVAL, "a member has more than 16,776,960 beads");
+        if (!c->have_pos) return bad(TILD_ESTATE, "a member's positions were never set");
+    }
+    if (n_steps == 0) return TILD_OK;
+    // scratch layout: descriptors, unit maps (plane, c2r, zcol, bead, tile), scan status words + ticket
+    size_t n_plane = 0, n_c2r = 0, n_zcol = 0, n_bead = 0, n_tile = 0;
+    size_t lds_plane = 0, lds_z = 0;
+    int max_plane = 0;
+    for (int32_t r = 0; r < n_ctx; ++r) {
+        const tild_ctx* c = ctxs[r];
+        n_plane += 2 * (size_t)c->L.d.mz;
+        n_c2r += 6 * (size_t)c->L.d.mz;
+        n_zcol += (size_t)c->L.n_zblocks;
+        n_bead += (size_t)((c->S.n + 255) / 256);
+        n_tile += (size_t)((c->S.nbins + kScanBins - 1) / kScanBins);
+        lds_plane = std::max(lds_plane, plane_lds_bytes(c->L));
+        lds_z = std::max(lds_z, z_lds_bytes(c->L));
+        max_plane = std::max(max_plane, c->L.d.mx * c->L.d.my);
+    }
+    const size_t nmap = n_plane + n_c2r + n_zcol + n_bead + n_tile;
+    const size_t desc_bytes = ((size_t)n_ctx * sizeof(RepDesc) + 255) / 256 * 256;
+    const size_t map_bytes = (nmap * sizeof(uint32_t) + 255) / 256 * 256;
+    const size_t status_words = n_tile + 1;
+    const size_t need = desc_bytes + map_bytes + status_words * sizeof(unsigned long long);
+    if (need > kStaticScratchBytes)
+        return bad(TILD_EINVAL, "the batch needs " + std::to_string(need) + " bytes of scratch; the limit is " +
+                                    std::to_string(kStaticScratchBytes));
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    DeviceGuard g(c0->device);
+    StaticSlot* slot = nullptr;
+    hipError_t e = static_slot(c0->device, &slot);
+    if (e != hipSuccess) return bad(TILD_EHIP, std::string("scratch set-up: ") + hipGetErrorString(e));
+    // the previous call's upload must have left the staging buffer
+    if (slot->copy_pending) {
+        e = hipEventSynchronize(slot->copied);
+        if (e != hipSuccess) return bad(TILD_EHIP, std::string("staging wait: ") + hipGetErrorString(e));
+        slot->copy_pending = false;
+    }
+    unsigned char* dev = static_cast<unsigned char*>(slot->ptr);
+    RepDesc* h_desc = reinterpret_cast<RepDesc*>(g_static_stage);
+    uint32_t* h_map = reinterpret_cast<uint32_t*>(g_static_stage + desc_bytes);
+    unsigned long long* d_status = reinterpret_cast<unsigned long long*>(dev + desc_bytes + map_bytes);
+    uint32_t* mp = h_map;
+    uint32_t* mc = mp + n_plane;
+    uint32_t* mz = mc + n_c2r;
+    uint32_t* mb = mz + n_zcol;
+    uint32_t* mt = mb + n_bead;
+    size_t status_off = 0;
+    for (int32_t r = 0; r < n_ctx; ++r) {
+        const tild_ctx* c = ctxs[r];
+        const Dims& d = c->L.d;
+        const uint32_t hi = (uint32_t)r << 16;
+        for (int u = 0; u < 2 * d.mz; ++u) *mp++ = hi | (uint32_t)u;
+        for (int u = 0; u < 6 * d.mz; ++u) *mc++ = hi | (uint32_t)u;
+        for (int u = 0; u < c->L.n_zblocks; ++u) *mz++ = hi | (uint32_t)u;
+        for (long long u = 0; u < (c->S.n + 255) / 256; ++u) *mb++ = hi | (uint32_t)u;
+        const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
+        for (int u = 0; u < ntiles; ++u) *mt++ = hi | (uint32_t)u;
+        RepDesc& R = h_desc[r];
+        std::memset(&R, 0, sizeof(R));
+        R.d = c->L.d;
+        R.px = c->L.px;
+        R.py = c->L.py;
+        R.pz = c->L.pz;
+        R.ph = c->L.ph;
+        R.S = c->S;
+        R.S.scan_status = d_status + status_off;
+        R.z_cols = c->L.z_cols;
+        R.n_zblocks = c->L.n_zblocks;
+        R.ntiles = ntiles;
+        R.step0 = (uint64_t)c->step;
+        status_off += (size_t)ntiles;
+    }
+    Launch L = c0->L;
+    L.stream = stream;
+    BatchMaps B{};
+    B.reps = reinterpret_cast<const RepDesc*>(dev);
+    B.plane = reinterpret_cast<const uint32_t*>(dev + desc_bytes);
+    B.c2r = B.plane + n_plane;
+    B.zcol = B.c2r + n_c2r;
+    B.bead = B.zcol + n_zcol;
+    B.tile = B.bead + n_bead;
+    B.n_plane = (int)n_plane;
+    B.n_c2r = (int)n_c2r;
+    B.n_zcol = (int)n_zcol;
+    B.n_bead = (int)n_bead;
+    B.n_tile = (int)n_tile;
+    B.ticket = d_status + n_tile;
+    B.plane_block = max_plane <= 96 * 96 ? 256 : 512;
+    e = hipMemcpyAsync(dev, g_static_stage, desc_bytes + nmap * sizeof(uint32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(slot->copied, stream);
+    if (e == hipSuccess) slot->copy_pending = true;
+    // the scan's status words and ticket start at zero: the previous call left later epochs in them
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((status_words + 255) / 256)), dim3(256), 0, stream, d_status,
+                           (long long)status_words);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = configure_batch_attributes(L, lds_plane, lds_z);
+    for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s) e = launch_batch_step(L, B, (int)s, lds_plane, lds_z);
+    if (e != hipSuccess) return bad(TILD_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+    for (int32_t r = 0; r < n_ctx; ++r) {
+        tild_ctx* c = ctxs[r];
+        if (n_steps & 1) {
+            std::swap(c->S.qshift, c->S.qshift_next);
+            std::swap(c->S.nbr, c->S.nbr_old);
+        }
+        c->step += n_steps;
+    }
+    return TILD_OK;
+}
