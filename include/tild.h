@@ -122,9 +122,12 @@ extern "C" {
                                    carried between steps is the half-step velocity
                                    u = D / (sqrt(b) dt) (tild_set_velocities, tild_get_velocities; zero
                                    at creation).  With TILD_COM_CORRECT the mean of D is removed. */
-#define TILD_DETERMINISTIC 4u /* accepted for compatibility: every result is already bitwise reproducible
-                                 run to run (the spread accumulates fixed-point integers in both precisions,
-                                 every reduction has a fixed order) */
+#define TILD_DETERMINISTIC 4u /* accepted for compatibility: steps, forces and energies are already bitwise
+                                 reproducible run to run (the spread accumulates fixed-point integers in
+                                 both precisions, every reduction has a fixed order).  The directional and
+                                 weighted counts of tild_hvp, tild_force_vjp and tild_adjoint_step are
+                                 summed with floating-point atomics: those results vary at the rounding
+                                 level (about 1e-13 relative in FP64) */
 
 /* tild_forces parts */
 #define TILD_PART_NONBONDED 1u
@@ -351,6 +354,42 @@ int tild_field_forces(tild_ctx* ctx, const void* field, void* out, int32_t dtype
 int tild_hvp(tild_ctx* ctx, const void* v, void* out, int32_t dtype, int32_t on_device);
 
 /*
+ * Transposed Jacobian of the context's force at the current positions:
+ *   out = (dF/dx)^T lam,  F = the non-bonded force of the context's route plus the bond force.
+ * On the ik route (Eq. PMM with Eq. bonds; F^ik is not the gradient of an
+ * energy, so dF/dx is not symmetric) this is
+ *   out_j = -sum_a lam_j,a sum_g grad W_j(g) d_a phi_{s_j}(g)          (the weights move with bead j)
+ *           + sum_g grad W_j(g) psi_{s_j}(g)                            (the field moves with every bead)
+ *           - (H_b lam)_j,
+ * psi = sum_a d_a phi^(a), phi^(a) the field of the counts sum_i lam_i,a W_i
+ * (the derivative operators i k^D are antisymmetric, the pair kernel
+ * symmetric); on the exact-gradient route it is -H lam (tild_hvp).
+ * lam, out: [n_beads][3] in ABI order, dtype, both host or both device
+ * memory (on_device).  Needs order >= 2 (ik) or >= 3 (exact gradient),
+ * TILD_EINVAL otherwise.  Host calls synchronise.
+ */
+int tild_force_vjp(tild_ctx* ctx, const void* lam, void* out, int32_t dtype, int32_t on_device);
+
+/*
+ * One backward step of the adjoint of Euler-Maruyama steps (Eq. EM with the
+ * context's force and its noise held fixed), at the current positions x_t:
+ *   dtheta[0] += (dt/gamma) (Pr lam) . dF/dchi(x_t),
+ *   dtheta[1] += (dt/gamma) (Pr lam) . dF/dkappa(x_t),
+ *   lam       <- lam + (dt/gamma) (dF/dx)(x_t)^T Pr lam,
+ * Pr removing the mean over the beads when TILD_COM_CORRECT is set; dF/dchi
+ * and dF/dkappa are the non-bonded forces with (chi, kappa) = (1, 0) and
+ * (0, 1) and no charges (the force is linear in both).  Run backwards over
+ * t = K-1 .. 0 from lam = dL/dx_K it gives dL/dx_0 and dL/d(chi, kappa).
+ *   lam:    device [n_beads][3] float64, ABI order, updated in place.
+ *   dtheta: device float64[2], added to.
+ * Asynchronous on the context's stream; its own sums run in a fixed order,
+ * while the transposed Jacobian accumulates grid counts with floating-point
+ * atomics (results vary at the rounding level).  Euler-Maruyama contexts
+ * with order >= 2 (ik) or >= 3 (exact gradient).
+ */
+int tild_adjoint_step(tild_ctx* ctx, double* lam, double* dtheta);
+
+/*
  * Batches: independent contexts (replicas of uneven box, grid and bead
  * count: the multiple boxes of replica exchange, parallel tempering or Gibbs
  * ensemble sampling the paper plans, Sec. "Planned future developments")
@@ -380,13 +419,24 @@ int tild_batch_step(tild_batch* batch, int64_t n_steps);
 /*
  * Choose the batch's plane-workgroup size (256 or 512 threads; the default
  * is set from the largest member plane) by timing trial_steps (1..1000)
- * batched steps with each, twice, on the members' own systems.  Every
- * member's positions and step counter are restored after each trial, so the
- * simulation state is unchanged (bitwise).  Synchronises; needs a temporary
- * device buffer of 24 bytes per bead.  The choice is stored in
- * *plane_block when it is not NULL.
+ * batched steps with each, twice, on the members' own systems with eager
+ * launches, then whether replaying the steps from a captured HIP graph is
+ * faster with that size.  Every member's positions and step counter are
+ * restored after each trial, so the simulation state is unchanged
+ * (bitwise).  Synchronises; needs a temporary device buffer of 24 bytes per
+ * bead.  The choices are stored in *plane_block (threads) and *graph (1 =
+ * graph replay) when those are not NULL.
  */
-int tild_batch_autotune(tild_batch* batch, int32_t trial_steps, int32_t* plane_block);
+int tild_batch_autotune(tild_batch* batch, int32_t trial_steps, int32_t* plane_block, int32_t* graph);
+/*
+ * Replay batched steps from captured HIP graphs (use_graph != 0, the default)
+ * or launch every kernel of every step from the host (0).  With graphs, the
+ * first call asking for n_steps steps captures them (every batched kernel of
+ * every step, on a private stream) and later calls of that many steps
+ * replay the graph after uploading the members' descriptors; a change of
+ * step count or plane-workgroup size captures again.
+ */
+int tild_batch_set_graph(tild_batch* batch, int32_t use_graph);
 int tild_batch_synchronize(tild_batch* batch);
 void tild_batch_destroy(tild_batch* batch);
 const char* tild_batch_last_error(const tild_batch* batch);

@@ -279,6 +279,37 @@ class Tild:
         self._check(self._lib.tild_hvp(self._ctx, pv, po, _dtype_code(v), dv))
         return out
 
+    def force_vjp(self, lam, out=None):
+        """(dF/dx)^T lam for the context's force (route and bonds) at the current positions ([n][3], ABI
+        order); lam and out both host arrays or both CUDA tensors (out defaults to lam's dtype)."""
+        if _is_torch(lam):
+            import torch
+            lam = lam.contiguous()
+            if out is None:
+                out = torch.empty_like(lam)
+        else:
+            lam = np.ascontiguousarray(lam)
+            if out is None:
+                out = np.empty_like(lam)
+        pv, dv = _ptr(lam)
+        po, do = _ptr(out)
+        if dv != do:
+            raise ValueError("lam and out must both be host arrays or both device tensors")
+        self._check(self._lib.tild_force_vjp(self._ctx, pv, po, _dtype_code(lam), dv))
+        return out
+
+    def adjoint_step(self, lam, dtheta):
+        """One backward Euler-Maruyama adjoint step at the current positions (tild_adjoint_step): lam, a
+        float64 CUDA tensor [n][3] (ABI order), is updated in place and dtheta, a float64 CUDA tensor [2],
+        receives the chi and kappa terms."""
+        import torch
+        if not (_is_torch(lam) and lam.is_cuda and lam.dtype == torch.float64 and lam.is_contiguous()):
+            raise ValueError("lam must be a contiguous float64 CUDA tensor")
+        if not (_is_torch(dtheta) and dtheta.is_cuda and dtheta.dtype == torch.float64 and dtheta.numel() >= 2):
+            raise ValueError("dtheta must be a float64 CUDA tensor of two values")
+        self._check(self._lib.tild_adjoint_step(self._ctx, ctypes.c_void_p(lam.data_ptr()),
+                                                ctypes.c_void_p(dtheta.data_ptr())))
+
     def set_interaction(self, chi: float, kappa: float, smear_a: float):
         self._check(self._lib.tild_set_interaction(self._ctx, float(chi), float(kappa), float(smear_a)))
 
@@ -317,6 +348,7 @@ class Batch:
         self._stream_obj = stream
         handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
         self._stream = ctypes.c_void_p(int(handle) if handle else None)
+        self.graph = True
         rc = self._lib.tild_batch_create(arr, len(self.members), self._stream, ctypes.byref(self._b))
         if rc != TILD_OK:
             raise TildError(rc, self._lib.tild_batch_last_error(None).decode())
@@ -332,10 +364,17 @@ class Batch:
         self._check(self._lib.tild_batch_synchronize(self._b))
 
     def autotune(self, trial_steps: int = 4) -> int:
-        """Time the plane-workgroup sizes on the members' own systems (state restored) and keep the fastest."""
-        pb = ctypes.c_int32(0)
-        self._check(self._lib.tild_batch_autotune(self._b, int(trial_steps), ctypes.byref(pb)))
+        """Time the plane-workgroup sizes and graph replay on the members' own systems (state restored) and
+        keep the fastest; returns the plane-workgroup size (self.graph tells whether graphs are replayed)."""
+        pb, gr = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self._lib.tild_batch_autotune(self._b, int(trial_steps), ctypes.byref(pb), ctypes.byref(gr)))
+        self.graph = bool(gr.value)
         return pb.value
+
+    def set_graph(self, use_graph: bool):
+        """Replay batched steps from captured HIP graphs (True, the default) or launch them eagerly."""
+        self._check(self._lib.tild_batch_set_graph(self._b, 1 if use_graph else 0))
+        self.graph = bool(use_graph)
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:

@@ -31,9 +31,9 @@ EXPORTS = [
     "tild_get_velocities", "tild_step", "tild_forces",
     "tild_energy", "tild_energy_grad", "tild_set_interaction", "tild_step_count", "tild_set_step_count", "tild_synchronize", "tild_destroy",
     "tild_last_error", "tild_profile_steps", "tild_kernel_name", "tild_stream_copy",
-    "tild_hvp", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create",
+    "tild_hvp", "tild_force_vjp", "tild_adjoint_step", "tild_interaction_forces", "tild_counts", "tild_field_forces", "tild_batch_create",
     "tild_batch_autotune", "tild_batch_step", "tild_batch_synchronize", "tild_batch_destroy", "tild_batch_last_error",
-    "tild_batch_step_static",
+    "tild_batch_step_static", "tild_batch_set_graph",
 ]
 
 
@@ -120,9 +120,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_field_forces.restype = ctypes.c_int
     lib.tild_hvp.argtypes = [vp, vp, vp, i32, i32]
     lib.tild_hvp.restype = ctypes.c_int
+    lib.tild_force_vjp.argtypes = [vp, vp, vp, i32, i32]
+    lib.tild_force_vjp.restype = ctypes.c_int
+    lib.tild_adjoint_step.argtypes = [vp, vp, vp]
+    lib.tild_adjoint_step.restype = ctypes.c_int
     lib.tild_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
     lib.tild_batch_create.restype = ctypes.c_int
-    lib.tild_batch_autotune.argtypes = [vp, i32, P(i32)]
+    lib.tild_batch_autotune.argtypes = [vp, i32, P(i32), P(i32)]
     lib.tild_batch_autotune.restype = ctypes.c_int
     lib.tild_batch_step.argtypes = [vp, i64]
     lib.tild_batch_step.restype = ctypes.c_int
@@ -133,6 +137,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_batch_last_error.argtypes = [vp]
     lib.tild_batch_last_error.restype = ctypes.c_char_p
     lib.tild_batch_step_static.argtypes = [P(vp), i32, i64, vp]
+    lib.tild_batch_set_graph.argtypes = [vp, i32]
+    lib.tild_batch_set_graph.restype = ctypes.c_int
     lib.tild_batch_step_static.restype = ctypes.c_int
     _lib = lib
     return lib

@@ -1,22 +1,21 @@
 """Backpropagation through Euler-Maruyama steps (adjoint with checkpoints).
 
-The forward run is the library's own stepping (tild_step) on the
-exact-gradient route, so that the force is F = -grad E and its Jacobian is
--H, H the energy Hessian (symmetric).  With the noise of every step held
-fixed (it is a pure function of seed, bead id and step index) the step map is
+The forward run is the library's own stepping (tild_step), on either force
+route.  With the noise of every step held fixed (it is a pure function of
+seed, bead id and step index) the step map is
   x_{t+1} = x_t + Pr[(dt/gamma) F(x_t) + sqrt(2 kT dt/gamma) xi_t],
-Pr removing the mean over beads when the centre-of-mass correction is on, and
-the adjoint of a loss L(x_K) runs backwards as
+Pr removing the mean over beads when the centre-of-mass correction is on,
+and the adjoint of a loss L(x_K) runs backwards as
   dL/dtheta += (dt/gamma) (Pr lambda) . dF/dtheta(x_t),
-  lambda    <- lambda - (dt/gamma) H(x_t) Pr lambda          (tild_hvp),
-for t = K-1 .. 0, from lambda = dL/dx_K.  Positions are kept every
+  lambda    <- lambda + (dt/gamma) (dF/dx)(x_t)^T Pr lambda,
+for t = K-1 .. 0, from lambda = dL/dx_K: one library call per step
+(tild_adjoint_step: the projection, the transposed force Jacobian of the
+context's route -- the ik route's, or -H on the exact-gradient route -- and
+the chi and kappa terms, all on the device).  Positions are kept every
 ``checkpoint`` steps and each segment is recomputed once on the way back.
-The energy is linear in chi and kappa, so dF/dchi and dF/dkappa are the
-forces of the interaction with (chi, kappa) = (1, 0) and (0, 1) and no
-charges (tild_interaction_forces).
 
-Every array stays on the device (torch CUDA tensors); the library's kernels
-do the spreads, transforms, gathers and Hessian products.
+This module only orders the calls and holds device memory; the loss is the
+caller's (density_mse for the differentiation workload).
 """
 
 from __future__ import annotations
@@ -25,7 +24,7 @@ from typing import Callable, Dict, Tuple
 
 import numpy as np
 
-from . import TILD_COM_CORRECT, TILD_FORCE_AD, TILD_FP32, Tild
+from . import TILD_FP32, Tild
 
 
 def _torch():
@@ -58,14 +57,11 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
                checkpoint: int = 10, t0: int = None) -> Tuple[float, "object", Dict[str, float]]:
     """Loss after ``steps`` steps from positions x0 (an (n, 3) array or CUDA tensor) starting at step index
     t0 (default: the context's step counter), and its gradients: (loss, dL/dx0 as a float64 CUDA tensor,
-    {"chi": dL/dchi, "kappa": dL/dkappa}).  The context must use the exact-gradient route (TILD_FORCE_AD)
-    and order >= 3; on return it holds the final positions and step counter."""
+    {"chi": dL/dchi, "kappa": dL/dkappa}).  The context integrates with Euler-Maruyama on either force route
+    (order >= 2 on the ik route, >= 3 on the exact-gradient route); on return it holds the final positions
+    and step counter."""
     torch = _torch()
     p = tild.params
-    if not (p.flags & TILD_FORCE_AD):
-        raise ValueError("em_adjoint needs a context on the exact-gradient route (force='ad')")
-    mu = p.dt / p.gamma
-    com = bool(p.flags & TILD_COM_CORRECT)
     t0 = tild.step_count if t0 is None else int(t0)
     x0 = torch.as_tensor(np.asarray(x0) if not hasattr(x0, "is_cuda") else x0, dtype=torch.float64).cuda()
 
@@ -85,9 +81,8 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
         done += k
         ck[done] = positions()
     loss, lam = loss_grad(tild)
-    lam = lam.double()
-    acc = {k: torch.zeros((), dtype=torch.float64, device="cuda") for k in ("chi", "kappa")}
-    f = torch.empty((tild.n, 3), dtype=torch.float64, device="cuda")
+    lam = lam.double().contiguous()
+    dtheta = torch.zeros(2, dtype=torch.float64, device="cuda")
     starts = sorted(ck)[:-1]
     try:
         for s0 in reversed(starts):
@@ -100,12 +95,10 @@ def em_adjoint(tild: Tild, x0, steps: int, loss_grad: Callable[[Tild], Tuple[flo
                 xs.append(positions())
             for t in range(s1 - 1, s0 - 1, -1):
                 tild.set_positions(xs[t - s0])
-                pl = lam - lam.mean(dim=0, keepdim=True) if com else lam
-                for name, (cc, kk) in (("chi", (1.0, 0.0)), ("kappa", (0.0, 1.0))):
-                    tild.interaction_forces(cc, kk, with_charges=False, out=f)
-                    acc[name] += (pl * f).sum()
-                lam = lam - mu * tild.hvp(pl.contiguous())
+                tild.step_count = t0 + t
+                tild.adjoint_step(lam, dtheta)
     finally:
         tild.set_positions(ck[steps])
         tild.step_count = t0 + steps
-    return loss, lam, {k: mu * float(v) for k, v in acc.items()}
+    g = dtheta.cpu().numpy()
+    return loss, lam, {"chi": float(g[0]), "kappa": float(g[1])}

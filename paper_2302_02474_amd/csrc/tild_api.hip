@@ -523,9 +523,12 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
         A(&S.vel, npos * 4 * real_sz);
         A(&S.vel_tmp, npos * 4 * real_sz);
     }
-    if (params->order >= 3) {  // Hessian-vector products
+    if (params->order >= 2) {  // Hessian-vector products (order >= 3), Jacobian products and adjoint steps
         A(&S.vdir, npos * 4 * real_sz);
         A(&S.hacc, npos * 4 * real_sz);
+        A(&S.field, 2 * (size_t)d.m * real_sz);
+        A((void**)&S.adj, npos * 3 * sizeof(double));
+        A((void**)&S.apart, (size_t)L.n_bblocks * 4 * sizeof(double));
     }
     const size_t nbins_pad = ((size_t)S.nbins + 32) / 32 * 32 + 32;  // vector scan reads whole 32-bin groups
     A((void**)&S.counts, nbins_pad * sizeof(uint32_t));
@@ -868,6 +871,92 @@ TILD_API int tild_hvp(tild_ctx* c, const void* v, void* out, int32_t dtype, int3
     return TILD_OK;
 }
 
+namespace {
+
+// out (device, dtype) = (dF/dx)^T lam (device, dtype) at the current positions, F the context's force
+// (non-bonded route and bonds): the ik route's transposed Jacobian, or -H lam on the exact-gradient route.
+hipError_t force_vjp(tild_ctx* c, const void* lam, void* out, int dtype) {
+    if (!c->L.force_ad) return launch_force_vjp_ik(c->L, c->S, lam, out, dtype);
+    hipError_t e = launch_hvp(c->L, c->S, lam, out, dtype);
+    if (e == hipSuccess) e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kScale, out, nullptr, dtype, -1.0, nullptr);
+    return e;
+}
+
+// Non-bonded forces of the interaction (chi, kappa), no charges, on the context's route, to out (device,
+// float64, ABI order).
+hipError_t pure_interaction_forces(tild_ctx* c, double chi, double kappa, double* out) {
+    Launch L = c->L;
+    L.ph.chi = chi;
+    L.ph.kappa = kappa;
+    L.ph.elec = 0;
+    hipError_t e = launch_spread_xy(L, c->S);
+    if (e == hipSuccess) e = launch_z_kmul(L, c->S, false);
+    if (e == hipSuccess) e = launch_xy_c2r(L, c->S);
+    if (e == hipSuccess) e = launch_update(L, c->S, 1, (uint64_t)c->step, out, TILD_FP64, TILD_PART_NONBONDED);
+    return e;
+}
+
+}  // namespace
+
+TILD_API int tild_force_vjp(tild_ctx* c, const void* lam, void* out, int32_t dtype, int32_t on_device) {
+    if (!c) return TILD_EINVAL;
+    if (((!lam || !out) && c->S.n > 0) || (dtype != TILD_FP32 && dtype != TILD_FP64))
+        return c->fail(TILD_EINVAL, "force_vjp: NULL array or bad dtype");
+    if (c->L.order < (c->L.force_ad ? 3 : 2))
+        return c->fail(TILD_EINVAL, "force_vjp: needs order >= 2 (ik route) or >= 3 (exact-gradient route)");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    DeviceGuard g(c->device);
+    const size_t bytes = (size_t)c->S.n * 3 * (dtype == TILD_FP32 ? 4 : 8);
+    hipError_t e = hipSuccess;
+    const void* src = lam;
+    if (!on_device && c->S.n > 0) {
+        for (int64_t i = 0; i < c->S.n * 3; ++i) {
+            const double x = dtype == TILD_FP32 ? (double)((const float*)lam)[i] : ((const double*)lam)[i];
+            if (!std::isfinite(x)) return c->fail(TILD_EINVAL, "force_vjp: non-finite vector");
+        }
+        e = hipMemcpyAsync(c->staging, lam, bytes, hipMemcpyHostToDevice, c->L.stream);
+        src = c->staging;
+    }
+    void* dst = on_device ? out : c->staging;  // lam is read before the result is written (stream order)
+    if (e == hipSuccess && c->S.n > 0) e = force_vjp(c, src, dst, dtype);
+    if (e == hipSuccess && !on_device && bytes) e = hipMemcpyAsync(out, c->staging, bytes, hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return c->hip_fail(e, "force_vjp");
+    if (!on_device) return check_flag(c);
+    return TILD_OK;
+}
+
+TILD_API int tild_adjoint_step(tild_ctx* c, double* lam, double* dtheta) {
+    if (!c) return TILD_EINVAL;
+    if ((!lam && c->S.n > 0) || !dtheta) return c->fail(TILD_EINVAL, "adjoint_step: NULL array");
+    if (c->L.order < (c->L.force_ad ? 3 : 2))
+        return c->fail(TILD_EINVAL, "adjoint_step: needs order >= 2 (ik route) or >= 3 (exact-gradient route)");
+    if (c->L.ph.gjf) return c->fail(TILD_EINVAL, "adjoint_step: Euler-Maruyama contexts only");
+    if (!c->have_pos) return c->fail(TILD_ESTATE, "positions were never set");
+    if (c->S.n == 0) return TILD_OK;
+    DeviceGuard g(c->device);
+    const double mu = c->p.dt / c->p.gamma;
+    double* pl = static_cast<double*>(c->staging);
+    double* mean = c->S.eout + 12;  // eout[12..14]: the mean of lambda
+    hipError_t e = hipSuccess;
+    // Pr lambda: lambda minus its mean over the beads with centre-of-mass correction
+    if (c->L.ph.com_correct)
+        e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kMean, lam, nullptr, TILD_FP64, 0.0, mean);
+    if (e == hipSuccess)
+        e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kProject, lam, pl, TILD_FP64, 0.0,
+                                   c->L.ph.com_correct ? mean : nullptr);
+    // dL/dtheta += mu (Pr lambda) . dF/dtheta, dF/dchi and dF/dkappa the forces of the pure interactions
+    if (e == hipSuccess) e = pure_interaction_forces(c, 1.0, 0.0, c->S.adj);
+    if (e == hipSuccess) e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kDotAdd, pl, c->S.adj, TILD_FP64, mu, dtheta);
+    if (e == hipSuccess) e = pure_interaction_forces(c, 0.0, 1.0, c->S.adj);
+    if (e == hipSuccess)
+        e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kDotAdd, pl, c->S.adj, TILD_FP64, mu, dtheta + 1);
+    // lambda += mu J^T Pr lambda
+    if (e == hipSuccess) e = force_vjp(c, pl, c->S.adj, TILD_FP64);
+    if (e == hipSuccess) e = launch_adjoint_vectors(c->L, c->S, AdjointOp::kAxpy, lam, c->S.adj, TILD_FP64, mu, nullptr);
+    if (e != hipSuccess) return c->hip_fail(e, "adjoint_step");
+    return TILD_OK;
+}
+
 TILD_API int tild_set_interaction(tild_ctx* c, double chi, double kappa, double smear_a) {
     if (!c) return TILD_EINVAL;
     if (!std::isfinite(chi) || !std::isfinite(kappa) || !std::isfinite(smear_a) || smear_a < 0.0)
@@ -1008,6 +1097,22 @@ TILD_API int tild_stream_copy(void* dst, const void* src, size_t bytes, int32_t 
 
 // ---------------------------------------------------------------- batches
 
+namespace {
+
+// Member indices ordered by grid size (then bead count), largest first.
+std::vector<int32_t> members_by_size(tild_ctx* const* ctxs, int32_t n_ctx) {
+    std::vector<int32_t> order((size_t)n_ctx);
+    for (int32_t r = 0; r < n_ctx; ++r) order[(size_t)r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const tild_ctx *ca = ctxs[a], *cb = ctxs[b];
+        if (ca->L.d.m != cb->L.d.m) return ca->L.d.m > cb->L.d.m;
+        return ca->S.n > cb->S.n;
+    });
+    return order;
+}
+
+}  // namespace
+
 struct tild_batch {
     std::vector<tild_ctx*> ctx;
     hipStream_t stream = nullptr;
@@ -1023,7 +1128,20 @@ struct tild_batch {
     std::vector<hipEvent_t> member_ev;
     hipEvent_t copy_ev = nullptr, done_ev = nullptr;
     bool copy_pending = false;
+    // steps replayed from a captured graph: n_steps launches of every batched kernel, captured on a
+    // private stream the first time a call asks for that many steps
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t exec_steps = 0;
+    int exec_block = 0;  // plane_block the graph was captured with
     std::string err;
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        exec_steps = 0;
+    }
 
     int fail(int code, const std::string& msg) {
         err = msg;
@@ -1048,6 +1166,8 @@ TILD_API void tild_batch_destroy(tild_batch* b) {
             if (e) (void)hipEventDestroy(e);
         if (b->copy_ev) (void)hipEventDestroy(b->copy_ev);
         if (b->done_ev) (void)hipEventDestroy(b->done_ev);
+        b->drop_graph();
+        if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     }
     delete b;
 }
@@ -1085,10 +1205,12 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
     b->L = c0->L;
     b->L.stream = b->stream;
     DeviceGuard g(b->device);
-    // unit maps, member by member; every member's scan keeps its own status words
+    // unit maps, member by member, the largest grids first (their planes and column blocks take longest,
+    // so the last round of workgroups holds the short ones); every member's scan keeps its own status words
     std::vector<uint32_t> plane, c2r, zcol, bead, tile;
     size_t nstatus = 0;
-    for (int32_t r = 0; r < n_ctx; ++r) {
+    b->status_off.assign((size_t)n_ctx, 0);
+    for (const int32_t r : members_by_size(ctxs, n_ctx)) {
         const tild_ctx* c = ctxs[r];
         const Dims& d = c->L.d;
         const uint32_t hi = (uint32_t)r << 16;
@@ -1098,7 +1220,7 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
         for (long long u = 0; u < (c->S.n + 255) / 256; ++u) bead.push_back(hi | (uint32_t)u);
         const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
         for (int u = 0; u < ntiles; ++u) tile.push_back(hi | (uint32_t)u);
-        b->status_off.push_back(nstatus);
+        b->status_off[(size_t)r] = nstatus;
         nstatus += (size_t)ntiles;
         b->lds_plane = std::max(b->lds_plane, plane_lds_bytes(c->L));
         b->lds_z = std::max(b->lds_z, z_lds_bytes(c->L));
@@ -1118,6 +1240,7 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
         e = hipEventCreateWithFlags(&b->member_ev[(size_t)r], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copy_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = configure_batch_attributes(b->L, b->lds_plane, b->lds_z);
     if (e != hipSuccess) {
         g_create_error = std::string("batch: device setup: ") + hipGetErrorString(e);
@@ -1180,8 +1303,33 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
         e = hipMemcpyAsync(b->d_desc, b->h_desc, b->ctx.size() * sizeof(RepDesc), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->copy_ev, b->stream);
     if (e == hipSuccess) b->copy_pending = true;
-    for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
-        e = launch_batch_step(b->L, b->B, (int)s, b->lds_plane, b->lds_z);
+    if (e == hipSuccess && b->use_graph) {
+        if (!b->exec || b->exec_steps != n_steps || b->exec_block != b->B.plane_block) {
+            // the kernels read every member's state from the descriptors uploaded above, so the graph
+            // of n_steps steps serves every later call of that many steps
+            b->drop_graph();
+            Launch Lc = b->L;
+            Lc.stream = b->cap_stream;
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
+                e = launch_batch_step(Lc, b->B, (int)s, b->lds_plane, b->lds_z);
+            const hipError_t ec = hipStreamEndCapture(b->cap_stream, &graph);
+            if (e == hipSuccess) e = ec;
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess) {
+                b->exec_steps = n_steps;
+                b->exec_block = b->B.plane_block;
+            } else {
+                b->drop_graph();
+            }
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
+    } else {
+        for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
+            e = launch_batch_step(b->L, b->B, (int)s, b->lds_plane, b->lds_z);
+    }
     if (e != hipSuccess) return b->hip_fail(e, "batch step");
     // the members' pointer pairs swap once per step; their step counters advance
     for (tild_ctx* c : b->ctx) {
@@ -1198,7 +1346,7 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
     return TILD_OK;
 }
 
-TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* plane_block) {
+TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* plane_block, int32_t* graph) {
     if (!b) return TILD_EINVAL;
     if (trial_steps < 1 || trial_steps > 1000) return b->fail(TILD_EINVAL, "autotune: trial_steps must be in [1, 1000]");
     for (tild_ctx* c : b->ctx)
@@ -1223,41 +1371,59 @@ TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* pl
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
-    const int cand[2] = {256, 512};
-    float best_ms[2] = {1e30f, 1e30f};
-    const int keep = b->B.plane_block;
+    const int keep_block = b->B.plane_block;
+    const bool keep_graph = b->use_graph;
     int rc = TILD_OK;
-    // each candidate twice, alternating; the state is restored after every trial
-    for (int rep = 0; rep < 4 && e == hipSuccess && rc == TILD_OK; ++rep) {
-        const int k = rep & 1;
-        b->B.plane_block = cand[k];
+    // one trial: trial_steps batched steps, timed on the batch's stream, the state restored afterwards
+    auto trial = [&](int block, bool use_graph) -> float {
+        b->B.plane_block = block;
+        b->use_graph = use_graph;
+        float ms = 1e30f;
         for (size_t r = 0; e == hipSuccess && r < b->ctx.size(); ++r) {
             e = hipEventRecord(b->member_ev[r], b->ctx[r]->L.stream);
             if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->member_ev[r], 0);
         }
         if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
-        if (e == hipSuccess) rc = tild_batch_step(b, trial_steps);
+        if (e == hipSuccess && rc == TILD_OK) rc = tild_batch_step(b, trial_steps);
         if (rc == TILD_OK && e == hipSuccess) e = hipEventRecord(t1, b->stream);
         if (rc == TILD_OK && e == hipSuccess) e = hipEventSynchronize(t1);
-        float ms = 0.f;
         if (rc == TILD_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        if (rc == TILD_OK && e == hipSuccess) best_ms[k] = std::min(best_ms[k], ms);
         for (size_t r = 0; rc == TILD_OK && r < b->ctx.size(); ++r) {
             rc = tild_set_positions(b->ctx[r], snap + off[r], TILD_FP64, 1);
             b->ctx[r]->step = step0[r];
         }
-    }
+        return ms;
+    };
+    // plane-workgroup sizes with eager launches, each twice, alternating; then the faster one replayed
+    // from a captured graph (one untimed call captures it)
+    const int cand[2] = {256, 512};
+    float best_ms[2] = {1e30f, 1e30f};
+    for (int rep = 0; rep < 4 && e == hipSuccess && rc == TILD_OK; ++rep)
+        best_ms[rep & 1] = std::min(best_ms[rep & 1], trial(cand[rep & 1], false));
+    const int block = best_ms[0] <= best_ms[1] ? cand[0] : cand[1];
+    float graph_ms = 1e30f;
+    if (e == hipSuccess && rc == TILD_OK) (void)trial(block, true);
+    for (int rep = 0; rep < 2 && e == hipSuccess && rc == TILD_OK; ++rep) graph_ms = std::min(graph_ms, trial(block, true));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
     (void)hipFree(snap);
     if (rc != TILD_OK || e != hipSuccess) {
-        b->B.plane_block = keep;
+        b->B.plane_block = keep_block;
+        b->use_graph = keep_graph;
         if (rc != TILD_OK) return b->fail(rc, "autotune: a trial step or the restore failed");
         return b->hip_fail(e, "autotune");
     }
-    b->B.plane_block = best_ms[0] <= best_ms[1] ? cand[0] : cand[1];
+    b->B.plane_block = block;
+    b->use_graph = graph_ms <= std::min(best_ms[0], best_ms[1]);
     if (plane_block) *plane_block = b->B.plane_block;
+    if (graph) *graph = b->use_graph ? 1 : 0;
+    return TILD_OK;
+}
+
+TILD_API int tild_batch_set_graph(tild_batch* b, int32_t use_graph) {
+    if (!b) return TILD_EINVAL;
+    b->use_graph = use_graph != 0;
     return TILD_OK;
 }
 

@@ -16,7 +16,7 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
                            (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, 1, so, (long long*)nullptr, R, B.plane,
-                           par, (const T*)nullptr, (T*)nullptr);
+                           par, (const T*)nullptr, (T*)nullptr, 0);
         if (L.ph.elec)
             hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
@@ -30,7 +30,7 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
                            (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
                            (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
-                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr);
+                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr);
         hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                            (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
                            L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,

@@ -247,6 +247,44 @@ __device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint
     }
 }
 
+// Weighted counts (adjoint of the ik route): every bead j of the P slabs
+// z-P+1 .. z adds q_j W_j(g), q_j = vdir[4 j + comp], to the node g of plane z
+// it reaches, accumulated in floating point (T atomics in LDS).
+template <typename T, int P>
+__device__ __forceinline__ void spread_plane_weighted(T* __restrict__ acc, const uint4* __restrict__ pos,
+                                                      const uint32_t* __restrict__ bin_start,
+                                                      const uint32_t* __restrict__ qs, const Dims d, int z, int K,
+                                                      const T* __restrict__ vdir, int comp, int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const uint4 q = pos[j];
+            const T qj = vdir[4 * (long long)j + comp];
+            const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+            const int gx = bf.gx;
+            T wx[P], wy[P], wzs[P];  // only wzs[c] survives unrolling
+            spline_weights<T, P>(bf.fx, wx);
+            spline_weights<T, P>(bf.fy, wy);
+            spline_weights<T, P>(bf.fz, wzs);
+            const RowOffsets<P> ro(bf.gy, pr);
+            const T w0 = qj * wzs[c];
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                T* row = acc + ro.o[b] + 2 * gx;
+                const T wyz = w0 * wy[b];
+#pragma unroll
+                for (int a = 0; a < P; ++a) atomicAdd(row + 2 * a, wyz * wx[a]);
+            }
+        }
+    }
+}
+
 // Add the ghost cells of the extended plane into the cells they alias
 // (columns first, over real and ghost rows, then rows).  A: uint32_t or
 // unsigned long long (fixed point, wrapping integer sums).  Ends with a barrier.
@@ -339,13 +377,17 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
 //
 // COUNTS: write the counts c_K(z) themselves (real, [2][mz][my][mx], x
 // fastest) to cout and stop before the transforms.
-template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false, bool COUNTS = false>
+//
+// WSP (with DIR): the weighted counts sum_j q_j W_j, q_j = vdir[4 j + comp],
+// instead of the directional ones.
+template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false, bool COUNTS = false, bool WSP = false>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
                 uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part,
                 const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
-                const T* __restrict__ vdir, T* __restrict__ cout) {
+                const T* __restrict__ vdir, T* __restrict__ cout, int comp) {
+    static_assert(!WSP || DIR, "weighted counts use the floating-point accumulation of DIR");
     using C = cplx<T>;
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
@@ -408,7 +450,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         for (int w = 0; w < BLOCK / 64; ++w) m = m > smax[w] ? m : smax[w];
         scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
-    if constexpr (DIR) {
+    if constexpr (WSP) {
+        spread_plane_weighted<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, comp, tid, BLOCK);
+        __syncthreads();
+        fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
+    } else if constexpr (DIR) {
         spread_plane_dir<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, tid, BLOCK);
         __syncthreads();
         fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
@@ -650,6 +696,61 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
     }
 }
 
+// Local part of the ik-route force Jacobian, transposed: with the gradient
+// plane d_a phi_K(z) in LDS, every bead j of the P slabs z-P+1 .. z gets its
+// plane-c term of
+//   vdir[4 j + a] sum_g d_b W_j(g) d_a phi_K(g),   b = x, y, z,
+// written to fpart[b][c][j].
+template <typename T, int P>
+__device__ __forceinline__ void push_plane_local(const T* __restrict__ Sr, const uint4* __restrict__ pos,
+                                                 const uint32_t* __restrict__ bin_start,
+                                                 const uint32_t* __restrict__ qs, const Dims d, int z, int K, int a,
+                                                 long long n, const T* __restrict__ vdir, T* __restrict__ fpart,
+                                                 int tid, int nthr) {
+    const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
+    const int pr = 4 * d.hxp;
+    const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const uint4 q = pos[j];
+            const T lam = vdir[4 * (long long)j + a];
+            const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
+            const int gx = bf.gx;
+            T wx[P], wy[P], dwx[P], dwy[P], wzs[P], dwzs[P];  // only entry c of the z weights survives
+            spline_weights<T, P>(bf.fx, wx);
+            spline_weights<T, P>(bf.fy, wy);
+            spline_dweights<T, P>(bf.fx, dwx);
+            spline_dweights<T, P>(bf.fy, dwy);
+            spline_weights<T, P>(bf.fz, wzs);
+            spline_dweights<T, P>(bf.fz, dwzs);
+            const RowOffsets<P> ro(bf.gy, pr);
+            T ax = 0, ay = 0, az = 0;
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                const T* row = Sr + ro.o[b] + 2 * gx;
+                T r = 0, rx = 0;
+#pragma unroll
+                for (int a2 = 0; a2 < P; ++a2) {
+                    const T v = row[2 * a2];
+                    r += wx[a2] * v;
+                    rx += dwx[a2] * v;
+                }
+                ax += wy[b] * rx;
+                ay += dwy[b] * r;
+                az += wy[b] * r;
+            }
+            fpart[((long long)0 * P + c) * n + j] = lam * ihx * wzs[c] * ax;
+            fpart[((long long)1 * P + c) * n + j] = lam * ihy * wzs[c] * ay;
+            fpart[((long long)2 * P + c) * n + j] = lam * ihz * dwzs[c] * az;
+        }
+    }
+}
+
 // Hessian-vector products: with the potential plane phi_K(z) in LDS, every
 // bead j of the P slabs z-P+1 .. z gets its plane-c term of
 //   (H v)_a = sum_b sum_g d^2 W_j(g) / dx_a dx_b v_jb phi_K(g),
@@ -833,13 +934,20 @@ __device__ __forceinline__ void fill_ghosts(T* __restrict__ Sr, const Dims d, in
 // FIELD (with AD): interpolate a given real field psi_K ([2][mz][my][mx],
 // x fastest) instead of transforming a spectrum: the forces
 // -sum_g grad W_i(g) psi_{s_i}(g).
-template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false, bool FIELD = false>
+//
+// XM (ik route, one component a = comp, one workgroup per plane and
+// species): 1 -- the local part of the transposed force Jacobian against
+// vdir (push_plane_local); 2 -- store the gradient plane d_a phi_K(z) in
+// fout ([2][mz][my][mx], x fastest), adding to what is there when comp > 0.
+template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false, bool FIELD = false,
+          int XM = 0>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_xy_c2r(const cplx<T>* __restrict__ zout, T* __restrict__ fpart, Dims d, FftPlan px, FftPlan py,
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
              long long* __restrict__ fsum_part, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
-             int parity, const T* __restrict__ vdir, const T* __restrict__ field) {
+             int parity, const T* __restrict__ vdir, const T* __restrict__ field, int comp, T* __restrict__ fout) {
+    static_assert(XM == 0 || (!AD && !BATCH), "the Jacobian modes run on the ik route of one context");
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C* S = reinterpret_cast<C*>(smem);
@@ -863,11 +971,15 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         qs = parity ? R.S.qshift_next : R.S.qshift;
         n = R.S.n;
         t = (int)(e & 0xffffu);
+    } else if constexpr (XM != 0) {
+        t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
     } else {
         t = AD ? xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz)
                : xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
     }
-    const int a = AD ? 2 : t % 3, z = AD ? t % d.mz : (t / 3) % d.mz, K = AD ? t / d.mz : t / (3 * d.mz);
+    constexpr bool ONE = AD || XM != 0;  // one workgroup per plane and species
+    const int a = AD ? 2 : (XM != 0 ? comp : t % 3);
+    const int z = ONE ? t % d.mz : (t / 3) % d.mz, K = ONE ? t / d.mz : t / (3 * d.mz);
     const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     C* twl = S + d.npg * zp;
@@ -923,6 +1035,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         }
         __syncthreads();
         T* Sr = reinterpret_cast<T*>(smem);
+        if constexpr (XM == 2) {
+            // rows 2p and 2p+1 are the real and imaginary parts of complex row p
+            T* dst = fout + ((long long)K * d.mz + z) * (long long)my * mx;
+            for (int i = tid; i < my * mx; i += BLOCK) {
+                const int y = i / mx, x = i - y * mx;
+                const T v = Sr[__mul24(y >> 1, 4 * hxp) + (y & 1) + 2 * x];
+                dst[i] = comp > 0 ? dst[i] + v : v;
+            }
+            return;
+        }
         fill_ghosts<T, P>(Sr, d, tid, BLOCK);
         if constexpr (AD && HESS) {
             push_plane_hess<T, P>(Sr, pos, bin_start, qs, d, z, K, n, vdir, fpart, tid, BLOCK);
@@ -933,6 +1055,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
             block_sum<long long, 3>(fsum, fred, tid, BLOCK);
             if (tid == 0)
                 for (int q = 0; q < 3; ++q) fsum_part[(K * d.mz + z) * 3 + q] = fsum[q];
+        } else if constexpr (XM == 1) {
+            push_plane_local<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, vdir, fpart, tid, BLOCK);
         } else {
             push_plane<T, P>(Sr, pos, bin_start, qs, d, z, K, a, n, fpart, tid, BLOCK);
         }
@@ -1612,11 +1736,12 @@ __global__ void __launch_bounds__(256) k_get_positions(const uint4* __restrict__
 
 // H v accumulation in sorted order: acc = (first ? bond term : acc) + sign * sum of
 // the P plane partials per axis; the bond term of U = k_b sum |d|^2 is
-// 2 k_b sum_partners (v_j - v_p).
+// bond_sign 2 k_b sum_partners (v_j - v_p).
 template <typename T, int P>
 __global__ void __launch_bounds__(256) k_hvp_accum(const T* __restrict__ fpart, long long n,
                                                    const T* __restrict__ vdir, const int32_t* __restrict__ nbr,
-                                                   int deg, double bond_k, T* __restrict__ acc, int first, T sign) {
+                                                   int deg, double bond_k, T* __restrict__ acc, int first, T sign,
+                                                   T bond_sign) {
     const long long j = blockIdx.x * 256LL + threadIdx.x;
     if (j >= n) return;
     T r[3];
@@ -1628,7 +1753,7 @@ __global__ void __launch_bounds__(256) k_hvp_accum(const T* __restrict__ fpart, 
         r[a] = (first ? (T)0 : acc[4 * j + a]) + sign * sa;
     }
     if (first) {
-        const T kb2 = (T)(2.0 * bond_k);
+        const T kb2 = bond_sign * (T)(2.0 * bond_k);
         for (int b = 0; b < deg; ++b) {
             const int p = nbr[j * deg + b];
             if (p < 0) continue;

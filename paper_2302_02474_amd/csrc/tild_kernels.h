@@ -62,7 +62,10 @@ struct DeviceState {
     void* vel;            // GJF only: [n][4] half-step velocity of sorted bead j {ux, uy, uz, 0}
     void* vel_tmp;        // GJF only: the same in the order of pos_tmp
     void* vdir;           // [n][4] direction v of a Hessian-vector product, sorted order
-    void* hacc;           // [n][4] accumulated H v, sorted order
+    void* hacc;           // [n][4] accumulated H v (or J^T v), sorted order
+    void* field;          // [2][mz][my][mx] working-precision grid field (order >= 2): the adjoint's psi
+    double* adj;          // [n][3] float64 work array of the adjoint step (order >= 2)
+    double* apart;        // [n_bblocks][4] float64 block partial sums of the adjoint step
     uint32_t* counts;     // [nbins] bin occupancy (kept zero between uses)
     uint32_t* bin_start;  // [nbins + 1] first sorted slot of each bin
     unsigned long long* scan_status;  // [ntiles + 1] look-back status words of the bin scan, then its ticket
@@ -171,6 +174,16 @@ hipError_t launch_velocities(const Launch& L, DeviceState& S, int op, void* v, i
 // v ([n][3] ABI order, dtype) -> out ([n][3] ABI order, dtype), through vdir
 // and hacc (order >= 3).
 hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out, int dtype);
+// Transposed Jacobian of the ik-route force (non-bonded and bonds) at the
+// current positions applied to lam ([n][3] ABI order, dtype) -> out ([n][3]
+// ABI order, dtype), through vdir, hacc and field (order >= 2, ik route).
+hipError_t launch_force_vjp_ik(const Launch& L, DeviceState& S, const void* lam, void* out, int dtype);
+// [n][3] ABI-order vector operations of the adjoint step (v of dtype 0 float / 1 double, w float64
+// unless stated): kMean out[0..2] = mean of v; kProject w (dtype) = v - out[0..2] (out NULL: copy);
+// kDotAdd out[0] += alpha v . w; kAxpy v += alpha w; kScale v *= alpha.  Sums in a fixed order (apart).
+enum class AdjointOp { kMean, kProject, kDotAdd, kAxpy, kScale };
+hipError_t launch_adjoint_vectors(const Launch& L, DeviceState& S, AdjointOp op, void* v, void* w, int dtype,
+                                  double alpha, double* out);
 // Counts c_K(g) ([2][mz][my][mx], x fastest, working precision) to device memory.
 hipError_t launch_counts(const Launch& L, DeviceState& S, void* out);
 // Forces -sum_g grad W_i(g) psi_{s_i}(g) of a given field psi ([2][mz][my][mx],

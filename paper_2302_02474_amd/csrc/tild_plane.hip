@@ -9,7 +9,7 @@ template <typename T, int B> static void spread_xy_b(const Launch& L, DeviceStat
         hipLaunchKernelGGL((k_spread_xy<T, B, decltype(Pc)::value>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                            L.stream, bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                            (const cplx<T>*)S.tw, L.ph, S.flag, S.noise_step ? 1 : 0, (uint64_t)S.step, S.noise_part,
-                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)nullptr);
+                           (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)nullptr, 0);
     });
 }
 template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& S, bool ad) {
@@ -19,12 +19,12 @@ template <typename T, int B> static void xy_c2r_b(const Launch& L, DeviceState& 
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
                                bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr);
         else
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, false>), dim3(L.d.mz, 2, 3), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
                                L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr);
     });
 }
 

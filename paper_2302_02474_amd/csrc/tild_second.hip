@@ -17,14 +17,14 @@ static hipError_t hvp_b(const Launch& L, DeviceState& S, const void* v, void* ou
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                                L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw,
                                L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr, 0, (T*)nullptr);
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
-                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1);
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 1, (T)1, (T)1);
             // the field of the directional counts, gathered with the weight gradients
             hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                                L.stream, bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                                (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
-                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr);
+                               (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir, (T*)nullptr, 0);
         }
     });
     return hipGetLastError();
@@ -38,10 +38,10 @@ template <typename T, int B> static hipError_t hvp_tail(const Launch& L, DeviceS
             hipLaunchKernelGGL((k_xy_c2r<T, B, P, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L), L.stream,
                                (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
                                bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
-                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr);
+                               (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr);
             // those partials are -sum grad W delta phi
             hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
-                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1);
+                               (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1, (T)1);
         }
     });
     const hipError_t e = hipGetLastError();
@@ -54,7 +54,7 @@ template <typename T, int B> static void counts_b(const Launch& L, DeviceState& 
         hipLaunchKernelGGL((k_spread_xy<T, B, P, false, false, true>), dim3(L.d.mz, 2), dim3(B), plane_lds_bytes(L),
                            L.stream, bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
                            (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part, (const RepDesc*)nullptr,
-                           (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)out);
+                           (const uint32_t*)nullptr, 0, (const T*)nullptr, (T*)out, 0);
     });
 }
 
@@ -77,7 +77,7 @@ template <typename T, int B> static void field_b(const Launch& L, DeviceState& S
                                plane_lds_bytes(L), L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py,
                                (const cplx<T>*)S.tw, L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part,
                                (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)nullptr,
-                               (const T*)field);
+                               (const T*)field, 0, (T*)nullptr);
     });
 }
 
@@ -112,6 +112,74 @@ hipError_t launch_hvp(const Launch& L, DeviceState& S, const void* v, void* out,
     return L.plane_block == 256 ? hvp_tail<double, 256>(L, S, out, dtype) : hvp_tail<double, 512>(L, S, out, dtype);
 }
 
+// Transposed Jacobian of the ik-route force against lambda (held in vdir):
+//   J^T lambda = -sum_a lambda_a sum_g grad W d_a phi    (local: weights move with the bead)
+//               + sum_g grad W psi                        (field: psi = sum_a d_a phi of the
+//                                                          lambda_a-weighted counts)
+//               - H_b lambda                              (bonds),
+// accumulated in hacc: acc = -H_b lambda - sum_a (local partials) - (field-gather partials),
+// the field gather giving -sum_g grad W psi.
+template <typename T, int B> static hipError_t vjp_b(const Launch& L, DeviceState& S, void* out, int dtype) {
+    const unsigned gb = blocks_for(S.n, 256);
+    const dim3 planes(L.d.mz, 2);
+    const size_t lds = plane_lds_bytes(L);
+    hipError_t e = hipSuccess;
+    with_order(L.order, [&](auto Pc) {
+        constexpr int P = decltype(Pc)::value;
+        if constexpr (P >= 2) {
+            // local part, one component of the gradient planes of the counts at a time
+            for (int a = 0; a < 3; ++a) {
+                hipLaunchKernelGGL((k_xy_c2r<T, B, P, false, false, false, false, 1>), planes, dim3(B), lds, L.stream,
+                                   (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                                   bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                                   (const uint32_t*)nullptr, 0, (const T*)S.vdir, (const T*)nullptr, a, (T*)nullptr);
+                hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                                   (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, a == 0 ? 1 : 0, (T)-1,
+                                   (T)-1);
+            }
+            // field part: psi = sum_a d_a phi[lambda_a-weighted counts], accumulated in S.field
+            for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+                hipLaunchKernelGGL((k_spread_xy<T, B, P, false, true, false, true>), planes, dim3(B), lds, L.stream,
+                                   bead_src(L, S), S.bin_start, S.qshift, (cplx<T>*)S.spec, L.d, L.px, L.py,
+                                   (const cplx<T>*)S.tw, L.ph, S.flag, 0, (uint64_t)0, S.noise_part,
+                                   (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, (const T*)S.vdir,
+                                   (T*)nullptr, a);
+                e = launch_z_kmul(L, S, false);
+                if (e == hipSuccess)
+                    hipLaunchKernelGGL((k_xy_c2r<T, B, P, false, false, false, false, 2>), planes, dim3(B), lds,
+                                       L.stream, (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py,
+                                       (const cplx<T>*)S.tw, L.ph, bead_src(L, S), S.bin_start, S.qshift, S.n,
+                                       S.fsum_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
+                                       (const T*)nullptr, (const T*)nullptr, a, (T*)S.field);
+            }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL((k_xy_c2r<T, B, P, true, false, false, true>), planes, dim3(B), lds, L.stream,
+                                   (const cplx<T>*)S.zout, (T*)S.fpart, L.d, L.px, L.py, (const cplx<T>*)S.tw, L.ph,
+                                   bead_src(L, S), S.bin_start, S.qshift, S.n, S.fsum_part, (const RepDesc*)nullptr,
+                                   (const uint32_t*)nullptr, 0, (const T*)nullptr, (const T*)S.field, 0,
+                                   (T*)nullptr);
+                hipLaunchKernelGGL((k_hvp_accum<T, P>), dim3(gb), dim3(256), 0, L.stream, (const T*)S.fpart, S.n,
+                                   (const T*)S.vdir, S.nbr, S.deg, L.ph.bond_k, (T*)S.hacc, 0, (T)-1, (T)-1);
+            }
+        }
+    });
+    if (e == hipSuccess) e = hipGetLastError();
+    return e != hipSuccess ? e : launch_bead_vectors(L, S, S.hacc, 1, out, dtype);
+}
+
+hipError_t launch_force_vjp_ik(const Launch& L, DeviceState& S, const void* lam, void* out, int dtype) {
+    if (S.n == 0) return hipSuccess;
+    if (L.order < 2 || L.force_ad) return hipErrorInvalidValue;
+    hipError_t e = launch_bead_vectors(L, S, S.vdir, 0, const_cast<void*>(lam), dtype);
+    // the gradient planes of the counts at the current positions (noise off)
+    if (e == hipSuccess) e = launch_spread_xy(L, S);
+    if (e == hipSuccess) e = launch_z_kmul(L, S, false);
+    if (e != hipSuccess) return e;
+    if (L.precision == 0) return L.plane_block == 256 ? vjp_b<float, 256>(L, S, out, dtype)
+                                                      : vjp_b<float, 512>(L, S, out, dtype);
+    return L.plane_block == 256 ? vjp_b<double, 256>(L, S, out, dtype) : vjp_b<double, 512>(L, S, out, dtype);
+}
+
 template <typename T> static hipError_t attr_second(const Launch& L, size_t lds) {
     hipError_t e = hipSuccess;
     auto set = [&](const void* f) {
@@ -124,14 +192,24 @@ template <typename T> static hipError_t attr_second(const Launch& L, size_t lds)
                 set((const void*)k_xy_c2r<T, 256, P, true, false, true>);
                 set((const void*)k_spread_xy<T, 256, P, false, true>);
             }
-            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 256, P, true, false, false, true>);
+            if constexpr (P >= 2) {
+                set((const void*)k_xy_c2r<T, 256, P, true, false, false, true>);
+                set((const void*)k_xy_c2r<T, 256, P, false, false, false, false, 1>);
+                set((const void*)k_xy_c2r<T, 256, P, false, false, false, false, 2>);
+                set((const void*)k_spread_xy<T, 256, P, false, true, false, true>);
+            }
             set((const void*)k_spread_xy<T, 256, P, false, false, true>);
         } else {
             if constexpr (P >= 3) {
                 set((const void*)k_xy_c2r<T, 512, P, true, false, true>);
                 set((const void*)k_spread_xy<T, 512, P, false, true>);
             }
-            if constexpr (P >= 2) set((const void*)k_xy_c2r<T, 512, P, true, false, false, true>);
+            if constexpr (P >= 2) {
+                set((const void*)k_xy_c2r<T, 512, P, true, false, false, true>);
+                set((const void*)k_xy_c2r<T, 512, P, false, false, false, false, 1>);
+                set((const void*)k_xy_c2r<T, 512, P, false, false, false, false, 2>);
+                set((const void*)k_spread_xy<T, 512, P, false, true, false, true>);
+            }
             set((const void*)k_spread_xy<T, 512, P, false, false, true>);
         }
     });

@@ -180,3 +180,120 @@ def test_second_order_calls_and_batches_accept_empty_systems():
     assert t.step_count == 3
     for c in (t, u, alone):
         c.close()
+
+
+# (chains, nA, nB, box, grid, P, chi, kappa, charged)
+VJP_CASES = [
+    (30, 5, 5, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.8, 3.0, False),
+    (25, 4, 6, (5.0, 6.0, 7.5), (10, 12, 18), 3, 0.5, 5.0, True),
+    (20, 5, 5, (6.0, 5.0, 6.0), (16, 15, 20), 5, 0.6, 4.0, False),
+    (20, 4, 4, (4.0, 3.0, 5.0), (8, 6, 10), 2, 1.0, 2.0, False),
+]
+
+
+@pytest.mark.parametrize("precision,tol", [(T.TILD_FP64, 1e-10), (T.TILD_FP32, 1e-5)])
+@pytest.mark.parametrize("case", range(len(VJP_CASES)))
+def test_force_vjp_ik_matches_oracle(case, precision, tol):
+    """(dF/dx)^T lambda of the ik-route force (Eq. PMM plus bonds) against the oracle's ik_force_vjp (which is
+    pinned by finite differences of the force through its transpose, the JVP)."""
+    nc, na, nb, box, grid, P, chi, kap, charged = VJP_CASES[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=920 + case)
+    x = snap_to_lattice(m.x, m.box)
+    el = dict(charges=(1.0, -0.6), bjerrum=1.5, charge_smear=0.4) if charged else {}
+    t = T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, precision=precision,
+                             **el), m.types, m.bonds)
+    t.set_positions(x)
+    lam = np.random.default_rng(case).normal(size=x.shape)
+    got = t.force_vjp(lam)
+    t.close()
+    po = _oracle_params(m, **{k: v for k, v in (("charges", el.get("charges", (0.0, 0.0))),
+                                                  ("bjerrum", el.get("bjerrum", 0.0)),
+                                                  ("charge_smear", el.get("charge_smear", 0.0)))})
+    ref = R.ik_force_vjp(x, m.types, m.bonds, po, lam)
+    err = rel(got, ref)
+    say(f"[vjp] {m.name} precision={precision}: rel err {err:.2e}")
+    assert err < tol
+
+
+def test_force_vjp_exact_gradient_route_is_minus_hvp():
+    m = make_custom(30, 5, 5, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.8, 3.0, seed_init=930)
+    x = snap_to_lattice(m.x, m.box)
+    t = T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, precision=T.TILD_FP64,
+                             force="ad"), m.types, m.bonds)
+    t.set_positions(x)
+    lam = np.random.default_rng(5).normal(size=x.shape)
+    np.testing.assert_array_equal(t.force_vjp(lam), -t.hvp(lam))
+    t.close()
+
+
+# relative bounds: loss, dL/dx0, dL/dchi and dL/dkappa.  The GPU's positions sit on the 2^-32 lattice, which
+# moves the FP64 trajectory by about 1e-9 relative; dL/dchi is a sum with cancellation (about 1e-4 of its terms)
+@pytest.mark.parametrize("precision,tols", [(T.TILD_FP64, (1e-9, 1e-6, 1e-6)), (T.TILD_FP32, (1e-6, 1e-5, 1e-4))])
+def test_em_adjoint_ik_route_matches_oracle(precision, tols):
+    """Backpropagation through 6 EM steps on the ik route (the force tild_step runs), with COM correction,
+    against the oracle's adjoint (pinned by differences of the loss)."""
+    import torch
+    m = make_custom(30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0, seed_init=931, dt=0.02)
+    x0 = snap_to_lattice(m.x, m.box)
+    target = _lamellar(m, 3.0)
+    p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
+                      precision, True)
+    t = T.Tild(p, m.types, m.bonds)
+    tt = torch.from_numpy(target).cuda()
+    loss, gx, g = A.em_adjoint(t, x0, 6, lambda c: A.density_mse(c, tt), checkpoint=4, t0=3)
+    t.close()
+    po = _oracle_params(m, com_correct=True)
+    to = target.transpose(2, 1, 0)
+    lo, gxo, go = R.em_adjoint(x0, m.types, m.bonds, po, 6, lambda y: R.density_mse(y, m.types, po, to), t0=3,
+                               force="ik")
+    say(f"[adj-ik] precision={precision}: loss {loss:.12g} oracle {lo:.12g}; dL/dchi {g['chi']:.10g} oracle "
+        f"{go['chi']:.10g}; dL/dkappa {g['kappa']:.10g} oracle {go['kappa']:.10g}; dL/dx0 rel "
+        f"{rel(gx.cpu().numpy(), gxo):.2e}")
+    tl, tx, tg = tols
+    assert abs(loss - lo) < tl * abs(lo)
+    assert rel(gx.cpu().numpy(), gxo) < tx
+    for k in ("chi", "kappa"):
+        assert abs(g[k] - go[k]) < tg * abs(go[k]), k
+
+
+def test_em_adjoint_ik_route_differentiation_workload():
+    """The 80,992-bead A16B16 melt at 64^3 on the ik route: 50 steps with checkpoints every 10 and the lamellar
+    loss.  FP64: dL/dchi against central differences at fixed noise (h and 2h combined); FP32 against FP64 to
+    1e-5 for the loss, dL/dchi, dL/dkappa and dL/dx0; the FP64 run repeated agrees to 1e-12 (the weighted
+    counts of the transposed Jacobian are summed with floating-point atomics, in no fixed order)."""
+    import torch
+    m = make_melt(4)
+    target = torch.from_numpy(_lamellar(m, 10.0)).cuda()
+    out = {}
+    for precision in (T.TILD_FP64, T.TILD_FP32):
+        p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT,
+                          m.seed, precision, True)
+        t = T.Tild(p, m.types, m.bonds)
+        loss, gx, g = A.em_adjoint(t, m.x, 50, lambda c: A.density_mse(c, target), checkpoint=10, t0=0)
+        out[precision] = (float(loss), gx.double().cpu().numpy(), g)
+        if precision == T.TILD_FP64:
+            loss2, gx2, g2 = A.em_adjoint(t, m.x, 50, lambda c: A.density_mse(c, target), checkpoint=10, t0=0)
+            rep = max(abs(loss2 - loss) / abs(loss), rel(gx2.cpu().numpy(), out[precision][1]),
+                      *(abs(g2[k] - g[k]) / abs(g[k]) for k in ("chi", "kappa")))
+            say(f"[adj-ik] FP64 repeat: largest relative difference {rep:.2e}")
+            assert rep < 1e-12
+
+            def run(chi):
+                t.set_interaction(chi, m.kappa, m.smear_a)
+                t.set_positions(m.x)
+                t.step_count = 0
+                t.step(50)
+                return A.density_mse(t, target)[0]
+            h = 1e-2 * m.chi
+            d1 = (run(m.chi + h) - run(m.chi - h)) / (2 * h)
+            d2 = (run(m.chi + 2 * h) - run(m.chi - 2 * h)) / (4 * h)
+            fd = (4 * d1 - d2) / 3
+            say(f"[adj-ik] 80,992 beads, 50 steps: loss {loss:.8g}, dL/dchi adjoint {g['chi']:.10g} FD {fd:.10g}")
+            assert abs(g["chi"] - fd) < 1e-4 * abs(fd)
+        t.close()
+    (l64, gx64, g64), (l32, gx32, g32) = out[T.TILD_FP64], out[T.TILD_FP32]
+    errs = dict(loss=abs(l32 - l64) / abs(l64), chi=abs(g32["chi"] - g64["chi"]) / abs(g64["chi"]),
+                kappa=abs(g32["kappa"] - g64["kappa"]) / abs(g64["kappa"]), x0=rel(gx32, gx64))
+    say(f"[adj-ik] FP32 against FP64: {errs}")
+    for k, v in errs.items():
+        assert v < 1e-5, (k, v)

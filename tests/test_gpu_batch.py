@@ -86,7 +86,7 @@ def test_autotune_leaves_the_state_unchanged():
         a.step_count = b.step_count = 5 * i
     with T.Batch(batched) as bt:
         pb = bt.autotune(3)
-        say(f"[batch] autotune chose {pb}-thread plane workgroups")
+        say(f"[batch] autotune chose {pb}-thread plane workgroups, graph replay {bt.graph}")
         assert pb in (256, 512)
         for i, b in enumerate(batched):
             assert b.step_count == 5 * i
@@ -194,4 +194,32 @@ def test_replica_workload_fp32_members_match_oracle():
         say(f"   displacement rel-RMS {err_x:.3e}, force {err_f:.3e}, non-bonded {err_nb:.3e}")
         assert err_x < 1e-5 and err_f < 1e-5 and err_nb < 1e-5
     for t in ts:
+        t.close()
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP32, T.TILD_FP64])
+def test_graph_replays_equal_eager_steps(precision):
+    """Batched steps replayed from a captured HIP graph equal the same steps launched eagerly, bit for bit, on
+    every replay: three calls of 5 steps (one capture, two replays) with host reads and synchronisation between
+    them, then a call of 2 steps (a new capture) and one more of 5 (captured again)."""
+    ms = [_member(i, precision) for i in range(len(MEMBERS))]
+    eager = [T.Tild(p, m.types, m.bonds) for m, p in ms]
+    graphed = [T.Tild(p, m.types, m.bonds) for m, p in ms]
+    for (m, _), a, b in zip(ms, eager, graphed):
+        a.set_positions(m.x)
+        b.set_positions(m.x)
+    with T.Batch(eager) as be, T.Batch(graphed) as bg:
+        be.set_graph(False)
+        bg.set_graph(True)
+        for k, n in enumerate((5, 5, 5, 2, 5)):
+            be.step(n)
+            bg.step(n)
+            be.synchronize()
+            bg.synchronize()
+            for a, b in zip(eager, graphed):
+                assert a.step_count == b.step_count
+                np.testing.assert_array_equal(a.get_positions(), b.get_positions())
+            say(f"[batch] call {k} ({n} steps): graph replay equals eager launches")
+        np.testing.assert_array_equal(eager[1].forces(), graphed[1].forces())
+    for t in eager + graphed:
         t.close()

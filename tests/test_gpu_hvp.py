@@ -93,3 +93,20 @@ def test_hvp_rejects_low_order():
         t.hvp(np.zeros((m.n, 3)))
     assert e.value.code == T.TILD_EINVAL
     t.close()
+
+
+@pytest.mark.parametrize("route", ["ad", "ik"])
+def test_second_order_products_repeat_to_rounding(route):
+    """H v (tild_hvp) and the transposed force Jacobian (tild_force_vjp) sum directional or weighted counts with
+    floating-point atomics: a repeated call agrees with the first to rounding (1e-13 relative in FP64), not
+    necessarily bit for bit; the 81k-bead workload at 64^3."""
+    m = make_melt(4)
+    t = T.Tild(T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, precision=T.TILD_FP64,
+                             force=route), m.types, m.bonds)
+    t.set_positions(m.x)
+    v = np.random.default_rng(17).normal(size=(m.n, 3))
+    f = t.hvp if route == "ad" else t.force_vjp
+    a, b = f(v), f(v)
+    t.close()
+    say(f"[repeat] {route}: relative difference {rel(b, a):.2e}")
+    assert rel(b, a) < 1e-13
