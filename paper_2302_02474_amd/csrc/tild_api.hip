@@ -420,10 +420,6 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     d.mz = params->grid[2];
     d.hx = d.mx / 2 + 1;
     d.npair = (d.my + 1) / 2;
-    // LDS plane: pair rows of 2 hxp complex, with room for P - 1 ghost columns
-    // and P - 1 ghost rows past the periodic edge
-    // (odd, so that consecutive pair rows start in different LDS bank groups)
-    d.hxp = std::max(d.hx, (d.mx + params->order) / 2) | 1;
     d.npg = (d.my + params->order) / 2;
     d.ylines = (d.mx % 2 == 0 && d.hx > 1) ? d.hx - 1 : d.hx;
     d.swc = d.ylines % 16 == 0 ? d.ylines : 0;
@@ -433,14 +429,26 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     d.ly = params->box[1];
     d.lz = params->box[2];
     // the two-pass tables follow the plain ones, for the lengths that use them
+    // ([n / r1][r1 + 1]: rows padded by one entry)
     int nt = d.mx + d.my + d.mz;
     bool planned = make_plan(d.mx, 0, nt, L.px);
-    nt += L.px.r1 ? d.mx : 0;
+    nt += L.px.r1 ? d.mx + d.mx / L.px.r1 : 0;
     planned = planned && make_plan(d.my, d.mx, nt, L.py);
-    nt += L.py.r1 ? d.my : 0;
+    nt += L.py.r1 ? d.my + d.my / L.py.r1 : 0;
     planned = planned && make_plan(d.mz, d.mx + d.my, nt, L.pz);
-    nt += L.pz.r1 ? d.mz : 0;
+    nt += L.pz.r1 ? d.mz + d.mz / L.pz.r1 : 0;
     d.ntw2 = nt - (d.mx + d.my + d.mz);
+    // LDS plane: pair rows of 2 hxp complex, with room for P - 1 ghost columns
+    // and P - 1 ghost rows past the periodic edge.  With the two-pass x
+    // transform, hxp = 4 (mod 16): eight consecutive rows then start in four
+    // bank groups two by two, which with the permuted intermediate order
+    // leaves every LDS access of both passes (rows and columns) at the
+    // two-cycle minimum of 64-bit accesses; otherwise hxp is odd, so that
+    // consecutive pair rows start in different bank groups.
+    {
+        const int h0 = std::max(d.hx, (d.mx + params->order) / 2);
+        d.hxp = L.px.r1 ? h0 + ((4 - h0 % 16) + 16) % 16 : (h0 | 1);
+    }
     if (!planned) {
         g_create_error = "internal: radix plan";
         delete c;
@@ -577,16 +585,22 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
             tw.push_back(-std::sin(ang));
         }
     }
-    // two-pass tables: w_n^(l k1) at [l][k1], l < n / r1, k1 < r1, for the lengths that use them
+    // two-pass tables: w_n^(l k1) at [l][k1], l < n / r1, k1 < r1 (row pitch r1 + 1, the pad entry 1), for
+    // the lengths that use them
     for (const FftPlan* pl : {&L.px, &L.py, &L.pz}) {
         if (!pl->r1) continue;
         const int n = pl->n;
-        for (int m = 0; m < n; ++m) {
-            const int l = m / pl->r1, k1 = m % pl->r1;
-            const double ang = 2.0 * M_PI * (double)((long long)l * k1 % n) / (double)n;
+        for (int m = 0; m < n + n / pl->r1; ++m) {
+            const int l = m / (pl->r1 + 1), k1 = m % (pl->r1 + 1);
+            const double ang = k1 == pl->r1 ? 0.0 : 2.0 * M_PI * (double)((long long)l * k1 % n) / (double)n;
             tw.push_back(std::cos(ang));
             tw.push_back(-std::sin(ang));
         }
+    }
+    if (tw.size() != 2 * (size_t)d.ntw()) {
+        g_create_error = "internal: twiddle table size";
+        tild_destroy(c);
+        return TILD_EINVAL;
     }
     std::vector<float> twf(tw.begin(), tw.end());
     std::vector<double> ut, vt;

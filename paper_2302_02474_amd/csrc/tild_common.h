@@ -33,7 +33,7 @@ struct Dims {
     int mx, my, mz;  // grid points
     int hx;          // mx/2 + 1
     int npair;       // (my + 1) / 2: row pairs packed into one complex row
-    int hxp;         // LDS half-row pitch: odd, >= hx and 2 hxp >= mx + P - 1
+    int hxp;         // LDS half-row pitch: >= hx and 2 hxp >= mx + P - 1 (4 mod 16 with a two-pass x transform, else odd)
     int npg;         // LDS row pairs including ghost rows: ceil((my + P - 1) / 2)
     int ylines;      // y transforms per plane: hx, or hx - 1 when the kx = 0 and mx/2 columns share one
     int swc;         // columns kx < swc of an LDS half spectrum are swizzled (ylines or 0)

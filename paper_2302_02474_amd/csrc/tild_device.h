@@ -510,7 +510,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         const int G = px.group, lane = tid % G;
         for (int p = tid / G; p < np; p += BLOCK / G) {
             const int base = p * zp;
-            fft_line<C, 0>(S, base, 1, px, twl, lane);
+            fft_line<C, 0, false, true>(S, base, 1, px, twl, lane);
             C ra[kPairItems], rb[kPairItems];
 #pragma unroll
             for (int u = 0; u < kPairItems; ++u) {
@@ -544,8 +544,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         for (int y = tid; y < my; y += BLOCK) S[hidx(d, y, 0)] = C{S[hidx(d, y, 0)].x, S[hidx(d, y, hx - 1)].x};
         __syncthreads();
     }
-    if (d.swc) fft_lines<C, 0, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
-    else fft_lines<C, 0>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
+    if (d.swc) fft_lines<C, 0, true, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, BLOCK);
+    else fft_lines<C, 0, false, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, BLOCK);
     __syncthreads();
     if (pair_n) {
         for (int ky = tid; ky <= my / 2; ky += BLOCK) {
@@ -843,8 +843,8 @@ __device__ __forceinline__ void inverse_xy_transform(cplx<T>* __restrict__ S, co
         }
         __syncthreads();
     }
-    if (d.swc) fft_lines<C, 1, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, nthr);
-    else fft_lines<C, 1>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, nthr);
+    if (d.swc) fft_lines<C, 1, true, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 15}, py, twl, tid, nthr);
+    else fft_lines<C, 1, false, true>(S, LineMap{d.ylines, d.ylines, 1, 0, hxp, 0}, py, twl, tid, nthr);
     __syncthreads();
     if (pair_n) {
         for (int y = tid; y < my; y += nthr) {
@@ -885,7 +885,7 @@ __device__ __forceinline__ void inverse_xy_transform(cplx<T>* __restrict__ S, co
                 if (x < mx) S[base + x] = rz[u];
             }
             wave_sync();
-            fft_line<C, 1>(S, base, 1, px, twl, lane);
+            fft_line<C, 1, false, true>(S, base, 1, px, twl, lane);
         }
     }
 }
@@ -980,7 +980,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     constexpr bool ONE = AD || XM != 0;  // one workgroup per plane and species
     const int a = AD ? 2 : (XM != 0 ? comp : t % 3);
     const int z = ONE ? t % d.mz : (t / 3) % d.mz, K = ONE ? t / d.mz : t / (3 * d.mz);
-    const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, np = d.npair, zp = 2 * hxp;
+    const int mx = d.mx, my = d.my, hx = d.hx, hxp = d.hxp, zp = 2 * hxp;
     const T kfx = (T)(kTwoPi / ph.lx), kfy = (T)(kTwoPi / ph.ly);
     C* twl = S + d.npg * zp;
     const int ntw = d.ntw();

@@ -29,7 +29,7 @@ struct FftPlan {
     int group;  // lanes per line: a power of two <= 64
     uint32_t codes;  // radix of pass st in bits 4 st .. 4 st + 3
     int r1;     // two-pass transform n = r1 r2 (line_fft2) when > 0, else the radix passes
-    int tw2;    // offset of its table w^(l k1), l < r2, k1 < r1, stored [l][k1]
+    int tw2;    // offset of its table w^(l k1), l < r2, k1 < r1, stored [l][k1] with row pitch r1 + 1
     __host__ __device__ __forceinline__ int radix(int st) const { return (int)((codes >> (4 * st)) & 15u); }
 };
 
@@ -299,16 +299,24 @@ __device__ __forceinline__ void line_passes_fixed(C* buf, const int base, const 
 // k = k1 + R1 k2:
 //   X[k1 + R1 k2] = sum_l w_N^(l k1) w_R2^(l k2) sum_m x[l + R2 m] w_R1^(m k1).
 // Pass A: each lane takes R2/G values of l, transforms over m in registers,
-// multiplies by w_N^(l k1) (table tw2[l R1 + k1]) and writes the result to
-// element k1 R2 + l -- the elements it read, so no other lane is disturbed.
-// Pass B: each lane takes R1/G values of k1, reads elements k1 R2 + l,
-// transforms over l and writes element k1 + R1 k2 (natural order).  Two
-// rounds of LDS traffic instead of one per radix pass.
-template <typename C, int INV, bool SWZ, int N, int R1, int R2, int G>
+// multiplies by w_N^(l k1) (table tw2[l (R1 + 1) + k1]: the padded pitch puts
+// the rows the lanes of a group read in different LDS banks) and writes the
+// result to element k1 R2 + l -- the elements it read, so no other lane is
+// disturbed.  Pass B: each lane takes R1/G values of k1, reads elements
+// k1 R2 + l, transforms over l and writes element k1 + R1 k2 (natural
+// order).  Two rounds of LDS traffic instead of one per radix pass.
+//
+// XP: the intermediate element (k1, l) is stored at k1 R2 + (l xor (k1 mod
+// R2)) instead, a permutation within each group of R2 that spreads the reads
+// of pass B (R2 elements of one k1 per lane) over the LDS banks when lines
+// are rows of the plane layout; the line's input and output stay in natural
+// order.
+template <typename C, int INV, bool SWZ, int N, int R1, int R2, int G, bool XP>
 __device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, const int swz,
                                           const C* __restrict__ tw2, const int lane) {
     static_assert(R1 * R2 == N && R1 % G == 0 && R2 % G == 0, "two-pass shape");
     constexpr int NA = R2 / G, NB = R1 / G;
+    auto mid = [](int k1, int l) { return k1 * R2 + (XP ? (l ^ (k1 & (R2 - 1))) : l); };
     // the lane index made opaque to the optimiser (see line_passes_fixed)
     int ln = lane;
     asm volatile("" : "+v"(ln));
@@ -324,7 +332,7 @@ __device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, 
         for (int d = 0; d < NA; ++d) {
             const int l = ln + d * G;
             dft_r<R1, INV>(v[d]);
-            const C* w = tw2 + l * R1;
+            const C* w = tw2 + l * (R1 + 1);
 #pragma unroll
             for (int k1 = 1; k1 < R1; ++k1) {
                 C wk = w[k1];
@@ -332,7 +340,7 @@ __device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, 
                 v[d][k1] = cmul(v[d][k1], wk);
             }
 #pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) buf[line_index<SWZ>(base, k1 * R2 + l, es, swz)] = v[d][k1];
+            for (int k1 = 0; k1 < R1; ++k1) buf[line_index<SWZ>(base, mid(k1, l), es, swz)] = v[d][k1];
         }
     }
     wave_sync();
@@ -342,7 +350,7 @@ __device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, 
         for (int d = 0; d < NB; ++d) {
             const int k1 = ln + d * G;
 #pragma unroll
-            for (int l = 0; l < R2; ++l) v[d][l] = buf[line_index<SWZ>(base, k1 * R2 + l, es, swz)];
+            for (int l = 0; l < R2; ++l) v[d][l] = buf[line_index<SWZ>(base, mid(k1, l), es, swz)];
         }
         wave_sync();
 #pragma unroll
@@ -357,8 +365,9 @@ __device__ __forceinline__ void line_fft2(C* buf, const int base, const int es, 
 }
 
 // Transform the line at `base` (elements `es` apart, swizzled with mask swz
-// when SWZ) in place; called by all G lanes of the owning group.
-template <typename C, int INV, bool SWZ = false>
+// when SWZ) in place; called by all G lanes of the owning group.  XP selects
+// the permuted intermediate order of the two-pass shapes (line_fft2).
+template <typename C, int INV, bool SWZ = false, bool XP = false>
 __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, const FftPlan plan,
                                          const C* __restrict__ twiddles, const int lane, const int swz = 0) {
     const C* tw = twiddles + plan.tw;
@@ -366,9 +375,9 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
     if (plan.r1) {
         const C* tw2 = twiddles + plan.tw2;
         switch (plan.n) {
-            case 64: line_fft2<C, INV, SWZ, 64, 8, 8, 8>(buf, base, es, swz, tw2, lane); return;
-            case 128: line_fft2<C, INV, SWZ, 128, 16, 8, 8>(buf, base, es, swz, tw2, lane); return;
-            case 256: line_fft2<C, INV, SWZ, 256, 16, 16, 16>(buf, base, es, swz, tw2, lane); return;
+            case 64: line_fft2<C, INV, SWZ, 64, 8, 8, 8, XP>(buf, base, es, swz, tw2, lane); return;
+            case 128: line_fft2<C, INV, SWZ, 128, 16, 8, 8, XP>(buf, base, es, swz, tw2, lane); return;
+            case 256: line_fft2<C, INV, SWZ, 256, 16, 16, 16, XP>(buf, base, es, swz, tw2, lane); return;
             default: break;
         }
     }
@@ -399,7 +408,7 @@ __device__ __forceinline__ void fft_line(C* buf, const int base, const int es, c
 // Transform every line of `lm` with the block's threads split into groups of
 // plan.group lanes.  Needs a block barrier before (inputs written by other
 // waves) and, if other waves read the result, after.
-template <typename C, int INV, bool SWZ = false>
+template <typename C, int INV, bool SWZ = false, bool XP = false>
 __device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPlan plan, const C* __restrict__ twiddles,
                                           int tid, int nthr) {
     const int G = plan.group;
@@ -408,7 +417,7 @@ __device__ __forceinline__ void fft_lines(C* buf, const LineMap lm, const FftPla
     const int dq = ngrp / lm.l1, dr = ngrp % lm.l1;
     int q = grp / lm.l1, r = grp % lm.l1;
     for (int l = grp; l < lm.lines; l += ngrp) {
-        fft_line<C, INV, SWZ>(buf, r * lm.s1 + q * lm.s2, lm.es, plan, twiddles, lane, lm.swz);
+        fft_line<C, INV, SWZ, XP>(buf, r * lm.s1 + q * lm.s2, lm.es, plan, twiddles, lane, lm.swz);
         q += dq;
         r += dr;
         if (r >= lm.l1) {
