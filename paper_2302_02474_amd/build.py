@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtild.so")
-SOURCES = ["tild_plane.hip", "tild_second.hip", "tild_batch.hip", "tild_kernels.hip", "tild_adjoint.hip", "tild_api.hip"]
+SOURCES = ["tild_plane.hip", "tild_plane_f64.hip", "tild_second.hip", "tild_second_f64.hip", "tild_batch.hip",
+           "tild_kernels.hip", "tild_adjoint.hip", "tild_api.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

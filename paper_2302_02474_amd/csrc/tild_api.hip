@@ -90,6 +90,7 @@ struct tild_ctx {
     Launch L{};
     DeviceState S{};
     int64_t step = 0;
+    int64_t noise_ready = -1;  // the step whose per-block noise sums noise_part holds (-1: none)
     bool have_pos = false;
     std::string err;
     void* staging = nullptr;  // device [n][3] doubles for host transfers
@@ -268,10 +269,13 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         auto mark = [&](int slot, int which) {
             if (ev && e == hipSuccess) e = hipEventRecord((*ev)[(size_t)(s * kNumSlots + slot) * 2 + which], c->L.stream);
         };
+        // the step's noise sums, for its centre-of-mass shift: left by the previous step's scatter, else
+        // drawn here
+        if (c->noise_ready != c->step && e == hipSuccess) e = launch_noise_sum(c->L, c->S, (uint64_t)c->step);
+        c->noise_ready = -1;
         mark(kSpreadXy, 0);
         c->S.noise_step = 1;
-        c->S.step = c->step;
-        if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);  // also sums the step's noise per plane
+        if (e == hipSuccess) e = launch_spread_xy(c->L, c->S);
         mark(kSpreadXy, 1);
         mark(kZKmul, 0);
         if (e == hipSuccess) e = launch_z_kmul(c->L, c->S, false);  // also forms the new shift
@@ -288,11 +292,12 @@ int run_steps(tild_ctx* c, int64_t n_steps, std::vector<hipEvent_t>* ev) {
         if (e == hipSuccess) e = launch_bin_scan(c->L, c->S);
         mark(kBinScan, 1);
         mark(kScatter, 0);
-        if (e == hipSuccess) e = launch_scatter(c->L, c->S, c->S.nbr);
+        if (e == hipSuccess) e = launch_scatter(c->L, c->S, c->S.nbr, c->step + 1);  // also the next step's noise sums
         mark(kScatter, 1);
         if (e == hipSuccess) std::swap(c->S.nbr, c->S.nbr_old);
         if (e != hipSuccess) return c->hip_fail(e, "step launch");
         ++c->step;
+        c->noise_ready = c->step;
     }
     return TILD_OK;
 }
@@ -477,6 +482,9 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     ph.lx = d.lx;
     ph.ly = d.ly;
     ph.lz = d.lz;
+    ph.qx = 4294967296.0 / d.lx;
+    ph.qy = 4294967296.0 / d.ly;
+    ph.qz = 4294967296.0 / d.lz;
     ph.a2 = params->smear_a * params->smear_a;
     ph.chi = params->chi;
     ph.kappa = params->kappa;
@@ -558,7 +566,7 @@ int create_impl(const tild_params* params, int64_t n_beads, const int32_t* types
     if (sampled) A((void**)&S.vtab, (size_t)(d.mx + d.my + d.mz) * sizeof(double));
     A((void**)&S.epart, (size_t)L.n_zblocks * kEpart * sizeof(double));
     A((void**)&S.bpart, (size_t)L.n_bblocks * 4 * sizeof(long long));
-    A((void**)&S.noise_part, (size_t)2 * d.mz * 3 * sizeof(long long));
+    A((void**)&S.noise_part, (size_t)std::max(L.n_bblocks, 2 * d.mz) * 3 * sizeof(long long));
     A((void**)&S.fsum_part, (size_t)2 * d.mz * 3 * sizeof(long long));
     A((void**)&S.flag, sizeof(uint32_t));
     A((void**)&S.eout, 16 * sizeof(double));
@@ -1326,6 +1334,7 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
             Lc.stream = b->cap_stream;
             hipGraph_t graph = nullptr;
             e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) e = launch_batch_noise(Lc, b->B);
             for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
                 e = launch_batch_step(Lc, b->B, (int)s, b->lds_plane, b->lds_z);
             const hipError_t ec = hipStreamEndCapture(b->cap_stream, &graph);
@@ -1341,17 +1350,23 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
         }
         if (e == hipSuccess) e = hipGraphLaunch(b->exec, b->stream);
     } else {
+        if (e == hipSuccess) e = launch_batch_noise(b->L, b->B);
         for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s)
             e = launch_batch_step(b->L, b->B, (int)s, b->lds_plane, b->lds_z);
     }
-    if (e != hipSuccess) return b->hip_fail(e, "batch step");
-    // the members' pointer pairs swap once per step; their step counters advance
+    if (e != hipSuccess) {
+        for (tild_ctx* c : b->ctx) c->noise_ready = -1;
+        return b->hip_fail(e, "batch step");
+    }
+    // the members' pointer pairs swap once per step; their step counters advance, and the last scatter left
+    // the noise sums of the step they reach
     for (tild_ctx* c : b->ctx) {
         if (n_steps & 1) {
             std::swap(c->S.qshift, c->S.qshift_next);
             std::swap(c->S.nbr, c->S.nbr_old);
         }
         c->step += n_steps;
+        c->noise_ready = c->step;
     }
     // later work on a member's stream waits for the batch
     e = hipEventRecord(b->done_ev, b->stream);
@@ -1405,6 +1420,7 @@ TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* pl
         for (size_t r = 0; rc == TILD_OK && r < b->ctx.size(); ++r) {
             rc = tild_set_positions(b->ctx[r], snap + off[r], TILD_FP64, 1);
             b->ctx[r]->step = step0[r];
+            b->ctx[r]->noise_ready = -1;
         }
         return ms;
     };
@@ -1627,8 +1643,12 @@ TILD_API int tild_batch_step_static(tild_ctx* const* ctxs, int32_t n_ctx, int64_
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = configure_batch_attributes(L, lds_plane, lds_z);
+    if (e == hipSuccess) e = launch_batch_noise(L, B);
     for (int64_t s = 0; e == hipSuccess && s < n_steps; ++s) e = launch_batch_step(L, B, (int)s, lds_plane, lds_z);
-    if (e != hipSuccess) return bad(TILD_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+    if (e != hipSuccess) {
+        for (int32_t r = 0; r < n_ctx; ++r) ctxs[r]->noise_ready = -1;
+        return bad(TILD_EHIP, std::string("batch step: ") + hipGetErrorString(e));
+    }
     for (int32_t r = 0; r < n_ctx; ++r) {
         tild_ctx* c = ctxs[r];
         if (n_steps & 1) {
@@ -1636,6 +1656,7 @@ TILD_API int tild_batch_step_static(tild_ctx* const* ctxs, int32_t n_ctx, int64_
             std::swap(c->S.nbr, c->S.nbr_old);
         }
         c->step += n_steps;
+        c->noise_ready = c->step;
     }
     return TILD_OK;
 }

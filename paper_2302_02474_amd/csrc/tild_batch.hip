@@ -15,8 +15,8 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         constexpr int P = decltype(Pc)::value;
         hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
                            (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
-                           (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, 1, so, (long long*)nullptr, R, B.plane,
-                           par, (const T*)nullptr, (T*)nullptr, 0);
+                           (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, R, B.plane, par, (const T*)nullptr,
+                           (T*)nullptr, 0);
         if (L.ph.elec)
             hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
@@ -30,7 +30,7 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
         hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
                            (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
                            (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
-                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr);
+                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr, 0);
         hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                            (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
                            L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,
@@ -42,7 +42,17 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
     hipLaunchKernelGGL((k_scatter<T, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                        (const uint2*)nullptr, (const uint32_t*)nullptr, (const int32_t*)nullptr, (uint4*)nullptr,
                        (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph, (const T*)nullptr, (T*)nullptr, R, B.bead, par,
-                       (uint4*)nullptr, (const uint32_t*)nullptr, L.d, L.order);
+                       (uint4*)nullptr, (const uint32_t*)nullptr, L.d, L.order, (long long*)nullptr, so + 1);
+}
+
+hipError_t launch_batch_noise(const Launch& L, const BatchMaps& B) {
+    if (L.precision == 0)
+        hipLaunchKernelGGL((k_noise_sum<float, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr, 0LL,
+                           L.ph, (uint64_t)0, (long long*)nullptr, B.reps, B.bead);
+    else
+        hipLaunchKernelGGL((k_noise_sum<double, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
+                           0LL, L.ph, (uint64_t)0, (long long*)nullptr, B.reps, B.bead);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z) {

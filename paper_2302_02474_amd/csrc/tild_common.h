@@ -238,8 +238,10 @@ __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
             k0 += WA;
             k1 += WB;
         }
-        const uint32_t hi0 = __umulhi(A, c.x), lo0 = A * c.x;
-        const uint32_t hi1 = __umulhi(B, c.z), lo1 = B * c.z;
+        // both halves of each 32 x 32 -> 64-bit product from one multiply
+        const uint64_t p0 = (uint64_t)A * c.x, p1 = (uint64_t)B * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
     }
     return c;

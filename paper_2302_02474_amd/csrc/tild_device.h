@@ -14,7 +14,8 @@
 //               partials) + bond force, Philox noise, Euler-Maruyama update,
 //               each moved bead's bin key and rank
 //   bin_scan    bin counts -> bin starts
-//   scatter     beads and bond partners into the new sorted order
+//   scatter     beads and bond partners into the new sorted order; the noise
+//               sums of the next step's centre-of-mass shift
 #pragma once
 
 #include "tild_kernels.h"
@@ -128,15 +129,10 @@ struct Walk2 {
 //
 // pos holds the beads' grid records in single precision, their fixed-point
 // positions in double precision (bead_frac).
-//
-// With `noise`, every bead of the plane's own slab (c = 0, so each bead once
-// over the grid) also adds its Gaussian increment of step `step` to nsum, in
-// 32.32 fixed point (exact for float increments, order-independent).
 template <typename T, int P>
 __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, const uint4* __restrict__ pos,
                                              const uint32_t* __restrict__ bin_start,
                                              const uint32_t* __restrict__ qs, const Dims d, int z, int K, T scale,
-                                             bool noise, bool two, uint64_t step, uint64_t seed, long long nsum[3],
                                              int tid, int nthr) {
     using A = typename std::conditional<sizeof(T) == 4, uint32_t, unsigned long long>::type;
     A* acc = reinterpret_cast<A*>(lds);
@@ -162,17 +158,6 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
                 const uint32_t j = jb + (uint32_t)(u * nthr);
                 if (j >= j1) break;
                 const uint4 q = qv[u];
-                if (c == 0 && noise) {
-                    // the step's noise; with `two` (GJF) also that of the next step
-                    for (int k = 0; k < (two ? 2 : 1); ++k) {
-                        T xi[3];
-                        Noise<T>::draw(q.w >> 1, step + (uint64_t)k, seed, xi);
-                        nsum[0] += llrint((double)xi[0] * kTwo32);
-                        nsum[1] += llrint((double)xi[1] * kTwo32);
-                        nsum[2] += llrint((double)xi[2] * kTwo32);
-                    }
-
-                }
                 const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
                 T wx[P], wy[P];
                 spline_weights<T, P>(bf.fx, wx);
@@ -384,8 +369,8 @@ template <typename T, int BLOCK, int P, bool BATCH = false, bool DIR = false, bo
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
     k_spread_xy(const uint4* __restrict__ pos, const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs,
                 cplx<T>* __restrict__ spec, Dims d, FftPlan px, FftPlan py, const cplx<T>* __restrict__ tw, Phys ph,
-                uint32_t* __restrict__ flag, int noise, uint64_t step, long long* __restrict__ noise_part,
-                const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
+                uint32_t* __restrict__ flag, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
+                int parity,
                 const T* __restrict__ vdir, T* __restrict__ cout, int comp) {
     static_assert(!WSP || DIR, "weighted counts use the floating-point accumulation of DIR");
     using C = cplx<T>;
@@ -393,7 +378,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax[BLOCK / 64];
-    __shared__ long long nred[3 * (BLOCK / 64)];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
@@ -411,8 +395,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         tw = (const C*)R.S.tw;
         ph = R.ph;
         flag = R.S.flag;
-        step += R.step0;  // step: the step's index within the batch call
-        noise_part = R.S.noise_part;
         t = (int)(e & 0xffffu);
     } else {
         t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
@@ -459,16 +441,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         __syncthreads();
         fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
     } else {
-        long long nsum[3] = {0, 0, 0};
-        spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, noise, ph.gjf != 0, step, ph.seed, nsum, tid,
-                           BLOCK);
-        if (noise) {
-            block_sum<long long, 3>(nsum, nred, tid, BLOCK);  // ends with a barrier
-            if (tid == 0)
-                for (int a = 0; a < 3; ++a) noise_part[(K * d.mz + z) * 3 + a] = nsum[a];
-        } else {
-            __syncthreads();
-        }
+        spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK);
+        __syncthreads();
         fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     }
     if constexpr (COUNTS) {
@@ -939,6 +913,9 @@ __device__ __forceinline__ void fill_ghosts(T* __restrict__ Sr, const Dims d, in
 // species): 1 -- the local part of the transposed force Jacobian against
 // vdir (push_plane_local); 2 -- store the gradient plane d_a phi_K(z) in
 // fout ([2][mz][my][mx], x fastest), adding to what is there when comp > 0.
+//
+// The ik route's stepping pass (XM = 0, not batched) runs on a 1-D grid over
+// units t0 .. t0 + gridDim.x - 1 of the 6 mz units t = (K mz + z) 3 + a.
 template <typename T, int BLOCK, int P, bool AD, bool BATCH = false, bool HESS = false, bool FIELD = false,
           int XM = 0>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
@@ -946,7 +923,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
              const cplx<T>* __restrict__ tw, Phys ph, const uint4* __restrict__ pos,
              const uint32_t* __restrict__ bin_start, const uint32_t* __restrict__ qs, long long n,
              long long* __restrict__ fsum_part, const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap,
-             int parity, const T* __restrict__ vdir, const T* __restrict__ field, int comp, T* __restrict__ fout) {
+             int parity, const T* __restrict__ vdir, const T* __restrict__ field, int comp, T* __restrict__ fout,
+             int t0) {
     static_assert(XM == 0 || (!AD && !BATCH), "the Jacobian modes run on the ik route of one context");
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -973,9 +951,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         t = (int)(e & 0xffffu);
     } else if constexpr (XM != 0) {
         t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
+    } else if constexpr (AD) {
+        t = xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz);
     } else {
-        t = AD ? xcd_contiguous(blockIdx.x + d.mz * blockIdx.y, 2 * d.mz)
-               : xcd_contiguous(blockIdx.x + d.mz * (blockIdx.y + 2 * blockIdx.z), 6 * d.mz);
+        t = t0 + xcd_contiguous(blockIdx.x, gridDim.x);  // units t0 .. t0 + gridDim.x - 1 of 6 mz
     }
     constexpr bool ONE = AD || XM != 0;  // one workgroup per plane and species
     const int a = AD ? 2 : (XM != 0 ? comp : t % 3);
@@ -1094,7 +1073,8 @@ struct ZPlane {
 // the shortest, also forms the step's centre-of-mass shift: the forces sum to
 // zero exactly (pairwise bonds; the ik route with the Nyquist derivative
 // zeroed), so the mean displacement is sqrt(2 kT dt/gamma) times the mean
-// Gaussian increment, which the spread pass summed per plane.
+// Gaussian increment, summed per 256-bead block (k_noise_sum, or the previous
+// step's scatter).
 // ELEC: the Coulomb kernel of Gaussian-smeared per-species charges joins the
 // pair kernel: Phi^_K += q_K W_e rho^_e with W_e = (4 pi l_B / V)
 // exp(-a_e^2 k^2) / k^2 and rho^_e = q_A c^_A + q_B c^_B (k = 0 left out),
@@ -1141,7 +1121,8 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
     if (noise_part && blk == nblk - 1) {
         __shared__ long long nred[3 * (BLOCK / 64)];
         long long v[3] = {0, 0, 0};
-        for (int i = threadIdx.x; i < 2 * d.mz; i += BLOCK)
+        const long long nb = (n + 255) / 256;  // the 256-bead blocks that summed the step's noise
+        for (long long i = threadIdx.x; i < nb; i += BLOCK)
             for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
         block_sum<long long, 3>(v, nred, threadIdx.x, BLOCK);
         if (threadIdx.x == 0) {
@@ -1397,7 +1378,7 @@ __global__ void __launch_bounds__(256)
         const uint32_t nsh[3] = {qs_new[0], qs_new[1], qs_new[2]};  // formed before this kernel
         uint32_t kb = 0xffffffffu;
         if (active) {
-            const double inv_l[3] = {kTwo32 / ph.lx, kTwo32 / ph.ly, kTwo32 / ph.lz};
+            const double inv_l[3] = {ph.qx, ph.qy, ph.qz};
             const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
             T xi[3];
             Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
@@ -1597,6 +1578,57 @@ __global__ void __launch_bounds__(256)
     if (tile == ntiles - 1 && tid == 0) bin_start[nbins] = s_excl + agg;
 }
 
+// The Gaussian increments of step `step` (GJF: steps step and step + 1; the
+// same draws the update takes) of bead j of a 256-bead block (j < 0: none),
+// summed over the block in 32.32 fixed point (exact for float increments, so
+// the total over blocks does not depend on the bead order) into out[0 .. 2].
+// Called by all 256 threads of the block.
+template <typename T>
+__device__ __forceinline__ void noise_sum_block(const uint4* __restrict__ pos, long long j, const Phys& ph,
+                                                uint64_t step, long long* __restrict__ out) {
+    __shared__ long long nred[3 * 4];
+    long long ns[3] = {0, 0, 0};
+    if (j >= 0) {
+        const uint32_t id = pos[j].w >> 1;
+        T xi[3];
+        Noise<T>::draw(id, step, ph.seed, xi);
+        if (ph.gjf) {
+            T x1[3];
+            Noise<T>::draw(id, step + 1, ph.seed, x1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xi[a] += x1[a];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ns[a] = llrint((double)xi[a] * kTwo32);
+    }
+    block_sum<long long, 3>(ns, nred, threadIdx.x, 256);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) out[a] = ns[a];
+}
+
+// Noise sums of step `step` per 256-bead block of pos (any order), as the
+// scatter of the previous step leaves them; for the first step of a run.
+// BATCH: every member of a batch, bead blocks named by the unit map, at each
+// member's own step.
+template <typename T, bool BATCH = false>
+__global__ void __launch_bounds__(256)
+    k_noise_sum(const uint4* __restrict__ pos, long long n, Phys ph, uint64_t step, long long* __restrict__ noise_part,
+                const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap) {
+    long long blk = blockIdx.x;
+    if constexpr (BATCH) {
+        const uint32_t e = umap[blockIdx.x];
+        const RepDesc& R = reps[e >> 16];
+        pos = R.S.pos;
+        n = R.S.n;
+        ph = R.ph;
+        step = R.step0;
+        noise_part = R.S.noise_part;
+        blk = (long long)(e & 0xffffu);
+    }
+    const long long j = blk * 256LL + threadIdx.x;
+    noise_sum_block<T>(pos, j < n ? j : -1, ph, step, noise_part + 3 * blk);
+}
+
 // Move every bead of the previous order to its sorted slot, translate its
 // bond partners (slots of the previous order) into sorted slots, and store
 // its harmonic bond force F = -2 k_b sum_partners d (d the minimum-image bond
@@ -1604,13 +1636,18 @@ __global__ void __launch_bounds__(256)
 // null) the half-step velocity moves with the bead.  Single precision: also
 // the bead's grid record {x, y, z, id << 1 | species} (grid_record, with the
 // current shift qs and order P) to grec[slot].
+//
+// With noise_part, the block also sums the Gaussian increments of step
+// noise_step (GJF: of steps noise_step and noise_step + 1) over its beads, for
+// the centre-of-mass shift of that step (noise_sum_block).
 template <typename T, bool BATCH = false>
 __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
               T* __restrict__ fbond, long long n, int deg, Phys ph, const T* __restrict__ vsrc, T* __restrict__ vdst,
               const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
-              uint4* __restrict__ grec, const uint32_t* __restrict__ qs, Dims d, int P) {
+              uint4* __restrict__ grec, const uint32_t* __restrict__ qs, Dims d, int P,
+              long long* __restrict__ noise_part, uint64_t noise_step) {
     // contiguous bead ranges per XCD: bond partners are near in the order
     long long blk = xcd_contiguous(blockIdx.x, gridDim.x);
     if constexpr (BATCH) {
@@ -1631,9 +1668,12 @@ __global__ void __launch_bounds__(256)
         grec = R.S.grec;
         qs = parity ? R.S.qshift : R.S.qshift_next;  // the shift the update of this step formed
         d = R.d;
+        noise_part = R.S.noise_part;  // batched steps always sum the next step's noise
+        noise_step += R.step0;        // noise_step: the step's index within the batch call, plus one
         blk = (long long)(e & 0xffffu);
     }
     const long long j = blk * 256LL + threadIdx.x;
+    if (noise_part) noise_sum_block<T>(pos_tmp, j < n ? j : -1, ph, noise_step, noise_part + 3 * blk);
     if (j >= n) return;
     const uint2 kj = kr[j];
     const long long nw = (long long)bin_start[kj.x] + kj.y;

@@ -17,6 +17,7 @@ constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
 // Physical constants of one context, passed by value to kernels.
 struct Phys {
     double lx, ly, lz;
+    double qx, qy, qz;  // 2^32 / L per axis: fixed-point units per length
     double a2;          // smear_a^2
     double chi, kappa;  // interaction parameters
     double inv_n;       // 1 / N
@@ -83,16 +84,15 @@ struct DeviceState {
     double* vtab;         // [mx + my + mz] per-axis factors of exp(-a^2 k^2) (virial); utab's array when equal
     double* epart;        // [n_zblocks][5] energy partials of the k-space pass
     long long* bpart;     // [n_bblocks][4] bond energy / virial partials (32.32 fixed point)
-    long long* noise_part;  // [2 mz][3] per-plane sums of the step's Gaussian increments (32.32 fixed point)
+    long long* noise_part;  // [max(n_bblocks, 2 mz)][3] per-256-bead-block sums of a step's Gaussian increments
+                            // (32.32 fixed point)
     long long* fsum_part;   // [2 mz][3] per-plane sums of the non-bonded forces (exact-gradient route)
     uint32_t* flag;       // [1] bit 0: non-finite value; bit 2: a grid plane too dense for the fixed-point spread
     double* eout;         // [16] reduced energies, virial, parameter gradients
     long long n;
     long long n_a, n_b;
     int deg;              // bond slots per bead (maximum degree)
-    int noise_step;       // set while stepping: the spread sums the noise of step `step`, the k-space
-                          // pass forms qshift_next from it
-    long long step;       // step index of the noise the spread sums
+    int noise_step;       // set while stepping: the k-space pass forms qshift_next from the noise sums
     int nbins;            // 2 * mz * my
 };
 
@@ -159,7 +159,10 @@ hipError_t launch_xy_c2r(const Launch& L, DeviceState& S, int route = -1);
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts, double out_sign = 1.0);
 hipError_t launch_bin_scan(const Launch& L, DeviceState& S);
-hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src);
+// noise_step >= 0: also the per-block noise sums of step noise_step (into noise_part)
+hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src, int64_t noise_step = -1);
+// per-block noise sums of step `step` (into noise_part), from the beads' ids in pos
+hipError_t launch_noise_sum(const Launch& L, DeviceState& S, uint64_t step);
 hipError_t launch_bond_energy(const Launch& L, DeviceState& S);
 hipError_t launch_reduce_energy(const Launch& L, DeviceState& S);
 // ABI-order input -> pos_tmp, key, rank (qshift reset to 0)
@@ -196,6 +199,8 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 // the step's index within the call (its parity selects the pointer pairs).
 // lds_plane / lds_z: the largest dynamic LDS any member needs.
 hipError_t launch_batch_step(const Launch& L, const BatchMaps& B, int s, size_t lds_plane, size_t lds_z);
+// every member's per-block noise sums of its current step (before the first batched step of a call)
+hipError_t launch_batch_noise(const Launch& L, const BatchMaps& B);
 hipError_t configure_batch_attributes(const Launch& L, size_t lds_plane, size_t lds_z);
 
 // Dynamic LDS a plane / z workgroup needs (bytes), used for validation.

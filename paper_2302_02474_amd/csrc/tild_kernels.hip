@@ -6,9 +6,9 @@
 namespace tild {
 
 // Exact-gradient route: the non-bonded forces do not sum to zero, so the
-// step's centre-of-mass shift comes from the per-plane noise and force sums
-// (32.32 fixed point, so the total is order-independent): the mean
-// displacement is (sqrt(2 kT dt/gamma) sum xi + (dt/gamma) sum F) / N.
+// step's centre-of-mass shift comes from the per-block noise sums and the
+// per-plane force sums (32.32 fixed point, so the total is order-independent):
+// the mean displacement is (sqrt(2 kT dt/gamma) sum xi + (dt/gamma) sum F) / N.
 __global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict__ noise_part,
                                                     const long long* __restrict__ fsum_part, int nplanes, long long n,
                                                     Phys ph, const uint32_t* __restrict__ qs,
@@ -16,11 +16,11 @@ __global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict_
     __shared__ long long red[6 * 4];
     const int tid = threadIdx.x;
     long long v[6] = {0, 0, 0, 0, 0, 0};
+    const long long nb = (n + 255) / 256;
+    for (long long i = tid; i < nb; i += 256)
+        for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
     for (int i = tid; i < nplanes; i += 256)
-        for (int a = 0; a < 3; ++a) {
-            v[a] += noise_part[3 * i + a];
-            v[3 + a] += fsum_part[3 * i + a];
-        }
+        for (int a = 0; a < 3; ++a) v[3 + a] += fsum_part[3 * i + a];
     block_sum<long long, 6>(v, red, tid, 256);
     if (tid == 0) {
         const double L[3] = {ph.lx, ph.ly, ph.lz};
@@ -199,18 +199,31 @@ hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src) {
+hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src, int64_t noise_step) {
     if (S.n == 0) return hipSuccess;
+    long long* np = noise_step >= 0 ? S.noise_part : nullptr;
+    const uint64_t ns = noise_step >= 0 ? (uint64_t)noise_step : 0u;
     if (L.precision == 0)
         hipLaunchKernelGGL((k_scatter<float, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph,
                            (const float*)S.vel_tmp, (float*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
-                           S.grec, S.qshift, L.d, L.order);
+                           S.grec, S.qshift, L.d, L.order, np, ns);
     else
         hipLaunchKernelGGL((k_scatter<double, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
                            S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph,
                            (const double*)S.vel_tmp, (double*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
-                           S.grec, S.qshift, L.d, L.order);
+                           S.grec, S.qshift, L.d, L.order, np, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_sum(const Launch& L, DeviceState& S, uint64_t step) {
+    const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
+    if (L.precision == 0)
+        hipLaunchKernelGGL((k_noise_sum<float, false>), dim3(g), dim3(256), 0, L.stream, S.pos, S.n, L.ph, step,
+                           S.noise_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr);
+    else
+        hipLaunchKernelGGL((k_noise_sum<double, false>), dim3(g), dim3(256), 0, L.stream, S.pos, S.n, L.ph, step,
+                           S.noise_part, (const RepDesc*)nullptr, (const uint32_t*)nullptr);
     return hipGetLastError();
 }
 
