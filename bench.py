@@ -277,6 +277,7 @@ def main() -> int:
                 "batched_bead_steps_per_s": n_rep / (batched_ms * 1e-3),
                 "sequential_bead_steps_per_s": n_rep / (seq_ms * 1e-3),
                 "speedup": round(seq_ms / batched_ms, 3), "plane_block_autotuned": plane_block,
+                "z_cols_autotuned": bt.z_cols,
                 "graph_replay_autotuned": bool(bt.graph)}
     print(f"[bench] 64 replicas ({n_rep} beads): batched {batched_ms:.4f} ms/step, one by one {seq_ms:.4f} ms/step",
           file=sys.stderr, flush=True)

@@ -420,14 +420,19 @@ int tild_batch_step(tild_batch* batch, int64_t n_steps);
  * Choose the batch's plane-workgroup size (256 or 512 threads; the default
  * is set from the largest member plane) by timing trial_steps (1..1000)
  * batched steps with each, twice, on the members' own systems with eager
- * launches, then whether replaying the steps from a captured HIP graph is
- * faster with that size.  Every member's positions and step counter are
- * restored after each trial, so the simulation state is unchanged
- * (bitwise).  Synchronises; needs a temporary device buffer of 24 bytes per
- * bead.  The choices are stored in *plane_block (threads) and *graph (1 =
+ * launches; then, with that size, the column block of the k-space pass
+ * (each member's own, or 8, 12, 16, 24 or 32 columns for every member,
+ * widths whose local memory does not fit skipped; twice each); then whether
+ * replaying the steps from a captured HIP graph is faster.  Every member's
+ * positions and step counter are restored after each trial, so the
+ * simulation state is unchanged (bitwise: the column block changes no
+ * result).  Synchronises; needs a temporary device buffer of 24 bytes per
+ * bead and rebuilds the batch's work-unit maps.  The choices are stored in
+ * *plane_block (threads), *z_cols (0 = each member's own) and *graph (1 =
  * graph replay) when those are not NULL.
  */
-int tild_batch_autotune(tild_batch* batch, int32_t trial_steps, int32_t* plane_block, int32_t* graph);
+int tild_batch_autotune(tild_batch* batch, int32_t trial_steps, int32_t* plane_block, int32_t* z_cols,
+                        int32_t* graph);
 /*
  * Replay batched steps from captured HIP graphs (use_graph != 0, the default)
  * or launch every kernel of every step from the host (0).  With graphs, the

@@ -349,6 +349,7 @@ class Batch:
         handle = stream if isinstance(stream, int) else getattr(stream, "cuda_stream", 0)
         self._stream = ctypes.c_void_p(int(handle) if handle else None)
         self.graph = True
+        self.z_cols = 0
         rc = self._lib.tild_batch_create(arr, len(self.members), self._stream, ctypes.byref(self._b))
         if rc != TILD_OK:
             raise TildError(rc, self._lib.tild_batch_last_error(None).decode())
@@ -364,10 +365,13 @@ class Batch:
         self._check(self._lib.tild_batch_synchronize(self._b))
 
     def autotune(self, trial_steps: int = 4) -> int:
-        """Time the plane-workgroup sizes and graph replay on the members' own systems (state restored) and
-        keep the fastest; returns the plane-workgroup size (self.graph tells whether graphs are replayed)."""
-        pb, gr = ctypes.c_int32(0), ctypes.c_int32(0)
-        self._check(self._lib.tild_batch_autotune(self._b, int(trial_steps), ctypes.byref(pb), ctypes.byref(gr)))
+        """Time the plane-workgroup sizes, the k-space column blocks and graph replay on the members' own
+        systems (state restored) and keep the fastest; returns the plane-workgroup size (self.z_cols holds the
+        column block, 0 = each member's own, and self.graph whether graphs are replayed)."""
+        pb, zc, gr = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self._lib.tild_batch_autotune(self._b, int(trial_steps), ctypes.byref(pb), ctypes.byref(zc),
+                                                  ctypes.byref(gr)))
+        self.z_cols = zc.value
         self.graph = bool(gr.value)
         return pb.value
 

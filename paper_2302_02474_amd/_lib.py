@@ -126,7 +126,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.tild_adjoint_step.restype = ctypes.c_int
     lib.tild_batch_create.argtypes = [P(vp), i32, vp, P(vp)]
     lib.tild_batch_create.restype = ctypes.c_int
-    lib.tild_batch_autotune.argtypes = [vp, i32, P(i32), P(i32)]
+    lib.tild_batch_autotune.argtypes = [vp, i32, P(i32), P(i32), P(i32)]
     lib.tild_batch_autotune.restype = ctypes.c_int
     lib.tild_batch_step.argtypes = [vp, i64]
     lib.tild_batch_step.restype = ctypes.c_int

@@ -1157,6 +1157,10 @@ struct tild_batch {
     hipGraphExec_t exec = nullptr;
     int64_t exec_steps = 0;
     int exec_block = 0;  // plane_block the graph was captured with
+    // column block of the batched k-space pass: 0 = each member's own (its single-context choice), else this
+    // many columns for every member; zc / nzb: the columns per block and blocks each member uses
+    int z_cols = 0;
+    std::vector<int> zc, nzb;
     std::string err;
 
     void drop_graph() {
@@ -1194,6 +1198,79 @@ TILD_API void tild_batch_destroy(tild_batch* b) {
     delete b;
 }
 
+namespace {
+
+// (Re)build a batch's unit maps, scan status words and LDS sizes for k-space column blocks of z_cols
+// columns (0: each member's own).  Member by member, the largest grids first (their planes and column
+// blocks take longest, so the last round of workgroups holds the short ones); every member's scan keeps
+// its own status words.  hipErrorInvalidValue if a member's column block would not fit the LDS.
+hipError_t build_batch_maps(tild_batch* b, int z_cols) {
+    const int32_t n_ctx = (int32_t)b->ctx.size();
+    std::vector<uint32_t> plane, c2r, zcol, bead, tile;
+    std::vector<int> zc((size_t)n_ctx), nzb((size_t)n_ctx);
+    std::vector<size_t> status_off((size_t)n_ctx, 0);
+    size_t nstatus = 0, lds_plane = 0, lds_z = 0;
+    for (const int32_t r : members_by_size(b->ctx.data(), n_ctx)) {
+        const tild_ctx* c = b->ctx[(size_t)r];
+        const Dims& d = c->L.d;
+        Launch Lz = c->L;
+        if (z_cols > 0) Lz.z_cols = (int)std::min<long long>(z_cols, d.hplane);
+        zc[(size_t)r] = Lz.z_cols;
+        nzb[(size_t)r] = (int)((d.hplane + Lz.z_cols - 1) / Lz.z_cols);
+        const uint32_t hi = (uint32_t)r << 16;
+        for (int u = 0; u < 2 * d.mz; ++u) plane.push_back(hi | (uint32_t)u);
+        for (int u = 0; u < 6 * d.mz; ++u) c2r.push_back(hi | (uint32_t)u);
+        for (int u = 0; u < nzb[(size_t)r]; ++u) zcol.push_back(hi | (uint32_t)u);
+        for (long long u = 0; u < (c->S.n + 255) / 256; ++u) bead.push_back(hi | (uint32_t)u);
+        const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
+        for (int u = 0; u < ntiles; ++u) tile.push_back(hi | (uint32_t)u);
+        status_off[(size_t)r] = nstatus;
+        nstatus += (size_t)ntiles;
+        lds_plane = std::max(lds_plane, plane_lds_bytes(c->L));
+        lds_z = std::max(lds_z, z_lds_bytes(Lz));
+        if (nzb[(size_t)r] > 65535) return hipErrorInvalidValue;
+    }
+    if (lds_z > 160 * 1024) return hipErrorInvalidValue;
+    const size_t nmap = plane.size() + c2r.size() + zcol.size() + bead.size() + tile.size();
+    std::vector<uint32_t> all;
+    all.reserve(nmap);
+    for (const auto* v : {&plane, &c2r, &zcol, &bead, &tile}) all.insert(all.end(), v->begin(), v->end());
+    // the old maps may still be read by queued work, and the graph captured over them is dropped
+    hipError_t e = hipStreamSynchronize(b->stream);
+    b->drop_graph();
+    if (b->maps) (void)hipFree(b->maps);
+    if (b->status) (void)hipFree(b->status);
+    b->maps = nullptr;
+    b->status = nullptr;
+    if (e == hipSuccess) e = hipMalloc((void**)&b->maps, nmap * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpy(b->maps, all.data(), nmap * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->status, (nstatus + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(b->status, 0, (nstatus + 1) * sizeof(unsigned long long));
+    if (e == hipSuccess) e = configure_batch_attributes(b->L, lds_plane, lds_z);
+    if (e != hipSuccess) return e;
+    BatchMaps& B = b->B;
+    B.plane = b->maps;
+    B.c2r = B.plane + plane.size();
+    B.zcol = B.c2r + c2r.size();
+    B.bead = B.zcol + zcol.size();
+    B.tile = B.bead + bead.size();
+    B.n_plane = (int)plane.size();
+    B.n_c2r = (int)c2r.size();
+    B.n_zcol = (int)zcol.size();
+    B.n_bead = (int)bead.size();
+    B.n_tile = (int)tile.size();
+    B.ticket = b->status + nstatus;
+    b->status_off = status_off;
+    b->zc = zc;
+    b->nzb = nzb;
+    b->z_cols = z_cols;
+    b->lds_plane = lds_plane;
+    b->lds_z = lds_z;
+    return hipSuccess;
+}
+
+}  // namespace
+
 TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_stream, tild_batch** out) {
     if (!out) return TILD_EINVAL;
     *out = nullptr;
@@ -1227,34 +1304,7 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
     b->L = c0->L;
     b->L.stream = b->stream;
     DeviceGuard g(b->device);
-    // unit maps, member by member, the largest grids first (their planes and column blocks take longest,
-    // so the last round of workgroups holds the short ones); every member's scan keeps its own status words
-    std::vector<uint32_t> plane, c2r, zcol, bead, tile;
-    size_t nstatus = 0;
-    b->status_off.assign((size_t)n_ctx, 0);
-    for (const int32_t r : members_by_size(ctxs, n_ctx)) {
-        const tild_ctx* c = ctxs[r];
-        const Dims& d = c->L.d;
-        const uint32_t hi = (uint32_t)r << 16;
-        for (int u = 0; u < 2 * d.mz; ++u) plane.push_back(hi | (uint32_t)u);
-        for (int u = 0; u < 6 * d.mz; ++u) c2r.push_back(hi | (uint32_t)u);
-        for (int u = 0; u < c->L.n_zblocks; ++u) zcol.push_back(hi | (uint32_t)u);
-        for (long long u = 0; u < (c->S.n + 255) / 256; ++u) bead.push_back(hi | (uint32_t)u);
-        const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
-        for (int u = 0; u < ntiles; ++u) tile.push_back(hi | (uint32_t)u);
-        b->status_off[(size_t)r] = nstatus;
-        nstatus += (size_t)ntiles;
-        b->lds_plane = std::max(b->lds_plane, plane_lds_bytes(c->L));
-        b->lds_z = std::max(b->lds_z, z_lds_bytes(c->L));
-    }
-    const size_t nmap = plane.size() + c2r.size() + zcol.size() + bead.size() + tile.size();
-    std::vector<uint32_t> all;
-    all.reserve(nmap);
-    for (const auto* v : {&plane, &c2r, &zcol, &bead, &tile}) all.insert(all.end(), v->begin(), v->end());
-    hipError_t e = hipMalloc((void**)&b->maps, nmap * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpy(b->maps, all.data(), nmap * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->status, (nstatus + 1) * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemset(b->status, 0, (nstatus + 1) * sizeof(unsigned long long));
+    hipError_t e = build_batch_maps(b, 0);
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_desc, (size_t)n_ctx * sizeof(RepDesc));
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_desc, (size_t)n_ctx * sizeof(RepDesc), hipHostMallocDefault);
     b->member_ev.assign((size_t)n_ctx, nullptr);
@@ -1263,7 +1313,6 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copy_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = configure_batch_attributes(b->L, b->lds_plane, b->lds_z);
     if (e != hipSuccess) {
         g_create_error = std::string("batch: device setup: ") + hipGetErrorString(e);
         tild_batch_destroy(b);
@@ -1271,17 +1320,6 @@ TILD_API int tild_batch_create(tild_ctx* const* ctxs, int32_t n_ctx, void* hip_s
     }
     BatchMaps& B = b->B;
     B.reps = b->d_desc;
-    B.plane = b->maps;
-    B.c2r = B.plane + plane.size();
-    B.zcol = B.c2r + c2r.size();
-    B.bead = B.zcol + zcol.size();
-    B.tile = B.bead + bead.size();
-    B.n_plane = (int)plane.size();
-    B.n_c2r = (int)c2r.size();
-    B.n_zcol = (int)zcol.size();
-    B.n_bead = (int)bead.size();
-    B.n_tile = (int)tile.size();
-    B.ticket = b->status + nstatus;
     // measured on MI355X with 64 replicas of 32^2..80^2 planes: 256-thread plane workgroups are 13 %
     // faster than 512 (several small planes per CU); larger planes keep 512
     int max_plane = 0;
@@ -1316,10 +1354,10 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
         R.ph = c->L.ph;
         R.S = c->S;
         R.S.scan_status = b->status + b->status_off[r];
-        R.z_cols = c->L.z_cols;
-        R.n_zblocks = c->L.n_zblocks;
         R.ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
         R.step0 = (uint64_t)c->step;
+        R.z_cols = b->zc[r];
+        R.n_zblocks = b->nzb[r];
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_desc, b->h_desc, b->ctx.size() * sizeof(RepDesc), hipMemcpyHostToDevice, b->stream);
@@ -1375,7 +1413,8 @@ TILD_API int tild_batch_step(tild_batch* b, int64_t n_steps) {
     return TILD_OK;
 }
 
-TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* plane_block, int32_t* graph) {
+TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* plane_block, int32_t* z_cols,
+                                int32_t* graph) {
     if (!b) return TILD_EINVAL;
     if (trial_steps < 1 || trial_steps > 1000) return b->fail(TILD_EINVAL, "autotune: trial_steps must be in [1, 1000]");
     for (tild_ctx* c : b->ctx)
@@ -1400,7 +1439,7 @@ TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* pl
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
-    const int keep_block = b->B.plane_block;
+    const int keep_block = b->B.plane_block, keep_z = b->z_cols;
     const bool keep_graph = b->use_graph;
     int rc = TILD_OK;
     // one trial: trial_steps batched steps, timed on the batch's stream, the state restored afterwards
@@ -1431,6 +1470,27 @@ TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* pl
     for (int rep = 0; rep < 4 && e == hipSuccess && rc == TILD_OK; ++rep)
         best_ms[rep & 1] = std::min(best_ms[rep & 1], trial(cand[rep & 1], false));
     const int block = best_ms[0] <= best_ms[1] ? cand[0] : cand[1];
+    // k-space column blocks with that size: each member's own, or one width for all members (widths whose
+    // LDS does not fit are skipped), each twice
+    const int zcand[6] = {0, 8, 12, 16, 24, 32};
+    float best_z_ms = std::min(best_ms[0], best_ms[1]);
+    int best_z = keep_z;
+    for (int rep = 0; rep < 2 && e == hipSuccess && rc == TILD_OK; ++rep)
+        for (const int zc : zcand) {
+            if (e != hipSuccess || rc != TILD_OK) break;
+            if (zc != b->z_cols) {
+                const hipError_t eb = build_batch_maps(b, zc);
+                if (eb == hipErrorInvalidValue) continue;  // does not fit: skipped
+                e = eb;
+                if (e != hipSuccess) break;
+            }
+            const float ms = trial(block, false);
+            if (ms < best_z_ms) {
+                best_z_ms = ms;
+                best_z = zc;
+            }
+        }
+    if (e == hipSuccess && rc == TILD_OK && b->z_cols != best_z) e = build_batch_maps(b, best_z);
     float graph_ms = 1e30f;
     if (e == hipSuccess && rc == TILD_OK) (void)trial(block, true);
     for (int rep = 0; rep < 2 && e == hipSuccess && rc == TILD_OK; ++rep) graph_ms = std::min(graph_ms, trial(block, true));
@@ -1441,12 +1501,14 @@ TILD_API int tild_batch_autotune(tild_batch* b, int32_t trial_steps, int32_t* pl
     if (rc != TILD_OK || e != hipSuccess) {
         b->B.plane_block = keep_block;
         b->use_graph = keep_graph;
+        if (b->z_cols != keep_z) (void)build_batch_maps(b, keep_z);
         if (rc != TILD_OK) return b->fail(rc, "autotune: a trial step or the restore failed");
         return b->hip_fail(e, "autotune");
     }
     b->B.plane_block = block;
-    b->use_graph = graph_ms <= std::min(best_ms[0], best_ms[1]);
+    b->use_graph = graph_ms <= best_z_ms;
     if (plane_block) *plane_block = b->B.plane_block;
+    if (z_cols) *z_cols = b->z_cols;
     if (graph) *graph = b->use_graph ? 1 : 0;
     return TILD_OK;
 }

@@ -9,19 +9,21 @@ namespace tild {
 // step's centre-of-mass shift comes from the per-block noise sums and the
 // per-plane force sums (32.32 fixed point, so the total is order-independent):
 // the mean displacement is (sqrt(2 kT dt/gamma) sum xi + (dt/gamma) sum F) / N.
-__global__ void __launch_bounds__(256) k_form_shift(const long long* __restrict__ noise_part,
-                                                    const long long* __restrict__ fsum_part, int nplanes, long long n,
-                                                    Phys ph, const uint32_t* __restrict__ qs,
-                                                    uint32_t* __restrict__ qs_next) {
-    __shared__ long long red[6 * 4];
+constexpr int kShiftBlock = 1024;  // one workgroup; its threads share the per-block and per-plane partials
+
+__global__ void __launch_bounds__(kShiftBlock) k_form_shift(const long long* __restrict__ noise_part,
+                                                            const long long* __restrict__ fsum_part, int nplanes,
+                                                            long long n, Phys ph, const uint32_t* __restrict__ qs,
+                                                            uint32_t* __restrict__ qs_next) {
+    __shared__ long long red[6 * (kShiftBlock / 64)];
     const int tid = threadIdx.x;
     long long v[6] = {0, 0, 0, 0, 0, 0};
     const long long nb = (n + 255) / 256;
-    for (long long i = tid; i < nb; i += 256)
+    for (long long i = tid; i < nb; i += kShiftBlock)
         for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
-    for (int i = tid; i < nplanes; i += 256)
+    for (int i = tid; i < nplanes; i += kShiftBlock)
         for (int a = 0; a < 3; ++a) v[3 + a] += fsum_part[3 * i + a];
-    block_sum<long long, 6>(v, red, tid, 256);
+    block_sum<long long, 6>(v, red, tid, kShiftBlock);
     if (tid == 0) {
         const double L[3] = {ph.lx, ph.ly, ph.lz};
         for (int a = 0; a < 3; ++a) {
@@ -177,7 +179,7 @@ static void update_t(const Launch& L, DeviceState& S, uint64_t step, void* out, 
 hipError_t launch_update(const Launch& L, DeviceState& S, int mode, uint64_t step, void* out, int out_dtype,
                          unsigned parts, double out_sign) {
     if (mode == 0 && L.force_ad)
-        hipLaunchKernelGGL(k_form_shift, dim3(1), dim3(256), 0, L.stream, S.noise_part, S.fsum_part, 2 * L.d.mz,
+        hipLaunchKernelGGL(k_form_shift, dim3(1), dim3(kShiftBlock), 0, L.stream, S.noise_part, S.fsum_part, 2 * L.d.mz,
                            S.n, L.ph, S.qshift, S.qshift_next);
     const bool gjf = mode == 0 && L.ph.gjf;
     if (L.precision == 0) {

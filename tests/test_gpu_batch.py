@@ -86,7 +86,8 @@ def test_autotune_leaves_the_state_unchanged():
         a.step_count = b.step_count = 5 * i
     with T.Batch(batched) as bt:
         pb = bt.autotune(3)
-        say(f"[batch] autotune chose {pb}-thread plane workgroups, graph replay {bt.graph}")
+        say(f"[batch] autotune chose {pb}-thread plane workgroups, k-space column block {bt.z_cols} "
+            f"(0 = each member's own), graph replay {bt.graph}")
         assert pb in (256, 512)
         for i, b in enumerate(batched):
             assert b.step_count == 5 * i
