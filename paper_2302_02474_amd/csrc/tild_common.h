@@ -218,6 +218,10 @@ __device__ __forceinline__ BeadFrac<T> bead_frac(const uint4 q, uint32_t sx, uin
     return b;
 }
 
+// a * b + c rounded once, in T.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Minimum-image separation (in box units * 2^32) of two fixed-point coordinates.
 __device__ __forceinline__ int32_t fixed_delta(uint32_t a, uint32_t b) { return (int32_t)(a - b); }
 

@@ -1281,22 +1281,57 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 
 // ------------------------------------------------------------ gather + bonds + update
 
-// Rank of the calling lane among the active lanes of its wavefront that hold
-// the same key in one run of consecutive lanes; the run's first lane takes
-// the whole run's places in the bin with a single atomic.
-__device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t* __restrict__ counts) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t prev = __shfl_up(kb, 1, 64);
-    const bool head = !active || lane == 0 || prev != kb;
-    const unsigned long long hm = __ballot(head);
-    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-    const int hl = 63 - __clzll(hm & upto);
-    const unsigned long long above = hm & ~upto;
-    const int nl = above ? __ffsll((long long)above) - 1 : 64;
-    uint32_t base = 0;
-    if (active && lane == hl) base = atomicAdd(&counts[kb], (uint32_t)(nl - hl));
-    base = __shfl(base, hl, 64);
-    return base + (uint32_t)(lane - hl);
+// Ranks r[b] of a workgroup's beads in their bins (keys kb[b], active act[b]).
+// The beads of a workgroup are consecutive in the sorted order and move at
+// most a few rows or planes per step, so their new keys fall in a narrow
+// range: the workgroup counts its beads per key in LDS over a window of
+// kRankWin keys from its smallest key, then reserves each key's places with a
+// single global atomic; a bead whose key lies beyond the window takes an
+// atomic of its own.  Called by all BLOCK threads.
+constexpr int kRankWin = 1024;
+template <int NB, int BLOCK>
+__device__ __forceinline__ void block_rank(const uint32_t kb[NB], const bool act[NB], uint32_t r[NB],
+                                           uint32_t* __restrict__ counts) {
+    static_assert(kRankWin % BLOCK == 0, "window entries per thread");
+    constexpr int PER = kRankWin / BLOCK;
+    __shared__ uint32_t s_cnt[kRankWin];
+    __shared__ uint32_t s_k0;
+    const int tid = threadIdx.x;
+    uint32_t kmin = 0xffffffffu;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if (act[b]) kmin = min(kmin, kb[b]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o, 64));
+    if (tid == 0) s_k0 = 0xffffffffu;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) s_cnt[tid + i * BLOCK] = 0u;
+    __syncthreads();
+    if ((tid & 63) == 0) atomicMin(&s_k0, kmin);
+    __syncthreads();
+    const uint32_t k0 = s_k0;
+    uint32_t lr[NB];
+    bool loc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        loc[b] = act[b] && kb[b] - k0 < (uint32_t)kRankWin;
+        lr[b] = loc[b] ? atomicAdd(&s_cnt[kb[b] - k0], 1u) : 0u;
+    }
+    __syncthreads();
+    // each thread owns window entries tid + i BLOCK: read the count, reserve
+    // the places, leave the first place in the entry
+    uint32_t c[PER], base[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) c[i] = s_cnt[tid + i * BLOCK];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) base[i] = c[i] ? atomicAdd(&counts[k0 + (uint32_t)(tid + i * BLOCK)], c[i]) : 0u;
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+        if (c[i]) s_cnt[tid + i * BLOCK] = base[i];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        r[b] = loc[b] ? s_cnt[kb[b] - k0] + lr[b] : (act[b] ? atomicAdd(&counts[kb[b]], 1u) : 0u);
 }
 
 // Beads in sorted order, one per thread: F = sum of the P plane partials of each
@@ -1317,8 +1352,9 @@ __device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t*
 // MODE 1: forces only, times out_sign, written to out[abi id] ([n][3], float
 //         or double).
 // BATCH (MODE 0): one launch for all members of a batch, 256-bead blocks
-// named by the unit map.
-template <typename T, int P, int MODE, bool BATCH = false>
+// named by the unit map.  NB (MODE 0 and 2): beads per thread, the block
+// covering NB * 256 consecutive beads.
+template <typename T, int P, int MODE, bool BATCH = false, int NB = 1>
 __global__ void __launch_bounds__(256)
     k_update(const uint4* __restrict__ pin, uint4* __restrict__ pout, const T* __restrict__ fbond,
              const T* __restrict__ fpart, const uint32_t* __restrict__ qs_new,
@@ -1332,7 +1368,7 @@ __global__ void __launch_bounds__(256)
     const bool need_bond = MODE != 1 || (parts & 2u);
     long long blk = blockIdx.x;
     if constexpr (BATCH) {
-        static_assert(MODE == 0, "batched steps use Euler-Maruyama");
+        static_assert(MODE == 0 && NB == 1, "batched steps use Euler-Maruyama, one bead per thread");
         const uint32_t e = umap[blockIdx.x];
         const RepDesc& R = reps[e >> 16];
         pin = R.S.pos;
@@ -1351,50 +1387,67 @@ __global__ void __launch_bounds__(256)
         blk = (long long)(e & 0xffffu);
     }
     if constexpr (MODE != 1) {
-        // one bead per thread; its loads are issued before the shift is formed
-        const long long j = blk * 256LL + tid;
-        const bool active = j < n;
-        uint4 q = uint4{0u, 0u, 0u, 0u};
-        T f[3] = {0, 0, 0};
-        T u[3] = {0, 0, 0};
-        if (active) {
-            q = pin[j];
-            f[0] = fbond[4 * j + 0];
-            f[1] = fbond[4 * j + 1];
-            f[2] = fbond[4 * j + 2];
+        // NB beads per thread, 256 apart (each 256-bead chunk is a contiguous
+        // run of the sorted order); every load of the thread's beads is issued
+        // before any of them is advanced (a lane past the end reads the last
+        // bead and discards it)
+        if (n <= 0) return;
+        uint4 q[NB];
+        T f[NB][3], u[NB][3], fp[NB][3][P], xi[NB][3];
+        bool act[NB];
+        long long jb[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            jb[b] = (blk * NB + b) * 256LL + tid;
+            act[b] = jb[b] < n;
+            const long long j = act[b] ? jb[b] : n - 1;
+            q[b] = pin[j];
+            f[b][0] = fbond[4 * j + 0];
+            f[b][1] = fbond[4 * j + 1];
+            f[b][2] = fbond[4 * j + 2];
             if constexpr (MODE == 2) {
-                u[0] = vin[4 * j + 0];
-                u[1] = vin[4 * j + 1];
-                u[2] = vin[4 * j + 2];
+                u[b][0] = vin[4 * j + 0];
+                u[b][1] = vin[4 * j + 1];
+                u[b][2] = vin[4 * j + 2];
             }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c = 0; c < P; ++c) fp[b][a][c] = fpart[((long long)a * P + c) * n + j];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 T sa = 0;
 #pragma unroll
-                for (int c = 0; c < P; ++c) sa += fpart[((long long)a * P + c) * n + j];
-                f[a] += sa;
+                for (int c = 0; c < P; ++c) sa += fp[b][a][c];
+                f[b][a] += sa;
             }
-        }
         const uint32_t nsh[3] = {qs_new[0], qs_new[1], qs_new[2]};  // formed before this kernel
-        uint32_t kb = 0xffffffffu;
-        if (active) {
+        uint32_t kb[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            kb[b] = 0xffffffffu;
+            if (!act[b]) continue;
+            const long long j = jb[b];
             const double inv_l[3] = {ph.qx, ph.qy, ph.qz};
             const T mob = (T)ph.mob_dt, amp = (T)ph.noise_amp;
-            T xi[3];
-            Noise<T>::draw(q.w >> 1, step, ph.seed, xi);
+            Noise<T>::draw(q[b].w >> 1, step, ph.seed, xi[b]);
             if constexpr (MODE == 2) {
                 T xi1[3];
-                Noise<T>::draw(q.w >> 1, step + 1, ph.seed, xi1);
-                xi[0] += xi1[0];
-                xi[1] += xi1[1];
-                xi[2] += xi1[2];
+                Noise<T>::draw(q[b].w >> 1, step + 1, ph.seed, xi1);
+                xi[b][0] += xi1[0];
+                xi[b][1] += xi1[1];
+                xi[b][2] += xi1[2];
             }
             long long dq[3] = {0, 0, 0};
             bool bad = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                T disp = mob * f[a] + amp * xi[a];
-                if constexpr (MODE == 2) disp += (T)ph.gjf_a * ((T)ph.gjf_vs * u[a]);
+                // explicit fused steps: every instantiation rounds alike
+                T disp = fma_t(mob, f[b][a], amp * xi[b][a]);
+                if constexpr (MODE == 2) disp = fma_t((T)ph.gjf_a, (T)ph.gjf_vs * u[b][a], disp);
                 const double sd = (double)disp * inv_l[a];
                 if (!(fabs(sd) < 4.0e18)) bad = true;  // also true for NaN
                 else dq[a] = llrint(sd);
@@ -1403,7 +1456,8 @@ __global__ void __launch_bounds__(256)
                 atomicOr(flag, 1u);
                 dq[0] = dq[1] = dq[2] = 0;
             }
-            const uint4 qn = uint4{q.x + (uint32_t)dq[0], q.y + (uint32_t)dq[1], q.z + (uint32_t)dq[2], q.w};
+            const uint4 qn =
+                uint4{q[b].x + (uint32_t)dq[0], q[b].y + (uint32_t)dq[1], q[b].z + (uint32_t)dq[2], q[b].w};
             pout[j] = qn;
             if constexpr (MODE == 2) {
                 // realised displacement: dq minus the step's shift (a small integer)
@@ -1416,10 +1470,13 @@ __global__ void __launch_bounds__(256)
                 }
                 vout[4 * j + 3] = (T)0;
             }
-            kb = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
+            kb[b] = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
         }
-        const uint32_t r = bin_rank(kb, active, counts);  // whole wavefronts take part
-        if (active) kr[j] = uint2{kb, r};
+        uint32_t r[NB];
+        block_rank<NB, 256>(kb, act, r, counts);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            if (act[b]) kr[jb[b]] = uint2{kb[b], r[b]};
     } else {
         const long long j = blockIdx.x * 256LL + tid;
         if (j < n) {
@@ -1579,31 +1636,37 @@ __global__ void __launch_bounds__(256)
 }
 
 // The Gaussian increments of step `step` (GJF: steps step and step + 1; the
-// same draws the update takes) of bead j of a 256-bead block (j < 0: none),
-// summed over the block in 32.32 fixed point (exact for float increments, so
-// the total over blocks does not depend on the bead order) into out[0 .. 2].
-// Called by all 256 threads of the block.
-template <typename T>
-__device__ __forceinline__ void noise_sum_block(const uint4* __restrict__ pos, long long j, const Phys& ph,
-                                                uint64_t step, long long* __restrict__ out) {
-    __shared__ long long nred[3 * 4];
-    long long ns[3] = {0, 0, 0};
-    if (j >= 0) {
-        const uint32_t id = pos[j].w >> 1;
-        T xi[3];
-        Noise<T>::draw(id, step, ph.seed, xi);
-        if (ph.gjf) {
-            T x1[3];
-            Noise<T>::draw(id, step + 1, ph.seed, x1);
+// draws the update takes) of the beads with ABI ids id[c] (valid[c]) of NB
+// 256-bead chunks, summed per chunk in 32.32 fixed point (exact for float
+// increments, so the total over chunks does not depend on the bead order) into
+// out[3 c .. 3 c + 2] for the first nout chunks (the others lie past the last
+// bead).  Called by all 256 threads of the block, lane t holding bead t of
+// every chunk.
+template <typename T, int NB>
+__device__ __forceinline__ void noise_sum_chunks(const uint32_t id[NB], const bool valid[NB], const Phys& ph,
+                                                 uint64_t step, long long* __restrict__ out, long long nout) {
+    __shared__ long long nred[3 * NB * 4];
+    long long ns[3 * NB];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) xi[a] += x1[a];
+    for (int c = 0; c < NB; ++c) {
+        ns[3 * c] = ns[3 * c + 1] = ns[3 * c + 2] = 0;
+        if (valid[c]) {
+            T xi[3];
+            Noise<T>::draw(id[c], step, ph.seed, xi);
+            if (ph.gjf) {
+                T x1[3];
+                Noise<T>::draw(id[c], step + 1, ph.seed, x1);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xi[a] += x1[a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) ns[3 * c + a] = llrint((double)xi[a] * kTwo32);
         }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ns[a] = llrint((double)xi[a] * kTwo32);
     }
-    block_sum<long long, 3>(ns, nred, threadIdx.x, 256);
+    block_sum<long long, 3 * NB>(ns, nred, threadIdx.x, 256);
     if (threadIdx.x == 0)
-        for (int a = 0; a < 3; ++a) out[a] = ns[a];
+        for (int q = 0; q < 3 * NB; ++q)
+            if (q < 3 * nout) out[q] = ns[q];
 }
 
 // Noise sums of step `step` per 256-bead block of pos (any order), as the
@@ -1626,7 +1689,9 @@ __global__ void __launch_bounds__(256)
         blk = (long long)(e & 0xffffu);
     }
     const long long j = blk * 256LL + threadIdx.x;
-    noise_sum_block<T>(pos, j < n ? j : -1, ph, step, noise_part + 3 * blk);
+    const bool valid[1] = {j < n};
+    const uint32_t id[1] = {valid[0] ? pos[j].w >> 1 : 0u};
+    noise_sum_chunks<T, 1>(id, valid, ph, step, noise_part + 3 * blk, 1);
 }
 
 // Move every bead of the previous order to its sorted slot, translate its
@@ -1638,9 +1703,16 @@ __global__ void __launch_bounds__(256)
 // current shift qs and order P) to grec[slot].
 //
 // With noise_part, the block also sums the Gaussian increments of step
-// noise_step (GJF: of steps noise_step and noise_step + 1) over its beads, for
-// the centre-of-mass shift of that step (noise_sum_block).
-template <typename T, bool BATCH = false>
+// noise_step (GJF: of steps noise_step and noise_step + 1) over each of its
+// 256-bead chunks, for the centre-of-mass shift of that step
+// (noise_sum_chunks).
+//
+// NB beads per thread, 256 apart, the block covering NB * 256 consecutive
+// beads.  DEG > 0: the partner table has exactly DEG columns, and the
+// partners' slots and positions are held in registers, so the dependent reads
+// of all NB beads (key and rank, then bin start) are in flight together;
+// DEG == 0: any width, one bead per thread.
+template <typename T, bool BATCH = false, int NB = 1, int DEG = 0>
 __global__ void __launch_bounds__(256)
     k_scatter(const uint4* __restrict__ pos_tmp, const uint2* __restrict__ kr, const uint32_t* __restrict__ bin_start,
               const int32_t* __restrict__ nbr_src, uint4* __restrict__ pos, int32_t* __restrict__ nbr_dst,
@@ -1648,9 +1720,11 @@ __global__ void __launch_bounds__(256)
               const RepDesc* __restrict__ reps, const uint32_t* __restrict__ umap, int parity,
               uint4* __restrict__ grec, const uint32_t* __restrict__ qs, Dims d, int P,
               long long* __restrict__ noise_part, uint64_t noise_step) {
+    static_assert(DEG > 0 || NB == 1, "a partner table of any width takes one bead per thread");
     // contiguous bead ranges per XCD: bond partners are near in the order
     long long blk = xcd_contiguous(blockIdx.x, gridDim.x);
     if constexpr (BATCH) {
+        static_assert(NB == 1 && DEG == 0, "batched scatter: one bead per thread");
         const uint32_t e = umap[blk];
         const RepDesc& R = reps[e >> 16];
         pos_tmp = R.S.pos_tmp;
@@ -1672,40 +1746,133 @@ __global__ void __launch_bounds__(256)
         noise_step += R.step0;        // noise_step: the step's index within the batch call, plus one
         blk = (long long)(e & 0xffffu);
     }
-    const long long j = blk * 256LL + threadIdx.x;
-    if (noise_part) noise_sum_block<T>(pos_tmp, j < n ? j : -1, ph, noise_step, noise_part + 3 * blk);
-    if (j >= n) return;
-    const uint2 kj = kr[j];
-    const long long nw = (long long)bin_start[kj.x] + kj.y;
-    const uint4 q = pos_tmp[j];
-    pos[nw] = q;
-    if constexpr (sizeof(T) == 4)
-        grec[nw] = uint4{grid_record(q.x - qs[0], d.mx, P), grid_record(q.y - qs[1], d.my, P),
-                         grid_record(q.z - qs[2], d.mz, P), q.w};
-    if (vdst) {
+    constexpr int DR = DEG > 0 ? DEG : 1;
+    long long jb[NB];
+    bool act[NB];
+    uint2 kj[NB];
+    uint4 q[NB];
+    int32_t pp[NB][DR];
+    // first reads: key and rank, position, partner slots (DEG > 0: a lane past
+    // the end reads the last bead and discards it)
 #pragma unroll
-        for (int a = 0; a < 4; ++a) vdst[4 * nw + a] = vsrc[4 * j + a];
-    }
-    const T c = (T)(-2.0 * ph.bond_k);
-    const T sx = (T)(ph.lx * kInvTwo32), sy = (T)(ph.ly * kInvTwo32), sz = (T)(ph.lz * kInvTwo32);
-    T f[3] = {0, 0, 0};
-    for (int b = 0; b < deg; ++b) {
-        const int p = nbr_src[j * deg + b];
-        int32_t np_ = -1;
-        if (p >= 0) {
-            const uint2 kp = kr[p];
-            np_ = (int32_t)(bin_start[kp.x] + kp.y);
-            const uint4 qp = pos_tmp[p];
-            f[0] += c * sx * (T)fixed_delta(q.x, qp.x);
-            f[1] += c * sy * (T)fixed_delta(q.y, qp.y);
-            f[2] += c * sz * (T)fixed_delta(q.z, qp.z);
+    for (int b = 0; b < NB; ++b) {
+        jb[b] = (blk * NB + b) * 256LL + threadIdx.x;
+        act[b] = jb[b] < n;
+        kj[b] = uint2{0u, 0u};
+        q[b] = uint4{0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int e = 0; e < DR; ++e) pp[b][e] = -1;
+        if constexpr (DEG > 0) {
+            const long long j = act[b] ? jb[b] : n - 1;
+            kj[b] = kr[j];
+            q[b] = pos_tmp[j];
+#pragma unroll
+            for (int e = 0; e < DEG; ++e) pp[b][e] = nbr_src[j * DEG + e];
+        } else if (act[b]) {
+            kj[b] = kr[jb[b]];
+            q[b] = pos_tmp[jb[b]];
         }
-        nbr_dst[nw * deg + b] = np_;
     }
-    fbond[4 * nw + 0] = f[0];
-    fbond[4 * nw + 1] = f[1];
-    fbond[4 * nw + 2] = f[2];
-    fbond[4 * nw + 3] = (T)0;
+    // the block's noise sums, drawn while its reads are in flight
+    auto noise_sums = [&]() {
+        if (!noise_part) return;
+        uint32_t id[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) id[b] = q[b].w >> 1;
+        noise_sum_chunks<T, NB>(id, act, ph, noise_step, noise_part + 3 * (blk * NB), (n + 255) / 256 - blk * NB);
+    };
+    // bond force factors per axis (explicit fused steps below: every
+    // instantiation rounds alike)
+    const T c = (T)(-2.0 * ph.bond_k);
+    const T csx = c * (T)(ph.lx * kInvTwo32), csy = c * (T)(ph.ly * kInvTwo32), csz = c * (T)(ph.lz * kInvTwo32);
+    if constexpr (DEG == 0) {
+        noise_sums();
+        const long long j = jb[0];
+        if (!act[0]) return;
+        const long long nw = (long long)bin_start[kj[0].x] + kj[0].y;
+        const uint4 qj = q[0];
+        pos[nw] = qj;
+        if constexpr (sizeof(T) == 4)
+            grec[nw] = uint4{grid_record(qj.x - qs[0], d.mx, P), grid_record(qj.y - qs[1], d.my, P),
+                             grid_record(qj.z - qs[2], d.mz, P), qj.w};
+        if (vdst) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) vdst[4 * nw + a] = vsrc[4 * j + a];
+        }
+        T f[3] = {0, 0, 0};
+        for (int b = 0; b < deg; ++b) {
+            const int p = nbr_src[j * deg + b];
+            int32_t np_ = -1;
+            if (p >= 0) {
+                const uint2 kp = kr[p];
+                np_ = (int32_t)(bin_start[kp.x] + kp.y);
+                const uint4 qp = pos_tmp[p];
+                f[0] = fma_t(csx, (T)fixed_delta(qj.x, qp.x), f[0]);
+                f[1] = fma_t(csy, (T)fixed_delta(qj.y, qp.y), f[1]);
+                f[2] = fma_t(csz, (T)fixed_delta(qj.z, qp.z), f[2]);
+            }
+            nbr_dst[nw * deg + b] = np_;
+        }
+        fbond[4 * nw + 0] = f[0];
+        fbond[4 * nw + 1] = f[1];
+        fbond[4 * nw + 2] = f[2];
+        fbond[4 * nw + 3] = (T)0;
+    } else {
+        // second reads: own bin start, partners' keys, ranks and positions (a
+        // missing partner reads the bead itself)
+        uint32_t bs[NB];
+        uint2 kp[NB][DEG];
+        uint4 qp[NB][DEG];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const long long j = act[b] ? jb[b] : n - 1;
+            bs[b] = bin_start[kj[b].x];
+#pragma unroll
+            for (int e = 0; e < DEG; ++e) {
+                const long long p = pp[b][e] >= 0 ? (long long)pp[b][e] : j;
+                kp[b][e] = kr[p];
+                qp[b][e] = pos_tmp[p];
+            }
+        }
+        noise_sums();
+        // third reads: the partners' bin starts
+        int32_t np_[NB][DEG];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < DEG; ++e) {
+                const int32_t s0 = (int32_t)(bin_start[kp[b][e].x] + kp[b][e].y);
+                np_[b][e] = pp[b][e] >= 0 ? s0 : -1;
+            }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (!act[b]) continue;
+            const long long j = jb[b], nw = (long long)bs[b] + kj[b].y;
+            const uint4 qj = q[b];
+            pos[nw] = qj;
+            if constexpr (sizeof(T) == 4)
+                grec[nw] = uint4{grid_record(qj.x - qs[0], d.mx, P), grid_record(qj.y - qs[1], d.my, P),
+                                 grid_record(qj.z - qs[2], d.mz, P), qj.w};
+            if (vdst) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) vdst[4 * nw + a] = vsrc[4 * j + a];
+            }
+            T f[3] = {0, 0, 0};
+#pragma unroll
+            for (int e = 0; e < DEG; ++e) {
+                if (pp[b][e] >= 0) {
+                    f[0] = fma_t(csx, (T)fixed_delta(qj.x, qp[b][e].x), f[0]);
+                    f[1] = fma_t(csy, (T)fixed_delta(qj.y, qp[b][e].y), f[1]);
+                    f[2] = fma_t(csz, (T)fixed_delta(qj.z, qp[b][e].z), f[2]);
+                }
+                nbr_dst[nw * DEG + e] = np_[b][e];
+            }
+            fbond[4 * nw + 0] = f[0];
+            fbond[4 * nw + 1] = f[1];
+            fbond[4 * nw + 2] = f[2];
+            fbond[4 * nw + 3] = (T)0;
+        }
+    }
 }
 
 // ------------------------------------------------------------ positions I/O

@@ -155,12 +155,13 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool
 template <typename T, int P, int MODE>
 static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts,
                      double out_sign) {
-    // one bead per thread, at least one block
-    const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256);
-    hipLaunchKernelGGL((k_update<T, P, MODE>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp, (const T*)S.fbond,
-                       (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype, parts, out_sign, S.kr,
-                       S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp, (const RepDesc*)nullptr,
-                       (const uint32_t*)nullptr, 0);
+    // steps: kStepBeads beads per thread; forces only: one; at least one block
+    constexpr int NB = MODE == 1 ? 1 : kStepBeads;
+    const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256 * NB);
+    hipLaunchKernelGGL((k_update<T, P, MODE, false, NB>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp,
+                       (const T*)S.fbond, (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype,
+                       parts, out_sign, S.kr, S.counts, S.flag, S.qshift, (const T*)S.vel, (T*)S.vel_tmp,
+                       (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0);
 }
 
 template <typename T, int MODE>
@@ -201,20 +202,32 @@ hipError_t launch_bin_scan(const Launch& L, DeviceState& S) {
     return hipGetLastError();
 }
 
+template <typename T, int NB, int DEG>
+static void scatter_t(const Launch& L, DeviceState& S, const int32_t* nbr_src, long long* np, uint64_t ns) {
+    hipLaunchKernelGGL((k_scatter<T, false, NB, DEG>), dim3(blocks_for(S.n, 256 * NB)), dim3(256), 0, L.stream,
+                       S.pos_tmp, S.kr, S.bin_start, nbr_src, S.pos, S.nbr_old, (T*)S.fbond, S.n, S.deg, L.ph,
+                       (const T*)S.vel_tmp, (T*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0, S.grec,
+                       S.qshift, L.d, L.order, np, ns);
+}
+
+template <typename T>
+static void scatter_deg(const Launch& L, DeviceState& S, const int32_t* nbr_src, long long* np, uint64_t ns) {
+    // partner tables up to kStepDeg columns wide are held in registers
+    switch (S.deg) {
+        case 1: scatter_t<T, kStepBeads, 1>(L, S, nbr_src, np, ns); break;
+        case 2: scatter_t<T, kStepBeads, 2>(L, S, nbr_src, np, ns); break;
+        case 3: scatter_t<T, kStepBeads, 3>(L, S, nbr_src, np, ns); break;
+        case 4: scatter_t<T, kStepBeads, 4>(L, S, nbr_src, np, ns); break;
+        default: scatter_t<T, 1, 0>(L, S, nbr_src, np, ns); break;
+    }
+}
+
 hipError_t launch_scatter(const Launch& L, DeviceState& S, const int32_t* nbr_src, int64_t noise_step) {
     if (S.n == 0) return hipSuccess;
     long long* np = noise_step >= 0 ? S.noise_part : nullptr;
     const uint64_t ns = noise_step >= 0 ? (uint64_t)noise_step : 0u;
-    if (L.precision == 0)
-        hipLaunchKernelGGL((k_scatter<float, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
-                           S.bin_start, nbr_src, S.pos, S.nbr_old, (float*)S.fbond, S.n, S.deg, L.ph,
-                           (const float*)S.vel_tmp, (float*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
-                           S.grec, S.qshift, L.d, L.order, np, ns);
-    else
-        hipLaunchKernelGGL((k_scatter<double, false>), dim3(blocks_for(S.n, 256)), dim3(256), 0, L.stream, S.pos_tmp, S.kr,
-                           S.bin_start, nbr_src, S.pos, S.nbr_old, (double*)S.fbond, S.n, S.deg, L.ph,
-                           (const double*)S.vel_tmp, (double*)S.vel, (const RepDesc*)nullptr, (const uint32_t*)nullptr, 0,
-                           S.grec, S.qshift, L.d, L.order, np, ns);
+    if (L.precision == 0) scatter_deg<float>(L, S, nbr_src, np, ns);
+    else scatter_deg<double>(L, S, nbr_src, np, ns);
     return hipGetLastError();
 }
 
