@@ -1281,6 +1281,24 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
 
 // ------------------------------------------------------------ gather + bonds + update
 
+// Rank of the calling lane among the active lanes of its wavefront that hold
+// the same key in one run of consecutive lanes; the run's first lane takes
+// the whole run's places in the bin with a single atomic.
+__device__ __forceinline__ uint32_t bin_rank(uint32_t kb, bool active, uint32_t* __restrict__ counts) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t prev = __shfl_up(kb, 1, 64);
+    const bool head = !active || lane == 0 || prev != kb;
+    const unsigned long long hm = __ballot(head);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int hl = 63 - __clzll(hm & upto);
+    const unsigned long long above = hm & ~upto;
+    const int nl = above ? __ffsll((long long)above) - 1 : 64;
+    uint32_t base = 0;
+    if (active && lane == hl) base = atomicAdd(&counts[kb], (uint32_t)(nl - hl));
+    base = __shfl(base, hl, 64);
+    return base + (uint32_t)(lane - hl);
+}
+
 // Ranks r[b] of a workgroup's beads in their bins (keys kb[b], active act[b]).
 // The beads of a workgroup are consecutive in the sorted order and move at
 // most a few rows or planes per step, so their new keys fall in a narrow
@@ -1472,8 +1490,18 @@ __global__ void __launch_bounds__(256)
             }
             kb[b] = bin_key(qn.y - nsh[1], qn.z - nsh[2], qn.w & 1u, d, P);
         }
+        // ranks: Euler-Maruyama moves about a third of the beads to another bin
+        // each step, which breaks the wavefront runs of equal keys, so the
+        // workgroup aggregates per key; GJF displacements are small (the
+        // velocity carries over), the runs stay long and one atomic per run is
+        // cheaper
         uint32_t r[NB];
-        block_rank<NB, 256>(kb, act, r, counts);
+        if constexpr (MODE == 0) {
+            block_rank<NB, 256>(kb, act, r, counts);
+        } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) r[b] = bin_rank(kb[b], act[b], counts);  // whole wavefronts take part
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b)
             if (act[b]) kr[jb[b]] = uint2{kb[b], r[b]};

@@ -155,8 +155,9 @@ hipError_t launch_z_kmul(const Launch& L, DeviceState& S, bool energy_only, bool
 template <typename T, int P, int MODE>
 static void update_p(const Launch& L, DeviceState& S, uint64_t step, void* out, int out_dtype, unsigned parts,
                      double out_sign) {
-    // steps: kStepBeads beads per thread; forces only: one; at least one block
-    constexpr int NB = MODE == 1 ? 1 : kStepBeads;
+    // Euler-Maruyama steps: kStepBeads beads per thread; GJF steps (two draws
+    // per bead, the velocities) and forces only: one; at least one block
+    constexpr int NB = MODE == 0 ? kStepBeads : 1;
     const unsigned g = blocks_for(S.n > 0 ? S.n : 1, 256 * NB);
     hipLaunchKernelGGL((k_update<T, P, MODE, false, NB>), dim3(g), dim3(256), 0, L.stream, S.pos, S.pos_tmp,
                        (const T*)S.fbond, (const T*)S.fpart, S.qshift_next, S.n, L.d, L.ph, step, out, out_dtype,
@@ -212,7 +213,12 @@ static void scatter_t(const Launch& L, DeviceState& S, const int32_t* nbr_src, l
 
 template <typename T>
 static void scatter_deg(const Launch& L, DeviceState& S, const int32_t* nbr_src, long long* np, uint64_t ns) {
-    // partner tables up to kStepDeg columns wide are held in registers
+    // partner tables up to four columns wide are held in registers; GJF (two
+    // draws per bead for the noise sums, the velocities) keeps one bead per thread
+    if (L.ph.gjf) {
+        scatter_t<T, 1, 0>(L, S, nbr_src, np, ns);
+        return;
+    }
     switch (S.deg) {
         case 1: scatter_t<T, kStepBeads, 1>(L, S, nbr_src, np, ns); break;
         case 2: scatter_t<T, kStepBeads, 2>(L, S, nbr_src, np, ns); break;
