@@ -1352,8 +1352,8 @@ __device__ __forceinline__ void block_rank(const uint32_t kb[NB], const bool act
         r[b] = loc[b] ? s_cnt[kb[b] - k0] + lr[b] : (act[b] ? atomicAdd(&counts[kb[b]], 1u) : 0u);
 }
 
-// Beads in sorted order, one per thread: F = sum of the P plane partials of each
-// component (non-bonded, ik route) + the stored bond force.
+// Beads in sorted order, NB per thread (MODE 1: one): F = sum of the P plane
+// partials of each component (non-bonded, ik route) + the stored bond force.
 // MODE 0: Euler-Maruyama step.  The centre-of-mass correction subtracts the
 //         mean displacement; the forces sum to zero exactly (pairwise bonds;
 //         the ik route with the Nyquist derivative zeroed conserves momentum),

@@ -13,7 +13,7 @@ namespace tild {
 constexpr int kZBlock = 512;         // threads per workgroup of the z pass
 constexpr int kEpart = 9;            // energy partials per z-pass workgroup
 constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
-constexpr int kStepBeads = 2;        // beads per thread of the update and the scatter of a step
+constexpr int kStepBeads = 2;        // beads per thread of the Euler-Maruyama update and the scatter
 
 // Physical constants of one context, passed by value to kernels.
 struct Phys {
