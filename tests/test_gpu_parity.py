@@ -133,6 +133,29 @@ def test_small_systems_fp32(case):
     compare_forces(m, T.TILD_FP32, TOL32)
 
 
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("case", range(len(SMALL)))
+def test_small_systems_trajectory(case, precision):
+    """Ten EM steps at every assignment order P = 1..7 and on uneven grids:
+    the step's update, bin keys and re-sort for each order against the
+    oracle's trajectory.  FP64 positions are 32-bit fixed-point box fractions,
+    so each step rounds a displacement to 2^-32 L: ten steps agree to about
+    1e-8 of the displacement (bound 1e-7)."""
+    nc, na, nb, box, grid, P, chi, kap = SMALL[case]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=300 + case, noise_seed=0xA11CE + case)
+    x0 = snap_to_lattice(m.x, m.box)
+    say(f"[trajectory] {m.name} precision={precision}")
+    t = gpu_ctx(m, precision)
+    t.set_positions(x0)
+    t.step(10)
+    xg = t.get_positions()
+    t.close()
+    xr = R.trajectory(x0, m.types, m.bonds, oracle_params(m), 10)
+    err = rel_rms(R.min_image(xg - x0, m.box), R.min_image(xr - x0, m.box))
+    say("   displacement rel-RMS", err)
+    assert err <= (1e-7 if precision == T.TILD_FP64 else TOL32)
+
+
 def test_workload0_forces_fp32_and_fp64():
     m = make_melt(0)
     compare_forces(m, T.TILD_FP32, TOL32)
