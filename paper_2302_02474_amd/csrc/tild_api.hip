@@ -1206,10 +1206,10 @@ namespace {
 // its own status words.  hipErrorInvalidValue if a member's column block would not fit the LDS.
 hipError_t build_batch_maps(tild_batch* b, int z_cols) {
     const int32_t n_ctx = (int32_t)b->ctx.size();
-    std::vector<uint32_t> plane, c2r, zcol, bead, tile;
+    std::vector<uint32_t> plane, c2r, zcol, bead, tile, plane_small, c2r_small;
     std::vector<int> zc((size_t)n_ctx), nzb((size_t)n_ctx);
     std::vector<size_t> status_off((size_t)n_ctx, 0);
-    size_t nstatus = 0, lds_plane = 0, lds_z = 0;
+    size_t nstatus = 0, lds_plane = 0, lds_z = 0, lds_small = 0;
     for (const int32_t r : members_by_size(b->ctx.data(), n_ctx)) {
         const tild_ctx* c = b->ctx[(size_t)r];
         const Dims& d = c->L.d;
@@ -1218,18 +1218,26 @@ hipError_t build_batch_maps(tild_batch* b, int z_cols) {
         zc[(size_t)r] = Lz.z_cols;
         nzb[(size_t)r] = (int)((d.hplane + Lz.z_cols - 1) / Lz.z_cols);
         const uint32_t hi = (uint32_t)r << 16;
-        for (int u = 0; u < 2 * d.mz; ++u) plane.push_back(hi | (uint32_t)u);
-        for (int u = 0; u < 6 * d.mz; ++u) c2r.push_back(hi | (uint32_t)u);
+        // small planes (LDS for eight workgroups per CU) go to a launch of their own with fewer threads per
+        // workgroup
+        const size_t lds = plane_lds_bytes(c->L);
+        const bool small = lds <= kSmallPlaneLds;
+        for (int u = 0; u < 2 * d.mz; ++u) (small ? plane_small : plane).push_back(hi | (uint32_t)u);
+        for (int u = 0; u < 6 * d.mz; ++u) (small ? c2r_small : c2r).push_back(hi | (uint32_t)u);
         for (int u = 0; u < nzb[(size_t)r]; ++u) zcol.push_back(hi | (uint32_t)u);
         for (long long u = 0; u < (c->S.n + 255) / 256; ++u) bead.push_back(hi | (uint32_t)u);
         const int ntiles = (c->S.nbins + kScanBins - 1) / kScanBins;
         for (int u = 0; u < ntiles; ++u) tile.push_back(hi | (uint32_t)u);
         status_off[(size_t)r] = nstatus;
         nstatus += (size_t)ntiles;
-        lds_plane = std::max(lds_plane, plane_lds_bytes(c->L));
+        if (small) lds_small = std::max(lds_small, lds);
+        else lds_plane = std::max(lds_plane, lds);
         lds_z = std::max(lds_z, z_lds_bytes(Lz));
         if (nzb[(size_t)r] > 65535) return hipErrorInvalidValue;
     }
+    const int n_plane_small = (int)plane_small.size(), n_c2r_small = (int)c2r_small.size();
+    plane.insert(plane.end(), plane_small.begin(), plane_small.end());
+    c2r.insert(c2r.end(), c2r_small.begin(), c2r_small.end());
     if (lds_z > 160 * 1024) return hipErrorInvalidValue;
     const size_t nmap = plane.size() + c2r.size() + zcol.size() + bead.size() + tile.size();
     std::vector<uint32_t> all;
@@ -1256,6 +1264,9 @@ hipError_t build_batch_maps(tild_batch* b, int z_cols) {
     B.tile = B.bead + bead.size();
     B.n_plane = (int)plane.size();
     B.n_c2r = (int)c2r.size();
+    B.n_plane_small = n_plane_small;
+    B.n_c2r_small = n_c2r_small;
+    B.lds_small = lds_small;
     B.n_zcol = (int)zcol.size();
     B.n_bead = (int)bead.size();
     B.n_tile = (int)tile.size();

@@ -13,10 +13,19 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
     const int par = s & 1;
     with_order(L.order, [&](auto Pc) {
         constexpr int P = decltype(Pc)::value;
-        hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(B.n_plane), dim3(PB), lp, L.stream, (const uint4*)nullptr,
-                           (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
-                           (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, R, B.plane, par, (const T*)nullptr,
-                           (T*)nullptr, 0);
+        // members of large planes, then those of small planes (fewer threads, their own LDS size)
+        const int nbig_plane = B.n_plane - B.n_plane_small, nbig_c2r = B.n_c2r - B.n_c2r_small;
+        if (nbig_plane > 0)
+            hipLaunchKernelGGL((k_spread_xy<T, PB, P, true>), dim3(nbig_plane), dim3(PB), lp, L.stream,
+                               (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr,
+                               (cplx<T>*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr,
+                               R, B.plane, par, (const T*)nullptr, (T*)nullptr, 0);
+        if (B.n_plane_small > 0)
+            hipLaunchKernelGGL((k_spread_xy<T, kSmallPlaneBlock, P, true>), dim3(B.n_plane_small),
+                               dim3(kSmallPlaneBlock), B.lds_small, L.stream, (const uint4*)nullptr,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, (cplx<T>*)nullptr, L.d, L.px, L.py,
+                               (const cplx<T>*)nullptr, L.ph, (uint32_t*)nullptr, R, B.plane + nbig_plane, par,
+                               (const T*)nullptr, (T*)nullptr, 0);
         if (L.ph.elec)
             hipLaunchKernelGGL((k_z_kmul<T, kZBlock, 0, true, true>), dim3(B.n_zcol), dim3(kZBlock), lz, L.stream,
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
@@ -27,10 +36,18 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
                                (const cplx<T>*)nullptr, (cplx<T>*)nullptr, L.d, L.pz, (const cplx<T>*)nullptr, L.ph, 1,
                                (double*)nullptr, 0, (const long long*)nullptr, 0LL, (const uint32_t*)nullptr,
                                (uint32_t*)nullptr, (const double*)nullptr, (const double*)nullptr, 4, R, B.zcol, par);
-        hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(B.n_c2r), dim3(PB), lp, L.stream,
-                           (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
-                           (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
-                           (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr, 0);
+        if (nbig_c2r > 0)
+            hipLaunchKernelGGL((k_xy_c2r<T, PB, P, false, true>), dim3(nbig_c2r), dim3(PB), lp, L.stream,
+                               (const cplx<T>*)nullptr, (T*)nullptr, L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph,
+                               (const uint4*)nullptr, (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL,
+                               (long long*)nullptr, R, B.c2r, par, (const T*)nullptr, (const T*)nullptr, 0,
+                               (T*)nullptr, 0);
+        if (B.n_c2r_small > 0)
+            hipLaunchKernelGGL((k_xy_c2r<T, kSmallPlaneBlock, P, false, true>), dim3(B.n_c2r_small),
+                               dim3(kSmallPlaneBlock), B.lds_small, L.stream, (const cplx<T>*)nullptr, (T*)nullptr,
+                               L.d, L.px, L.py, (const cplx<T>*)nullptr, L.ph, (const uint4*)nullptr,
+                               (const uint32_t*)nullptr, (const uint32_t*)nullptr, 0LL, (long long*)nullptr, R,
+                               B.c2r + nbig_c2r, par, (const T*)nullptr, (const T*)nullptr, 0, (T*)nullptr, 0);
         hipLaunchKernelGGL((k_update<T, P, 0, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
                            (uint4*)nullptr, (const T*)nullptr, (const T*)nullptr, (const uint32_t*)nullptr, 0LL, L.d,
                            L.ph, so, (void*)nullptr, 0, 0u, 1.0, (uint2*)nullptr, (uint32_t*)nullptr,

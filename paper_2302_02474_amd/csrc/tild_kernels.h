@@ -13,6 +13,8 @@ namespace tild {
 constexpr int kZBlock = 512;         // threads per workgroup of the z pass
 constexpr int kEpart = 9;            // energy partials per z-pass workgroup
 constexpr int kScanBins = 1024;      // bins per workgroup of the bin scan
+constexpr int kSmallPlaneBlock = 128;        // threads per plane workgroup of a batch's small planes
+constexpr size_t kSmallPlaneLds = 20 * 1024;  // LDS bound of a small plane (eight workgroups per CU)
 constexpr int kStepBeads = 2;        // beads per thread of the Euler-Maruyama update and the scatter
 
 // Physical constants of one context, passed by value to kernels.
@@ -122,7 +124,11 @@ struct BatchMaps {
     const uint32_t* tile;   // bin scan tiles, ntiles per member
     int n_plane, n_c2r, n_zcol, n_bead, n_tile;
     unsigned long long* ticket;  // the batch's scan ticket
-    int plane_block;  // threads per plane workgroup (256 or 512) for every member
+    int plane_block;  // threads per plane workgroup (256 or 512) for the members of large planes
+    // the last n_plane_small / n_c2r_small units of plane / c2r belong to members of small planes, launched
+    // separately with kSmallPlaneBlock threads and lds_small bytes of LDS, so more of their workgroups fit a CU
+    int n_plane_small, n_c2r_small;
+    size_t lds_small;
 };
 
 struct Launch {
