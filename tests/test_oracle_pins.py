@@ -795,13 +795,18 @@ def test_gjf_com_correction_removes_mean_displacement_and_velocity():
 
 
 def test_structure_factor_ideal_gas_is_one():
+    # For uncorrelated uniform positions S(k) (k != 0) is exponentially
+    # distributed with unit mean, so a mean over m configurations has standard
+    # deviation 1/sqrt(m): 0.07 per wavevector at m = 200, 0.032 for the mean of
+    # the five.  The bounds are 4 and 3 of those; the draws have a seed of their
+    # own, so the result does not depend on which tests ran before.
+    g = np.random.default_rng(20230205)
     L = np.array([20.0, 20.0, 20.0])
-    x = rng.uniform(0, 1, size=(4000, 3)) * L
     nv = np.array([[1, 0, 0], [0, 2, 0], [1, 1, 1], [3, 0, 2], [0, 0, 4]])
-    S = np.mean([R.structure_factor_exact(rng.uniform(0, 1, size=(4000, 3)) * L, L, nv)
-                 for _ in range(60)], axis=0)
-    np.testing.assert_allclose(S, 1.0, atol=0.3)
-    assert abs(S.mean() - 1) < 0.12
+    S = np.mean([R.structure_factor_exact(g.uniform(0, 1, size=(4000, 3)) * L, L, nv)
+                 for _ in range(200)], axis=0)
+    np.testing.assert_allclose(S, 1.0, atol=0.28)
+    assert abs(S.mean() - 1) < 0.1
 
 
 def test_generator_ideal_chain_statistics():
