@@ -1236,6 +1236,9 @@ hipError_t build_batch_maps(tild_batch* b, int z_cols) {
         if (nzb[(size_t)r] > 65535) return hipErrorInvalidValue;
     }
     const int n_plane_small = (int)plane_small.size(), n_c2r_small = (int)c2r_small.size();
+    int deg_all = b->ctx[0]->S.deg;
+    for (const tild_ctx* c : b->ctx)
+        if (c->S.deg != deg_all) deg_all = 0;
     plane.insert(plane.end(), plane_small.begin(), plane_small.end());
     c2r.insert(c2r.end(), c2r_small.begin(), c2r_small.end());
     if (lds_z > 160 * 1024) return hipErrorInvalidValue;
@@ -1267,6 +1270,7 @@ hipError_t build_batch_maps(tild_batch* b, int z_cols) {
     B.n_plane_small = n_plane_small;
     B.n_c2r_small = n_c2r_small;
     B.lds_small = lds_small;
+    B.deg = deg_all >= 1 && deg_all <= 4 ? deg_all : 0;
     B.n_zcol = (int)zcol.size();
     B.n_bead = (int)bead.size();
     B.n_tile = (int)tile.size();

@@ -56,10 +56,22 @@ static void batch_step_t(const Launch& L, const BatchMaps& B, int s, size_t lp, 
     });
     hipLaunchKernelGGL(k_bin_scan<true>, dim3(B.n_tile), dim3(256), 0, L.stream, (uint32_t*)nullptr,
                        (uint32_t*)nullptr, 0, (unsigned long long*)nullptr, B.ticket, (uint32_t*)nullptr, R, B.tile);
-    hipLaunchKernelGGL((k_scatter<T, true>), dim3(B.n_bead), dim3(256), 0, L.stream, (const uint4*)nullptr,
-                       (const uint2*)nullptr, (const uint32_t*)nullptr, (const int32_t*)nullptr, (uint4*)nullptr,
-                       (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph, (const T*)nullptr, (T*)nullptr, R, B.bead, par,
-                       (uint4*)nullptr, (const uint32_t*)nullptr, L.d, L.order, (long long*)nullptr, so + 1);
+    // partners in registers where every member's partner table has the same width (1..4)
+    auto scatter = [&](auto Dc) {
+        constexpr int DEG = decltype(Dc)::value;
+        hipLaunchKernelGGL((k_scatter<T, true, 1, DEG>), dim3(B.n_bead), dim3(256), 0, L.stream,
+                           (const uint4*)nullptr, (const uint2*)nullptr, (const uint32_t*)nullptr,
+                           (const int32_t*)nullptr, (uint4*)nullptr, (int32_t*)nullptr, (T*)nullptr, 0LL, 0, L.ph,
+                           (const T*)nullptr, (T*)nullptr, R, B.bead, par, (uint4*)nullptr, (const uint32_t*)nullptr,
+                           L.d, L.order, (long long*)nullptr, so + 1);
+    };
+    switch (B.deg) {
+        case 1: scatter(std::integral_constant<int, 1>{}); break;
+        case 2: scatter(std::integral_constant<int, 2>{}); break;
+        case 3: scatter(std::integral_constant<int, 3>{}); break;
+        case 4: scatter(std::integral_constant<int, 4>{}); break;
+        default: scatter(std::integral_constant<int, 0>{}); break;
+    }
 }
 
 hipError_t launch_batch_noise(const Launch& L, const BatchMaps& B) {

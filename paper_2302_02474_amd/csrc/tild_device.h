@@ -1736,7 +1736,7 @@ __global__ void __launch_bounds__(256)
 // (noise_sum_chunks).
 //
 // NB beads per thread, 256 apart, the block covering NB * 256 consecutive
-// beads.  DEG > 0: the partner table has exactly DEG columns, and the
+// beads.  DEG > 0: the partner table (of every member, BATCH) has exactly DEG columns, and the
 // partners' slots and positions are held in registers, so the dependent reads
 // of all NB beads (key and rank, then bin start) are in flight together;
 // DEG == 0: any width, one bead per thread.
@@ -1752,7 +1752,7 @@ __global__ void __launch_bounds__(256)
     // contiguous bead ranges per XCD: bond partners are near in the order
     long long blk = xcd_contiguous(blockIdx.x, gridDim.x);
     if constexpr (BATCH) {
-        static_assert(NB == 1 && DEG == 0, "batched scatter: one bead per thread");
+        static_assert(NB == 1, "batched scatter: one bead per thread");
         const uint32_t e = umap[blk];
         const RepDesc& R = reps[e >> 16];
         pos_tmp = R.S.pos_tmp;

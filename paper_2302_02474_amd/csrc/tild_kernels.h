@@ -129,6 +129,7 @@ struct BatchMaps {
     // separately with kSmallPlaneBlock threads and lds_small bytes of LDS, so more of their workgroups fit a CU
     int n_plane_small, n_c2r_small;
     size_t lds_small;
+    int deg;  // the members' common partner-table width when it is 1..4 (partners held in registers), else 0
 };
 
 struct Launch {
