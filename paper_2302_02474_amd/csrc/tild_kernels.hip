@@ -216,7 +216,13 @@ static void scatter_deg(const Launch& L, DeviceState& S, const int32_t* nbr_src,
     // partner tables up to four columns wide are held in registers; GJF (two
     // draws per bead for the noise sums, the velocities) keeps one bead per thread
     if (L.ph.gjf) {
-        scatter_t<T, 1, 0>(L, S, nbr_src, np, ns);
+        switch (S.deg) {
+            case 1: scatter_t<T, 1, 1>(L, S, nbr_src, np, ns); break;
+            case 2: scatter_t<T, 1, 2>(L, S, nbr_src, np, ns); break;
+            case 3: scatter_t<T, 1, 3>(L, S, nbr_src, np, ns); break;
+            case 4: scatter_t<T, 1, 4>(L, S, nbr_src, np, ns); break;
+            default: scatter_t<T, 1, 0>(L, S, nbr_src, np, ns); break;
+        }
         return;
     }
     switch (S.deg) {
