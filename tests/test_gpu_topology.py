@@ -118,3 +118,36 @@ def test_branched_topology_trajectory_matches_oracle(arms, arm_len, n_stars, pre
         else:
             tol = TOL64 if k == "bond0" else TOL64_STEPS  # the bond forces at the input positions are exact
         assert v <= tol, (k, v)
+
+
+@pytest.mark.parametrize("mix", ["stars3", "chains_and_stars4"])
+def test_batched_topologies_equal_members_stepped_alone(mix):
+    """A batch whose members all have 3-partner tables (the batched scatter
+    holds the partners in registers), and one that mixes 2- and 4-partner
+    tables (the path of any width): positions and forces after batched steps
+    equal, bit for bit, those of the members stepped alone."""
+    if mix == "stars3":
+        ms = [stars(40 + 10 * i, 3, 3, (6.0 + i, 6.0, 7.0), (16, 12, 16), seed=50 + i) for i in range(3)]
+    else:
+        ms = [stars(60, 1 + 1, 4, (6.0, 6.0, 6.0), (12, 12, 12), seed=60),  # arms 2: linear chains
+              stars(50, 4, 2, (7.0, 6.0, 8.0), (16, 12, 16), seed=61)]
+    degs = [int(np.bincount(m.bonds.ravel(), minlength=m.n).max()) for m in ms]
+    say(f"[topology batch] {mix}: partner-table widths {degs}")
+    alone, batched = [], []
+    for i, m in enumerate(ms):
+        p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT,
+                          m.seed + i, T.TILD_FP32)
+        for dst in (alone, batched):
+            t = T.Tild(p, m.types, m.bonds)
+            t.set_positions(snap_to_lattice(m.x, m.box))
+            dst.append(t)
+    with T.Batch(batched) as bt:
+        bt.step(5)
+        bt.synchronize()
+        for a in alone:
+            a.step(5)
+        for a, b in zip(alone, batched):
+            np.testing.assert_array_equal(a.get_positions(), b.get_positions())
+            np.testing.assert_array_equal(a.forces(T.TILD_PART_TOTAL), b.forces(T.TILD_PART_TOTAL))
+    for t in alone + batched:
+        t.close()
