@@ -612,19 +612,15 @@ __device__ __forceinline__ void push_plane_ad(const T* __restrict__ Sr, const ui
         if (s < 0) s += d.mz;
         const int b0 = (K * d.mz + s) * d.my;
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
-        constexpr int U = 4;  // beads in flight per thread
-        for (uint32_t jb = j0 + (uint32_t)tid; jb < j1; jb += U * (uint32_t)nthr) {
-            uint4 qv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = jb + (uint32_t)(u * nthr);
-                qv[u] = pos[j < j1 ? j : j1 - 1u];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t j = jb + (uint32_t)(u * nthr);
-                if (j >= j1) break;
-                const uint4 q = qv[u];
+        // one bead per thread at a time, the next bead's record prefetched
+        // (see push_plane)
+        const uint32_t jt = j0 + (uint32_t)tid;
+        if (jt < j1) {
+            uint4 qn = pos[jt];
+            for (uint32_t j = jt; j < j1; j += (uint32_t)nthr) {
+                const uint4 q = qn;
+                const uint32_t jn = j + (uint32_t)nthr;
+                qn = pos[jn < j1 ? jn : j1 - 1u];
                 const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
                 const int gx = bf.gx;
                 T wx[P], wy[P], dwx[P], dwy[P];
