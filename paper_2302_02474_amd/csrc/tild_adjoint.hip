@@ -19,14 +19,21 @@ __global__ void __launch_bounds__(256) k_sum3(const TV* __restrict__ v, long lon
         for (int a = 0; a < 3; ++a) part[3 * blockIdx.x + a] = s[a];
 }
 
-// mean[a] = (sum over blocks, in block order, of part[blk][a]) / n, by one thread.
-__global__ void k_mean3(const double* __restrict__ part, int nblk, long long n, double* __restrict__ mean) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int a = 0; a < 3; ++a) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[3 * b + a];
-        mean[a] = n > 0 ? s / (double)n : 0.0;
-    }
+// The partial sums of one reduction, combined in a fixed order by one block of
+// kSumBlock threads: thread t adds blocks t, t + kSumBlock, ... in turn, then
+// the threads' sums are added by a fixed tree (block_sum).
+constexpr int kSumBlock = 256;
+
+// mean[a] = (sum of part[blk][a] over the blocks) / n.
+__global__ void __launch_bounds__(kSumBlock) k_mean3(const double* __restrict__ part, int nblk, long long n,
+                                                     double* __restrict__ mean) {
+    __shared__ double red[3 * (kSumBlock / 64)];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kSumBlock)
+        for (int a = 0; a < 3; ++a) s[a] += part[3 * b + a];
+    block_sum<double, 3>(s, red, threadIdx.x, kSumBlock);
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) mean[a] = n > 0 ? s[a] / (double)n : 0.0;
 }
 
 // pl = v - mean (mean may be NULL: pl = v).
@@ -51,12 +58,14 @@ __global__ void __launch_bounds__(256) k_dot3(const TV* __restrict__ a, const do
     if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// acc[0] += scale * (sum over blocks, in block order, of part[blk]), by one thread.
-__global__ void k_add_sum(const double* __restrict__ part, int nblk, double scale, double* __restrict__ acc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
-    acc[0] += scale * s;
+// acc[0] += scale * (sum of part[blk] over the blocks).
+__global__ void __launch_bounds__(kSumBlock) k_add_sum(const double* __restrict__ part, int nblk, double scale,
+                                                       double* __restrict__ acc) {
+    __shared__ double red[kSumBlock / 64];
+    double s[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += kSumBlock) s[0] += part[b];
+    block_sum<double, 1>(s, red, threadIdx.x, kSumBlock);
+    if (threadIdx.x == 0) acc[0] += scale * s[0];
 }
 
 // y += alpha x over 3 n values.
@@ -85,7 +94,7 @@ static hipError_t adjoint_vectors(const Launch& L, DeviceState& S, AdjointOp op,
     switch (op) {
         case AdjointOp::kMean:  // out[0..2] = mean of v
             hipLaunchKernelGGL(k_sum3<TV>, dim3(gb), dim3(256), 0, L.stream, (const TV*)v, n, part);
-            hipLaunchKernelGGL(k_mean3, dim3(1), dim3(64), 0, L.stream, (const double*)part, (int)gb, n, out);
+            hipLaunchKernelGGL(k_mean3, dim3(1), dim3(kSumBlock), 0, L.stream, (const double*)part, (int)gb, n, out);
             break;
         case AdjointOp::kProject:  // w (TV) = v - out[0..2] (out may be NULL)
             hipLaunchKernelGGL(k_project3<TV>, dim3(g3), dim3(256), 0, L.stream, (const TV*)v, (const double*)out, n,
@@ -93,7 +102,8 @@ static hipError_t adjoint_vectors(const Launch& L, DeviceState& S, AdjointOp op,
             break;
         case AdjointOp::kDotAdd:  // out[0] += alpha v . w (w float64)
             hipLaunchKernelGGL(k_dot3<TV>, dim3(gb), dim3(256), 0, L.stream, (const TV*)v, (const double*)w, n, part);
-            hipLaunchKernelGGL(k_add_sum, dim3(1), dim3(64), 0, L.stream, (const double*)part, (int)gb, alpha, out);
+            hipLaunchKernelGGL(k_add_sum, dim3(1), dim3(kSumBlock), 0, L.stream, (const double*)part, (int)gb, alpha,
+                               out);
             break;
         case AdjointOp::kAxpy:  // v += alpha w (w float64)
             hipLaunchKernelGGL(k_axpy3<TV>, dim3(g3), dim3(256), 0, L.stream, (TV*)v, (const double*)w, alpha, n);
