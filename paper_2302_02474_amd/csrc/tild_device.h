@@ -229,12 +229,16 @@ __device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint
 
 // Weighted counts (adjoint of the ik route): every bead j of the P slabs
 // z-P+1 .. z adds q_j W_j(g), q_j = vdir[4 j + comp], to the node g of plane z
-// it reaches, accumulated in floating point (T atomics in LDS).
-template <typename T, int P>
-__device__ __forceinline__ void spread_plane_weighted(T* __restrict__ acc, const uint4* __restrict__ pos,
+// it reaches, accumulated as fixed-point integers (A: int32 cells in single
+// precision, int64 in double) at the scale weighted_scale chose: each
+// contribution rounded to the nearest multiple of 1/scale, the sums exact and
+// independent of their order.
+template <typename T, int P, typename A>
+__device__ __forceinline__ void spread_plane_weighted(A* __restrict__ acc, const uint4* __restrict__ pos,
                                                       const uint32_t* __restrict__ bin_start,
                                                       const uint32_t* __restrict__ qs, const Dims d, int z, int K,
-                                                      const T* __restrict__ vdir, int comp, int tid, int nthr) {
+                                                      const T* __restrict__ vdir, int comp, T scale, int tid,
+                                                      int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
     const int pr = 4 * d.hxp;
 #pragma unroll
@@ -253,16 +257,41 @@ __device__ __forceinline__ void spread_plane_weighted(T* __restrict__ acc, const
             spline_weights<T, P>(bf.fy, wy);
             spline_weights<T, P>(bf.fz, wzs);
             const RowOffsets<P> ro(bf.gy, pr);
-            const T w0 = qj * wzs[c];
+            const T w0 = qj * wzs[c] * scale;
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                T* row = acc + ro.o[b] + 2 * gx;
+                A* row = acc + ro.o[b] + 2 * gx;
                 const T wyz = w0 * wy[b];
 #pragma unroll
-                for (int a = 0; a < P; ++a) atomicAdd(row + 2 * a, wyz * wx[a]);
+                for (int a = 0; a < P; ++a) {
+                    if constexpr (sizeof(T) == 4)
+                        atomicAdd(row + 2 * a, (A)__float2int_rn(wyz * wx[a]));
+                    else
+                        atomicAdd(row + 2 * a, (A)__double2ll_rn(wyz * wx[a]));
+                }
             }
         }
     }
+}
+
+// Largest |vdir[4 j + comp]| over the beads of the P slabs z-P+1 .. z that
+// this thread visits.
+template <typename T, int P>
+__device__ __forceinline__ T weight_max(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K,
+                                        const T* __restrict__ vdir, int comp, int tid, int nthr) {
+    T m = 0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const T v = fabs(vdir[4 * (long long)j + comp]);
+            m = v > m ? v : m;
+        }
+    }
+    return m;
 }
 
 // Add the ghost cells of the extended plane into the cells they alias
@@ -339,6 +368,20 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
     return (T)ldexp(1.0, k);
 }
 
+// Scale 2^k of the weighted counts of a plane: every cell's |sum q_j W_j(g)|
+// is at most qmax (maxcount wmax + 1), kept below half the integer range
+// (the rounding of each contribution adds at most half a unit per bead).
+template <typename T>
+__device__ __forceinline__ T weighted_scale(uint32_t maxcount, double wmax, double qmax) {
+    const double limit = sizeof(T) == 4 ? 2147483647.0 : 4611686018427387904.0;
+    const double bound = ((double)maxcount * wmax + 1.0) * qmax;
+    if (!(bound > 0.0)) return (T)1;  // no weight on this plane
+    int e = 0;
+    (void)frexp(limit / bound, &e);  // limit / bound >= 2^(e-1)
+    e = e - 2 < -120 ? -120 : (e - 2 > 120 ? 120 : e - 2);
+    return (T)ldexp(1.0, e);
+}
+
 // Plane z of species K: counts minus their mean N_K/M, then the forward
 // transform to the half spectrum H[ky][kx], kx = 0 .. mx/2.  Rows 2p and 2p+1
 // are transformed together as one complex row c_2p + i c_2p+1, stored at
@@ -354,6 +397,9 @@ __device__ __forceinline__ T spread_scale(uint32_t maxcount, double wmax, uint32
 //
 // DIR: the directional counts sum_j grad W_j . v_j (vdir) instead of the
 // counts, accumulated in floating point, with no mean to subtract and no noise.
+// WSP (with DIR): the weighted counts sum_j q_j W_j (spread_plane_weighted),
+// accumulated in fixed point at a scale from the plane's count bound and
+// largest |q_j|.
 //
 // COUNTS: write the counts c_K(z) themselves (real, [2][mz][my][mx], x
 // fastest) to cout and stop before the transforms.
@@ -373,6 +419,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax[BLOCK / 64];
+    __shared__ T sqmax[WSP ? BLOCK / 64 : 1];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
@@ -405,32 +452,47 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
 #pragma unroll
     for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
     uint32_t mine = 0;
-    if constexpr (!DIR) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
+    T qmine = 0;
+    if constexpr (!DIR || WSP) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
+    if constexpr (WSP) qmine = weight_max<T, P>(bin_start, d, z, K, vdir, comp, tid, BLOCK);
     for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
 #pragma unroll
     for (int u = 0; u < 3; ++u)
         if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
     for (int i = tid + 3 * BLOCK; i < ntw; i += BLOCK) twl[i] = tw[i];
-    if constexpr (!DIR) {
+    if constexpr (!DIR || WSP) {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             const uint32_t other = __shfl_xor(mine, o, 64);
             mine = mine > other ? mine : other;
+            if constexpr (WSP) {
+                const T qo = __shfl_xor(qmine, o, 64);
+                qmine = qmine > qo ? qmine : qo;
+            }
         }
-        if ((tid & 63) == 0) smax[tid >> 6] = mine;
+        if ((tid & 63) == 0) {
+            smax[tid >> 6] = mine;
+            if constexpr (WSP) sqmax[tid >> 6] = qmine;
+        }
     }
     __syncthreads();
     T scale = (T)1;
-    if constexpr (!DIR) {
+    if constexpr (!DIR || WSP) {
         uint32_t m = 0;
+        T qm = 0;
 #pragma unroll
-        for (int w = 0; w < BLOCK / 64; ++w) m = m > smax[w] ? m : smax[w];
-        scale = spread_scale<T>(m, ph.wmax, flag, tid);
+        for (int w = 0; w < BLOCK / 64; ++w) {
+            m = m > smax[w] ? m : smax[w];
+            if constexpr (WSP) qm = qm > sqmax[w] ? qm : sqmax[w];
+        }
+        if constexpr (WSP) scale = weighted_scale<T>(m, ph.wmax, (double)qm);
+        else scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
     if constexpr (WSP) {
-        spread_plane_weighted<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, comp, tid, BLOCK);
+        spread_plane_weighted<T, P>(reinterpret_cast<A*>(smem), pos, bin_start, qs, d, z, K, vdir, comp, scale, tid,
+                                    BLOCK);
         __syncthreads();
-        fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
+        fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     } else if constexpr (DIR) {
         spread_plane_dir<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, tid, BLOCK);
         __syncthreads();
@@ -456,7 +518,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         Walk2 w(tid, zp, BLOCK);
         for (int i = tid; i < np * zp; i += BLOCK, w.next()) {
             T vr = 0, vi = 0;
-            if constexpr (DIR) {
+            if constexpr (DIR && !WSP) {
                 const T* Sf = reinterpret_cast<const T*>(smem);
                 const T re = Sf[2 * i], im = Sf[2 * i + 1];
                 if (w.x < mx) {
