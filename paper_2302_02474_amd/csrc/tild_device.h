@@ -184,13 +184,15 @@ __device__ __forceinline__ void spread_plane(unsigned char* __restrict__ lds, co
 
 // Directional counts (adjoint and Hessian-vector products): every bead j of
 // the P slabs z-P+1 .. z adds grad W_j(g) . v_j to the node g of plane z it
-// reaches, accumulated in floating point (T atomics in LDS).  vdir: [n][4]
-// per sorted bead.
-template <typename T, int P>
-__device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint4* __restrict__ pos,
+// reaches, accumulated as fixed-point integers (A: int32 cells in single
+// precision, int64 in double) at the scale weighted_scale chose from the
+// plane's largest |v_x|/h_x + |v_y|/h_y + |v_z|/h_z (a B-spline and its
+// derivative are at most 1).  vdir: [n][4] per sorted bead.
+template <typename T, int P, typename A>
+__device__ __forceinline__ void spread_plane_dir(A* __restrict__ acc, const uint4* __restrict__ pos,
                                                  const uint32_t* __restrict__ bin_start,
                                                  const uint32_t* __restrict__ qs, const Dims d, int z, int K,
-                                                 const T* __restrict__ vdir, int tid, int nthr) {
+                                                 const T* __restrict__ vdir, T scale, int tid, int nthr) {
     const uint32_t sx = qs[0], sy = qs[1], sz = qs[2];
     const int pr = 4 * d.hxp;
     const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
@@ -202,8 +204,8 @@ __device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint
         const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
         for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
             const uint4 q = pos[j];
-            const T vx = vdir[4 * (long long)j] * ihx, vy = vdir[4 * (long long)j + 1] * ihy;
-            const T vz = vdir[4 * (long long)j + 2] * ihz;
+            const T vx = vdir[4 * (long long)j] * ihx * scale, vy = vdir[4 * (long long)j + 1] * ihy * scale;
+            const T vz = vdir[4 * (long long)j + 2] * ihz * scale;
             const BeadFrac<T> bf = bead_frac<T, P>(q, sx, sy, sz, d.mx, d.my, d.mz);
             const int gx = bf.gx;
             T wx[P], wy[P], dwx[P], dwy[P];
@@ -218,13 +220,40 @@ __device__ __forceinline__ void spread_plane_dir(T* __restrict__ acc, const uint
             const RowOffsets<P> ro(bf.gy, pr);
 #pragma unroll
             for (int b = 0; b < P; ++b) {
-                T* row = acc + ro.o[b] + 2 * gx;
+                A* row = acc + ro.o[b] + 2 * gx;
                 const T cy = wy[b] * wzs[c] * vx, cr = dwy[b] * wzs[c] * vy + wy[b] * dwzs[c] * vz;
 #pragma unroll
-                for (int a = 0; a < P; ++a) atomicAdd(row + 2 * a, dwx[a] * cy + wx[a] * cr);
+                for (int a = 0; a < P; ++a) {
+                    if constexpr (sizeof(T) == 4)
+                        atomicAdd(row + 2 * a, (A)__float2int_rn(dwx[a] * cy + wx[a] * cr));
+                    else
+                        atomicAdd(row + 2 * a, (A)__double2ll_rn(dwx[a] * cy + wx[a] * cr));
+                }
             }
         }
     }
+}
+
+// Largest |v_x| ih_x + |v_y| ih_y + |v_z| ih_z over the beads of the P slabs
+// z-P+1 .. z that this thread visits (vdir [n][4]).
+template <typename T, int P>
+__device__ __forceinline__ T dir_weight_max(const uint32_t* __restrict__ bin_start, const Dims d, int z, int K,
+                                            const T* __restrict__ vdir, int tid, int nthr) {
+    const T ihx = (T)(d.mx / d.lx), ihy = (T)(d.my / d.ly), ihz = (T)(d.mz / d.lz);
+    T m = 0;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+        int s = z - c;
+        if (s < 0) s += d.mz;
+        const int b0 = (K * d.mz + s) * d.my;
+        const uint32_t j0 = bin_start[b0], j1 = bin_start[b0 + d.my];
+        for (uint32_t j = j0 + (uint32_t)tid; j < j1; j += (uint32_t)nthr) {
+            const T v = fabs(vdir[4 * (long long)j]) * ihx + fabs(vdir[4 * (long long)j + 1]) * ihy +
+                        fabs(vdir[4 * (long long)j + 2]) * ihz;
+            m = v > m ? v : m;
+        }
+    }
+    return m;
 }
 
 // Weighted counts (adjoint of the ik route): every bead j of the P slabs
@@ -396,10 +425,9 @@ __device__ __forceinline__ T weighted_scale(uint32_t maxcount, double wmax, doub
 // per-context arguments.
 //
 // DIR: the directional counts sum_j grad W_j . v_j (vdir) instead of the
-// counts, accumulated in floating point, with no mean to subtract and no noise.
-// WSP (with DIR): the weighted counts sum_j q_j W_j (spread_plane_weighted),
-// accumulated in fixed point at a scale from the plane's count bound and
-// largest |q_j|.
+// counts, with no mean to subtract and no noise; WSP (with DIR): the weighted
+// counts sum_j q_j W_j (spread_plane_weighted).  Both accumulate in fixed
+// point at a scale from the plane's count bound and largest bead weight.
 //
 // COUNTS: write the counts c_K(z) themselves (real, [2][mz][my][mx], x
 // fastest) to cout and stop before the transforms.
@@ -419,7 +447,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     using SA = typename std::conditional<sizeof(T) == 4, int32_t, long long>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t smax[BLOCK / 64];
-    __shared__ T sqmax[WSP ? BLOCK / 64 : 1];
+    __shared__ T sqmax[DIR ? BLOCK / 64 : 1];
     C* S = reinterpret_cast<C*>(smem);
     const int tid = threadIdx.x;
     // one XCD takes a run of consecutive planes, whose bead slabs overlap
@@ -453,39 +481,42 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
     for (int u = 0; u < 3; ++u) twv[u] = tid + u * BLOCK < ntw ? tw[tid + u * BLOCK] : C{0, 0};
     uint32_t mine = 0;
     T qmine = 0;
-    if constexpr (!DIR || WSP) mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
+    mine = stencil_count_max<P>(bin_start, d, z, K, tid, BLOCK);
     if constexpr (WSP) qmine = weight_max<T, P>(bin_start, d, z, K, vdir, comp, tid, BLOCK);
+    else if constexpr (DIR) qmine = dir_weight_max<T, P>(bin_start, d, z, K, vdir, tid, BLOCK);
     for (int i = tid; i < d.npg * zp; i += BLOCK) S[i] = C{0, 0};  // zero bits: integer or float zero
 #pragma unroll
     for (int u = 0; u < 3; ++u)
         if (tid + u * BLOCK < ntw) twl[tid + u * BLOCK] = twv[u];
     for (int i = tid + 3 * BLOCK; i < ntw; i += BLOCK) twl[i] = tw[i];
-    if constexpr (!DIR || WSP) {
+    {
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             const uint32_t other = __shfl_xor(mine, o, 64);
             mine = mine > other ? mine : other;
-            if constexpr (WSP) {
+            if constexpr (DIR) {
                 const T qo = __shfl_xor(qmine, o, 64);
                 qmine = qmine > qo ? qmine : qo;
             }
         }
         if ((tid & 63) == 0) {
             smax[tid >> 6] = mine;
-            if constexpr (WSP) sqmax[tid >> 6] = qmine;
+            if constexpr (DIR) sqmax[tid >> 6] = qmine;
         }
     }
     __syncthreads();
     T scale = (T)1;
-    if constexpr (!DIR || WSP) {
+    {
         uint32_t m = 0;
         T qm = 0;
 #pragma unroll
         for (int w = 0; w < BLOCK / 64; ++w) {
             m = m > smax[w] ? m : smax[w];
-            if constexpr (WSP) qm = qm > sqmax[w] ? qm : sqmax[w];
+            if constexpr (DIR) qm = qm > sqmax[w] ? qm : sqmax[w];
         }
+        // weighted counts: weight peak wmax; directional: the bound is per bead
         if constexpr (WSP) scale = weighted_scale<T>(m, ph.wmax, (double)qm);
+        else if constexpr (DIR) scale = weighted_scale<T>(m, 1.0, (double)qm);
         else scale = spread_scale<T>(m, ph.wmax, flag, tid);
     }
     if constexpr (WSP) {
@@ -494,9 +525,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         __syncthreads();
         fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     } else if constexpr (DIR) {
-        spread_plane_dir<T, P>(reinterpret_cast<T*>(smem), pos, bin_start, qs, d, z, K, vdir, tid, BLOCK);
+        spread_plane_dir<T, P>(reinterpret_cast<A*>(smem), pos, bin_start, qs, d, z, K, vdir, scale, tid, BLOCK);
         __syncthreads();
-        fold_ghosts<T, P>(reinterpret_cast<T*>(smem), d, tid, BLOCK);
+        fold_ghosts<A, P>(reinterpret_cast<A*>(smem), d, tid, BLOCK);
     } else {
         spread_plane<T, P>(smem, pos, bin_start, qs, d, z, K, scale, tid, BLOCK);
         __syncthreads();
@@ -518,14 +549,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(size
         Walk2 w(tid, zp, BLOCK);
         for (int i = tid; i < np * zp; i += BLOCK, w.next()) {
             T vr = 0, vi = 0;
-            if constexpr (DIR && !WSP) {
-                const T* Sf = reinterpret_cast<const T*>(smem);
-                const T re = Sf[2 * i], im = Sf[2 * i + 1];
-                if (w.x < mx) {
-                    vr = re;
-                    if (2 * w.p + 1 < my) vi = im;
-                }
-            } else {
+            {
                 const A* Si = reinterpret_cast<const A*>(smem);
                 const A re = Si[2 * i], im = Si[2 * i + 1];
                 if (w.x < mx) {
