@@ -1156,6 +1156,27 @@ struct ZPlane {
 // and the energy partials gain sum W_e |rho^_e|^2 and its virial terms.
 // BATCH: one launch for all members of a batch (stepping only: noise sums
 // given, four outputs); each member's last column block forms its shift.
+// This thread's share of the sums over blocks of part[3 blk + a], a < 3, nb
+// blocks (nb > 0): eight blocks' words in flight per thread (the last loads
+// clamped to block nb - 1 and discarded).
+template <int NTHR>
+__device__ __forceinline__ void noise_total(const long long* __restrict__ part, long long nb, long long v[3]) {
+    constexpr int U = 8;
+    for (long long i0 = threadIdx.x; i0 < nb; i0 += U * NTHR) {
+        long long x[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + (long long)u * NTHR, ic = i < nb ? i : nb - 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) x[u][a] = part[3 * ic + a];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[a] += i0 + (long long)u * NTHR < nb ? x[u][a] : 0;
+    }
+}
+
 template <typename T, int BLOCK, int ENERGY_ONLY, bool ELEC, bool BATCH = false>
 __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ spec, cplx<T>* __restrict__ zout, Dims d,
                                                   FftPlan pz, const cplx<T>* __restrict__ tw, Phys ph, int cb,
@@ -1197,8 +1218,7 @@ __global__ void __launch_bounds__(BLOCK) k_z_kmul(const cplx<T>* __restrict__ sp
         __shared__ long long nred[3 * (BLOCK / 64)];
         long long v[3] = {0, 0, 0};
         const long long nb = (n + 255) / 256;  // the 256-bead blocks that summed the step's noise
-        for (long long i = threadIdx.x; i < nb; i += BLOCK)
-            for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
+        if (nb > 0) noise_total<BLOCK>(noise_part, nb, v);
         block_sum<long long, 3>(v, nred, threadIdx.x, BLOCK);
         if (threadIdx.x == 0) {
             const double L[3] = {ph.lx, ph.ly, ph.lz};

@@ -19,10 +19,8 @@ __global__ void __launch_bounds__(kShiftBlock) k_form_shift(const long long* __r
     const int tid = threadIdx.x;
     long long v[6] = {0, 0, 0, 0, 0, 0};
     const long long nb = (n + 255) / 256;
-    for (long long i = tid; i < nb; i += kShiftBlock)
-        for (int a = 0; a < 3; ++a) v[a] += noise_part[3 * i + a];
-    for (int i = tid; i < nplanes; i += kShiftBlock)
-        for (int a = 0; a < 3; ++a) v[3 + a] += fsum_part[3 * i + a];
+    if (nb > 0) noise_total<kShiftBlock>(noise_part, nb, v);
+    if (nplanes > 0) noise_total<kShiftBlock>(fsum_part, nplanes, v + 3);
     block_sum<long long, 6>(v, red, tid, kShiftBlock);
     if (tid == 0) {
         const double L[3] = {ph.lx, ph.ly, ph.lz};
