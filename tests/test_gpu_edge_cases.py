@@ -1,0 +1,141 @@
+"""GPU parity on the degenerate inputs of the particle-mesh step: one bead,
+thousands of beads crowded into one grid cell (the largest per-cell counts,
+where the fixed-point spread scale must shrink so no accumulator overflows),
+and beads placed exactly on grid nodes and on the periodic edge of the box,
+with bonds across that edge.  Each is compared with the FP64 oracle: forces,
+energy and virial at the input positions, then the displacement after a few
+steps from the same noise."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2302_02474_amd as T
+from oracle import tild_ref as R
+from synth import snap_to_lattice
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL64 = 1e-9
+# FP64 after steps: each step rounds a bead's displacement to the 32-bit
+# fixed-point position lattice (2^-32 of the box, about 2e-9 here)
+TOL64_STEPS = 1e-7
+STEPS = 5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    torch.cuda.init()
+
+
+def rel_rms(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+BOX = (6.0, 5.0, 7.0)
+GRID = (16, 12, 20)
+KW = dict(smear_a=0.5, chi=0.8, kappa=5.0, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0, seed=0xED6E)
+
+
+def single_bead():
+    return np.array([[1.234, 2.5, 3.9]]), np.array([1], np.int32), np.zeros((0, 2), np.int32)
+
+
+def crowded():
+    """3000 beads within +-0.05 of one point (a cell is about 0.35 wide), both
+    species, plus 200 spread over the box; dimers among the crowded beads."""
+    rng = np.random.Generator(np.random.PCG64(20230206))
+    xc = np.array([2.0, 2.0, 2.0]) + rng.uniform(-0.05, 0.05, (3000, 3))
+    xs = rng.uniform(0.0, 1.0, (200, 3)) * np.asarray(BOX)
+    types = (np.arange(3200) % 2).astype(np.int32)
+    bonds = np.stack([np.arange(0, 1000, 2), np.arange(1, 1000, 2)], axis=1).astype(np.int32)
+    return np.vstack([xc, xs]), types, bonds
+
+
+def on_nodes_and_edges():
+    """100 chains of 4 beads, bonds one grid spacing long along one axis.  Each
+    coordinate sits on a grid node, one lattice step (2^-32 of the box) either
+    side of one, on the box's lower edge (0) or on its last representable point
+    (L - L 2^-32); two thirds of the chains start at L - h or at that last
+    point, so their first bond crosses the periodic edge."""
+    rng = np.random.Generator(np.random.PCG64(20230207))
+    box, grid = np.asarray(BOX), np.asarray(GRID)
+    h = box / grid
+    eps = box * 2.0 ** -32
+    x = np.empty((400, 3))
+    for c in range(100):
+        anchor = np.empty(3)
+        for a in range(3):
+            node = rng.integers(0, grid[a]) * h[a]
+            anchor[a] = [node, node + eps[a], node - eps[a], 0.0, box[a] - eps[a]][rng.integers(0, 5)]
+        ax = c % 3  # the chain runs along this axis
+        start = (c // 3) % 3
+        if start == 0:
+            anchor[ax] = box[ax] - h[ax]
+        elif start == 1:
+            anchor[ax] = box[ax] - eps[ax]
+        for k in range(4):
+            x[4 * c + k] = anchor
+            x[4 * c + k, ax] = anchor[ax] + k * h[ax]
+    x = np.mod(x, box)
+    types = rng.integers(0, 2, 400).astype(np.int32)
+    idx = np.arange(400).reshape(100, 4)
+    bonds = np.concatenate([idx[:, [0, 1]], idx[:, [1, 2]], idx[:, [2, 3]]]).astype(np.int32)
+    return x, types, bonds
+
+
+SYSTEMS = {"single bead": single_bead, "crowded cell": crowded, "nodes and edges": on_nodes_and_edges}
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("order", [4, 3])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_degenerate_inputs_match_oracle(name, order, precision):
+    x, types, bonds = SYSTEMS[name]()
+    box = np.asarray(BOX)
+    x0 = snap_to_lattice(x, box)
+    # one bead: its momentum-conserving force is zero and the centre-of-mass
+    # correction would hold it still, so its steps run without the correction
+    com = len(x0) > 1
+    say(f"[edge] {name}: n={len(x0)}, bonds={len(bonds)}, P={order}, precision={precision}, com={com}")
+    p = T.make_params(BOX, GRID, order, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"],
+                      KW["gamma"], KW["kT"], KW["seed"], precision, com)
+    t = T.Tild(p, types, bonds)
+    t.set_positions(x0)
+    f0 = t.forces(T.TILD_PART_TOTAL)
+    e0 = t.energy()
+    t.step(STEPS)
+    xg = t.get_positions()
+    t.close()
+    pr = R.Params(box=BOX, grid=GRID, order=order, com_correct=com, transform="dense", **KW)
+    ev = R.evaluate(x0, types, bonds, pr)
+    xr = R.trajectory(x0, types, bonds, pr, STEPS)
+    if len(x0) > 1:
+        fscale = np.sqrt((ev["F"] ** 2).sum(axis=1).mean())
+    else:
+        # the lone bead's force vanishes (momentum conservation) as a sum of
+        # terms of the size of the force between two like beads one smear
+        # length apart: that force is the scale of its rounding error
+        x2 = snap_to_lattice(x0 + np.array([[0.0, 0.0, 0.0], [KW["smear_a"], 0.0, 0.0]]), box)
+        ev2 = R.evaluate(x2, np.array([1, 1], np.int32), np.zeros((0, 2), np.int32), pr)
+        fscale = np.linalg.norm(ev2["F"][0])
+    errs = dict(force=np.linalg.norm(f0 - ev["F"]) / (fscale * np.sqrt(len(x0))),
+                disp=rel_rms(R.min_image(xg - x0, box), R.min_image(xr - x0, box)))
+    say("   errors", errs, "E", e0["E"], ev["E"])
+    tol = TOL32 if precision == T.TILD_FP32 else TOL64
+    assert errs["force"] <= tol, errs
+    assert errs["disp"] <= (TOL32 if precision == T.TILD_FP32 else TOL64_STEPS), errs
+    for k in ("E_bond", "E_chi", "E_kappa", "E"):
+        assert abs(e0[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e0[k], ev[k])
+    np.testing.assert_allclose(e0["W"], ev["W"], rtol=tol, atol=tol * max(np.abs(ev["W"]).max(), 1.0))
