@@ -139,3 +139,30 @@ def test_degenerate_inputs_match_oracle(name, order, precision):
     for k in ("E_bond", "E_chi", "E_kappa", "E"):
         assert abs(e0[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e0[k], ev[k])
     np.testing.assert_allclose(e0["W"], ev["W"], rtol=tol, atol=tol * max(np.abs(ev["W"]).max(), 1.0))
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP32, T.TILD_FP64])
+def test_degenerate_inputs_batched_equal_members_alone(precision):
+    """The three degenerate systems as one batch: positions and forces after
+    batched steps equal, bit for bit, those of each system stepped alone."""
+    box = np.asarray(BOX)
+    alone, batched = [], []
+    for i, name in enumerate(SYSTEMS):
+        x, types, bonds = SYSTEMS[name]()
+        p = T.make_params(BOX, GRID, 4, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"],
+                          KW["gamma"], KW["kT"], KW["seed"] + i, precision)
+        for dst in (alone, batched):
+            t = T.Tild(p, types, bonds)
+            t.set_positions(snap_to_lattice(x, box))
+            dst.append(t)
+    say(f"[edge batch] members {[t.n for t in batched]}, precision={precision}")
+    with T.Batch(batched) as bt:
+        bt.step(STEPS)
+        bt.synchronize()
+        for a in alone:
+            a.step(STEPS)
+        for a, b in zip(alone, batched):
+            np.testing.assert_array_equal(a.get_positions(), b.get_positions())
+            np.testing.assert_array_equal(a.forces(T.TILD_PART_TOTAL), b.forces(T.TILD_PART_TOTAL))
+    for t in alone + batched:
+        t.close()
