@@ -166,3 +166,48 @@ def test_degenerate_inputs_batched_equal_members_alone(precision):
             np.testing.assert_array_equal(a.forces(T.TILD_PART_TOTAL), b.forces(T.TILD_PART_TOTAL))
     for t in alone + batched:
         t.close()
+
+
+ROUTES = {  # make_params / oracle keywords of each route
+    "exact gradient": dict(force="ad"),
+    "charged, ik": dict(force="ik", charges=(1.0, -1.0), bjerrum=1.0, charge_smear=0.5),
+    "charged, exact gradient": dict(force="ad", charges=(1.0, -1.0), bjerrum=1.0, charge_smear=0.5),
+}
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("route", list(ROUTES))
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_degenerate_inputs_other_force_routes(name, route, precision):
+    """The exact-gradient force and smeared electrostatics (+-1 charges) on the
+    degenerate inputs: non-bonded forces and energies at the input positions
+    against the oracle."""
+    x, types, bonds = SYSTEMS[name]()
+    box = np.asarray(BOX)
+    x0 = snap_to_lattice(x, box)
+    kw = ROUTES[route]
+    elec = {k: v for k, v in kw.items() if k != "force"}
+    say(f"[edge route] {name}: {route}, n={len(x0)}, precision={precision}")
+    p = T.make_params(BOX, GRID, 4, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"], KW["gamma"],
+                      KW["kT"], KW["seed"], precision, True, "analytic", kw["force"], **elec)
+    t = T.Tild(p, types, bonds)
+    t.set_positions(x0)
+    f_nb = t.forces(T.TILD_PART_NONBONDED)
+    e = t.energy()
+    t.close()
+    pr = R.Params(box=BOX, grid=GRID, order=4, **KW, **elec)
+    ad = kw["force"] == "ad"
+    ev = R.evaluate(x0, types, bonds, pr, want_ad=ad)
+    ref = ev["F_nb_ad"] if ad else ev["F_nb"]
+    if len(x0) > 1:
+        fscale = np.sqrt((ref ** 2).sum(axis=1).mean())
+    else:  # as in the plain route: the force between two like beads one smear length apart
+        x2 = snap_to_lattice(x0 + np.array([[0.0, 0.0, 0.0], [KW["smear_a"], 0.0, 0.0]]), box)
+        ev2 = R.evaluate(x2, np.array([1, 1], np.int32), np.zeros((0, 2), np.int32), pr, want_ad=ad)
+        fscale = np.linalg.norm((ev2["F_nb_ad"] if ad else ev2["F_nb"])[0])
+    err = np.linalg.norm(f_nb - ref) / (fscale * np.sqrt(len(x0)))
+    say(f"   F_nb error {err:.3e}; E {e['E']:.12g} oracle {ev['E']:.12g}")
+    tol = TOL32 if precision == T.TILD_FP32 else TOL64
+    assert err <= tol
+    for k in ("E_elec", "E"):
+        assert abs(e[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e[k], ev[k])
