@@ -211,3 +211,43 @@ def test_degenerate_inputs_other_force_routes(name, route, precision):
     assert err <= tol
     for k in ("E_elec", "E"):
         assert abs(e[k] - ev[k]) <= tol * max(1.0, abs(ev[k])), (k, e[k], ev[k])
+
+
+# FP64 GJF: five steps at dt = 0.005 move a bead about 0.02 (about 0.004 a
+# step), a tenth of what five EM steps move it, while each step still rounds
+# positions to the 2^-32 lattice (about 1.6e-9 here): the lattice alone puts
+# the relative displacement error near 2e-7 and the half-step velocity error
+# (one step's displacement over sqrt(b) dt) near 3e-7, so the bound is 1e-6
+@pytest.mark.parametrize("precision,xtol,utol", [(T.TILD_FP64, 1e-6, 1e-6), (T.TILD_FP32, 1e-5, 1e-5)])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_degenerate_inputs_gjf_match_oracle(name, precision, xtol, utol):
+    """GJF steps on the degenerate inputs: the GPU's two-step form from the
+    oracle's state after one step of the published velocity form (positions
+    put on the lattice for both), then five steps of each; positions and
+    half-step velocities compared."""
+    x, types, bonds = SYSTEMS[name]()
+    box = np.asarray(BOX)
+    x0 = snap_to_lattice(x, box)
+    com = len(x0) > 1
+    mass = 1.3
+    po = R.Params(box=BOX, grid=GRID, order=4, com_correct=com, mass=mass, **KW)
+    v0 = np.random.Generator(np.random.PCG64(20230208)).normal(0.0, np.sqrt(po.kT / mass), size=x0.shape)
+    x1, v1, dx1 = R.gjf_trajectory(x0, v0, types, bonds, po, 1)
+    x1 = snap_to_lattice(x1, box)
+    xk, _, dxk = R.gjf_trajectory(x1, v1, types, bonds, po, STEPS, t0=1)
+    say(f"[edge gjf] {name}: n={len(x0)}, precision={precision}, com={com}")
+    p = T.make_params(BOX, GRID, 4, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"], KW["gamma"],
+                      KW["kT"], KW["seed"], precision, com, "analytic", "ik", "gjf", mass)
+    t = T.Tild(p, types, bonds)
+    t.set_positions(x1)
+    t.set_velocities(R.half_step_velocity(dx1, po))
+    t.step_count = 1
+    t.step(STEPS)
+    xg = t.get_positions()
+    ug = t.get_velocities()
+    t.close()
+    err_x = rel_rms(R.min_image(xg - x1, box), R.min_image(xk - x1, box))
+    err_u = rel_rms(ug, R.half_step_velocity(dxk, po))
+    say(f"   displacement rel-RMS {err_x:.3e}, half-step velocity rel-RMS {err_u:.3e}")
+    assert err_x < xtol
+    assert err_u < utol
