@@ -43,6 +43,25 @@ def rel_rms(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def lone_bead_force_scale(x0, box, pr, ad=False):
+    """The force between two like beads one smear length apart.  A lone bead's
+    force is a sum of terms of that size that cancels (exactly on the ik
+    route, by momentum conservation; nearly on the exact-gradient route), so
+    its rounding error is measured against this scale."""
+    x2 = snap_to_lattice(x0 + np.array([[0.0, 0.0, 0.0], [pr.smear_a, 0.0, 0.0]]), box)
+    ev2 = R.evaluate(x2, np.array([1, 1], np.int32), np.zeros((0, 2), np.int32), pr, want_ad=ad)
+    return np.linalg.norm((ev2["F_nb_ad"] if ad else ev2["F_nb"])[0])
+
+
+def force_error(f, ref, x0, box, pr, ad=False):
+    """RMS of f - ref over the RMS of ref (over the lone-bead scale for one bead)."""
+    if len(x0) > 1:
+        scale = np.sqrt((ref ** 2).sum(axis=1).mean())
+    else:
+        scale = lone_bead_force_scale(x0, box, pr, ad)
+    return np.linalg.norm(f - ref) / (scale * np.sqrt(len(x0)))
+
+
 BOX = (6.0, 5.0, 7.0)
 GRID = (16, 12, 20)
 KW = dict(smear_a=0.5, chi=0.8, kappa=5.0, bond_k=1.5, dt=0.005, gamma=1.0, kT=1.0, seed=0xED6E)
@@ -121,16 +140,7 @@ def test_degenerate_inputs_match_oracle(name, order, precision):
     pr = R.Params(box=BOX, grid=GRID, order=order, com_correct=com, transform="dense", **KW)
     ev = R.evaluate(x0, types, bonds, pr)
     xr = R.trajectory(x0, types, bonds, pr, STEPS)
-    if len(x0) > 1:
-        fscale = np.sqrt((ev["F"] ** 2).sum(axis=1).mean())
-    else:
-        # the lone bead's force vanishes (momentum conservation) as a sum of
-        # terms of the size of the force between two like beads one smear
-        # length apart: that force is the scale of its rounding error
-        x2 = snap_to_lattice(x0 + np.array([[0.0, 0.0, 0.0], [KW["smear_a"], 0.0, 0.0]]), box)
-        ev2 = R.evaluate(x2, np.array([1, 1], np.int32), np.zeros((0, 2), np.int32), pr)
-        fscale = np.linalg.norm(ev2["F"][0])
-    errs = dict(force=np.linalg.norm(f0 - ev["F"]) / (fscale * np.sqrt(len(x0))),
+    errs = dict(force=force_error(f0, ev["F"], x0, box, pr),
                 disp=rel_rms(R.min_image(xg - x0, box), R.min_image(xr - x0, box)))
     say("   errors", errs, "E", e0["E"], ev["E"])
     tol = TOL32 if precision == T.TILD_FP32 else TOL64
@@ -199,13 +209,7 @@ def test_degenerate_inputs_other_force_routes(name, route, precision):
     ad = kw["force"] == "ad"
     ev = R.evaluate(x0, types, bonds, pr, want_ad=ad)
     ref = ev["F_nb_ad"] if ad else ev["F_nb"]
-    if len(x0) > 1:
-        fscale = np.sqrt((ref ** 2).sum(axis=1).mean())
-    else:  # as in the plain route: the force between two like beads one smear length apart
-        x2 = snap_to_lattice(x0 + np.array([[0.0, 0.0, 0.0], [KW["smear_a"], 0.0, 0.0]]), box)
-        ev2 = R.evaluate(x2, np.array([1, 1], np.int32), np.zeros((0, 2), np.int32), pr, want_ad=ad)
-        fscale = np.linalg.norm((ev2["F_nb_ad"] if ad else ev2["F_nb"])[0])
-    err = np.linalg.norm(f_nb - ref) / (fscale * np.sqrt(len(x0)))
+    err = force_error(f_nb, ref, x0, box, pr, ad)
     say(f"   F_nb error {err:.3e}; E {e['E']:.12g} oracle {ev['E']:.12g}")
     tol = TOL32 if precision == T.TILD_FP32 else TOL64
     assert err <= tol
@@ -251,3 +255,38 @@ def test_degenerate_inputs_gjf_match_oracle(name, precision, xtol, utol):
     say(f"   displacement rel-RMS {err_x:.3e}, half-step velocity rel-RMS {err_u:.3e}")
     assert err_x < xtol
     assert err_u < utol
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("force", ["ik", "ad"])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_degenerate_inputs_second_order_match_oracle(name, force, precision):
+    """The energy gradient (positions and the interaction parameters) and the
+    Hessian-vector product on the degenerate inputs.  The crowded cell puts
+    the largest weighted counts into the direction-weighted spread, whose
+    fixed-point scale is set from a bound on them."""
+    x, types, bonds = SYSTEMS[name]()
+    box = np.asarray(BOX)
+    x0 = snap_to_lattice(x, box)
+    say(f"[edge second order] {name}: force={force}, n={len(x0)}, precision={precision}")
+    p = T.make_params(BOX, GRID, 4, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"], KW["gamma"],
+                      KW["kT"], KW["seed"], precision, True, "analytic", force)
+    v = np.random.Generator(np.random.PCG64(20230209)).normal(size=x0.shape)
+    t = T.Tild(p, types, bonds)
+    t.set_positions(x0)
+    vals, gx = t.energy_grad()
+    hv = t.hvp(v)
+    t.close()
+    pr = R.Params(box=BOX, grid=GRID, order=4, **KW)
+    ev = R.evaluate(x0, types, bonds, pr, want_ad=True)
+    g = R.energy_parameter_gradients(ev["chat"], pr.smear_a, pr.L, pr.M, pr.chi, pr.kappa, len(x0))
+    hv_ref = R.hessian_vector_product(x0, types, bonds, pr, v)
+    gx_ref = -(ev["F_nb_ad"] + ev["F_bond"])
+    err_g, err_h = force_error(gx, gx_ref, x0, box, pr, True), rel_rms(hv, hv_ref)
+    say(f"   dE/dx error {err_g:.3e}, H v rel-RMS {err_h:.3e}; dE/d(chi, kappa, a)",
+        (vals["dE_dchi"], vals["dE_dkappa"], vals["dE_da"]), "oracle", g)
+    tol = TOL32 if precision == T.TILD_FP32 else TOL64
+    assert err_g <= tol and err_h <= tol
+    assert abs(vals["E"] - ev["E"]) <= tol * max(1.0, abs(ev["E"]))
+    for got, ref in zip((vals["dE_dchi"], vals["dE_dkappa"], vals["dE_da"]), g):
+        assert abs(got - ref) <= tol * max(1.0, abs(ref)), (got, ref)
