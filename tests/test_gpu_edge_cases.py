@@ -290,3 +290,35 @@ def test_degenerate_inputs_second_order_match_oracle(name, force, precision):
     assert abs(vals["E"] - ev["E"]) <= tol * max(1.0, abs(ev["E"]))
     for got, ref in zip((vals["dE_dchi"], vals["dE_dkappa"], vals["dE_da"]), g):
         assert abs(got - ref) <= tol * max(1.0, abs(ref)), (got, ref)
+
+
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("charged", [False, True])
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_degenerate_inputs_force_vjp_match_oracle(name, charged, precision):
+    """(dF/dx)^T lambda of the ik-route force on the degenerate inputs against
+    the oracle's; the crowded cell puts the largest weighted counts into the
+    lambda-weighted spread, whose fixed-point scale is set from a bound on
+    them."""
+    x, types, bonds = SYSTEMS[name]()
+    box = np.asarray(BOX)
+    x0 = snap_to_lattice(x, box)
+    el = dict(charges=(1.0, -1.0), bjerrum=1.0, charge_smear=0.5) if charged else {}
+    say(f"[edge vjp] {name}: charged={charged}, n={len(x0)}, precision={precision}")
+    p = T.make_params(BOX, GRID, 4, KW["smear_a"], KW["chi"], KW["kappa"], KW["bond_k"], KW["dt"], KW["gamma"],
+                      KW["kT"], KW["seed"], precision, True, **el)
+    lam = np.random.Generator(np.random.PCG64(20230210)).normal(size=x0.shape)
+    t = T.Tild(p, types, bonds)
+    t.set_positions(x0)
+    got = t.force_vjp(lam)
+    t.close()
+    pr = R.Params(box=BOX, grid=GRID, order=4, **KW, **el)
+    ref = R.ik_force_vjp(x0, types, bonds, pr, lam)
+    if len(x0) > 1:
+        err = rel_rms(got, ref)
+    else:
+        # a lone bead's ik force is zero wherever it sits, so its Jacobian is
+        # zero: measured against the pair force over the smear length, times |lambda|
+        err = np.linalg.norm(got - ref) / (lone_bead_force_scale(x0, box, pr) / pr.smear_a * np.linalg.norm(lam))
+    say(f"   rel-RMS {err:.3e}")
+    assert err <= (TOL32 if precision == T.TILD_FP32 else TOL64)
