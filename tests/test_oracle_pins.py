@@ -338,6 +338,37 @@ def test_nonbonded_momentum_conservation(extra):
 
 
 @pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
+@pytest.mark.parametrize("P", [3, 4, 5])
+def test_lattice_translation_and_reflection_symmetry(extra, P):
+    """The mesh is invariant under a shift of every bead by a whole grid
+    spacing and under the reflection x -> L - x, which maps nodes onto nodes
+    (the centred spline is even): energy, virial and forces follow exactly
+    (up to rounding), with the reflected axis's force negated.  A stencil
+    start off by a node, or a sign or index slip in either force route, breaks
+    the reflection."""
+    p = small_params(order=P, grid=(8, 10, 7), **extra)
+    x, t, b = random_system(50, p, seed=21)
+    ev = R.evaluate(x, t, b, p, want_ad=True)
+    h = p.L / p.M
+    for a in range(3):
+        xs = x.copy()
+        xs[:, a] = np.mod(xs[:, a] + 2 * h[a], p.L[a])
+        es = R.evaluate(xs, t, b, p, want_ad=True)
+        xr = x.copy()
+        xr[:, a] = np.mod(p.L[a] - xr[:, a], p.L[a])
+        er = R.evaluate(xr, t, b, p, want_ad=True)
+        flip = np.ones(3)
+        flip[a] = -1.0
+        for key in ("F", "F_nb_ad"):
+            scale = np.abs(ev[key]).max()
+            np.testing.assert_allclose(es[key], ev[key], rtol=0, atol=1e-11 * scale)
+            np.testing.assert_allclose(er[key], ev[key] * flip, rtol=0, atol=1e-11 * scale)
+        for e2 in (es, er):
+            assert abs(e2["E"] - ev["E"]) <= 1e-12 * abs(ev["E"])
+            np.testing.assert_allclose(e2["W"], ev["W"], rtol=0, atol=1e-11 * np.abs(ev["W"]).max())
+
+
+@pytest.mark.parametrize("extra", [{}, CHARGED], ids=["neutral", "charged"])
 def test_energy_gradient_force_is_exact_finite_difference(extra):
     p = small_params(**extra)
     x, t, b = random_system(20, p, seed=11)
