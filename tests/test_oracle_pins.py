@@ -696,6 +696,27 @@ def test_free_diffusion_msd():
     assert abs(msd / expect - 1) < 0.03
 
 
+def test_constant_force_drift_is_force_over_friction():
+    """Beads under a constant force F drift at the terminal velocity F / gamma
+    of overdamped motion, and spread about the drifting mean as free
+    diffusion does (2 kT t / gamma per axis), at gamma != 1."""
+    p = R.Params(box=(200.0,) * 3, grid=(8,) * 3, order=2, smear_a=0.5, chi=0.0, kappa=0.0,
+                 dt=0.01, gamma=2.5, kT=0.8, seed=4, com_correct=False)
+    n, steps = 20000, 40
+    F = np.array([3.0, -1.0, 0.5])
+    x0 = np.full((n, 3), 100.0)
+    x = x0.copy()
+    ids = np.arange(n)
+    for t in range(steps):
+        x = R.em_update(x, np.broadcast_to(F, x.shape).copy(), ids, t, p)
+    d = x - x0
+    T = p.dt * steps
+    se = np.sqrt(2 * p.kT * T / p.gamma / n)  # standard error of the mean displacement per axis
+    np.testing.assert_allclose(d.mean(axis=0), F * T / p.gamma, rtol=0, atol=5 * se)
+    var = d.var(axis=0)
+    np.testing.assert_allclose(var, 2 * p.kT * T / p.gamma, rtol=0.05)
+
+
 def test_dimer_bond_length_matches_discrete_em_stationary_variance():
     """Isolated dimers under EM: the bond vector is an AR(1) process whose
     stationary variance per axis is kT / (2 k_b (1 - 2 k_b dt / gamma))."""
