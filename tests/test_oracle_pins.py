@@ -472,7 +472,7 @@ def _lamellar_target(p, n_a, period):
 @pytest.mark.parametrize("com", [True, False])
 def test_em_adjoint_matches_finite_differences(com):
     """Gradients of a density loss after 6 EM steps (fixed noise) by chi, kappa and along a direction in x0."""
-    p = small_params(dt=0.02, com_correct=com)
+    p = small_params(dt=0.04, gamma=2.0, com_correct=com)
     x, t, b = random_system(40, p, seed=31)
     target = _lamellar_target(p, int(np.sum(t == 0)), p.L[0] / 2)
     lg = lambda y, q=p: R.density_mse(y, t, q, target)
@@ -553,7 +553,7 @@ def test_ik_force_vjp_is_the_transpose_of_the_jvp(extra):
 def test_em_adjoint_ik_route_matches_finite_differences(com):
     """The adjoint through 6 EM steps with the ik-route force: dL/dchi, dL/dkappa and dL/dx0 along a
     direction against central differences with the noise held fixed."""
-    p = small_params(dt=0.02, com_correct=com)
+    p = small_params(dt=0.04, gamma=2.0, com_correct=com)
     x, t, b = random_system(40, p, seed=32)
     target = _lamellar_target(p, int(np.sum(t == 0)), p.L[0] / 2)
     lg = lambda y, q=p: R.density_mse(y, t, q, target)
