@@ -229,11 +229,13 @@ def test_force_vjp_exact_gradient_route_is_minus_hvp():
 # relative bounds: loss, dL/dx0, dL/dchi and dL/dkappa.  The GPU's positions sit on the 2^-32 lattice, which
 # moves the FP64 trajectory by about 1e-9 relative; dL/dchi is a sum with cancellation (about 1e-4 of its terms)
 @pytest.mark.parametrize("precision,tols", [(T.TILD_FP64, (1e-9, 1e-6, 1e-6)), (T.TILD_FP32, (1e-6, 1e-5, 1e-4))])
-def test_em_adjoint_ik_route_matches_oracle(precision, tols):
+@pytest.mark.parametrize("gamma,dt", [(1.0, 0.02), (2.0, 0.04)])
+def test_em_adjoint_ik_route_matches_oracle(precision, tols, gamma, dt):
     """Backpropagation through 6 EM steps on the ik route (the force tild_step runs), with COM correction,
-    against the oracle's adjoint (pinned by differences of the loss)."""
+    against the oracle's adjoint (pinned by differences of the loss); at gamma = 2 the friction's place in
+    the forward and backward steps matters (the same dt / gamma as at gamma = 1)."""
     import torch
-    m = make_custom(30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0, seed_init=931, dt=0.02)
+    m = make_custom(30, 6, 4, (6.0, 6.0, 6.0), (16, 16, 16), 4, 0.5, 5.0, seed_init=931, dt=dt, gamma=gamma)
     x0 = snap_to_lattice(m.x, m.box)
     target = _lamellar(m, 3.0)
     p = T.make_params(m.box, m.grid, m.order, m.smear_a, m.chi, m.kappa, m.bond_k, m.dt, m.gamma, m.kT, m.seed,
@@ -246,7 +248,7 @@ def test_em_adjoint_ik_route_matches_oracle(precision, tols):
     to = target.transpose(2, 1, 0)
     lo, gxo, go = R.em_adjoint(x0, m.types, m.bonds, po, 6, lambda y: R.density_mse(y, m.types, po, to), t0=3,
                                force="ik")
-    say(f"[adj-ik] precision={precision}: loss {loss:.12g} oracle {lo:.12g}; dL/dchi {g['chi']:.10g} oracle "
+    say(f"[adj-ik] precision={precision} gamma={gamma}: loss {loss:.12g} oracle {lo:.12g}; dL/dchi {g['chi']:.10g} oracle "
         f"{go['chi']:.10g}; dL/dkappa {g['kappa']:.10g} oracle {go['kappa']:.10g}; dL/dx0 rel "
         f"{rel(gx.cpu().numpy(), gxo):.2e}")
     tl, tx, tg = tols
