@@ -156,6 +156,27 @@ def test_small_systems_trajectory(case, precision):
     assert err <= (1e-7 if precision == T.TILD_FP64 else TOL32)
 
 
+@pytest.mark.parametrize("precision", [T.TILD_FP64, T.TILD_FP32])
+@pytest.mark.parametrize("gamma,kT", [(2.5, 0.7), (0.6, 1.8)])
+def test_trajectory_at_other_friction_and_temperature(gamma, kT, precision):
+    """Ten EM steps with gamma and kT away from 1: the drift (dt/gamma) F and
+    the noise amplitude sqrt(2 kT dt/gamma) of the update, and the noise sums
+    of the centre-of-mass shift, against the oracle's trajectory."""
+    nc, na, nb, box, grid, P, chi, kap = SMALL[1]
+    m = make_custom(nc, na, nb, box, grid, P, chi, kap, seed_init=340, noise_seed=0xF71C, gamma=gamma, kT=kT)
+    x0 = snap_to_lattice(m.x, m.box)
+    say(f"[trajectory] {m.name} gamma={gamma} kT={kT} precision={precision}")
+    t = gpu_ctx(m, precision)
+    t.set_positions(x0)
+    t.step(10)
+    xg = t.get_positions()
+    t.close()
+    xr = R.trajectory(x0, m.types, m.bonds, oracle_params(m), 10)
+    err = rel_rms(R.min_image(xg - x0, m.box), R.min_image(xr - x0, m.box))
+    say("   displacement rel-RMS", err)
+    assert err <= (1e-7 if precision == T.TILD_FP64 else TOL32)
+
+
 def test_workload0_forces_fp32_and_fp64():
     m = make_melt(0)
     compare_forces(m, T.TILD_FP32, TOL32)
