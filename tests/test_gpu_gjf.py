@@ -40,21 +40,22 @@ def gjf_params(m, precision, force="ik", dt=0.05, gamma=1.0, mass=1.3, com=True)
 
 @pytest.mark.parametrize("precision,xtol,utol", [(T.TILD_FP64, 1e-7, 1e-6), (T.TILD_FP32, 1e-5, 1e-5)])
 @pytest.mark.parametrize("force", ["ik", "ad"])
-def test_gjf_trajectory_matches_oracle(precision, xtol, utol, force):
+@pytest.mark.parametrize("gamma", [1.0, 2.2])
+def test_gjf_trajectory_matches_oracle(precision, xtol, utol, force, gamma):
     """The GPU carries the half-step velocity and applies the two-step form of
     GJF; the oracle runs the published velocity form.  Both start from the
     oracle's state after one step (the two forms agree from there on)."""
     m = make_melt(0)
     x0 = snap_to_lattice(m.x, m.box)
     po = R.Params(box=tuple(m.box), grid=tuple(int(v) for v in m.grid), order=m.order, smear_a=m.smear_a,
-                  chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=0.05, gamma=1.0, kT=m.kT, seed=m.seed,
+                  chi=m.chi, kappa=m.kappa, bond_k=m.bond_k, dt=0.05, gamma=gamma, kT=m.kT, seed=m.seed,
                   com_correct=True, mass=1.3)
     v0 = np.random.default_rng(11).normal(0, np.sqrt(po.kT / po.mass), size=x0.shape)
     x1, v1, dx1 = R.gjf_trajectory(x0, v0, m.types, m.bonds, po, 1, force=force)
     K = 12
     xk, _, dxk = R.gjf_trajectory(x1, v1, m.types, m.bonds, po, K, t0=1, force=force)
-    say(f"[gjf] force={force} precision={precision} n={m.n} K={K}")
-    t = T.Tild(gjf_params(m, precision, force), m.types, m.bonds)
+    say(f"[gjf] force={force} gamma={gamma} precision={precision} n={m.n} K={K}")
+    t = T.Tild(gjf_params(m, precision, force, gamma=gamma), m.types, m.bonds)
     t.set_positions(x1)
     t.set_velocities(R.half_step_velocity(dx1, po))
     t.step_count = 1
